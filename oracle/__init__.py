@@ -1,0 +1,157 @@
+"""CPU fp64 oracle for batched postfix-program fitness evaluation.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the benchmark's CPU-baseline leg, never by the product path.  It shares no
+code with the HIP library.
+
+``gp_oracle.c`` is the reference (plain interpreter, plain fp64 sums);
+``tree_eval`` is a second, independent evaluator (recursive, over a parsed
+expression tree, pure Python) used to cross-check it on brute-force sets;
+``gcl`` parses the paper's textual GCL genomes.
+
+Op numbering of the interchange format (node = op | arg << 8):
+LOAD 0, CONST 1, ADD 2, SUB 3, MUL 4, DIV 5, SIN 6, COS 7, EXP 8, LOG 9,
+SQRT 10, ABS 11; oracle-only GCL extension DUP 12, SWAP 13, DEL 14, SQUARE 15.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gp_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libgp_oracle.so")
+
+LOAD, CONST, ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, ABS = range(12)
+DUP, SWAP, DEL, SQUARE = 12, 13, 14, 15
+
+M64, M32E, M32E_UP, M32E_DN = 0, 1, 2, 3
+
+ST_VALID, ST_EMPTY, ST_BAD_OP, ST_BAD_VAR, ST_BAD_CONST = 0, 1, 2, 3, 4
+ST_UNDERFLOW, ST_TOO_DEEP, ST_FINAL_DEPTH = 5, 6, 7
+
+#: every op of the benchmark set (LOAD..ABS)
+MASK_BENCH = (1 << 12) - 1
+#: benchmark set plus the GCL stack ops and SQUARE
+MASK_GCL = (1 << 16) - 1
+
+THETA = float(np.float32(0.001))
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/libgp_oracle.so``."""
+    if not force and os.path.exists(_LIB_PATH) and \
+            os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+                           "-pthread", "-fno-fast-math", "-ffp-contract=off",
+                           "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        vp = ctypes.c_void_p
+        i64, i32, u32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+        L.oracle_check_program.argtypes = [vp, i64, i64, i32, u32, vp]
+        L.oracle_check_program.restype = ctypes.c_int
+        L.oracle_validate.argtypes = [vp, vp, i64, i64, i32, u32, vp, vp]
+        L.oracle_validate.restype = None
+        L.oracle_program_outputs.argtypes = [vp, i64, vp, i64, vp, i32, i64, i64,
+                                             u32, ctypes.c_int, vp]
+        L.oracle_program_outputs.restype = ctypes.c_int
+        L.oracle_fitness.argtypes = [vp, vp, i64, vp, i64, vp, i32, i64, vp, i64,
+                                     f64, u32, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.oracle_fitness.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _prep(nodes, offsets, consts, X, y=None):
+    nodes = np.ascontiguousarray(nodes, dtype=np.uint32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    consts = np.ascontiguousarray(consts, dtype=np.float32)
+    if consts.size == 0:
+        consts = np.zeros(1, np.float32)[:0]
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    if X.ndim == 1:
+        X = X.reshape(1, -1)
+    if y is not None:
+        y = np.ascontiguousarray(y, dtype=np.float32)
+    return nodes, offsets, consts, X, y
+
+
+def validate(nodes, offsets, n_consts, n_vars, allowed_mask=MASK_BENCH):
+    """Per-program (status, max_depth)."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.uint32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    P = offsets.size - 1
+    status = np.empty(P, np.int32)
+    maxd = np.empty(P, np.int32)
+    lib().oracle_validate(_ptr(nodes), _ptr(offsets), P, int(n_consts), int(n_vars),
+                          allowed_mask, _ptr(status), _ptr(maxd))
+    return status, maxd
+
+
+def fitness(nodes, offsets, consts, X, y, tax=0.0, allowed_mask=MASK_BENCH,
+            mode=M64, n_threads=0, return_threads=False):
+    """Fitness per program: (F, mse, status).
+
+    X is variable major, shape (n_vars, n_cases) or (n_vars, ld) with
+    ld >= n_cases = len(y).  Invalid programs: status != 0 and F = NaN.
+    """
+    nodes, offsets, consts, X, y = _prep(nodes, offsets, consts, X, y)
+    P = offsets.size - 1
+    n_vars, ld = X.shape
+    n_cases = y.size
+    assert ld >= n_cases
+    F = np.empty(P, np.float64)
+    mse = np.empty(P, np.float64)
+    status = np.empty(P, np.int32)
+    used = lib().oracle_fitness(_ptr(nodes), _ptr(offsets), P, _ptr(consts), consts.size,
+                                _ptr(X), n_vars, ld, _ptr(y), n_cases, float(tax),
+                                allowed_mask, mode, int(n_threads), _ptr(F), _ptr(mse),
+                                _ptr(status))
+    if return_threads:
+        return F, mse, status, used
+    return F, mse, status
+
+
+def program_outputs(prog, consts, X, n_cases=None, allowed_mask=MASK_BENCH, mode=M64):
+    """Per-case outputs f(x_i) of one program (a 1-D node array)."""
+    prog = np.ascontiguousarray(prog, dtype=np.uint32)
+    _, _, consts, X, _ = _prep(prog, [0, prog.size], consts, X)
+    n_vars, ld = X.shape
+    n = ld if n_cases is None else n_cases
+    out = np.empty(n, np.float64)
+    st = lib().oracle_program_outputs(_ptr(prog), prog.size, _ptr(consts), consts.size,
+                                      _ptr(X), n_vars, ld, n, allowed_mask, mode, _ptr(out))
+    if st != ST_VALID:
+        raise ValueError("invalid program (status %d)" % st)
+    return out
+
+
+def subset(nodes, offsets, idx):
+    """Programs ``idx`` of a flat population as a new (nodes, offsets)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    lens = offsets[idx + 1] - offsets[idx]
+    new_off = np.zeros(idx.size + 1, np.int64)
+    np.cumsum(lens, out=new_off[1:])
+    parts = [nodes[offsets[i]:offsets[i + 1]] for i in idx]
+    new_nodes = np.concatenate(parts) if parts else np.zeros(0, np.uint32)
+    return new_nodes.astype(np.uint32), new_off

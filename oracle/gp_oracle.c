@@ -1,0 +1,327 @@
+/*
+ * gp_oracle.c -- plain, slow, obviously correct CPU reference for the
+ * batched fitness evaluation ("Scoring", paper Table 1) of postfix
+ * symbolic-regression programs.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header or table with the HIP
+ * library: the op numbering below is the interchange format of the program
+ * arrays and is written out here independently.
+ *
+ * What is computed (the plain definition, no blocking, fusion or reordering):
+ *
+ *   F(p)       = +inf                     if invalid(p)
+ *              = MSE(p) + tau * len(p)    otherwise
+ *   MSE(p)     = (1/n) * sum_i (f_p(x_i) - y_i)^2         (fp64, plain loop)
+ *   invalid(p) = some f_p(x_i) is NaN or +-inf, or MSE(p) > FLT_MAX
+ *   f_p(x_i)   = postfix (RPN) evaluation of p on case i
+ *
+ * Sources in the paper:
+ *   - RPN stack machine: unary ops replace the top element, binary ops replace
+ *     the top two (Sec. "Genome Computer Language (GCL)").
+ *   - Stack limit of 32 elements (same section, StackSize).
+ *   - Op semantics and operand order: SUB is second-top minus top, DIV is
+ *     second-top divided by top (GCL command table, Table 3).
+ *   - Invalid values (NaN, Inf) are kept and handled per case, not removed
+ *     (Sec. "Fitness Functions", the text around Eq. 1-2); here any invalid
+ *     case output gives the program the worst fitness, +inf.
+ *   - Length tax = "Tax on Length" / parsimony pressure (Table 1 and the
+ *     ScriptLengthTaxRateInternal paragraph), charged per node.
+ *   - Inputs and targets are fp32 (MLSetup data interface, float[] / float).
+ *   - One aggregate per individual over all fitness cases (Sec. "Dividing
+ *     Tasks Between CPU and GPU").
+ *
+ * Readings where the paper is silent (each one is listed in the design notes):
+ *   - DIV is protected: |b| <= theta gives 1, else a/b; theta = fp32(0.001).
+ *     Written so that a NaN divisor still yields NaN.
+ *   - LOG (the paper's LN) is protected: |a| <= theta gives 0, else ln|a|.
+ *   - SQRT is protected: sqrt(|a|).
+ *   - ABS is |a| (not a GCL command; part of the benchmark op set).
+ *   - Every op result is passed through R(v): a finite fp64 value whose fp32
+ *     rounding would overflow becomes +-inf, so the fp32 overflow range is
+ *     emulated; NaN passes through; underflow is not emulated.
+ *   - A valid program never underflows the stack, never exceeds depth 32 and
+ *     ends with exactly one element.  len = number of nodes, leaves included.
+ *
+ * Modes:
+ *   ORACLE_M64   fp64 values with the R(v) overflow emulation (the reference).
+ *   ORACLE_M32E  as M64, but each op result is also rounded to fp32: the
+ *                result of a correctly rounded fp32 evaluator.  Sums stay fp64.
+ *   ORACLE_M32E_UP / ORACLE_M32E_DN
+ *                M32E with every sin/cos/exp/log result moved one fp32 ulp up
+ *                (down): used only to certify that a program is chaotic.
+ *
+ * Oracle-only GCL extension (so the paper's printed genomes can run):
+ *   DUP, SWAP, DEL, SQUARE (GCL command table).
+ */
+#include <math.h>
+#include <float.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+#include <unistd.h>
+
+/* ---- program interchange format: node = op | (arg << 8) ---------------- */
+enum {
+    OP_LOAD = 0,   /* arg = input variable index (zero based)            */
+    OP_CONST = 1,  /* arg = index into the constant pool                 */
+    OP_ADD = 2, OP_SUB = 3, OP_MUL = 4, OP_DIV = 5,
+    OP_SIN = 6, OP_COS = 7, OP_EXP = 8, OP_LOG = 9, OP_SQRT = 10, OP_ABS = 11,
+    /* oracle-only GCL extension */
+    OP_DUP = 12, OP_SWAP = 13, OP_DEL = 14, OP_SQUARE = 15,
+    OP_COUNT = 16
+};
+
+enum {
+    ORACLE_M64 = 0, ORACLE_M32E = 1, ORACLE_M32E_UP = 2, ORACLE_M32E_DN = 3
+};
+
+/* per-program validation status */
+enum {
+    ST_VALID = 0, ST_EMPTY = 1, ST_BAD_OP = 2, ST_BAD_VAR = 3, ST_BAD_CONST = 4,
+    ST_UNDERFLOW = 5, ST_TOO_DEEP = 6, ST_FINAL_DEPTH = 7
+};
+
+#define STACK_LIMIT 32
+
+/* theta = the fp32 number nearest to 0.001 (protected DIV and LOG). */
+static double theta(void) { return (double)0.001f; }
+
+/* Stack effect of one op: how many values it needs, and how the depth
+ * changes.  Returns 0 for an unknown op. */
+static int op_shape(uint32_t op, int* needs, int* delta)
+{
+    switch (op) {
+    case OP_LOAD: case OP_CONST: *needs = 0; *delta = +1; return 1;
+    case OP_ADD: case OP_SUB: case OP_MUL: case OP_DIV:
+        *needs = 2; *delta = -1; return 1;
+    case OP_SIN: case OP_COS: case OP_EXP: case OP_LOG: case OP_SQRT:
+    case OP_ABS: case OP_SQUARE:
+        *needs = 1; *delta = 0; return 1;
+    case OP_DUP: *needs = 1; *delta = +1; return 1;
+    case OP_SWAP: *needs = 2; *delta = 0; return 1;
+    case OP_DEL: *needs = 1; *delta = -1; return 1;
+    default: return 0;
+    }
+}
+
+/* Validate one program; writes its maximum stack depth. */
+int oracle_check_program(const uint32_t* prog, int64_t len, int64_t n_consts,
+                         int32_t n_vars, uint32_t allowed_mask,
+                         int32_t* max_depth_out)
+{
+    int depth = 0, max_depth = 0;
+    if (max_depth_out) *max_depth_out = 0;
+    if (len <= 0) return ST_EMPTY;
+    for (int64_t i = 0; i < len; ++i) {
+        uint32_t op = prog[i] & 0xFFu;
+        uint32_t arg = prog[i] >> 8;
+        int needs, delta;
+        if (!op_shape(op, &needs, &delta)) return ST_BAD_OP;
+        if (!((allowed_mask >> op) & 1u)) return ST_BAD_OP;
+        if (op == OP_LOAD && (int64_t)arg >= (int64_t)n_vars) return ST_BAD_VAR;
+        if (op == OP_CONST && (int64_t)arg >= n_consts) return ST_BAD_CONST;
+        if (depth < needs) return ST_UNDERFLOW;
+        depth += delta;
+        if (depth > STACK_LIMIT) return ST_TOO_DEEP;
+        if (depth > max_depth) max_depth = depth;
+    }
+    if (max_depth_out) *max_depth_out = max_depth;
+    if (depth != 1) return ST_FINAL_DEPTH;
+    return ST_VALID;
+}
+
+void oracle_validate(const uint32_t* nodes, const int64_t* offsets,
+                     int64_t n_programs, int64_t n_consts, int32_t n_vars,
+                     uint32_t allowed_mask, int32_t* status, int32_t* max_depth)
+{
+    for (int64_t p = 0; p < n_programs; ++p) {
+        int32_t md = 0;
+        status[p] = oracle_check_program(nodes + offsets[p],
+                                         offsets[p + 1] - offsets[p],
+                                         n_consts, n_vars, allowed_mask, &md);
+        if (max_depth) max_depth[p] = md;
+    }
+}
+
+/* Smallest magnitude whose fp32 rounding (to nearest, ties to even) is
+ * infinite: halfway between FLT_MAX = (2 - 2^-23) * 2^127 and 2^128. */
+static double fp32_overflow_edge(void) { return ldexp(2.0 - ldexp(1.0, -24), 127); }
+
+/* R(v): fp32 overflow-range emulation. */
+static double clamp_range(double v)
+{
+    if (isfinite(v) && fabs(v) >= fp32_overflow_edge())
+        return copysign(INFINITY, v);
+    return v;
+}
+
+static double round_mode(double v, int mode)
+{
+    v = clamp_range(v);
+    if (mode != ORACLE_M64 && isfinite(v)) v = (double)(float)v;
+    return v;
+}
+
+/* Transcendental results in the perturbed certification modes. */
+static double nudge(double v, int mode)
+{
+    if (!isfinite(v)) return v;
+    float f = (float)v;
+    if (mode == ORACLE_M32E_UP) f = nextafterf(f, INFINITY);
+    if (mode == ORACLE_M32E_DN) f = nextafterf(f, -INFINITY);
+    return (double)f;
+}
+
+/* Evaluate one valid program on one case.  X is variable major:
+ * X[v * ld_x + i].  Inputs and constants are fp32 read exactly as fp64. */
+static double eval_case(const uint32_t* prog, int64_t len, const float* consts,
+                        const float* X, int64_t ld_x, int64_t i, int mode)
+{
+    double st[STACK_LIMIT];
+    int sp = 0;                 /* number of values on the stack */
+    const double th = theta();
+    for (int64_t k = 0; k < len; ++k) {
+        uint32_t op = prog[k] & 0xFFu;
+        uint32_t arg = prog[k] >> 8;
+        double a, b, v;
+        switch (op) {
+        case OP_LOAD: st[sp++] = (double)X[(int64_t)arg * ld_x + i]; break;
+        case OP_CONST: st[sp++] = (double)consts[arg]; break;
+        case OP_ADD: case OP_SUB: case OP_MUL: case OP_DIV:
+            b = st[--sp];       /* top */
+            a = st[--sp];       /* second from top */
+            if (op == OP_ADD) v = a + b;
+            else if (op == OP_SUB) v = a - b;
+            else if (op == OP_MUL) v = a * b;
+            else v = (fabs(b) <= th) ? 1.0 : a / b;
+            st[sp++] = round_mode(v, mode);
+            break;
+        case OP_SIN: case OP_COS: case OP_EXP: case OP_LOG:
+            a = st[--sp];
+            if (op == OP_SIN) v = sin(a);
+            else if (op == OP_COS) v = cos(a);
+            else if (op == OP_EXP) v = exp(a);
+            else v = (fabs(a) <= th) ? 0.0 : log(fabs(a));
+            v = round_mode(v, mode);
+            if (mode == ORACLE_M32E_UP || mode == ORACLE_M32E_DN) v = nudge(v, mode);
+            st[sp++] = v;
+            break;
+        case OP_SQRT: a = st[--sp]; st[sp++] = round_mode(sqrt(fabs(a)), mode); break;
+        case OP_ABS: a = st[--sp]; st[sp++] = fabs(a); break;
+        case OP_SQUARE: a = st[--sp]; st[sp++] = round_mode(a * a, mode); break;
+        case OP_DUP: a = st[sp - 1]; st[sp++] = a; break;
+        case OP_SWAP: a = st[sp - 1]; st[sp - 1] = st[sp - 2]; st[sp - 2] = a; break;
+        case OP_DEL: --sp; break;
+        default: return NAN;    /* unreachable for a validated program */
+        }
+    }
+    return st[0];
+}
+
+/* Per-case outputs f_p(x_i) of one program (for tests).  Returns the
+ * validation status; out is left untouched for an invalid program. */
+int oracle_program_outputs(const uint32_t* prog, int64_t len,
+                           const float* consts, int64_t n_consts,
+                           const float* X, int32_t n_vars, int64_t ld_x,
+                           int64_t n_cases, uint32_t allowed_mask, int mode,
+                           double* out)
+{
+    int st = oracle_check_program(prog, len, n_consts, n_vars, allowed_mask, NULL);
+    if (st != ST_VALID) return st;
+    for (int64_t i = 0; i < n_cases; ++i)
+        out[i] = eval_case(prog, len, consts, X, ld_x, i, mode);
+    return ST_VALID;
+}
+
+/* Fitness of one program; also returns the fp64 MSE (NaN if invalid). */
+static double program_fitness(const uint32_t* prog, int64_t len,
+                              const float* consts, const float* X, int64_t ld_x,
+                              const float* y, int64_t n_cases, double tax,
+                              int mode, double* mse_out)
+{
+    double sum = 0.0;
+    int bad = 0;
+    for (int64_t i = 0; i < n_cases; ++i) {
+        double f = eval_case(prog, len, consts, X, ld_x, i, mode);
+        if (!isfinite(f)) { bad = 1; break; }
+        double r = f - (double)y[i];
+        sum += r * r;
+    }
+    if (bad) { *mse_out = NAN; return INFINITY; }
+    double mse = sum / (double)n_cases;
+    *mse_out = mse;
+    if (mse > (double)FLT_MAX) return INFINITY;
+    return mse + tax * (double)len;
+}
+
+typedef struct {
+    const uint32_t* nodes; const int64_t* offsets;
+    const float* consts; int64_t n_consts;
+    const float* X; int32_t n_vars; int64_t ld_x;
+    const float* y; int64_t n_cases; double tax;
+    uint32_t allowed_mask; int mode;
+    double* out; double* mse; int32_t* status;
+    int64_t p0, p1;
+} job_t;
+
+static void* run_job(void* arg)
+{
+    job_t* j = (job_t*)arg;
+    for (int64_t p = j->p0; p < j->p1; ++p) {
+        const uint32_t* prog = j->nodes + j->offsets[p];
+        int64_t len = j->offsets[p + 1] - j->offsets[p];
+        int st = oracle_check_program(prog, len, j->n_consts, j->n_vars,
+                                      j->allowed_mask, NULL);
+        if (j->status) j->status[p] = st;
+        double mse = NAN;
+        if (st != ST_VALID) {
+            j->out[p] = NAN;    /* not a scorable program */
+        } else {
+            j->out[p] = program_fitness(prog, len, j->consts, j->X, j->ld_x,
+                                        j->y, j->n_cases, j->tax, j->mode, &mse);
+        }
+        if (j->mse) j->mse[p] = mse;
+    }
+    return NULL;
+}
+
+/* Fitness of every program.  Structurally invalid programs get NaN and a
+ * nonzero status.  n_threads <= 0 uses every online core.  Returns the
+ * number of threads used. */
+int oracle_fitness(const uint32_t* nodes, const int64_t* offsets,
+                   int64_t n_programs, const float* consts, int64_t n_consts,
+                   const float* X, int32_t n_vars, int64_t ld_x,
+                   const float* y, int64_t n_cases, double tax,
+                   uint32_t allowed_mask, int mode, int n_threads,
+                   double* out_fitness, double* out_mse, int32_t* status)
+{
+    if (n_threads <= 0) n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 256) n_threads = 256;
+    if ((int64_t)n_threads > n_programs) n_threads = n_programs > 0 ? (int)n_programs : 1;
+
+    job_t jobs[256];
+    pthread_t tids[256];
+    /* contiguous program ranges balanced by node count */
+    int64_t total = offsets[n_programs] - offsets[0];
+    int64_t p = 0;
+    for (int t = 0; t < n_threads; ++t) {
+        int64_t target = offsets[0] + (total * (t + 1)) / n_threads;
+        int64_t q = p;
+        while (q < n_programs && (offsets[q + 1] <= target || q == p)) ++q;
+        if (t == n_threads - 1) q = n_programs;
+        job_t j = { nodes, offsets, consts, n_consts, X, n_vars, ld_x, y,
+                    n_cases, tax, allowed_mask, mode, out_fitness, out_mse,
+                    status, p, q };
+        jobs[t] = j;
+        p = q;
+    }
+    for (int t = 0; t < n_threads; ++t)
+        pthread_create(&tids[t], NULL, run_job, &jobs[t]);
+    for (int t = 0; t < n_threads; ++t)
+        pthread_join(tids[t], NULL);
+    return n_threads;
+}

@@ -1,0 +1,307 @@
+"""Seeded synthetic workloads: random postfix populations and fitness cases.
+
+This module is plain input generation; it holds none of the scoring
+arithmetic and imports nothing from the library or from the oracle, so both
+sides can be fed the same arrays.
+
+Program arrays (the library's interchange format):
+    nodes   uint32[sum len]   node = op | (arg << 8)
+    offsets int64[P + 1]      program p is nodes[offsets[p]:offsets[p+1]]
+    consts  float32[C]        constant pool, CONST arg indexes it
+    X       float32[n_vars][n_cases]  variable major
+    y       float32[n_cases]
+
+Op numbering: LOAD 0, CONST 1, ADD 2, SUB 3, MUL 4, DIV 5, SIN 6, COS 7,
+EXP 8, LOG 9, SQRT 10, ABS 11.
+
+Workload recipes (fixed for this project; the paper benchmarks on data it
+does not ship, so these stand in for it):
+  1 plain eval      1,000 programs, len U{3..32}, {+,-,*,/,sin,cos,exp,log},
+                    3 vars, 1,024 cases, X ~ U(-1,1),
+                    y = x0^2 + sin(x1) x2 + N(0, sd 0.01), tax 0
+  2 full generation 100,000 programs, len U{3..64}, set 1 + {sqrt, abs},
+                    5 vars, 4,096 cases, X ~ U(-3,3), y = dense degree<=3
+                    polynomial (56 monomials, coef U(-1,1)) + N(0, 0.05),
+                    tax 1e-3
+  3 batched uneven  1,000,000 programs, len clip(Geom(1/24), 3, 128), set 2,
+                    10 vars, 16,384 cases, X ~ N(0,1), y as 2 (286 monomials)
+  4 precision       50,000 programs, len U{3..64}, set 2, 3 vars,
+                    1,048,576 cases, X ~ U(-10,10), y = degree-3 polynomial
+                    (20 monomials) scaled to max|y| = 1e4, no noise
+  5 serving         64 runs, each n_vars U{1..20}, cases log-U[256, 65536],
+                    X ~ N(0,1), y = <=32 random degree<=3 monomials + N(0,
+                    0.05); requests of log-U[1k, 200k] programs, len
+                    U{3..128}, set 2
+
+Program sampler: length L from the config's law; tokens left to right with
+current depth d and r tokens still to come after this one.  A class is
+feasible when: leaf d+1 <= 32 and d <= r; unary d >= 1 and d-1 <= r; binary
+d >= 2 and d-2 <= r.  A feasible class is picked uniformly, then an op
+uniformly inside it; a leaf is a variable (uniform index) with probability
+1/2, else a constant U(-5,5) rounded to fp32.  Never dead-ends, always ends
+at depth 1, never exceeds depth 32.  (With no unary op in the set, the
+lengths must be odd and a class is also required to leave an even number of
+tokens to pair up.)
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+LOAD, CONST, ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, ABS = range(12)
+BINARY = (ADD, SUB, MUL, DIV)
+UNARY_1 = (SIN, COS, EXP, LOG)
+UNARY_2 = (SIN, COS, EXP, LOG, SQRT, ABS)
+STACK_LIMIT = 32
+
+
+def op_mask(ops):
+    m = (1 << LOAD) | (1 << CONST)
+    for o in ops:
+        m |= 1 << o
+    return m
+
+
+MASK_1 = op_mask(BINARY + UNARY_1)
+MASK_2 = op_mask(BINARY + UNARY_2)
+
+
+@dataclass
+class Population:
+    nodes: np.ndarray
+    offsets: np.ndarray
+    consts: np.ndarray
+
+    @property
+    def n_programs(self):
+        return self.offsets.size - 1
+
+    @property
+    def lengths(self):
+        return np.diff(self.offsets)
+
+    def take(self, idx):
+        """Programs ``idx`` as a new population (constants re-indexed)."""
+        idx = np.asarray(idx, dtype=np.int64)
+        lens = self.offsets[idx + 1] - self.offsets[idx]
+        off = np.zeros(idx.size + 1, np.int64)
+        np.cumsum(lens, out=off[1:])
+        sel = _ranges(self.offsets[idx], lens)
+        nodes = self.nodes[sel].copy()
+        is_c = (nodes & 0xFF) == CONST
+        old = (nodes[is_c] >> 8).astype(np.int64)
+        consts = self.consts[old].copy()
+        nodes[is_c] = CONST | (np.arange(old.size, dtype=np.uint32) << 8)
+        return Population(nodes.astype(np.uint32), off, consts.astype(np.float32))
+
+
+def _ranges(starts, lens):
+    total = int(lens.sum())
+    rep = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+    return np.arange(total, dtype=np.int64) + rep
+
+
+@dataclass
+class Dataset:
+    X: np.ndarray          # float32 [n_vars, n_cases]
+    y: np.ndarray          # float32 [n_cases]
+
+    @property
+    def n_vars(self):
+        return self.X.shape[0]
+
+    @property
+    def n_cases(self):
+        return self.y.size
+
+
+@dataclass
+class Workload:
+    name: str
+    pop: Population
+    data: Dataset
+    tax: float
+    allowed_mask: int
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def node_evals(self):
+        return int(self.pop.offsets[-1]) * int(self.data.n_cases)
+
+
+def _rngs(k, seed=None):
+    ss = np.random.SeedSequence(1000 + k if seed is None else seed)
+    kids = ss.spawn(5)
+    return [np.random.Generator(np.random.PCG64(s)) for s in kids]
+
+
+def sample_programs(rng, lengths, n_vars, unary, binary=BINARY,
+                    const_lo=-5.0, const_hi=5.0, p_var=0.5):
+    """Vectorised sampler (see module docstring)."""
+    lengths = np.asarray(lengths, dtype=np.int64)
+    P = lengths.size
+    offsets = np.zeros(P + 1, np.int64)
+    np.cumsum(lengths, out=offsets[1:])
+    total = int(offsets[-1])
+    nodes = np.zeros(total, np.uint32)
+    is_const = np.zeros(total, bool)
+    const_val = np.zeros(total, np.float32)
+    depth = np.zeros(P, np.int64)
+    unary = np.asarray(unary, np.uint32)
+    binary = np.asarray(binary, np.uint32)
+    has_unary = unary.size > 0
+    if not has_unary:
+        assert np.all(lengths % 2 == 1), "without unary ops lengths must be odd"
+    maxL = int(lengths.max()) if P else 0
+    order = np.argsort(-lengths, kind="stable")
+    sorted_len = lengths[order]
+    for t in range(maxL):
+        n_act = int(np.searchsorted(-sorted_len, -t, side="left"))
+        act = order[:n_act]
+        d = depth[act]
+        r = lengths[act] - t - 1
+        f_leaf = (d + 1 <= STACK_LIMIT) & (d <= r)
+        f_un = (d >= 1) & (d - 1 <= r) & has_unary
+        f_bin = (d >= 2) & (d - 2 <= r)
+        if not has_unary:
+            # without depth-neutral ops the remaining tokens must pair up
+            even = ((r - d) % 2) == 0
+            f_leaf &= even
+            f_bin &= even
+        nf = f_leaf.astype(np.int64) + f_un + f_bin
+        pick = np.minimum((rng.random(n_act) * nf).astype(np.int64), nf - 1)
+        # pick-th feasible class in the order leaf, unary, binary
+        cls = np.where(f_leaf & (pick == 0), 0,
+              np.where(f_un & (pick == f_leaf.astype(np.int64)), 1, 2))
+        pos = offsets[act] + t
+        u_op = rng.integers(0, max(unary.size, 1), n_act)
+        b_op = rng.integers(0, binary.size, n_act)
+        var_leaf = rng.random(n_act) < p_var
+        var_idx = rng.integers(0, n_vars, n_act)
+        cval = rng.uniform(const_lo, const_hi, n_act).astype(np.float32)
+        leaf = cls == 0
+        if has_unary:
+            nodes[pos[cls == 1]] = unary[u_op[cls == 1]]
+        nodes[pos[cls == 2]] = binary[b_op[cls == 2]]
+        lv = leaf & var_leaf
+        nodes[pos[lv]] = LOAD | (var_idx[lv].astype(np.uint32) << 8)
+        lc = leaf & ~var_leaf
+        is_const[pos[lc]] = True
+        const_val[pos[lc]] = cval[lc]
+        depth[act] = d + np.where(cls == 0, 1, np.where(cls == 1, 0, -1))
+    assert np.all(depth == 1)
+    cpos = np.nonzero(is_const)[0]
+    consts = const_val[cpos].copy()
+    nodes[cpos] = CONST | (np.arange(cpos.size, dtype=np.uint32) << 8)
+    return Population(nodes, offsets, consts)
+
+
+def monomials(n_vars, degree=3):
+    """All exponent tuples of total degree <= degree (constant term first)."""
+    out = []
+    for deg in range(degree + 1):
+        for combo in itertools.combinations_with_replacement(range(n_vars), deg):
+            out.append(combo)
+    return out
+
+
+def poly_eval(X64, terms, coefs):
+    y = np.zeros(X64.shape[1], np.float64)
+    for combo, c in zip(terms, coefs):
+        t = np.full(X64.shape[1], c, np.float64)
+        for v in combo:
+            t = t * X64[v]
+        y += t
+    return y
+
+
+def length_law(k, rng, n):
+    if k == 1:
+        return rng.integers(3, 33, n)
+    if k in (2, 4):
+        return rng.integers(3, 65, n)
+    if k == 3:
+        return np.clip(rng.geometric(1.0 / 24.0, n), 3, 128)
+    if k == 5:
+        return rng.integers(3, 129, n)
+    raise ValueError(k)
+
+
+CONFIG_SIZES = {1: (1_000, 1_024, 3), 2: (100_000, 4_096, 5),
+                3: (1_000_000, 16_384, 10), 4: (50_000, 1_048_576, 3)}
+
+
+def make_dataset(k, n_cases=None, seed=None):
+    rp, rx, rpoly, rnoise, _ = _rngs(k, seed)
+    _, n_default, n_vars = CONFIG_SIZES[k]
+    n = n_default if n_cases is None else int(n_cases)
+    if k == 1:
+        X = rx.uniform(-1, 1, (n_vars, n)).astype(np.float32)
+        X64 = X.astype(np.float64)
+        y = X64[0] ** 2 + np.sin(X64[1]) * X64[2] + rnoise.normal(0, 0.01, n)
+    elif k == 2:
+        X = rx.uniform(-3, 3, (n_vars, n)).astype(np.float32)
+        terms = monomials(n_vars)
+        y = poly_eval(X.astype(np.float64), terms, rpoly.uniform(-1, 1, len(terms)))
+        y += rnoise.normal(0, 0.05, n)
+    elif k == 3:
+        X = rx.standard_normal((n_vars, n)).astype(np.float32)
+        terms = monomials(n_vars)
+        y = poly_eval(X.astype(np.float64), terms, rpoly.uniform(-1, 1, len(terms)))
+        y += rnoise.normal(0, 0.05, n)
+    elif k == 4:
+        X = rx.uniform(-10, 10, (n_vars, n)).astype(np.float32)
+        terms = monomials(n_vars)
+        y = poly_eval(X.astype(np.float64), terms, rpoly.uniform(-1, 1, len(terms)))
+        y *= 1e4 / np.max(np.abs(y))
+    else:
+        raise ValueError(k)
+    return Dataset(np.ascontiguousarray(X), y.astype(np.float32))
+
+
+def make_config(k, n_programs=None, n_cases=None, seed=None):
+    """Workload k (1..4) at its full size, or with sizes overridden."""
+    rp = _rngs(k, seed)[0]
+    P_default, _, n_vars = CONFIG_SIZES[k]
+    P = P_default if n_programs is None else int(n_programs)
+    unary = UNARY_1 if k == 1 else UNARY_2
+    pop = sample_programs(rp, length_law(k, rp, P), n_vars, unary)
+    data = make_dataset(k, n_cases, seed)
+    tax = 0.0 if k == 1 else 1e-3
+    mask = MASK_1 if k == 1 else MASK_2
+    return Workload("config%d" % k, pop, data, tax, mask)
+
+
+# ---------------------------------------------------------------- serving
+@dataclass
+class ServingRun:
+    run_id: int
+    data: Dataset
+
+
+def make_serving_runs(n_runs=64, seed=None, max_cases=65536):
+    """Config 5 datasets: one resident dataset per evolutionary run."""
+    _, rx, rpoly, rnoise, _ = _rngs(5, seed)
+    runs = []
+    for r in range(n_runs):
+        n_vars = int(rx.integers(1, 21))
+        n = int(np.exp(rx.uniform(np.log(256), np.log(max_cases + 1))))
+        n = min(max(n, 256), max_cases)
+        X = rx.standard_normal((n_vars, n)).astype(np.float32)
+        terms = monomials(n_vars)
+        n_terms = int(rpoly.integers(1, 33))
+        pick = rpoly.choice(len(terms), size=min(n_terms, len(terms)), replace=False)
+        coefs = rpoly.uniform(-1, 1, pick.size)
+        y = poly_eval(X.astype(np.float64), [terms[i] for i in pick], coefs)
+        y += rnoise.normal(0, 0.05, n)
+        runs.append(ServingRun(r, Dataset(X, y.astype(np.float32))))
+    return runs
+
+
+def make_serving_request(rng, run, min_pop=1_000, max_pop=200_000):
+    """One scoring request (a population) for ``run``."""
+    P = int(np.exp(rng.uniform(np.log(min_pop), np.log(max_pop + 1))))
+    P = min(max(P, min_pop), max_pop)
+    return sample_programs(rng, rng.integers(3, 129, P), run.data.n_vars, UNARY_2)
