@@ -29,6 +29,7 @@ LOAD, CONST, ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, ABS = range(12)
 DUP, SWAP, DEL, SQUARE = 12, 13, 14, 15
 
 M64, M32E, M32E_UP, M32E_DN = 0, 1, 2, 3
+M32E_RAND = 16      # M32E_RAND + seed: random +-2 ulp elementary functions
 
 ST_VALID, ST_EMPTY, ST_BAD_OP, ST_BAD_VAR, ST_BAD_CONST = 0, 1, 2, 3, 4
 ST_UNDERFLOW, ST_TOO_DEEP, ST_FINAL_DEPTH = 5, 6, 7

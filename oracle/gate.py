@@ -1,0 +1,122 @@
+"""Parity gate between a device result and the fp64 oracle.
+
+TEST INFRASTRUCTURE ONLY.
+
+A finite program passes when |F_dev - F_64| <= 1e-4 |F_64| + 1e-12 (the
+relative tolerance of the fitness requirement, plus an absolute floor for
+closed-form zeros).  NaN/inf classification must be identical.  A program
+that fails either test is examined further with the oracle's fp32-emulating
+modes; it is excused only when the arithmetic itself explains it:
+
+  * fp32 ill-conditioned: the correctly rounded fp32 evaluation (M32E)
+    differs from M64 by more than 1e-5 relative, and the device result
+    matches M32E within the tolerance;
+  * chaotic: moving every transcendental result one fp32 ulp (M32E_UP /
+    M32E_DN), or by seeded pseudo-random amounts within +-2 ulps (M32E_RAND;
+    the accuracy class of fp32 elementary-function libraries), changes F by
+    more than the tolerance, or changes its class;
+  * certified class flip: the device class differs from M64's but equals
+    M32E's (an fp32 overflow-range or threshold flip), or equals that of a
+    perturbed run (chaotic).
+
+Everything else is a failure.  Counts of each category are reported.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import M32E, M32E_DN, M32E_RAND, M32E_UP, M64, fitness, subset
+
+N_RANDOM = 4        # seeded random-perturbation runs per suspicious program
+
+REL = 1e-4
+ABS = 1e-12
+
+
+@dataclass
+class GateReport:
+    n: int = 0
+    n_invalid_programs: int = 0
+    n_pass: int = 0
+    n_ill_conditioned: int = 0
+    n_chaotic: int = 0
+    n_class_flip_certified: int = 0
+    n_fail: int = 0
+    max_rel_err: float = 0.0          # over passing finite programs
+    failures: list = field(default_factory=list)
+
+    def ok(self):
+        return self.n_fail == 0
+
+    def summary(self):
+        return ("n=%d pass=%d ill=%d chaotic=%d flip=%d fail=%d invalid=%d max_rel=%.3g"
+                % (self.n, self.n_pass, self.n_ill_conditioned, self.n_chaotic,
+                   self.n_class_flip_certified, self.n_fail, self.n_invalid_programs,
+                   self.max_rel_err))
+
+
+def _close(a, b, rel=REL, abs_=ABS):
+    return np.abs(a - b) <= rel * np.abs(b) + abs_
+
+
+def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
+          status=None, n_threads=0, max_failures=20):
+    """Gate F_dev (float64[P]) against the oracle.  Returns a GateReport."""
+    F_dev = np.asarray(F_dev, np.float64)
+    if F64 is None:
+        F64, _, status = fitness(nodes, offsets, consts, X, y, tax, allowed_mask, M64,
+                                 n_threads)
+    rep = GateReport(n=F_dev.size)
+    valid = status == 0
+    rep.n_invalid_programs = int(np.sum(~valid))
+    bad_invalid = np.nonzero(~valid & ~np.isnan(F_dev))[0]
+    for p in bad_invalid[:max_failures]:
+        rep.failures.append((int(p), "invalid program not NaN", F_dev[p], F64[p]))
+    rep.n_fail += bad_invalid.size
+
+    fin64 = np.isfinite(F64)
+    find = np.isfinite(F_dev)
+    same_class = fin64 == find
+    good = valid & same_class & (~fin64 | _close(F_dev, F64))
+    rep.n_pass = int(np.sum(good))
+    both = valid & fin64 & find & good
+    if both.any():
+        rel = np.abs(F_dev[both] - F64[both]) / np.maximum(np.abs(F64[both]), 1e-300)
+        rep.max_rel_err = float(rel.max())
+
+    sus = np.nonzero(valid & ~good)[0]
+    if sus.size:
+        sn, so = subset(np.asarray(nodes, np.uint32), np.asarray(offsets, np.int64), sus)
+        F32, _, _ = fitness(sn, so, consts, X, y, tax, allowed_mask, M32E, n_threads)
+        pert = [fitness(sn, so, consts, X, y, tax, allowed_mask, m, n_threads)[0]
+                 for m in [M32E_UP, M32E_DN] + [M32E_RAND + s for s in range(N_RANDOM)]]
+        pert = np.stack(pert)
+        for i, p in enumerate(sus):
+            fd, f64, f32 = F_dev[p], F64[p], F32[i]
+            if np.isfinite(fd) != np.isfinite(f64):
+                if np.isfinite(f32) == np.isfinite(fd):
+                    rep.n_class_flip_certified += 1
+                    continue
+                if np.any(np.isfinite(pert[:, i]) == np.isfinite(fd)):
+                    rep.n_chaotic += 1
+                    continue
+                rep.n_fail += 1
+                if len(rep.failures) < max_failures:
+                    rep.failures.append((int(p), "class", fd, f64, f32))
+                continue
+            # both finite, value mismatch
+            ill = not _close(f32, f64, rel=1e-5, abs_=ABS) if np.isfinite(f32) else True
+            if ill and np.isfinite(f32) and _close(fd, f32):
+                rep.n_ill_conditioned += 1
+                continue
+            chaotic = (not np.all(np.isfinite(pert[:, i]))
+                       or not np.all(_close(pert[:, i], f32)))
+            if chaotic:
+                rep.n_chaotic += 1
+                continue
+            rep.n_fail += 1
+            if len(rep.failures) < max_failures:
+                rep.failures.append((int(p), "value", fd, f64, f32))
+    return rep

@@ -51,6 +51,12 @@
  *   ORACLE_M32E_UP / ORACLE_M32E_DN
  *                M32E with every sin/cos/exp/log result moved one fp32 ulp up
  *                (down): used only to certify that a program is chaotic.
+ *   ORACLE_M32E_RAND + s (s >= 0)
+ *                M32E with every sin/cos/exp/log result moved by a pseudo-
+ *                random d in {-2,...,+2} fp32 ulps, d drawn from SplitMix64
+ *                (Steele, Lea, Flood 2014) keyed by (s, node, case): an fp32
+ *                evaluator whose elementary functions are within 2 ulps.
+ *                Also certification only.
  *
  * Oracle-only GCL extension (so the paper's printed genomes can run):
  *   DUP, SWAP, DEL, SQUARE (GCL command table).
@@ -75,7 +81,8 @@ enum {
 };
 
 enum {
-    ORACLE_M64 = 0, ORACLE_M32E = 1, ORACLE_M32E_UP = 2, ORACLE_M32E_DN = 3
+    ORACLE_M64 = 0, ORACLE_M32E = 1, ORACLE_M32E_UP = 2, ORACLE_M32E_DN = 3,
+    ORACLE_M32E_RAND = 16
 };
 
 /* per-program validation status */
@@ -165,13 +172,30 @@ static double round_mode(double v, int mode)
     return v;
 }
 
-/* Transcendental results in the perturbed certification modes. */
-static double nudge(double v, int mode)
+/* SplitMix64 finalizer (Steele, Lea, Flood 2014). */
+static uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+/* Transcendental results in the perturbed certification modes; k = node
+ * index, i = case index. */
+static double nudge(double v, int mode, int64_t k, int64_t i)
 {
     if (!isfinite(v)) return v;
     float f = (float)v;
     if (mode == ORACLE_M32E_UP) f = nextafterf(f, INFINITY);
-    if (mode == ORACLE_M32E_DN) f = nextafterf(f, -INFINITY);
+    else if (mode == ORACLE_M32E_DN) f = nextafterf(f, -INFINITY);
+    else if (mode >= ORACLE_M32E_RAND) {
+        uint64_t h = splitmix64(splitmix64((uint64_t)(mode - ORACLE_M32E_RAND)) ^
+                                splitmix64(((uint64_t)k << 40) ^ (uint64_t)i));
+        int d = (int)(h % 5u) - 2;
+        for (; d > 0; --d) f = nextafterf(f, INFINITY);
+        for (; d < 0; ++d) f = nextafterf(f, -INFINITY);
+    }
     return (double)f;
 }
 
@@ -206,7 +230,7 @@ static double eval_case(const uint32_t* prog, int64_t len, const float* consts,
             else if (op == OP_EXP) v = exp(a);
             else v = (fabs(a) <= th) ? 0.0 : log(fabs(a));
             v = round_mode(v, mode);
-            if (mode == ORACLE_M32E_UP || mode == ORACLE_M32E_DN) v = nudge(v, mode);
+            if (mode >= ORACLE_M32E_UP) v = nudge(v, mode, k, i);
             st[sp++] = v;
             break;
         case OP_SQRT: a = st[--sp]; st[sp++] = round_mode(sqrt(fabs(a)), mode); break;
@@ -246,7 +270,7 @@ static double program_fitness(const uint32_t* prog, int64_t len,
     int bad = 0;
     for (int64_t i = 0; i < n_cases; ++i) {
         double f = eval_case(prog, len, consts, X, ld_x, i, mode);
-        if (!isfinite(f)) { bad = 1; break; }
+        if (!isfinite(f)) bad = 1;
         double r = f - (double)y[i];
         sum += r * r;
     }

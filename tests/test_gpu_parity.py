@@ -1,0 +1,277 @@
+"""GPU parity: the HIP path (through the C ABI) against the fp64 oracle.
+
+Floating point: the gate of oracle.gate (1e-4 relative + 1e-12 absolute,
+identical NaN/inf classes, fp32-certified exceptions counted).  Integer and
+exact work (the exact-arithmetic family, constant indexing, validation
+status codes) must be bit-exact.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import gate
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_06731_amd as gp
+    gp.lib()        # raises if the HIP library is not built
+    return gp
+
+
+def _say(msg):
+    print("[gpu] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(gp, pop_nodes, pop_offsets, consts, X, y, tax, mask, status=False):
+    return gp.evaluate(pop_nodes, pop_offsets, consts, X, y, tax, mask, return_status=status)
+
+
+def _gate(F, nodes, offsets, consts, X, y, tax, mask, label):
+    rep = gate.check(F, nodes, offsets, consts, X, y, tax, mask)
+    _say(label + ": " + rep.summary())
+    assert rep.ok(), rep.failures[:10]
+    return rep
+
+
+# ------------------------------------------------------------ workloads
+@pytest.mark.parametrize("k,P,n", [(1, None, None), (2, 4000, None), (3, 3000, 4000),
+                                   (4, 48, 1 << 20), (2, 2000, 1025), (2, 2000, 7)])
+def test_config_parity(k, P, n):
+    gp = _need_gpu()
+    from paper_2607_06731_amd import synth
+    w = synth.make_config(k, n_programs=P, n_cases=n)
+    _say("config %d P=%d n=%d" % (k, w.pop.n_programs, w.data.n_cases))
+    F = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
+             w.allowed_mask)
+    _gate(F, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
+          w.allowed_mask, "config %d" % k)
+
+
+def test_config2_full_size_sampled():
+    """Full config-2 launch (100,000 programs x 4,096 cases) gated on a
+    seeded sample of 400 programs, stratified by length."""
+    gp = _need_gpu()
+    from paper_2607_06731_amd import synth
+    w = synth.make_config(2)
+    _say("config 2 full size")
+    F = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
+             w.allowed_mask)
+    rng = np.random.default_rng(42)
+    L = w.pop.lengths
+    idx = np.concatenate([rng.choice(np.nonzero(L == l)[0], 7, replace=False)
+                          for l in range(3, 65)])[:400]
+    sub = w.pop.take(idx)
+    _gate(F[idx], sub.nodes, sub.offsets, sub.consts, w.data.X, w.data.y, w.tax,
+          w.allowed_mask, "config 2 full (sampled)")
+    # every structurally valid program got a number or +inf, never NaN
+    assert not np.isnan(F).any()
+
+
+# ------------------------------------------------------------ pins on GPU
+def test_brute_force_special_values():
+    gp = _need_gpu()
+    from tests.test_oracle_pins import SPECIAL, THETA, brute_force_programs
+    seqs = brute_force_programs(5)
+    st, _ = oracle.validate(np.array([t for s in seqs for t in s], np.uint32),
+                            np.concatenate([[0], np.cumsum([len(s) for s in seqs])]),
+                            1, 2, oracle.MASK_BENCH)
+    valid = [s for s, c in zip(seqs, st) if c == 0]
+    assert len(valid) == 13989
+    lens = np.array([len(s) for s in valid], np.int64)
+    off = np.zeros(lens.size + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    nodes = np.array([t for s in valid for t in s], np.uint32)
+    consts = np.array([-0.0011], np.float32)
+    x0 = np.repeat(np.array(SPECIAL, np.float32), 5)
+    x1 = np.tile(np.array([0.0, -THETA, 1.0, 44.0, -89.0], np.float32), len(SPECIAL))
+    X = np.stack([x0, x1]).astype(np.float32)
+    y = (0.5 * x0 - x1).astype(np.float32)
+    _say("brute force 13989 programs")
+    F = _run(gp, nodes, off, consts, X, y, 0.0, oracle.MASK_BENCH)
+    _gate(F, nodes, off, consts, X, y, 0.0, oracle.MASK_BENCH, "brute force")
+    # plus the same programs on moderate inputs, where nearly all are finite
+    rng = np.random.default_rng(9)
+    X2 = rng.uniform(-2, 2, (2, 700)).astype(np.float32)
+    y2 = rng.uniform(-1, 1, 700).astype(np.float32)
+    F2 = _run(gp, nodes, off, consts, X2, y2, 1e-3, oracle.MASK_BENCH)
+    _gate(F2, nodes, off, consts, X2, y2, 1e-3, oracle.MASK_BENCH, "brute force moderate")
+
+
+def test_exact_family_bitwise():
+    gp = _need_gpu()
+    from tests.test_oracle_pins import exact_family
+    pop, X, y = exact_family(n_programs=2000, n_cases=1024, seed=8)
+    F64, mse, st = oracle.fitness(pop.nodes, pop.offsets, pop.consts, X, y, 0.0)
+    F32, _, _ = oracle.fitness(pop.nodes, pop.offsets, pop.consts, X, y, 0.0, mode=oracle.M32E)
+    # keep programs whose fp32 evaluation is exact and whose sum of squares
+    # stays below 2^24 * 4^e (scaled partial sums exact in fp32)
+    keep = (F64 == F32) & np.isfinite(F64) & (F64 * 1024 < 2 ** 24)
+    assert keep.sum() > 500
+    _say("exact family")
+    F = _run(gp, pop.nodes, pop.offsets, pop.consts, X, y, 0.0, oracle.MASK_BENCH)
+    assert np.array_equal(F[keep], F64[keep])
+
+
+def test_const_index_family_bitwise():
+    gp = _need_gpu()
+    P = 1_000_000
+    nodes = (oracle.CONST | (np.arange(P, dtype=np.uint32) << 8)).astype(np.uint32)
+    offsets = np.arange(P + 1, dtype=np.int64)
+    consts = (np.arange(P) % 4096).astype(np.float32)
+    X = np.zeros((1, 4), np.float32)
+    y = np.zeros(4, np.float32)
+    _say("const index family 1e6")
+    F = _run(gp, nodes, offsets, consts, X, y, 0.0, oracle.MASK_BENCH)
+    assert np.array_equal(F, (np.arange(P) % 4096).astype(np.float64) ** 2)
+
+
+def test_quadratic_root_translation():
+    gp = _need_gpu()
+    from tests.test_oracle_pins import _quadratic_data, prog
+    from oracle import ADD, DIV, MUL, SQRT, SUB
+    X = _quadratic_data(4096, seed=3)
+    a, b, c = (X[i].astype(np.float64) for i in range(3))
+    root = (-b + np.sqrt(b * b - 4 * a * c)) / (2 * a)
+    p = prog(("x", 1), ("x", 1), MUL, ("c", 0), ("x", 0), MUL, ("x", 2), MUL, SUB,
+             SQRT, ("x", 1), SUB, ("x", 0), DIV, ("c", 1), MUL)
+    y = root.astype(np.float32)
+    consts = np.array([4, 0.5], np.float32)
+    _say("quadratic root")
+    F = _run(gp, p, [0, p.size], consts, X, y, 0.0, oracle.MASK_BENCH)
+    F64, _, _ = oracle.fitness(p, [0, p.size], consts, X, y, 0.0)
+    assert abs(F[0] - F64[0]) <= 1e-4 * F64[0] + 1e-10
+
+
+def test_precision_pin_million_cases():
+    """c0 = 0 against y_i = 16((i mod 1024) - 511.5): exact MSE known."""
+    gp = _need_gpu()
+    from fractions import Fraction
+    n, m, h = 1 << 20, 1024, 16.0
+    i = np.arange(n)
+    y = (h * ((i % m) - (m - 1) / 2.0)).astype(np.float32)
+    X = np.zeros((1, n), np.float32)
+    nodes = np.array([oracle.CONST], np.uint32)
+    _say("precision pin 2^20 cases")
+    F = _run(gp, nodes, [0, 1], np.array([0.0], np.float32), X, y, 0.0, oracle.MASK_BENCH)
+    exact = float(Fraction(int(h) ** 2 * (m * m - 1), 12))
+    assert abs(F[0] - exact) <= 1e-9 * exact
+
+
+# ------------------------------------------------------------ edge cases
+def test_invalid_programs_get_status_and_nan():
+    gp = _need_gpu()
+    from oracle import ADD, CONST, LOAD, SIN
+    P = [
+        [LOAD | (0 << 8), LOAD | (1 << 8), ADD],   # ok
+        [],                                          # empty
+        [LOAD | (0 << 8), 200],                      # bad op
+        [LOAD | (7 << 8)],                           # bad var
+        [CONST | (5 << 8)],                          # bad const
+        [LOAD | (0 << 8), ADD],                      # underflow
+        [LOAD] * 33 + [ADD] * 32,                    # too deep
+        [LOAD, LOAD],                                # final depth 2
+        [LOAD, SIN],                                 # disallowed below
+    ]
+    lens = np.array([len(p) for p in P], np.int64)
+    off = np.zeros(len(P) + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    nodes = np.array([t for p in P for t in p], np.uint32)
+    consts = np.array([1.0], np.float32)
+    X = np.ones((2, 100), np.float32)
+    y = np.zeros(100, np.float32)
+    mask = oracle.MASK_BENCH & ~(1 << SIN)
+    _say("invalid programs")
+    F, st = _run(gp, nodes, off, consts, X, y, 0.0, mask, status=True)
+    st_o, _ = oracle.validate(nodes, off, 1, 2, mask)
+    assert np.array_equal(st, st_o)
+    assert F[0] == 4.0 and np.isnan(F[1:]).all()
+
+
+def test_deep_and_long_programs():
+    gp = _need_gpu()
+    from oracle import ADD, COS, LOAD, MUL, SIN, SUB
+    rng = np.random.default_rng(4)
+    progs = []
+    for d in (8, 9, 16, 17, 31, 32):     # class boundaries
+        progs.append([LOAD | (int(rng.integers(0, 3)) << 8) for _ in range(d)] +
+                     [int(rng.choice([ADD, SUB, MUL])) for _ in range(d - 1)])
+    progs.append([LOAD] + [SIN, COS] * 2000)         # 4001 nodes
+    lens = np.array([len(p) for p in progs], np.int64)
+    off = np.zeros(len(progs) + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    nodes = np.array([t for p in progs for t in p], np.uint32)
+    X = rng.uniform(-1, 1, (3, 3000)).astype(np.float32)
+    y = rng.uniform(-1, 1, 3000).astype(np.float32)
+    _say("deep and long programs")
+    F = _run(gp, nodes, off, np.zeros(0, np.float32), X, y, 1e-3, oracle.MASK_BENCH)
+    _gate(F, nodes, off, np.zeros(0, np.float32), X, y, 1e-3, oracle.MASK_BENCH, "deep/long")
+
+
+def test_no_variables_and_single_case():
+    gp = _need_gpu()
+    from oracle import ADD, CONST, MUL
+    nodes = np.array([CONST | (0 << 8), CONST | (1 << 8), MUL, CONST | (2 << 8), ADD], np.uint32)
+    consts = np.array([1.5, -2.0, 0.25], np.float32)
+    X = np.zeros((0, 1), np.float32)
+    y = np.array([1.0], np.float32)
+    _say("no variables, one case")
+    F = _run(gp, nodes, [0, 5], consts, X, y, 0.5, oracle.MASK_BENCH)
+    assert F[0] == (-2.75 - 1.0) ** 2 + 0.5 * 5
+
+
+def test_empty_population():
+    gp = _need_gpu()
+    _say("empty population")
+    F = _run(gp, np.zeros(0, np.uint32), [0], np.zeros(0, np.float32),
+             np.ones((1, 10), np.float32), np.zeros(10, np.float32), 0.0, 0)
+    assert F.size == 0
+
+
+def test_deterministic_and_batch_independent():
+    gp = _need_gpu()
+    from paper_2607_06731_amd import synth
+    w = synth.make_config(2, n_programs=6000, n_cases=4096)
+    _say("determinism")
+    F1 = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax, w.allowed_mask)
+    F2 = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax, w.allowed_mask)
+    assert np.array_equal(F1, F2)
+    idx = np.random.default_rng(0).choice(6000, 500, replace=False)
+    sub = w.pop.take(idx)
+    F3 = _run(gp, sub.nodes, sub.offsets, sub.consts, w.data.X, w.data.y, w.tax, w.allowed_mask)
+    assert np.array_equal(F3, F1[idx])
+
+
+def test_commutativity_bitwise():
+    gp = _need_gpu()
+    from oracle import ADD, MUL
+    from paper_2607_06731_amd import synth
+    w = synth.make_config(2, n_programs=200, n_cases=2048)
+    pop = w.pop
+    progs = []
+    for p in range(0, 100, 2):
+        a = pop.nodes[pop.offsets[p]:pop.offsets[p + 1]]
+        b = pop.nodes[pop.offsets[p + 1]:pop.offsets[p + 2]]
+        for op in (ADD, MUL):
+            progs.append(np.concatenate([a, b, [op]]))
+            progs.append(np.concatenate([b, a, [op]]))
+    lens = np.array([len(p) for p in progs], np.int64)
+    off = np.zeros(len(progs) + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    nodes = np.concatenate(progs).astype(np.uint32)
+    # both orders must land in the same stack-depth class (<= 16), which
+    # fixes the same case tiling and hence the same summation order
+    _, md = oracle.validate(nodes, off, pop.consts.size, w.data.n_vars, w.allowed_mask)
+    same = (md[0::2] <= 16) & (md[1::2] <= 16)
+    assert same.sum() > 50
+    _say("commutativity")
+    F = _run(gp, nodes, off, pop.consts, w.data.X, w.data.y, w.tax, w.allowed_mask)
+    assert np.array_equal(F[0::2][same], F[1::2][same])

@@ -1,0 +1,106 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+that include/gpeval.h declares, validates on the host exactly like the
+oracle's independent validator, and rejects bad arguments synchronously
+(before any device work)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2607_06731_amd as gp
+from paper_2607_06731_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[\w\s\*]+?\b(gp_\w+)\s*\(", text, re.M):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(gp.LIB_PATH):
+        from paper_2607_06731_amd import _build
+        _build.build()
+    return gp.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert "gp_eval" in names and "gp_validate" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version(L):
+    assert L.gp_version() >= 1
+
+
+def test_host_validate_matches_oracle_on_brute_force():
+    from tests.test_oracle_pins import brute_force_programs
+    seqs = brute_force_programs(4)
+    lens = np.array([len(s) for s in seqs], np.int64)
+    off = np.zeros(lens.size + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    nodes = np.array([t for s in seqs for t in s], np.uint32)
+    st_o, md_o = oracle.validate(nodes, off, 1, 2, oracle.MASK_BENCH)
+    st_g, md_g, first = gp.gp_validate(nodes, off, 1, 2, gp.GP_ALL_OPS)
+    assert np.array_equal(st_o == 0, st_g == 0)
+    assert np.array_equal(md_o[st_o == 0], md_g[st_g == 0])
+
+
+def test_host_validate_status_codes():
+    rng = np.random.default_rng(1)
+    w = synth.make_config(2, n_programs=2000, n_cases=64)
+    nodes = w.pop.nodes.copy()
+    # mutate: random opcodes, operand indices and truncations
+    idx = rng.choice(nodes.size, 300, replace=False)
+    nodes[idx[:100]] = rng.integers(0, 16, 100).astype(np.uint32)
+    nodes[idx[100:200]] = (nodes[idx[100:200]] & 0xFF) | (rng.integers(0, 9, 100).astype(np.uint32) << 8)
+    st_o, _ = oracle.validate(nodes, w.pop.offsets, w.pop.consts.size, 5, w.allowed_mask)
+    st_g, _, first = gp.gp_validate(nodes, w.pop.offsets, w.pop.consts.size, 5, w.allowed_mask)
+    assert np.array_equal(st_o, st_g)
+    bad = np.nonzero(st_g)[0]
+    assert first == (bad[0] if bad.size else -1)
+
+
+def test_eval_rejects_bad_arguments_before_device_work(L):
+    c = ctypes.c_void_p(1)   # never dereferenced: checks fail first
+    # negative sizes
+    assert L.gp_eval(c, c, -1, 0, c, 0, c, 1, 1, c, 1, 0.0, 0, c, None, None) == gp.GP_E_INVALID_ARG
+    assert L.gp_eval(c, c, 1, 1, c, 0, c, 1, 1, c, 0, 0.0, 0, c, None, None) == gp.GP_E_INVALID_ARG
+    # ld_x < n_cases
+    assert L.gp_eval(c, c, 1, 1, c, 0, c, 1, 10, c, 11, 0.0, 0, c, None, None) == gp.GP_E_INVALID_ARG
+    # too many constants for a 24-bit operand
+    assert L.gp_eval(c, c, 1, 1, c, 1 << 25, c, 1, 10, c, 10, 0.0, 0, c, None, None) == gp.GP_E_TOO_LARGE
+    assert b"n_consts" in L.gp_last_error()
+    # empty population is a no-op
+    assert L.gp_eval(None, c, 0, 0, None, 0, None, 0, 1, c, 1, 0.0, 0, None, None, None) == gp.GP_OK
+
+
+def test_binding_refuses_host_tensors():
+    import torch
+    with pytest.raises(TypeError):
+        gp._dev_ptr(torch.zeros(3, dtype=torch.float32), torch.float32, "x")
+
+
+def test_no_oracle_in_product_path():
+    # the product package must not import or reference the oracle
+    pkg = os.path.join(ROOT, "paper_2607_06731_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "gp_oracle" not in text, fn

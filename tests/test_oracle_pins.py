@@ -167,6 +167,20 @@ class TestOverflowEmulation:
         q = prog(("x", 0), ("x", 0), ADD)
         assert one_case(q, [0.5], mode=M32E_UP) == 1.0
 
+    def test_random_mode_stays_within_two_ulps(self):
+        X = np.linspace(-3, 3, 512).astype(np.float32).reshape(1, -1)
+        p = prog(("x", 0), EXP)
+        base = oracle.program_outputs(p, [], X, mode=M32E).astype(np.float32)
+        seen = set()
+        for seed in range(3):
+            v = oracle.program_outputs(p, [], X, mode=oracle.M32E_RAND + seed).astype(np.float32)
+            d = (v.view(np.int32).astype(np.int64) - base.view(np.int32).astype(np.int64))
+            assert np.all(np.abs(d) <= 2)
+            seen.update(np.unique(d).tolist())
+            again = oracle.program_outputs(p, [], X, mode=oracle.M32E_RAND + seed)
+            assert np.array_equal(again, v.astype(np.float64))      # deterministic
+        assert seen == {-2, -1, 0, 1, 2}
+
 
 class TestValidator:
     """Stack discipline (RPN; 32-element limit; final depth 1)."""
