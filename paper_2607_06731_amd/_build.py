@@ -16,6 +16,9 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # no contraction: the compensated sums rely on separately rounded ops
     "-ffp-contract=off",
+    # branches on wave-uniform values (the opcode dispatch) stay plain scalar
+    # branches instead of being rewritten into structured exec-mask flow
+    "-mllvm", "-structurizecfg-skip-uniform-regions",
     "-Wno-unused-command-line-argument",
 ]
 

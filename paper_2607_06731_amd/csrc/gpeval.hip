@@ -268,16 +268,10 @@ __global__ __launch_bounds__(kBucketBlock) void k_class_scatter(
 }
 
 // ------------------------------------------------------------ evaluation
-struct EvalArgs {
-    const uint2* code;
-    const ProgMeta* meta;
-    const int32_t* order;
-    const int32_t* class_info;
-    uint32_t* work_counter;
-    const float* X;
-    const float* y;
-    float2* part;           // [n_programs][part_stride]
-    uint8_t* part_bad;      // [n_programs][part_stride]
+// Scalars of one class launch (pointers travel as restrict-qualified kernel
+// parameters so that uniform loads of programs and metadata become scalar
+// memory loads).
+struct EvalConst {
     int64_t ld_x;
     int64_t n_cases;
     int32_t cls;
@@ -306,10 +300,35 @@ __device__ __forceinline__ void acc_pair(float& hi, float& lo, float h2, float l
     lo = (lo + l2) + e;
 }
 
+// The value stack below the top lives in VGPR arrays of 32 floats ("chunks"):
+// chunk c holds cases [c*J, (c+1)*J) of every slot, element index slot*J + o.
+// A uniform dynamic index into a 32-element vector compiles to GPR-index-mode
+// moves (smaller vectors are expanded into compare/select chains).
+#define GP_CHUNK_PUT(slot, j, v)                                                   \
+    do {                                                                           \
+        const uint32_t i_ = (slot) * J + ((j) % J);                                \
+        if ((j) / J == 0) c0[i_] = (v);                                            \
+        else if ((j) / J == 1) c1[i_] = (v);                                       \
+        else if ((j) / J == 2) c2[i_] = (v);                                       \
+        else c3[i_] = (v);                                                         \
+    } while (0)
+#define GP_CHUNK_GET(slot, j)                                                      \
+    (((j) / J == 0) ? c0[(slot) * J + ((j) % J)]                                   \
+     : ((j) / J == 1) ? c1[(slot) * J + ((j) % J)]                                 \
+     : ((j) / J == 2) ? c2[(slot) * J + ((j) % J)] : c3[(slot) * J + ((j) % J)])
+
 template <int MAXD, int K>
-__global__ __launch_bounds__(kWG) void k_eval(EvalArgs a)
+__global__ __launch_bounds__(kWG) void k_eval(
+    const uint2* __restrict__ code, const ProgMeta* __restrict__ meta,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ class_info,
+    uint32_t* __restrict__ work_counter, const float* __restrict__ X,
+    const float* __restrict__ y, float2* __restrict__ part,
+    uint8_t* __restrict__ part_bad, EvalConst a)
 {
     static_assert(K == 2 || K == 4, "cases per lane");
+    static_assert(MAXD == 8 || MAXD == 16 || MAXD == 32, "stack class");
+    constexpr int J = 32 / MAXD;                  // cases per 32-float chunk
+    static_assert(K % J == 0 && K / J <= 4, "chunking");
     constexpr int SUB = kWG * K;                  // cases per sub-tile
     extern __shared__ float lds[];
     float* xt = lds;                              // [n_vars][SUB]
@@ -321,17 +340,17 @@ __global__ __launch_bounds__(kWG) void k_eval(EvalArgs a)
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int lo = tid * K;                       // this lane's first case in a sub-tile
-    const int start = a.class_info[2 * a.cls];
-    const int count = a.class_info[2 * a.cls + 1];
+    const int start = class_info[2 * a.cls];
+    const int count = class_info[2 * a.cls + 1];
     const int n_groups = (count + a.G - 1) / a.G;
     const uint32_t n_items = (uint32_t)n_groups * (uint32_t)a.n_tiles;
     int64_t staged = -1;                          // sub-tile currently in LDS
 
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(a.work_counter, 1u);
+        if (tid == 0) s_item = atomicAdd(work_counter, 1u);
         if (tid < a.G) wbad[tid] = 0u;
         __syncthreads();
-        const uint32_t item = s_item;
+        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= n_items) break;
         const int tile = (int)(item / (uint32_t)n_groups);
         const int grp = (int)(item % (uint32_t)n_groups);
@@ -347,7 +366,7 @@ __global__ __launch_bounds__(kWG) void k_eval(EvalArgs a)
                 for (int i = tid; i < a.n_vars * SUB; i += kWG) {
                     const int v = i / SUB, c = i - v * SUB;
                     const int64_t gi = base + c;
-                    xt[i] = gi < a.n_cases ? a.X[(int64_t)v * a.ld_x + gi] : 0.f;
+                    xt[i] = gi < a.n_cases ? X[(int64_t)v * a.ld_x + gi] : 0.f;
                 }
                 staged = sub_idx;
                 __syncthreads();
@@ -358,94 +377,96 @@ __global__ __launch_bounds__(kWG) void k_eval(EvalArgs a)
             for (int j = 0; j < K; ++j) {
                 const int64_t gi = base + lo + j;
                 live[j] = gi < a.n_cases;
-                yv[j] = live[j] ? a.y[gi] : 0.f;
+                yv[j] = live[j] ? y[gi] : 0.f;
             }
 
             for (int g = 0; g < gn; ++g) {
-                const int pid = a.order[start + g0 + g];
-                const ProgMeta m = a.meta[pid];
-                const uint2* pc = a.code + m.start;
+                const int pid = order[start + g0 + g];
+                const ProgMeta m = meta[pid];
+                const uint2* pc = code + m.start;
                 const int len = m.len;
 
-                // value stack: element i (below the top) lives in slot i of
-                // s0..s3 (one array per case so each stays a VGPR vector);
-                // the top lives in tos[]
-                float s0[MAXD], s1[MAXD], s2[MAXD], s3[MAXD];
+                float c0[32], c1[32], c2[32], c3[32];
                 float tos[K];
 #pragma unroll
                 for (int j = 0; j < K; ++j) tos[j] = 0.f;
 
+                uint2 w_next = pc[0];
                 for (int n = 0; n < len; ++n) {
-                    const uint2 w = pc[n];
+                    // fetch the next node while this one executes
+                    const uint2 w = w_next;
+                    w_next = pc[min(n + 1, len - 1)];
                     const uint32_t op = w.x & 0xFFu;
                     const uint32_t rd = min((w.x >> 8) & 0xFFu, (uint32_t)(MAXD - 1));
                     const uint32_t wr = min((w.x >> 16) & 0xFFu, (uint32_t)(MAXD - 1));
-                    // save the old top (slot MAXD-1 is a scratch slot that
-                    // never holds a live element) and fetch second-from-top
-                    s0[wr] = tos[0];
-                    s1[wr] = tos[1];
-                    if constexpr (K > 2) { s2[wr] = tos[2]; s3[wr] = tos[3]; }
-                    float sv[K];
-                    sv[0] = s0[rd];
-                    sv[1] = s1[rd];
-                    if constexpr (K > 2) { sv[2] = s2[rd]; sv[3] = s3[rd]; }
-                    switch (op) {
-                    case GP_LOAD: {
-                        const float* xp = xt + (size_t)w.y * SUB + lo;
+                    if (op <= GP_CONST) {
+                        // leaf: the old top moves into the stack (slot MAXD-1
+                        // never holds a live element, so a push onto an empty
+                        // stack writes there), the new value becomes the top
 #pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = xp[j];
-                        break;
-                    }
-                    case GP_CONST: {
-                        const float c = __uint_as_float(w.y);
+                        for (int j = 0; j < K; ++j) GP_CHUNK_PUT(wr, j, tos[j]);
+                        if (op == GP_LOAD) {
+                            const float* xp = xt + (size_t)w.y * SUB + lo;
 #pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = c;
-                        break;
-                    }
-                    case GP_ADD:
+                            for (int j = 0; j < K; ++j) tos[j] = xp[j];
+                        } else {
+                            const float c = __uint_as_float(w.y);
 #pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = sv[j] + tos[j];
-                        break;
-                    case GP_SUB:
+                            for (int j = 0; j < K; ++j) tos[j] = c;
+                        }
+                    } else if (op <= GP_DIV) {
+                        // binary: a = second from top (stack slot rd), b = top
+                        float sv[K];
 #pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = sv[j] - tos[j];
-                        break;
-                    case GP_MUL:
+                        for (int j = 0; j < K; ++j) sv[j] = GP_CHUNK_GET(rd, j);
+                        switch (op) {
+                        case GP_ADD:
 #pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = sv[j] * tos[j];
-                        break;
-                    case GP_DIV:
+                            for (int j = 0; j < K; ++j) tos[j] = sv[j] + tos[j];
+                            break;
+                        case GP_SUB:
 #pragma unroll
-                        for (int j = 0; j < K; ++j)
-                            tos[j] = fabsf(tos[j]) <= 0.001f ? 1.f : sv[j] / tos[j];
-                        break;
-                    case GP_SIN:
+                            for (int j = 0; j < K; ++j) tos[j] = sv[j] - tos[j];
+                            break;
+                        case GP_MUL:
 #pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = sinf(tos[j]);
-                        break;
-                    case GP_COS:
+                            for (int j = 0; j < K; ++j) tos[j] = sv[j] * tos[j];
+                            break;
+                        default:
 #pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = cosf(tos[j]);
-                        break;
-                    case GP_EXP:
+                            for (int j = 0; j < K; ++j)
+                                tos[j] = fabsf(tos[j]) <= 0.001f ? 1.f : sv[j] / tos[j];
+                            break;
+                        }
+                    } else {
+                        // unary: replaces the top
+                        switch (op) {
+                        case GP_SIN:
 #pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = expf(tos[j]);
-                        break;
-                    case GP_LOG:
+                            for (int j = 0; j < K; ++j) tos[j] = sinf(tos[j]);
+                            break;
+                        case GP_COS:
 #pragma unroll
-                        for (int j = 0; j < K; ++j)
-                            tos[j] = fabsf(tos[j]) <= 0.001f ? 0.f : logf(fabsf(tos[j]));
-                        break;
-                    case GP_SQRT:
+                            for (int j = 0; j < K; ++j) tos[j] = cosf(tos[j]);
+                            break;
+                        case GP_EXP:
 #pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = sqrtf(fabsf(tos[j]));
-                        break;
-                    case GP_ABS:
+                            for (int j = 0; j < K; ++j) tos[j] = expf(tos[j]);
+                            break;
+                        case GP_LOG:
 #pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = fabsf(tos[j]);
-                        break;
-                    default:
-                        break;
+                            for (int j = 0; j < K; ++j)
+                                tos[j] = fabsf(tos[j]) <= 0.001f ? 0.f : logf(fabsf(tos[j]));
+                            break;
+                        case GP_SQRT:
+#pragma unroll
+                            for (int j = 0; j < K; ++j) tos[j] = sqrtf(fabsf(tos[j]));
+                            break;
+                        default:
+#pragma unroll
+                            for (int j = 0; j < K; ++j) tos[j] = fabsf(tos[j]);
+                            break;
+                        }
                     }
                 }
 
@@ -488,13 +509,13 @@ __global__ __launch_bounds__(kWG) void k_eval(EvalArgs a)
         }
         // combine the wavefronts in fixed order and store the tile partial
         if (tid < gn) {
-            const int pid = a.order[start + g0 + tid];
+            const int pid = order[start + g0 + tid];
             float h = wpart[tid * kWaves].x, l = wpart[tid * kWaves].y;
 #pragma unroll
             for (int w = 1; w < kWaves; ++w) acc_pair(h, l, wpart[tid * kWaves + w].x, wpart[tid * kWaves + w].y);
             const int64_t slot = (int64_t)pid * a.part_stride + tile;
-            a.part[slot] = make_float2(h, l);
-            a.part_bad[slot] = (uint8_t)(wbad[tid] != 0u);
+            part[slot] = make_float2(h, l);
+            part_bad[slot] = (uint8_t)(wbad[tid] != 0u);
         }
         __syncthreads();
     }
@@ -605,8 +626,20 @@ size_t eval_lds_bytes(int n_vars, int G)
            (size_t)G * sizeof(uint32_t);
 }
 
+struct EvalPtrs {
+    const uint2* code;
+    const ProgMeta* meta;
+    const int32_t* order;
+    const int32_t* class_info;
+    uint32_t* work_counter;
+    const float* X;
+    const float* y;
+    float2* part;
+    uint8_t* part_bad;
+};
+
 template <int MAXD, int K>
-int launch_eval(const EvalArgs& args, hipStream_t stream, int cus)
+int launch_eval(const EvalPtrs& p, const EvalConst& args, hipStream_t stream, int cus)
 {
     const size_t lds = eval_lds_bytes<MAXD, K>(args.n_vars, args.G);
     if (lds > 64 * 1024) {
@@ -617,7 +650,8 @@ int launch_eval(const EvalArgs& args, hipStream_t stream, int cus)
     GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval<MAXD, K>, kWG, lds));
     if (per_cu < 1) return set_error(GP_E_TOO_LARGE, "n_vars=%d needs %zu bytes of LDS per workgroup", args.n_vars, lds);
     const int grid = cus * per_cu;
-    hipLaunchKernelGGL((k_eval<MAXD, K>), dim3(grid), dim3(kWG), lds, stream, args);
+    hipLaunchKernelGGL((k_eval<MAXD, K>), dim3(grid), dim3(kWG), lds, stream, p.code, p.meta,
+                       p.order, p.class_info, p.work_counter, p.X, p.y, p.part, p.part_bad, args);
     GP_HIP_TRY(hipGetLastError());
     return GP_OK;
 }
@@ -789,21 +823,20 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
     GP_HIP_TRY(hipGetLastError());
 
     const int e = scale_exponent(n_cases);
-    EvalArgs ea{};
-    ea.code = code; ea.meta = meta; ea.order = order; ea.class_info = class_info;
-    ea.X = X; ea.y = y; ea.part = part; ea.part_bad = part_bad;
+    EvalPtrs ep{code, meta, order, class_info, nullptr, X, y, part, part_bad};
+    EvalConst ea{};
     ea.ld_x = ld_x; ea.n_cases = n_cases; ea.n_vars = n_vars; ea.G = 8;
     ea.part_stride = stride;
     ea.scale = ldexpf(1.0f, -e);
     for (int c = 0; c < kClasses; ++c) {
         if ((rc = ce.mark(1 + c, stream)) != GP_OK) return rc;
         ea.cls = c;
-        ea.work_counter = counters + c;
+        ep.work_counter = counters + c;
         ea.passes = ts[c].passes;
         ea.n_tiles = ts[c].n_tiles;
-        if (c == 0) rc = launch_eval<8, 4>(ea, stream, cus);
-        else if (c == 1) rc = launch_eval<16, 4>(ea, stream, cus);
-        else rc = launch_eval<32, 2>(ea, stream, cus);
+        if (c == 0) rc = launch_eval<8, 4>(ep, ea, stream, cus);
+        else if (c == 1) rc = launch_eval<16, 4>(ep, ea, stream, cus);
+        else rc = launch_eval<32, 2>(ep, ea, stream, cus);
         if (rc != GP_OK) return rc;
     }
 
