@@ -17,7 +17,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libgpeval.so")
+#: the in-tree build; GPEVAL_LIB may point at another build of the same source
+LIB_PATH = os.environ.get("GPEVAL_LIB") or os.path.join(_PKG, "libgpeval.so")
 
 GP_OK, GP_E_INVALID_ARG, GP_E_BAD_PROGRAM, GP_E_TOO_LARGE, GP_E_NO_MEMORY, GP_E_HIP = \
     0, -1, -2, -3, -4, -5

@@ -70,20 +70,26 @@ int set_error(int code, const char* fmt, ...)
 constexpr int kWG = 256;                 // 4 wavefronts of 64
 constexpr int kWaves = kWG / 64;
 constexpr int kClasses = 3;              // max depth <= 8, <= 16, <= 32
-constexpr int kClassDepth[kClasses] = {8, 16, 32};
 constexpr int kMaxTiles = 32;            // case tiles per program (cap)
 constexpr uint32_t kNoSlot = 0xFFu;      // staged write slot: nothing to save
 constexpr int kBucketBlock = 1024;       // programs per partition block
 
 // Per-program record written by k_prepare.
 struct ProgMeta {
-    int64_t start;      // first node
-    int32_t len;        // node count
-    uint8_t maxd;       // maximum stack depth
-    uint8_t cls;        // depth class, 0xFF if invalid
-    int16_t status;     // GP_PROG_*
+    int64_t start;      // first node (original and staged code share it)
+    int32_t len;        // node count (the length taxed)
+    int32_t slen;       // staged instruction count (<= len)
 };
 static_assert(sizeof(ProgMeta) == 16, "ProgMeta layout");
+
+// Staged-only opcodes (superinstructions).  A leaf directly followed by a
+// binary op folds into "top = top OP leaf"; a leaf directly followed by a
+// unary op folds into "save top; top = f(leaf)".  The leaf's load and the
+// op still run for every case: only the push/pop and one dispatch go.
+constexpr uint32_t kOpBinVar = 12;      // 12..15: ADD..DIV, leaf = X[var]
+constexpr uint32_t kOpBinConst = 16;    // 16..19: ADD..DIV, leaf = constant
+constexpr uint32_t kOpUnVar = 20;       // 20..25: SIN..ABS of X[var]
+constexpr uint32_t kOpUnConst = 26;     // 26..31: SIN..ABS of a constant
 
 __host__ __device__ inline int depth_class(int maxd)
 {
@@ -91,8 +97,15 @@ __host__ __device__ inline int depth_class(int maxd)
 }
 
 // Cases per lane for a depth class: deeper stacks hold fewer cases per
-// lane so that the register stack (MAXD * K VGPRs) stays bounded.
-__host__ __device__ constexpr int class_k(int c) { return c == 2 ? 2 : 4; }
+// lane so that the register stack (MAXD * K VGPRs) stays bounded.  (8 cases
+// per lane for the shallow class measured slower on gfx950: occupancy drops
+// from 5 to 3 waves per SIMD and LDS input reads are exposed.)  Depends only
+// on the class and the dataset, never on the rest of the population.
+int class_k(int c, int n_vars)
+{
+    if (c == 0) return 4;
+    return c == 1 ? 4 : 2;
+}
 
 // Tile geometry for one class: a tile is `passes` consecutive sub-tiles of
 // 256*K cases.  Depends only on (n_cases, K), so a program's summation
@@ -126,6 +139,11 @@ int scale_exponent(int64_t n)
 }
 
 // ------------------------------------------------------------- k_prepare
+// Stack slots are stored pre-scaled: element `slot` of a class with maximum
+// depth MAXD lives at index slot * (32 / MAXD) of each 32-float VGPR chunk,
+// so the kernel uses a 5-bit field directly (always inside the chunk).
+__host__ __device__ constexpr int class_depth(int c) { return c == 0 ? 8 : (c == 1 ? 16 : 32); }
+
 __global__ __launch_bounds__(256) void k_prepare(
     const uint32_t* __restrict__ nodes, const int64_t* __restrict__ offsets,
     int64_t n_programs, int64_t n_nodes, const float* __restrict__ consts,
@@ -138,6 +156,7 @@ __global__ __launch_bounds__(256) void k_prepare(
     const int64_t s = offsets[p], e = offsets[p + 1];
     int status = GP_PROG_OK;
     int depth = 0, maxd = 0;
+    // pass 1: validate (GCL stack discipline, operand ranges, allowed ops)
     if (s < 0 || e < s || e > n_nodes || e - s > INT32_MAX) {
         status = GP_PROG_BAD_OFFSETS;
     } else if (e == s) {
@@ -147,40 +166,67 @@ __global__ __launch_bounds__(256) void k_prepare(
             const uint32_t w = nodes[k];
             const uint32_t op = w & 0xFFu, arg = w >> 8;
             if (op >= GP_N_OPS || !((allowed >> op) & 1u)) { status = GP_PROG_BAD_OP; break; }
-            uint2 c;
-            if (op == GP_LOAD || op == GP_CONST) {
-                if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) { status = GP_PROG_BAD_VAR; break; }
-                if (op == GP_CONST && (int64_t)arg >= n_consts) { status = GP_PROG_BAD_CONST; break; }
-                if (depth + 1 > GP_MAX_STACK) { status = GP_PROG_TOO_DEEP; break; }
-                // the old top (element depth-1) moves into slot depth-1
-                const uint32_t wr = depth >= 1 ? (uint32_t)(depth - 1) : kNoSlot;
-                c.x = op | (wr << 16);
-                c.y = op == GP_LOAD ? arg : __float_as_uint(consts[arg]);
-                ++depth;
-            } else if (op <= GP_DIV) {
-                if (depth < 2) { status = GP_PROG_UNDERFLOW; break; }
-                // second from top (element depth-2) is read from slot depth-2
-                c.x = op | ((uint32_t)(depth - 2) << 8) | (kNoSlot << 16);
-                c.y = 0;
-                --depth;
-            } else {
-                if (depth < 1) { status = GP_PROG_UNDERFLOW; break; }
-                c.x = op | (kNoSlot << 16);
-                c.y = 0;
-            }
+            if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) { status = GP_PROG_BAD_VAR; break; }
+            if (op == GP_CONST && (int64_t)arg >= n_consts) { status = GP_PROG_BAD_CONST; break; }
+            const int need = op <= GP_CONST ? 0 : (op <= GP_DIV ? 2 : 1);
+            if (depth < need) { status = GP_PROG_UNDERFLOW; break; }
+            depth += op <= GP_CONST ? 1 : (op <= GP_DIV ? -1 : 0);
+            if (depth > GP_MAX_STACK) { status = GP_PROG_TOO_DEEP; break; }
             if (depth > maxd) maxd = depth;
-            code[k] = c;
         }
         if (status == GP_PROG_OK && depth != 1) status = GP_PROG_FINAL_DEPTH;
+    }
+    const int c = status == GP_PROG_OK ? depth_class(maxd) : -1;
+    // pass 2: stage 8-byte instructions {op | read index << 8 | write index
+    // << 16, variable index or constant bits}, folding a leaf into the op
+    // that directly follows it
+    int64_t sk = s;                              // next staged slot
+    if (c >= 0) {
+        const uint32_t J = 32u / (uint32_t)class_depth(c);
+        const uint32_t dummy = 32u - J;          // slot MAXD-1: never live
+        depth = 0;
+        for (int64_t k = s; k < e; ++k) {
+            const uint32_t w = nodes[k];
+            const uint32_t op = w & 0xFFu, arg = w >> 8;
+            uint2 cw;
+            if (op <= GP_CONST) {
+                const uint32_t payload = op == GP_LOAD ? arg : __float_as_uint(consts[arg]);
+                // the old top (element depth-1) would move into slot depth-1
+                const uint32_t wr = depth >= 1 ? (uint32_t)(depth - 1) * J : dummy;
+                const uint32_t nx = k + 1 < e ? (nodes[k + 1] & 0xFFu) : 0xFFu;
+                if (depth >= 1 && nx >= GP_ADD && nx <= GP_DIV) {
+                    // top = top OP leaf: no push, no pop
+                    cw.x = (op == GP_LOAD ? kOpBinVar : kOpBinConst) + (nx - GP_ADD);
+                    cw.y = payload;
+                    ++k;                         // the binary node is consumed
+                } else if (nx >= GP_SIN && nx < GP_N_OPS) {
+                    cw.x = ((op == GP_LOAD ? kOpUnVar : kOpUnConst) + (nx - GP_SIN)) | (wr << 16);
+                    cw.y = payload;
+                    ++depth;
+                    ++k;                         // the unary node is consumed
+                } else {
+                    cw.x = op | (wr << 16);
+                    cw.y = payload;
+                    ++depth;
+                }
+            } else if (op <= GP_DIV) {
+                // second from top (element depth-2) is read from slot depth-2
+                cw.x = op | (((uint32_t)(depth - 2) * J) << 8);
+                cw.y = 0;
+                --depth;
+            } else {
+                cw.x = op;
+                cw.y = 0;
+            }
+            code[sk++] = cw;
+        }
     }
     ProgMeta m;
     m.start = s;
     m.len = (int32_t)(status == GP_PROG_BAD_OFFSETS ? 0 : e - s);
-    m.maxd = (uint8_t)maxd;
-    m.cls = status == GP_PROG_OK ? (uint8_t)depth_class(maxd) : (uint8_t)0xFF;
-    m.status = (int16_t)status;
+    m.slen = (int32_t)(sk - s);
     meta[p] = m;
-    cls[p] = m.cls;
+    cls[p] = c >= 0 ? (uint8_t)c : (uint8_t)0xFF;
     if (out_status) out_status[p] = status;
 }
 
@@ -301,21 +347,45 @@ __device__ __forceinline__ void acc_pair(float& hi, float& lo, float h2, float l
 }
 
 // The value stack below the top lives in VGPR arrays of 32 floats ("chunks"):
-// chunk c holds cases [c*J, (c+1)*J) of every slot, element index slot*J + o.
-// A uniform dynamic index into a 32-element vector compiles to GPR-index-mode
-// moves (smaller vectors are expanded into compare/select chains).
-#define GP_CHUNK_PUT(slot, j, v)                                                   \
+// chunk c holds cases [c*J, (c+1)*J) of every slot, element index
+// slot*J + (case mod J), J = 32 / MAXD.  A uniform dynamic index into a
+// 32-element vector compiles to GPR-index-mode moves (smaller vectors would
+// be expanded into compare/select chains).  `ix` is the staged, pre-scaled
+// slot index (5 bits, so always inside the chunk).
+#define GP_CHUNK_PUT(ix, j, v)                                                     \
     do {                                                                           \
-        const uint32_t i_ = (slot) * J + ((j) % J);                                \
+        const uint32_t i_ = (ix) + ((j) % J);                                      \
         if ((j) / J == 0) c0[i_] = (v);                                            \
         else if ((j) / J == 1) c1[i_] = (v);                                       \
         else if ((j) / J == 2) c2[i_] = (v);                                       \
         else c3[i_] = (v);                                                         \
     } while (0)
-#define GP_CHUNK_GET(slot, j)                                                      \
-    (((j) / J == 0) ? c0[(slot) * J + ((j) % J)]                                   \
-     : ((j) / J == 1) ? c1[(slot) * J + ((j) % J)]                                 \
-     : ((j) / J == 2) ? c2[(slot) * J + ((j) % J)] : c3[(slot) * J + ((j) % J)])
+#define GP_CHUNK_GET(ix, j)                                                        \
+    (((j) / J == 0) ? c0[(ix) + ((j) % J)]                                         \
+     : ((j) / J == 1) ? c1[(ix) + ((j) % J)]                                       \
+     : ((j) / J == 2) ? c2[(ix) + ((j) % J)] : c3[(ix) + ((j) % J)])
+
+// out[j] = a[j] OP b[j] for the four binary ops (b = top of stack, a = the
+// element below it; SUB and DIV take a - b and a / b, GCL command table).
+#define GP_BINARY_AB(bop, a, b, out)                                               \
+    do {                                                                           \
+        switch (bop) {                                                             \
+        case GP_ADD:                                                               \
+            _Pragma("unroll") for (int j = 0; j < K; ++j) out[j] = a[j] + b[j];    \
+            break;                                                                 \
+        case GP_SUB:                                                               \
+            _Pragma("unroll") for (int j = 0; j < K; ++j) out[j] = a[j] - b[j];    \
+            break;                                                                 \
+        case GP_MUL:                                                               \
+            _Pragma("unroll") for (int j = 0; j < K; ++j) out[j] = a[j] * b[j];    \
+            break;                                                                 \
+        default:                                                                   \
+            _Pragma("unroll") for (int j = 0; j < K; ++j)                          \
+                out[j] = fabsf(b[j]) <= 0.001f ? 1.f : a[j] / b[j];                \
+            break;                                                                 \
+        }                                                                          \
+    } while (0)
+#define GP_BINARY(bop, a, top) GP_BINARY_AB(bop, a, top, top)
 
 template <int MAXD, int K>
 __global__ __launch_bounds__(kWG) void k_eval(
@@ -325,7 +395,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
     const float* __restrict__ y, float2* __restrict__ part,
     uint8_t* __restrict__ part_bad, EvalConst a)
 {
-    static_assert(K == 2 || K == 4, "cases per lane");
+    static_assert(K == 2 || K == 4 || K == 8, "cases per lane");
     static_assert(MAXD == 8 || MAXD == 16 || MAXD == 32, "stack class");
     constexpr int J = 32 / MAXD;                  // cases per 32-float chunk
     static_assert(K % J == 0 && K / J <= 4, "chunking");
@@ -384,21 +454,23 @@ __global__ __launch_bounds__(kWG) void k_eval(
                 const int pid = order[start + g0 + g];
                 const ProgMeta m = meta[pid];
                 const uint2* pc = code + m.start;
-                const int len = m.len;
+                const uint2* const pend = pc + m.slen;
 
                 float c0[32], c1[32], c2[32], c3[32];
                 float tos[K];
 #pragma unroll
                 for (int j = 0; j < K; ++j) tos[j] = 0.f;
 
-                uint2 w_next = pc[0];
-                for (int n = 0; n < len; ++n) {
-                    // fetch the next node while this one executes
+                // the staging buffer has one padding node after the last
+                // program, so fetching one node ahead never leaves it
+                uint2 w_next = *pc;
+                do {
                     const uint2 w = w_next;
-                    w_next = pc[min(n + 1, len - 1)];
+                    ++pc;
+                    w_next = *pc;
                     const uint32_t op = w.x & 0xFFu;
-                    const uint32_t rd = min((w.x >> 8) & 0xFFu, (uint32_t)(MAXD - 1));
-                    const uint32_t wr = min((w.x >> 16) & 0xFFu, (uint32_t)(MAXD - 1));
+                    const uint32_t rd = (w.x >> 8) & 31u;
+                    const uint32_t wr = (w.x >> 16) & 31u;
                     if (op <= GP_CONST) {
                         // leaf: the old top moves into the stack (slot MAXD-1
                         // never holds a live element, so a push onto an empty
@@ -419,28 +491,41 @@ __global__ __launch_bounds__(kWG) void k_eval(
                         float sv[K];
 #pragma unroll
                         for (int j = 0; j < K; ++j) sv[j] = GP_CHUNK_GET(rd, j);
-                        switch (op) {
-                        case GP_ADD:
+                        GP_BINARY(op, sv, tos);
+                    } else if (op >= kOpBinVar && op < kOpUnVar) {
+                        // top = top OP leaf
+                        float lv[K];
+                        if (op < kOpBinConst) {
+                            const float* xp = xt + (size_t)w.y * SUB + lo;
 #pragma unroll
-                            for (int j = 0; j < K; ++j) tos[j] = sv[j] + tos[j];
-                            break;
-                        case GP_SUB:
+                            for (int j = 0; j < K; ++j) lv[j] = xp[j];
+                        } else {
+                            const float c = __uint_as_float(w.y);
 #pragma unroll
-                            for (int j = 0; j < K; ++j) tos[j] = sv[j] - tos[j];
-                            break;
-                        case GP_MUL:
-#pragma unroll
-                            for (int j = 0; j < K; ++j) tos[j] = sv[j] * tos[j];
-                            break;
-                        default:
-#pragma unroll
-                            for (int j = 0; j < K; ++j)
-                                tos[j] = fabsf(tos[j]) <= 0.001f ? 1.f : sv[j] / tos[j];
-                            break;
+                            for (int j = 0; j < K; ++j) lv[j] = c;
                         }
+                        const uint32_t bop = GP_ADD + ((op - kOpBinVar) & 3u);
+                        GP_BINARY_AB(bop, tos, lv, tos);
                     } else {
+                        uint32_t uop = op;
+                        if (op >= kOpUnVar) {
+                            // f(leaf): the old top is saved first
+#pragma unroll
+                            for (int j = 0; j < K; ++j) GP_CHUNK_PUT(wr, j, tos[j]);
+                            if (op < kOpUnConst) {
+                                const float* xp = xt + (size_t)w.y * SUB + lo;
+#pragma unroll
+                                for (int j = 0; j < K; ++j) tos[j] = xp[j];
+                                uop = op - kOpUnVar + GP_SIN;
+                            } else {
+                                const float c = __uint_as_float(w.y);
+#pragma unroll
+                                for (int j = 0; j < K; ++j) tos[j] = c;
+                                uop = op - kOpUnConst + GP_SIN;
+                            }
+                        }
                         // unary: replaces the top
-                        switch (op) {
+                        switch (uop) {
                         case GP_SIN:
 #pragma unroll
                             for (int j = 0; j < K; ++j) tos[j] = sinf(tos[j]);
@@ -468,7 +553,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
                             break;
                         }
                     }
-                }
+                } while (pc != pend);
 
                 // fused residual, validity and scaled compensated square sum
                 float hi = 0.f, lo_ = 0.f;
@@ -524,6 +609,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
 // ------------------------------------------------------------ k_reduce
 struct ReduceArgs {
     const ProgMeta* meta;
+    const uint8_t* cls;
     const float2* part;
     const uint8_t* part_bad;
     double* out;
@@ -538,9 +624,10 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n_programs) return;
+    const int c = a.cls[p];
+    if (c >= kClasses) { a.out[p] = __builtin_nan(""); return; }
     const ProgMeta m = a.meta[p];
-    if (m.status != GP_PROG_OK) { a.out[p] = __builtin_nan(""); return; }
-    const int nt = a.n_tiles[m.cls];
+    const int nt = a.n_tiles[c];
     double s = 0.0;
     bool bad = false;
     for (int t = 0; t < nt; ++t) {
@@ -572,7 +659,7 @@ Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride)
     Layout L;
     const int64_t n_blk = (n_programs + kBucketBlock - 1) / kBucketBlock;
     size_t off = 0;
-    L.code = off;       off = align_up(off + (size_t)n_nodes * sizeof(uint2));
+    L.code = off;       off = align_up(off + (size_t)(n_nodes + 1) * sizeof(uint2));
     L.meta = off;       off = align_up(off + (size_t)n_programs * sizeof(ProgMeta));
     L.cls = off;        off = align_up(off + (size_t)n_programs);
     L.order = off;      off = align_up(off + (size_t)n_programs * 4);
@@ -784,7 +871,7 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
     TileShape ts[kClasses];
     int32_t stride = 1;
     for (int c = 0; c < kClasses; ++c) {
-        ts[c] = tile_shape(n_cases, class_k(c));
+        ts[c] = tile_shape(n_cases, class_k(c, n_vars));
         if (ts[c].n_tiles > stride) stride = ts[c].n_tiles;
     }
     const Layout L = make_layout(n_programs, n_nodes, stride);
@@ -841,7 +928,7 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
     }
 
     ReduceArgs ra{};
-    ra.meta = meta; ra.part = part; ra.part_bad = part_bad; ra.out = out_fitness;
+    ra.meta = meta; ra.cls = cls; ra.part = part; ra.part_bad = part_bad; ra.out = out_fitness;
     ra.n_programs = n_programs; ra.part_stride = stride;
     for (int c = 0; c < kClasses; ++c) ra.n_tiles[c] = ts[c].n_tiles;
     ra.unscale = ldexp(1.0, 2 * e) / (double)n_cases;
