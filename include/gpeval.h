@@ -127,6 +127,22 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
             double tax_on_length, uint32_t allowed_op_mask,
             double* out_fitness, int32_t* out_status, hipStream_t stream);
 
+/*
+ * gp_predict -- per-case outputs f_p(x_i) of every program (the paper's
+ * ExecuteGenome utility, Sec. "Useful Utilities": run a genome on input
+ * data).  Same program and input arguments as gp_eval (device pointers);
+ * out: float32, out[p * ld_out + i] for i < n_cases, ld_out >= n_cases,
+ * caller-owned device memory of n_programs * ld_out floats.  Values are the
+ * fp32 results of the same interpreter gp_eval runs (NaN and +-inf kept).
+ * Programs that fail validation get a NaN row and a nonzero out_status.
+ * Asynchronous on `stream`; shares gp_eval's per-stream workspace.
+ */
+int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
+               int64_t n_nodes, const float* consts, int64_t n_consts,
+               const float* X, int32_t n_vars, int64_t ld_x, int64_t n_cases,
+               uint32_t allowed_op_mask, float* out, int64_t ld_out, int32_t* out_status,
+               hipStream_t stream);
+
 /* Release every cached workspace of the calling process (all devices). */
 void gp_release_workspaces(void);
 

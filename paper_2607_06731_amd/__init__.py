@@ -50,6 +50,9 @@ def lib():
         L.gp_eval.argtypes = [vp, vp, i64, i64, vp, i64, vp, i32, i64, vp, i64,
                               ctypes.c_double, u32, vp, vp, vp]
         L.gp_eval.restype = ctypes.c_int
+        L.gp_predict.argtypes = [vp, vp, i64, i64, vp, i64, vp, i32, i64, i64, u32, vp, i64,
+                                 vp, vp]
+        L.gp_predict.restype = ctypes.c_int
         L.gp_release_workspaces.argtypes = []
         L.gp_release_workspaces.restype = None
         L.gp_timing_enable.argtypes = [ctypes.c_int]
@@ -151,6 +154,40 @@ def gp_eval(nodes, offsets, consts, X, y, tax_on_length, out_fitness,
                        _dev_ptr(out_status, torch.int32, "out_status"), _stream_handle(stream))
     _check(rc)
     return out_fitness
+
+
+def gp_predict(nodes, offsets, consts, X, out, out_status=None, allowed_op_mask=0,
+               n_cases=None, stream=None):
+    """Per-case outputs into out float32[P, ld_out] (device tensors)."""
+    import torch
+    P = offsets.numel() - 1
+    if X.dim() != 2:
+        raise ValueError("X must be 2-D [n_vars, ld_x]")
+    n = X.shape[1] if n_cases is None else int(n_cases)
+    if out.dim() != 2 or out.shape[0] != P or out.stride(1) != 1:
+        raise ValueError("out must be [n_programs, ld_out] with unit column stride")
+    rc = lib().gp_predict(_dev_ptr(nodes, torch.uint32, "nodes"),
+                          _dev_ptr(offsets, torch.int64, "offsets"), P, nodes.numel(),
+                          _dev_ptr(consts, torch.float32, "consts"), consts.numel(),
+                          _dev_ptr(X, torch.float32, "X"), X.shape[0], X.shape[1], n,
+                          int(allowed_op_mask), ctypes.c_void_p(out.data_ptr()), out.stride(0),
+                          _dev_ptr(out_status, torch.int32, "out_status"), _stream_handle(stream))
+    _check(rc)
+    return out
+
+
+def predict(nodes, offsets, consts, X, allowed_op_mask=0, device="cuda"):
+    """numpy in, numpy out: per-case outputs float32[P, n_cases]."""
+    import torch
+    pop = DevicePopulation(nodes, offsets, consts, device)
+    Xn = np.ascontiguousarray(X, np.float32)
+    if Xn.ndim == 1:
+        Xn = Xn.reshape(1, -1)
+    Xd = torch.from_numpy(Xn).to(device)
+    out = torch.empty((pop.n_programs, Xn.shape[1]), dtype=torch.float32, device=device)
+    gp_predict(pop.nodes, pop.offsets, pop.consts, Xd, out, allowed_op_mask=allowed_op_mask)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
 
 
 class DevicePopulation:

@@ -346,6 +346,61 @@ __device__ __forceinline__ void acc_pair(float& hi, float& lo, float h2, float l
     lo = (lo + l2) + e;
 }
 
+// ------------------------------------------------------------------ sin/cos
+// Constants from gen_sin_poly.py: minimax odd polynomial for sin on
+// |r| <= pi/2 + 0.01 (relative error 5.7e-10 before fp32 evaluation) and a
+// three-part fp32 split of pi for Cody-Waite reduction.  Measured against
+// correctly rounded results: <= 1.75 ulp for |x| <= 2^17, including inputs
+// next to multiples of pi; larger or non-finite inputs take the library
+// path (which carries a Payne-Hanek reduction).
+constexpr float kSinC0 = -1.666666716e-01f;
+constexpr float kSinC1 = 8.333351463e-03f;
+constexpr float kSinC2 = -1.984328410e-04f;
+constexpr float kSinC3 = 2.763883458e-06f;
+constexpr float kSinC4 = -2.573010249e-08f;
+constexpr float kPiA = 3.141592741e+00f;
+constexpr float kPiB = -8.742277657e-08f;
+constexpr float kPiC = -3.430249020e-15f;
+constexpr float kInvPi = 3.183098733e-01f;
+constexpr float kTrigFastLimit = 131072.0f;
+
+// sin(r) for |r| <= pi/2 (+ margin)
+__device__ __forceinline__ float sin_poly(float r)
+{
+    const float u = r * r;
+    float q = fmaf(u, kSinC4, kSinC3);
+    q = fmaf(u, q, kSinC2);
+    q = fmaf(u, q, kSinC1);
+    q = fmaf(u, q, kSinC0);
+    return fmaf(u * r, q, r);
+}
+
+// r = x - kh * pi in three fused steps (exact first step for |x| <= 2^17)
+__device__ __forceinline__ float reduce_pi(float x, float kh)
+{
+    float r = fmaf(-kh, kPiA, x);
+    r = fmaf(-kh, kPiB, r);
+    return fmaf(-kh, kPiC, r);
+}
+
+// sin x = (-1)^k sin(x - k pi), k = rint(x / pi)
+__device__ __forceinline__ float sin_fast(float x)
+{
+    const float k = rintf(x * kInvPi);
+    const float s = sin_poly(reduce_pi(x, k));
+    const int ki = (int)k;
+    return __int_as_float(__float_as_int(s) ^ (ki << 31));
+}
+
+// cos x = -(-1)^k sin(x - (k + 1/2) pi), k = rint(x / pi - 1/2)
+__device__ __forceinline__ float cos_fast(float x)
+{
+    const float k = rintf(fmaf(x, kInvPi, -0.5f));
+    const float s = sin_poly(reduce_pi(x, k + 0.5f));
+    const int ki = (int)k;
+    return __int_as_float(__float_as_int(s) ^ ((ki + 1) << 31));
+}
+
 // The value stack below the top lives in VGPR arrays of 32 floats ("chunks"):
 // chunk c holds cases [c*J, (c+1)*J) of every slot, element index
 // slot*J + (case mod J), J = 32 / MAXD.  A uniform dynamic index into a
@@ -386,6 +441,133 @@ __device__ __forceinline__ void acc_pair(float& hi, float& lo, float h2, float l
         }                                                                          \
     } while (0)
 #define GP_BINARY(bop, a, top) GP_BINARY_AB(bop, a, top, top)
+
+// Runs one staged program on K cases per lane; xl points at this lane's
+// first case of the LDS input tile (row stride SUB).  The top of the stack
+// is returned in tos[].
+template <int MAXD, int K, int SUB>
+__device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
+                                            const uint2* __restrict__ pend,
+                                            const float* __restrict__ xl, float (&tos)[K])
+{
+    constexpr int J = 32 / MAXD;                  // cases per 32-float chunk
+    static_assert(K % J == 0 && K / J <= 4, "chunking");
+    float c0[32], c1[32], c2[32], c3[32];
+#pragma unroll
+    for (int j = 0; j < K; ++j) tos[j] = 0.f;
+
+    // the staging buffer has one padding node after the last
+    // program, so fetching one node ahead never leaves it
+    uint2 w_next = *pc;
+    do {
+        const uint2 w = w_next;
+        ++pc;
+        w_next = *pc;
+        const uint32_t op = w.x & 0xFFu;
+        const uint32_t rd = (w.x >> 8) & 31u;
+        const uint32_t wr = (w.x >> 16) & 31u;
+        if (op <= GP_CONST) {
+            // leaf: the old top moves into the stack (slot MAXD-1
+            // never holds a live element, so a push onto an empty
+            // stack writes there), the new value becomes the top
+#pragma unroll
+            for (int j = 0; j < K; ++j) GP_CHUNK_PUT(wr, j, tos[j]);
+            if (op == GP_LOAD) {
+                const float* xp = xl + (size_t)w.y * SUB;
+#pragma unroll
+                for (int j = 0; j < K; ++j) tos[j] = xp[j];
+            } else {
+                const float c = __uint_as_float(w.y);
+#pragma unroll
+                for (int j = 0; j < K; ++j) tos[j] = c;
+            }
+        } else if (op <= GP_DIV) {
+            // binary: a = second from top (stack slot rd), b = top
+            float sv[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) sv[j] = GP_CHUNK_GET(rd, j);
+            GP_BINARY(op, sv, tos);
+        } else if (op >= kOpBinVar && op < kOpUnVar) {
+            // top = top OP leaf
+            float lv[K];
+            if (op < kOpBinConst) {
+                const float* xp = xl + (size_t)w.y * SUB;
+#pragma unroll
+                for (int j = 0; j < K; ++j) lv[j] = xp[j];
+            } else {
+                const float c = __uint_as_float(w.y);
+#pragma unroll
+                for (int j = 0; j < K; ++j) lv[j] = c;
+            }
+            const uint32_t bop = GP_ADD + ((op - kOpBinVar) & 3u);
+            GP_BINARY_AB(bop, tos, lv, tos);
+        } else {
+            uint32_t uop = op;
+            if (op >= kOpUnVar) {
+                // f(leaf): the old top is saved first
+#pragma unroll
+                for (int j = 0; j < K; ++j) GP_CHUNK_PUT(wr, j, tos[j]);
+                if (op < kOpUnConst) {
+                    const float* xp = xl + (size_t)w.y * SUB;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) tos[j] = xp[j];
+                    uop = op - kOpUnVar + GP_SIN;
+                } else {
+                    const float c = __uint_as_float(w.y);
+#pragma unroll
+                    for (int j = 0; j < K; ++j) tos[j] = c;
+                    uop = op - kOpUnConst + GP_SIN;
+                }
+            }
+            // unary: replaces the top
+            switch (uop) {
+            case GP_SIN:
+            case GP_COS: {
+                // fast path for |x| <= 2^17; the library function (with a
+                // large-argument reduction) for the rest
+                bool big = false;
+#pragma unroll
+                for (int j = 0; j < K; ++j) big |= !(fabsf(tos[j]) <= kTrigFastLimit);
+                float f[K];
+                if (uop == GP_SIN) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) f[j] = sin_fast(tos[j]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) f[j] = cos_fast(tos[j]);
+                }
+                if (__ballot(big) != 0ull) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j)
+                        if (!(fabsf(tos[j]) <= kTrigFastLimit))
+                            f[j] = uop == GP_SIN ? sinf(tos[j]) : cosf(tos[j]);
+                }
+#pragma unroll
+                for (int j = 0; j < K; ++j) tos[j] = f[j];
+                break;
+            }
+            case GP_EXP:
+#pragma unroll
+                for (int j = 0; j < K; ++j) tos[j] = expf(tos[j]);
+                break;
+            case GP_LOG:
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    tos[j] = fabsf(tos[j]) <= 0.001f ? 0.f : logf(fabsf(tos[j]));
+                break;
+            case GP_SQRT:
+#pragma unroll
+                for (int j = 0; j < K; ++j) tos[j] = sqrtf(fabsf(tos[j]));
+                break;
+            default:
+#pragma unroll
+                for (int j = 0; j < K; ++j) tos[j] = fabsf(tos[j]);
+                break;
+            }
+        }
+    } while (pc != pend);
+
+}
 
 template <int MAXD, int K>
 __global__ __launch_bounds__(kWG) void k_eval(
@@ -453,107 +635,8 @@ __global__ __launch_bounds__(kWG) void k_eval(
             for (int g = 0; g < gn; ++g) {
                 const int pid = order[start + g0 + g];
                 const ProgMeta m = meta[pid];
-                const uint2* pc = code + m.start;
-                const uint2* const pend = pc + m.slen;
-
-                float c0[32], c1[32], c2[32], c3[32];
                 float tos[K];
-#pragma unroll
-                for (int j = 0; j < K; ++j) tos[j] = 0.f;
-
-                // the staging buffer has one padding node after the last
-                // program, so fetching one node ahead never leaves it
-                uint2 w_next = *pc;
-                do {
-                    const uint2 w = w_next;
-                    ++pc;
-                    w_next = *pc;
-                    const uint32_t op = w.x & 0xFFu;
-                    const uint32_t rd = (w.x >> 8) & 31u;
-                    const uint32_t wr = (w.x >> 16) & 31u;
-                    if (op <= GP_CONST) {
-                        // leaf: the old top moves into the stack (slot MAXD-1
-                        // never holds a live element, so a push onto an empty
-                        // stack writes there), the new value becomes the top
-#pragma unroll
-                        for (int j = 0; j < K; ++j) GP_CHUNK_PUT(wr, j, tos[j]);
-                        if (op == GP_LOAD) {
-                            const float* xp = xt + (size_t)w.y * SUB + lo;
-#pragma unroll
-                            for (int j = 0; j < K; ++j) tos[j] = xp[j];
-                        } else {
-                            const float c = __uint_as_float(w.y);
-#pragma unroll
-                            for (int j = 0; j < K; ++j) tos[j] = c;
-                        }
-                    } else if (op <= GP_DIV) {
-                        // binary: a = second from top (stack slot rd), b = top
-                        float sv[K];
-#pragma unroll
-                        for (int j = 0; j < K; ++j) sv[j] = GP_CHUNK_GET(rd, j);
-                        GP_BINARY(op, sv, tos);
-                    } else if (op >= kOpBinVar && op < kOpUnVar) {
-                        // top = top OP leaf
-                        float lv[K];
-                        if (op < kOpBinConst) {
-                            const float* xp = xt + (size_t)w.y * SUB + lo;
-#pragma unroll
-                            for (int j = 0; j < K; ++j) lv[j] = xp[j];
-                        } else {
-                            const float c = __uint_as_float(w.y);
-#pragma unroll
-                            for (int j = 0; j < K; ++j) lv[j] = c;
-                        }
-                        const uint32_t bop = GP_ADD + ((op - kOpBinVar) & 3u);
-                        GP_BINARY_AB(bop, tos, lv, tos);
-                    } else {
-                        uint32_t uop = op;
-                        if (op >= kOpUnVar) {
-                            // f(leaf): the old top is saved first
-#pragma unroll
-                            for (int j = 0; j < K; ++j) GP_CHUNK_PUT(wr, j, tos[j]);
-                            if (op < kOpUnConst) {
-                                const float* xp = xt + (size_t)w.y * SUB + lo;
-#pragma unroll
-                                for (int j = 0; j < K; ++j) tos[j] = xp[j];
-                                uop = op - kOpUnVar + GP_SIN;
-                            } else {
-                                const float c = __uint_as_float(w.y);
-#pragma unroll
-                                for (int j = 0; j < K; ++j) tos[j] = c;
-                                uop = op - kOpUnConst + GP_SIN;
-                            }
-                        }
-                        // unary: replaces the top
-                        switch (uop) {
-                        case GP_SIN:
-#pragma unroll
-                            for (int j = 0; j < K; ++j) tos[j] = sinf(tos[j]);
-                            break;
-                        case GP_COS:
-#pragma unroll
-                            for (int j = 0; j < K; ++j) tos[j] = cosf(tos[j]);
-                            break;
-                        case GP_EXP:
-#pragma unroll
-                            for (int j = 0; j < K; ++j) tos[j] = expf(tos[j]);
-                            break;
-                        case GP_LOG:
-#pragma unroll
-                            for (int j = 0; j < K; ++j)
-                                tos[j] = fabsf(tos[j]) <= 0.001f ? 0.f : logf(fabsf(tos[j]));
-                            break;
-                        case GP_SQRT:
-#pragma unroll
-                            for (int j = 0; j < K; ++j) tos[j] = sqrtf(fabsf(tos[j]));
-                            break;
-                        default:
-#pragma unroll
-                            for (int j = 0; j < K; ++j) tos[j] = fabsf(tos[j]);
-                            break;
-                        }
-                    }
-                } while (pc != pend);
+                run_program<MAXD, K, SUB>(code + m.start, code + m.start + m.slen, xt + lo, tos);
 
                 // fused residual, validity and scaled compensated square sum
                 float hi = 0.f, lo_ = 0.f;
@@ -604,6 +687,68 @@ __global__ __launch_bounds__(kWG) void k_eval(
         }
         __syncthreads();
     }
+}
+
+// ------------------------------------------------------------ k_predict
+// Per-case outputs f_p(x_i) of the programs of one depth class: persistent
+// workgroups pull (program, sub-tile) items; each lane writes its K values.
+template <int MAXD, int K>
+__global__ __launch_bounds__(kWG) void k_predict(
+    const uint2* __restrict__ code, const ProgMeta* __restrict__ meta,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ class_info,
+    uint32_t* __restrict__ work_counter, const float* __restrict__ X,
+    float* __restrict__ out, int64_t ld_out, EvalConst a)
+{
+    constexpr int SUB = kWG * K;
+    extern __shared__ float lds[];
+    float* xt = lds;                              // [n_vars][SUB]
+    __shared__ uint32_t s_item;
+    const int tid = threadIdx.x;
+    const int lo = tid * K;
+    const int start = class_info[2 * a.cls];
+    const int count = class_info[2 * a.cls + 1];
+    const int64_t n_sub = (a.n_cases + SUB - 1) / SUB;
+    const uint64_t n_items = (uint64_t)count * (uint64_t)n_sub;
+    int64_t staged = -1;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(work_counter, 1u);
+        __syncthreads();
+        const uint64_t item = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (item >= n_items) break;
+        const int64_t sub = (int64_t)(item / (uint64_t)count);
+        const int g = (int)(item % (uint64_t)count);
+        const int64_t base = sub * SUB;
+        if (sub != staged) {
+            for (int i = tid; i < a.n_vars * SUB; i += kWG) {
+                const int v = i / SUB, c = i - v * SUB;
+                const int64_t gi = base + c;
+                xt[i] = gi < a.n_cases ? X[(int64_t)v * a.ld_x + gi] : 0.f;
+            }
+            staged = sub;
+            __syncthreads();
+        }
+        const int pid = order[start + g];
+        const ProgMeta m = meta[pid];
+        float tos[K];
+        run_program<MAXD, K, SUB>(code + m.start, code + m.start + m.slen, xt + lo, tos);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int64_t gi = base + lo + j;
+            if (gi < a.n_cases) out[(int64_t)pid * ld_out + gi] = tos[j];
+        }
+        __syncthreads();
+    }
+}
+
+// NaN rows for programs that failed validation (one workgroup per program).
+__global__ __launch_bounds__(256) void k_fill_invalid(const uint8_t* __restrict__ cls,
+                                                      int64_t n_cases, float* __restrict__ out,
+                                                      int64_t ld_out)
+{
+    const int64_t p = blockIdx.x;
+    if (cls[p] < kClasses) return;
+    for (int64_t i = threadIdx.x; i < n_cases; i += 256) out[p * ld_out + i] = __builtin_nanf("");
 }
 
 // ------------------------------------------------------------ k_reduce
@@ -776,6 +921,24 @@ struct CallEvents {
     }
 };
 
+template <int MAXD, int K>
+int launch_predict(const EvalPtrs& p, float* out, int64_t ld_out, const EvalConst& args,
+                   hipStream_t stream, int cus)
+{
+    const size_t lds = (size_t)args.n_vars * kWG * K * sizeof(float);
+    if (lds > 64 * 1024) {
+        GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_predict<MAXD, K>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    int per_cu = 0;
+    GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_predict<MAXD, K>, kWG, lds));
+    if (per_cu < 1) return set_error(GP_E_TOO_LARGE, "n_vars=%d needs %zu bytes of LDS per workgroup", args.n_vars, lds);
+    hipLaunchKernelGGL((k_predict<MAXD, K>), dim3(cus * per_cu), dim3(kWG), lds, stream, p.code,
+                       p.meta, p.order, p.class_info, p.work_counter, p.X, out, ld_out, args);
+    GP_HIP_TRY(hipGetLastError());
+    return GP_OK;
+}
+
 int check_common(int64_t n_programs, int64_t n_nodes, int64_t n_consts, int32_t n_vars,
                  int64_t ld_x, int64_t n_cases)
 {
@@ -790,6 +953,79 @@ int check_common(int64_t n_programs, int64_t n_nodes, int64_t n_consts, int32_t 
     if (n_cases < 1) return set_error(GP_E_INVALID_ARG, "n_cases < 1");
     if (n_cases > (int64_t(1) << 40)) return set_error(GP_E_TOO_LARGE, "n_cases > 2^40");
     if (n_vars > 0 && ld_x < n_cases) return set_error(GP_E_INVALID_ARG, "ld_x < n_cases");
+    return GP_OK;
+}
+
+int check_pointers(const uint32_t* nodes, int64_t n_nodes, const float* consts, int64_t n_consts,
+                   const float* X, int32_t n_vars)
+{
+    if (n_nodes > 0 && !nodes) return set_error(GP_E_INVALID_ARG, "nodes is NULL");
+    if (n_consts > 0 && !consts) return set_error(GP_E_INVALID_ARG, "consts is NULL");
+    if (n_vars > 0 && !X) return set_error(GP_E_INVALID_ARG, "X is NULL");
+    return GP_OK;
+}
+
+int device_cus(int* cus)
+{
+    int dev = 0;
+    GP_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_dev_mutex);
+    DeviceInfo& di = g_dev[dev];
+    if (di.cus == 0) GP_HIP_TRY(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    *cus = di.cus;
+    return GP_OK;
+}
+
+// Device views of one call's workspace.
+struct Staged {
+    uint2* code;
+    ProgMeta* meta;
+    uint8_t* cls;
+    int32_t* order;
+    int32_t* class_info;
+    uint32_t* counters;
+    float2* part;
+    uint8_t* part_bad;
+};
+
+// Validation, staging and the stable depth-class partition, on `stream`.
+int stage_population(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
+                     int64_t n_nodes, const float* consts, int64_t n_consts, int32_t n_vars,
+                     uint32_t allowed_op_mask, int32_t* out_status, int32_t part_stride,
+                     hipStream_t stream, Staged* st)
+{
+    const uint32_t allowed = allowed_op_mask ? allowed_op_mask : GP_ALL_OPS;
+    const Layout L = make_layout(n_programs, n_nodes, part_stride);
+    void* wsv = nullptr;
+    int rc = get_workspace(stream, L.total, &wsv);
+    if (rc != GP_OK) return rc;
+    char* ws = static_cast<char*>(wsv);
+    st->code = reinterpret_cast<uint2*>(ws + L.code);
+    st->meta = reinterpret_cast<ProgMeta*>(ws + L.meta);
+    st->cls = reinterpret_cast<uint8_t*>(ws + L.cls);
+    st->order = reinterpret_cast<int32_t*>(ws + L.order);
+    int32_t* blk_counts = reinterpret_cast<int32_t*>(ws + L.blk_counts);
+    int32_t* blk_base = reinterpret_cast<int32_t*>(ws + L.blk_base);
+    st->class_info = reinterpret_cast<int32_t*>(ws + L.class_info);
+    st->counters = reinterpret_cast<uint32_t*>(ws + L.counters);
+    st->part = reinterpret_cast<float2*>(ws + L.part);
+    st->part_bad = reinterpret_cast<uint8_t*>(ws + L.part_bad);
+
+    const int32_t n_blk = (int32_t)((n_programs + kBucketBlock - 1) / kBucketBlock);
+    const unsigned grid_p = (unsigned)((n_programs + 255) / 256);
+    hipLaunchKernelGGL(k_prepare, dim3(grid_p), dim3(256), 0, stream, nodes, offsets, n_programs,
+                       n_nodes, consts, n_consts, n_vars, allowed, st->code, st->meta, st->cls,
+                       out_status);
+    GP_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_class_count, dim3(n_blk), dim3(kBucketBlock), 0, stream, st->cls,
+                       n_programs, n_blk, blk_counts);
+    GP_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_class_scan, dim3(1), dim3(1024), 0, stream, blk_counts, n_blk, blk_base,
+                       st->class_info, st->counters);
+    GP_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_class_scatter, dim3(n_blk), dim3(kBucketBlock), 0, stream, st->cls,
+                       n_programs, n_blk, blk_base, st->order);
+    GP_HIP_TRY(hipGetLastError());
     return GP_OK;
 }
 
@@ -852,65 +1088,27 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
     if (rc != GP_OK) return rc;
     if (n_programs == 0) return GP_OK;
     if (!offsets || !out_fitness || !y) return set_error(GP_E_INVALID_ARG, "NULL offsets, y or out_fitness");
-    if (n_nodes > 0 && !nodes) return set_error(GP_E_INVALID_ARG, "nodes is NULL");
-    if (n_consts > 0 && !consts) return set_error(GP_E_INVALID_ARG, "consts is NULL");
-    if (n_vars > 0 && !X) return set_error(GP_E_INVALID_ARG, "X is NULL");
+    if ((rc = check_pointers(nodes, n_nodes, consts, n_consts, X, n_vars)) != GP_OK) return rc;
     if (!std::isfinite(tax_on_length)) return set_error(GP_E_INVALID_ARG, "tax_on_length is not finite");
-    const uint32_t allowed = allowed_op_mask ? allowed_op_mask : GP_ALL_OPS;
 
-    int dev = 0;
-    GP_HIP_TRY(hipGetDevice(&dev));
     int cus = 0;
-    {
-        std::lock_guard<std::mutex> lk(g_dev_mutex);
-        DeviceInfo& di = g_dev[dev];
-        if (di.cus == 0) GP_HIP_TRY(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
-        cus = di.cus;
-    }
-
+    if ((rc = device_cus(&cus)) != GP_OK) return rc;
     TileShape ts[kClasses];
     int32_t stride = 1;
     for (int c = 0; c < kClasses; ++c) {
         ts[c] = tile_shape(n_cases, class_k(c, n_vars));
         if (ts[c].n_tiles > stride) stride = ts[c].n_tiles;
     }
-    const Layout L = make_layout(n_programs, n_nodes, stride);
-    void* wsv = nullptr;
-    rc = get_workspace(stream, L.total, &wsv);
-    if (rc != GP_OK) return rc;
-    char* ws = static_cast<char*>(wsv);
-    uint2* code = reinterpret_cast<uint2*>(ws + L.code);
-    ProgMeta* meta = reinterpret_cast<ProgMeta*>(ws + L.meta);
-    uint8_t* cls = reinterpret_cast<uint8_t*>(ws + L.cls);
-    int32_t* order = reinterpret_cast<int32_t*>(ws + L.order);
-    int32_t* blk_counts = reinterpret_cast<int32_t*>(ws + L.blk_counts);
-    int32_t* blk_base = reinterpret_cast<int32_t*>(ws + L.blk_base);
-    int32_t* class_info = reinterpret_cast<int32_t*>(ws + L.class_info);
-    uint32_t* counters = reinterpret_cast<uint32_t*>(ws + L.counters);
-    float2* part = reinterpret_cast<float2*>(ws + L.part);
-    uint8_t* part_bad = reinterpret_cast<uint8_t*>(ws + L.part_bad);
-
     CallEvents ce;
-    rc = ce.begin();
-    if (rc != GP_OK) return rc;
-    const int32_t n_blk = (int32_t)((n_programs + kBucketBlock - 1) / kBucketBlock);
-    const unsigned grid_p = (unsigned)((n_programs + 255) / 256);
+    if ((rc = ce.begin()) != GP_OK) return rc;
     if ((rc = ce.mark(0, stream)) != GP_OK) return rc;
-    hipLaunchKernelGGL(k_prepare, dim3(grid_p), dim3(256), 0, stream, nodes, offsets, n_programs,
-                       n_nodes, consts, n_consts, n_vars, allowed, code, meta, cls, out_status);
-    GP_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_class_count, dim3(n_blk), dim3(kBucketBlock), 0, stream, cls, n_programs,
-                       n_blk, blk_counts);
-    GP_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_class_scan, dim3(1), dim3(1024), 0, stream, blk_counts, n_blk, blk_base,
-                       class_info, counters);
-    GP_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_class_scatter, dim3(n_blk), dim3(kBucketBlock), 0, stream, cls, n_programs,
-                       n_blk, blk_base, order);
-    GP_HIP_TRY(hipGetLastError());
+    Staged st;
+    rc = stage_population(nodes, offsets, n_programs, n_nodes, consts, n_consts, n_vars,
+                          allowed_op_mask, out_status, stride, stream, &st);
+    if (rc != GP_OK) return rc;
 
     const int e = scale_exponent(n_cases);
-    EvalPtrs ep{code, meta, order, class_info, nullptr, X, y, part, part_bad};
+    EvalPtrs ep{st.code, st.meta, st.order, st.class_info, nullptr, X, y, st.part, st.part_bad};
     EvalConst ea{};
     ea.ld_x = ld_x; ea.n_cases = n_cases; ea.n_vars = n_vars; ea.G = 8;
     ea.part_stride = stride;
@@ -918,7 +1116,7 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
     for (int c = 0; c < kClasses; ++c) {
         if ((rc = ce.mark(1 + c, stream)) != GP_OK) return rc;
         ea.cls = c;
-        ep.work_counter = counters + c;
+        ep.work_counter = st.counters + c;
         ea.passes = ts[c].passes;
         ea.n_tiles = ts[c].n_tiles;
         if (c == 0) rc = launch_eval<8, 4>(ep, ea, stream, cus);
@@ -928,16 +1126,55 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
     }
 
     ReduceArgs ra{};
-    ra.meta = meta; ra.cls = cls; ra.part = part; ra.part_bad = part_bad; ra.out = out_fitness;
+    ra.meta = st.meta; ra.cls = st.cls; ra.part = st.part; ra.part_bad = st.part_bad;
+    ra.out = out_fitness;
     ra.n_programs = n_programs; ra.part_stride = stride;
     for (int c = 0; c < kClasses; ++c) ra.n_tiles[c] = ts[c].n_tiles;
     ra.unscale = ldexp(1.0, 2 * e) / (double)n_cases;
     ra.tax = tax_on_length;
     if ((rc = ce.mark(4, stream)) != GP_OK) return rc;
-    hipLaunchKernelGGL(k_reduce, dim3(grid_p), dim3(256), 0, stream, ra);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((n_programs + 255) / 256)), dim3(256), 0, stream, ra);
     GP_HIP_TRY(hipGetLastError());
     if ((rc = ce.mark(5, stream)) != GP_OK) return rc;
     ce.commit();
+    return GP_OK;
+}
+
+int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
+               int64_t n_nodes, const float* consts, int64_t n_consts,
+               const float* X, int32_t n_vars, int64_t ld_x, int64_t n_cases,
+               uint32_t allowed_op_mask, float* out, int64_t ld_out, int32_t* out_status,
+               hipStream_t stream)
+{
+    int rc = check_common(n_programs, n_nodes, n_consts, n_vars, ld_x, n_cases);
+    if (rc != GP_OK) return rc;
+    if (n_programs == 0) return GP_OK;
+    if (!offsets || !out) return set_error(GP_E_INVALID_ARG, "NULL offsets or out");
+    if (ld_out < n_cases) return set_error(GP_E_INVALID_ARG, "ld_out < n_cases");
+    if ((rc = check_pointers(nodes, n_nodes, consts, n_consts, X, n_vars)) != GP_OK) return rc;
+    // work items (program, sub-tile) are counted in 32 bits
+    if ((double)n_programs * (double)((n_cases + 511) / 512) > 2.0e9)
+        return set_error(GP_E_TOO_LARGE, "n_programs * n_cases too large for one gp_predict call");
+    int cus = 0;
+    if ((rc = device_cus(&cus)) != GP_OK) return rc;
+    Staged st;
+    rc = stage_population(nodes, offsets, n_programs, n_nodes, consts, n_consts, n_vars,
+                          allowed_op_mask, out_status, 0, stream, &st);
+    if (rc != GP_OK) return rc;
+    EvalPtrs ep{st.code, st.meta, st.order, st.class_info, nullptr, X, nullptr, nullptr, nullptr};
+    EvalConst ea{};
+    ea.ld_x = ld_x; ea.n_cases = n_cases; ea.n_vars = n_vars;
+    for (int c = 0; c < kClasses; ++c) {
+        ea.cls = c;
+        ep.work_counter = st.counters + c;
+        if (c == 0) rc = launch_predict<8, 4>(ep, out, ld_out, ea, stream, cus);
+        else if (c == 1) rc = launch_predict<16, 4>(ep, out, ld_out, ea, stream, cus);
+        else rc = launch_predict<32, 2>(ep, out, ld_out, ea, stream, cus);
+        if (rc != GP_OK) return rc;
+    }
+    hipLaunchKernelGGL(k_fill_invalid, dim3((unsigned)n_programs), dim3(256), 0, stream, st.cls,
+                       n_cases, out, ld_out);
+    GP_HIP_TRY(hipGetLastError());
     return GP_OK;
 }
 

@@ -1,0 +1,165 @@
+"""Per-case checks through gp_predict (the ExecuteGenome-style utility).
+
+Each op is run as a one-op program over dense sweeps of inputs and compared,
+case by case, with the oracle's M32E mode (the correctly rounded fp32 value
+of the fp64 result).  Bounds: +, -, *, |.|, protected DIV and SQRT exact
+(they are correctly rounded in fp32), elementary functions within 2 ulps
+(the envelope the parity gate's chaos certificate assumes).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import (ABS, ADD, CONST, COS, DIV, EXP, LOAD, LOG, MUL, SIN, SQRT,
+                    SUB)
+
+pytestmark = pytest.mark.gpu
+
+ULP_BOUND = {SIN: 2.0, COS: 2.0, EXP: 2.0, LOG: 2.0, SQRT: 0.0, ABS: 0.0,
+             ADD: 0.0, SUB: 0.0, MUL: 0.0, DIV: 0.0}
+
+
+def _gp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_06731_amd as gp
+    gp.lib()
+    return gp
+
+
+def _say(msg):
+    print("[gpu] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def ulp_err(got, ref):
+    """|got - ref| in units of the fp32 spacing at ref (both fp32 values)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    both_nan = np.isnan(got) & np.isnan(ref)
+    same_inf = np.isinf(got) & np.isinf(ref) & (np.sign(got) == np.sign(ref))
+    sp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    e = np.abs(got - ref) / sp
+    e[both_nan | same_inf | (got == ref)] = 0.0
+    e[np.isnan(got) != np.isnan(ref)] = np.inf
+    return e
+
+
+def sweep(rng, n=200_000):
+    parts = [rng.uniform(-4, 4, n), rng.uniform(-100, 100, n),
+             rng.uniform(-1e4, 1e4, n), rng.uniform(-2e5, 2e5, n // 4),
+             np.exp(rng.uniform(-80, 80, n)) * rng.choice([-1, 1], n),
+             np.array([0.0, -0.0, 1e-40, -1e-40, np.inf, -np.inf, np.nan,
+                       1e38, -1e38, 88.0, 88.7, 89.0, 0.001, -0.001,
+                       float(np.float32(0.001)), float(np.nextafter(np.float32(0.001), 1)),
+                       131072.0, 131072.5, -131072.0, 3e6])]
+    k = np.arange(-40000, 40000)
+    parts.append(k * np.pi)
+    parts.append((k + 0.5) * np.pi)
+    x = np.concatenate(parts).astype(np.float32)
+    return np.concatenate([x, np.nextafter(x, np.float32(np.inf))])
+
+
+@pytest.mark.parametrize("op", [SIN, COS, EXP, LOG, SQRT, ABS])
+def test_unary_ulps(op):
+    gp = _gp()
+    x = sweep(np.random.default_rng(op))
+    X = x.reshape(1, -1)
+    prog = np.array([LOAD, op], np.uint32)
+    _say("unary op %d on %d inputs" % (op, x.size))
+    got = gp.predict(prog, [0, 2], np.zeros(0, np.float32), X)[0]
+    ref = oracle.program_outputs(prog, [], X, mode=oracle.M32E)
+    e = ulp_err(got, ref)
+    worst = np.argsort(e)[-5:]
+    _say("op %d: max ulp %.3f mean %.4f worst x=%s" % (op, e.max(), e.mean(), x[worst]))
+    assert e.max() <= ULP_BOUND[op], (x[worst], got[worst], ref[worst])
+
+
+@pytest.mark.parametrize("op", [ADD, SUB, MUL, DIV])
+def test_binary_ulps(op):
+    gp = _gp()
+    rng = np.random.default_rng(10 + op)
+    a = sweep(rng, 50_000)
+    b = rng.permutation(sweep(rng, 50_000))
+    n = min(a.size, b.size)
+    X = np.stack([a[:n], b[:n]])
+    for prog in ([LOAD, LOAD | (1 << 8), op], [LOAD | (1 << 8), LOAD, op]):
+        prog = np.array(prog, np.uint32)
+        got = gp.predict(prog, [0, 3], np.zeros(0, np.float32), X)[0]
+        ref = oracle.program_outputs(prog, [], X, mode=oracle.M32E)
+        e = ulp_err(got, ref)
+        _say("op %d: max ulp %.3f" % (op, e.max()))
+        assert e.max() <= ULP_BOUND[op]
+
+
+def test_leaf_folding_forms():
+    """Every staged form: plain leaves, top OP leaf (variable and constant),
+    f(leaf) (variable and constant), stack binary ops, against M32E
+    per case (exact ops only, so the comparison is bitwise)."""
+    gp = _gp()
+    c = lambda j: CONST | (j << 8)
+    v = lambda j: LOAD | (j << 8)
+    progs = [
+        [v(0)], [c(0)],
+        [v(0), v(1), ADD], [v(0), c(1), SUB], [c(0), v(1), MUL], [c(0), c(1), DIV],
+        [v(0), ABS], [c(1), ABS], [v(1), v(0), ABS, SUB],
+        [v(0), v(1), v(0), MUL, SUB, c(1), DIV, ABS],
+        [v(0), v(1), ADD, v(0), v(1), SUB, MUL],
+        [c(0), v(0), v(1), v(0), v(1), ADD, SUB, MUL, DIV],
+    ]
+    lens = np.array([len(p) for p in progs], np.int64)
+    off = np.zeros(lens.size + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    nodes = np.array([t for p in progs for t in p], np.uint32)
+    consts = np.array([1.25, -3.5], np.float32)
+    rng = np.random.default_rng(2)
+    X = rng.uniform(-5, 5, (2, 3000)).astype(np.float32)
+    _say("leaf folding forms")
+    got = gp.predict(nodes, off, consts, X)
+    for p in range(len(progs)):
+        ref = oracle.program_outputs(nodes[off[p]:off[p + 1]], consts, X, mode=oracle.M32E)
+        assert np.array_equal(got[p].astype(np.float64), ref), p
+
+
+def test_predict_invalid_rows_and_status():
+    gp = _gp()
+    import torch
+    progs = [[LOAD, LOAD | (1 << 8), ADD], [LOAD, ADD], [LOAD | (5 << 8)], [LOAD, SIN]]
+    lens = np.array([len(p) for p in progs], np.int64)
+    off = np.zeros(lens.size + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    nodes = np.array([t for p in progs for t in p], np.uint32)
+    X = np.ones((2, 777), np.float32)
+    pop = gp.DevicePopulation(nodes, off, np.zeros(0, np.float32))
+    Xd = torch.from_numpy(X).cuda()
+    out = torch.zeros((4, 800), dtype=torch.float32, device="cuda")
+    st = torch.zeros(4, dtype=torch.int32, device="cuda")
+    _say("predict invalid rows")
+    gp.gp_predict(pop.nodes, pop.offsets, pop.consts, Xd, out, st,
+                  allowed_op_mask=oracle.MASK_BENCH & ~(1 << SIN))
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.all(o[0, :777] == 2.0) and np.all(o[0, 777:] == 0.0)   # ld_out padding untouched
+    assert np.isnan(o[1:, :777]).all()
+    assert st.cpu().numpy().tolist() == [0, 5, 3, 2]
+
+
+def test_predict_agrees_with_eval():
+    """MSE recomputed from gp_predict outputs equals gp_eval's fitness
+    within the compensated-sum error."""
+    gp = _gp()
+    from paper_2607_06731_amd import synth
+    w = synth.make_config(2, n_programs=300, n_cases=2000)
+    _say("predict vs eval")
+    f = gp.predict(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X).astype(np.float64)
+    F = gp.evaluate(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
+                    w.allowed_mask)
+    fin = np.isfinite(f).all(axis=1)
+    mse = ((f - w.data.y.astype(np.float64)) ** 2).mean(axis=1)
+    Fp = np.where(fin & (mse <= np.finfo(np.float32).max), mse + w.tax * w.pop.lengths, np.inf)
+    both = np.isfinite(Fp)
+    assert np.array_equal(both, np.isfinite(F))
+    assert np.all(np.abs(F[both] - Fp[both]) <= 1e-6 * np.abs(Fp[both]) + 1e-12)
