@@ -448,8 +448,11 @@ __device__ __forceinline__ float cos_fast(float x)
 template <int MAXD, int K, int SUB>
 __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                                             const uint2* __restrict__ pend,
-                                            const float* __restrict__ xl, float (&tos)[K])
+                                            const float* __restrict__ xl_, float (&tos)[K])
 {
+    // each lane's K cases are contiguous and 4K-byte aligned in the tile
+    const float* __restrict__ xl =
+        static_cast<const float*>(__builtin_assume_aligned(xl_, 4 * K));
     constexpr int J = 32 / MAXD;                  // cases per 32-float chunk
     static_assert(K % J == 0 && K / J <= 4, "chunking");
     float c0[32], c1[32], c2[32], c3[32];
@@ -528,22 +531,22 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                 bool big = false;
 #pragma unroll
                 for (int j = 0; j < K; ++j) big |= !(fabsf(tos[j]) <= kTrigFastLimit);
-                float f[K];
-                if (uop == GP_SIN) {
+                if (__builtin_expect(__ballot(big) != 0ull, 0)) {
 #pragma unroll
-                    for (int j = 0; j < K; ++j) f[j] = sin_fast(tos[j]);
+                    for (int j = 0; j < K; ++j) {
+                        const float x = tos[j];
+                        if (fabsf(x) <= kTrigFastLimit)
+                            tos[j] = uop == GP_SIN ? sin_fast(x) : cos_fast(x);
+                        else
+                            tos[j] = uop == GP_SIN ? sinf(x) : cosf(x);
+                    }
+                } else if (uop == GP_SIN) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) tos[j] = sin_fast(tos[j]);
                 } else {
 #pragma unroll
-                    for (int j = 0; j < K; ++j) f[j] = cos_fast(tos[j]);
+                    for (int j = 0; j < K; ++j) tos[j] = cos_fast(tos[j]);
                 }
-                if (__ballot(big) != 0ull) {
-#pragma unroll
-                    for (int j = 0; j < K; ++j)
-                        if (!(fabsf(tos[j]) <= kTrigFastLimit))
-                            f[j] = uop == GP_SIN ? sinf(tos[j]) : cosf(tos[j]);
-                }
-#pragma unroll
-                for (int j = 0; j < K; ++j) tos[j] = f[j];
                 break;
             }
             case GP_EXP:
