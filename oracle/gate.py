@@ -11,10 +11,10 @@ modes; it is excused only when the arithmetic itself explains it:
   * fp32 ill-conditioned: the correctly rounded fp32 evaluation (M32E)
     differs from M64 by more than 1e-5 relative, and the device result
     matches M32E within the tolerance;
-  * chaotic: moving every transcendental result one fp32 ulp (M32E_UP /
-    M32E_DN), or by seeded pseudo-random amounts within +-2 ulps (M32E_RAND;
-    the accuracy class of fp32 elementary-function libraries), changes F by
-    more than the tolerance, or changes its class;
+  * chaotic: moving every sin/cos/exp/log/sqrt result one fp32 ulp
+    (M32E_UP / M32E_DN), or by seeded pseudo-random amounts within +-2 ulps
+    (M32E_RAND; the accuracy class of fp32 elementary-function code),
+    changes F by more than the tolerance, or changes its class;
   * certified class flip: the device class differs from M64's but equals
     M32E's (an fp32 overflow-range or threshold flip), or equals that of a
     perturbed run (chaotic).

@@ -49,14 +49,15 @@
  *   ORACLE_M32E  as M64, but each op result is also rounded to fp32: the
  *                result of a correctly rounded fp32 evaluator.  Sums stay fp64.
  *   ORACLE_M32E_UP / ORACLE_M32E_DN
- *                M32E with every sin/cos/exp/log result moved one fp32 ulp up
- *                (down): used only to certify that a program is chaotic.
+ *                M32E with every sin/cos/exp/log/sqrt result moved one fp32
+ *                ulp up (down): used only to certify that a program is
+ *                chaotic.
  *   ORACLE_M32E_RAND + s (s >= 0)
- *                M32E with every sin/cos/exp/log result moved by a pseudo-
- *                random d in {-2,...,+2} fp32 ulps, d drawn from SplitMix64
- *                (Steele, Lea, Flood 2014) keyed by (s, node, case): an fp32
- *                evaluator whose elementary functions are within 2 ulps.
- *                Also certification only.
+ *                M32E with every sin/cos/exp/log/sqrt result moved by a
+ *                pseudo-random d in {-2,...,+2} fp32 ulps, d drawn from
+ *                SplitMix64 (Steele, Lea, Flood 2014) keyed by (s, node,
+ *                case): an fp32 evaluator whose elementary functions are
+ *                within 2 ulps.  Also certification only.
  *
  * Oracle-only GCL extension (so the paper's printed genomes can run):
  *   DUP, SWAP, DEL, SQUARE (GCL command table).
@@ -233,7 +234,12 @@ static double eval_case(const uint32_t* prog, int64_t len, const float* consts,
             if (mode >= ORACLE_M32E_UP) v = nudge(v, mode, k, i);
             st[sp++] = v;
             break;
-        case OP_SQRT: a = st[--sp]; st[sp++] = round_mode(sqrt(fabs(a)), mode); break;
+        case OP_SQRT:
+            a = st[--sp];
+            v = round_mode(sqrt(fabs(a)), mode);
+            if (mode >= ORACLE_M32E_UP) v = nudge(v, mode, k, i);
+            st[sp++] = v;
+            break;
         case OP_ABS: a = st[--sp]; st[sp++] = fabs(a); break;
         case OP_SQUARE: a = st[--sp]; st[sp++] = round_mode(a * a, mode); break;
         case OP_DUP: a = st[sp - 1]; st[sp++] = a; break;

@@ -108,8 +108,11 @@ int class_k(int c, int n_vars)
 }
 
 // Tile geometry for one class: a tile is `passes` consecutive sub-tiles of
-// 256*K cases.  Depends only on (n_cases, K), so a program's summation
-// order never depends on the rest of the population.
+// 256*K cases; a work item covers one tile of G programs.  Up to 32 tiles
+// per program keep enough work items for small depth classes (larger
+// tiles were measured slower: too few items to fill 256 CUs).  Depends
+// only on (n_cases, K), so a program's summation order never depends on
+// the rest of the population.
 struct TileShape {
     int32_t sub;        // cases per sub-tile (256 * K)
     int32_t passes;     // sub-tiles per tile
@@ -401,6 +404,33 @@ __device__ __forceinline__ float cos_fast(float x)
     return __int_as_float(__float_as_int(s) ^ ((ki + 1) << 31));
 }
 
+// --------------------------------------------------------- sqrt|a|, ln|a|
+// sqrt|a| with the hardware square root (faithful, <= 1 ulp); magnitudes
+// below 2^-100 are scaled by 2^64 first (and the root by 2^-32 after), so
+// no denormal reaches the instruction.
+__device__ __forceinline__ float sqrt_abs(float a)
+{
+    const float x = fabsf(a);
+    const bool tiny = x < 0x1p-100f;
+    const float r = __builtin_amdgcn_sqrtf(tiny ? x * 0x1p64f : x);
+    return tiny ? r * 0x1p-32f : r;
+}
+
+// Protected logarithm: 0 for |a| <= fp32(0.001), else ln|a| =
+// log2|a| * ln 2 with ln 2 split into an fp32 head (rounded toward zero)
+// and a positive fp32 tail, so log2|a| = +inf gives +inf + +inf = +inf.
+// The hardware log2 only ever sees |a| > 0.001 (never a denormal); NaN
+// propagates (the comparison with the threshold is false for NaN).
+constexpr float kLn2Hi = 6.931471229e-01f;    // fp32 below ln 2
+constexpr float kLn2Lo = 5.769998879e-08f;    // fp32(ln 2 - kLn2Hi) > 0
+__device__ __forceinline__ float log_protected(float a)
+{
+    const float x = fabsf(a);
+    const float l2 = __builtin_amdgcn_logf(x);
+    const float ln = fmaf(l2, kLn2Hi, l2 * kLn2Lo);
+    return x <= 0.001f ? 0.f : ln;
+}
+
 // The value stack below the top lives in VGPR arrays of 32 floats ("chunks"):
 // chunk c holds cases [c*J, (c+1)*J) of every slot, element index
 // slot*J + (case mod J), J = 32 / MAXD.  A uniform dynamic index into a
@@ -443,16 +473,15 @@ __device__ __forceinline__ float cos_fast(float x)
 #define GP_BINARY(bop, a, top) GP_BINARY_AB(bop, a, top, top)
 
 // Runs one staged program on K cases per lane; xl points at this lane's
-// first case of the LDS input tile (row stride SUB).  The top of the stack
-// is returned in tos[].
+// first case of the LDS input tile.  A sub-tile's cases are laid out case-
+// major: case j of lane t is element j*256 + t of a variable's row (row
+// stride SUB), so each of the K reads of a LOAD is a conflict-free,
+// lane-contiguous LDS access.  The top of the stack is returned in tos[].
 template <int MAXD, int K, int SUB>
 __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                                             const uint2* __restrict__ pend,
-                                            const float* __restrict__ xl_, float (&tos)[K])
+                                            const float* __restrict__ xl, float (&tos)[K])
 {
-    // each lane's K cases are contiguous and 4K-byte aligned in the tile
-    const float* __restrict__ xl =
-        static_cast<const float*>(__builtin_assume_aligned(xl_, 4 * K));
     constexpr int J = 32 / MAXD;                  // cases per 32-float chunk
     static_assert(K % J == 0 && K / J <= 4, "chunking");
     float c0[32], c1[32], c2[32], c3[32];
@@ -478,7 +507,7 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
             if (op == GP_LOAD) {
                 const float* xp = xl + (size_t)w.y * SUB;
 #pragma unroll
-                for (int j = 0; j < K; ++j) tos[j] = xp[j];
+                for (int j = 0; j < K; ++j) tos[j] = xp[j * kWG];
             } else {
                 const float c = __uint_as_float(w.y);
 #pragma unroll
@@ -496,7 +525,7 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
             if (op < kOpBinConst) {
                 const float* xp = xl + (size_t)w.y * SUB;
 #pragma unroll
-                for (int j = 0; j < K; ++j) lv[j] = xp[j];
+                for (int j = 0; j < K; ++j) lv[j] = xp[j * kWG];
             } else {
                 const float c = __uint_as_float(w.y);
 #pragma unroll
@@ -513,7 +542,7 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                 if (op < kOpUnConst) {
                     const float* xp = xl + (size_t)w.y * SUB;
 #pragma unroll
-                    for (int j = 0; j < K; ++j) tos[j] = xp[j];
+                    for (int j = 0; j < K; ++j) tos[j] = xp[j * kWG];
                     uop = op - kOpUnVar + GP_SIN;
                 } else {
                     const float c = __uint_as_float(w.y);
@@ -555,12 +584,11 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                 break;
             case GP_LOG:
 #pragma unroll
-                for (int j = 0; j < K; ++j)
-                    tos[j] = fabsf(tos[j]) <= 0.001f ? 0.f : logf(fabsf(tos[j]));
+                for (int j = 0; j < K; ++j) tos[j] = log_protected(tos[j]);
                 break;
             case GP_SQRT:
 #pragma unroll
-                for (int j = 0; j < K; ++j) tos[j] = sqrtf(fabsf(tos[j]));
+                for (int j = 0; j < K; ++j) tos[j] = sqrt_abs(tos[j]);
                 break;
             default:
 #pragma unroll
@@ -594,7 +622,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    const int lo = tid * K;                       // this lane's first case in a sub-tile
+    const int lo = tid;                           // this lane's first case in a sub-tile
     const int start = class_info[2 * a.cls];
     const int count = class_info[2 * a.cls + 1];
     const int n_groups = (count + a.G - 1) / a.G;
@@ -630,7 +658,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
             bool live[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                const int64_t gi = base + lo + j;
+                const int64_t gi = base + lo + j * kWG;
                 live[j] = gi < a.n_cases;
                 yv[j] = live[j] ? y[gi] : 0.f;
             }
@@ -707,7 +735,7 @@ __global__ __launch_bounds__(kWG) void k_predict(
     float* xt = lds;                              // [n_vars][SUB]
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
-    const int lo = tid * K;
+    const int lo = tid;
     const int start = class_info[2 * a.cls];
     const int count = class_info[2 * a.cls + 1];
     const int64_t n_sub = (a.n_cases + SUB - 1) / SUB;
@@ -737,7 +765,7 @@ __global__ __launch_bounds__(kWG) void k_predict(
         run_program<MAXD, K, SUB>(code + m.start, code + m.start + m.slen, xt + lo, tos);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const int64_t gi = base + lo + j;
+            const int64_t gi = base + lo + j * kWG;
             if (gi < a.n_cases) out[(int64_t)pid * ld_out + gi] = tos[j];
         }
         __syncthreads();

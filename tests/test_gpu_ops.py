@@ -2,9 +2,10 @@
 
 Each op is run as a one-op program over dense sweeps of inputs and compared,
 case by case, with the oracle's M32E mode (the correctly rounded fp32 value
-of the fp64 result).  Bounds: +, -, *, |.|, protected DIV and SQRT exact
-(they are correctly rounded in fp32), elementary functions within 2 ulps
-(the envelope the parity gate's chaos certificate assumes).
+of the fp64 result).  Bounds: +, -, *, |.| and protected DIV exact (they
+are correctly rounded in fp32), elementary functions
+and the square root within 2 ulps (the envelope the parity gate's chaos
+certificate assumes).
 """
 import sys
 
@@ -17,7 +18,7 @@ from oracle import (ABS, ADD, CONST, COS, DIV, EXP, LOAD, LOG, MUL, SIN, SQRT,
 
 pytestmark = pytest.mark.gpu
 
-ULP_BOUND = {SIN: 2.0, COS: 2.0, EXP: 2.0, LOG: 2.0, SQRT: 0.0, ABS: 0.0,
+ULP_BOUND = {SIN: 2.0, COS: 2.0, EXP: 2.0, LOG: 2.0, SQRT: 2.0, ABS: 0.0,
              ADD: 0.0, SUB: 0.0, MUL: 0.0, DIV: 0.0}
 
 
