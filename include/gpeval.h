@@ -43,6 +43,7 @@
 #ifndef GPEVAL_H
 #define GPEVAL_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -86,7 +87,8 @@ enum gp_op {
 enum gp_prog_status {
     GP_PROG_OK = 0, GP_PROG_EMPTY = 1, GP_PROG_BAD_OP = 2, GP_PROG_BAD_VAR = 3,
     GP_PROG_BAD_CONST = 4, GP_PROG_UNDERFLOW = 5, GP_PROG_TOO_DEEP = 6,
-    GP_PROG_FINAL_DEPTH = 7, GP_PROG_BAD_OFFSETS = 8
+    GP_PROG_FINAL_DEPTH = 7, GP_PROG_BAD_OFFSETS = 8,
+    GP_PROG_BAD_TABLE = 9     /* gp_eval_batched: invalid dataset/request table */
 };
 
 /* Thread-local text for the last non-OK status returned on this thread. */
@@ -128,6 +130,50 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
             double* out_fitness, int32_t* out_status, hipStream_t stream);
 
 /*
+ * gp_eval_batched -- score the populations of several requests, each
+ * against its own resident dataset, in one launch (scoring requests of
+ * many concurrent evolutionary runs; the paper spreads populations over
+ * the available devices and batches them, Sec. "Hardware Optimized").
+ *
+ * requests_dev: n_requests device entries; each names its own program
+ * arrays (same format as gp_eval), its dataset (index into datasets_dev)
+ * and its own outputs (out_fitness: n_programs doubles; out_status: NULL
+ * or n_programs ints).  datasets_dev: n_datasets device entries (X, y,
+ * n_vars, ld_x, n_cases, tax as in gp_eval).  The host passes the sums of
+ * n_programs and n_nodes over the requests and upper bounds on n_vars and
+ * n_cases (they size the workspace and LDS tiles).  Requests may be empty
+ * (n_programs 0).  Host-side errors: GP_E_INVALID_ARG for NULL tables or
+ * counts < 1, GP_E_TOO_LARGE for more than 4096 requests or sizes beyond
+ * gp_eval's limits.  Device-side: if the tables are inconsistent with the
+ * host's totals and bounds (a count out of range, a NULL array that is
+ * needed, a dataset index out of range, sums that differ), no program is
+ * evaluated and every program gets NaN and GP_PROG_BAD_TABLE, written
+ * only where a request's own entry makes the write safe.  Each program's
+ * result is bit-identical to scoring its request alone with gp_eval on
+ * the same dataset.  Nothing is copied: the call reads the programs where
+ * they are, so inputs must stay alive until the stream has passed it.
+ */
+typedef struct {
+    const float* X; const float* y;
+    int64_t ld_x; int64_t n_cases;
+    double tax_on_length;
+    int32_t n_vars; int32_t reserved;
+} gp_dataset;
+
+typedef struct {
+    const uint32_t* nodes; const int64_t* offsets; const float* consts;
+    int64_t n_programs; int64_t n_nodes; int64_t n_consts;
+    double* out_fitness; int32_t* out_status;
+    int32_t dataset; int32_t reserved;
+} gp_request;
+
+int gp_eval_batched(const gp_request* requests_dev, int32_t n_requests,
+                    const gp_dataset* datasets_dev, int32_t n_datasets,
+                    int64_t total_programs, int64_t total_nodes,
+                    int32_t max_n_vars, int64_t max_n_cases, uint32_t allowed_op_mask,
+                    hipStream_t stream);
+
+/*
  * gp_predict -- per-case outputs f_p(x_i) of every program (the paper's
  * ExecuteGenome utility, Sec. "Useful Utilities": run a genome on input
  * data).  Same program and input arguments as gp_eval (device pointers);
@@ -143,8 +189,161 @@ int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs
                uint32_t allowed_op_mask, float* out, int64_t ld_out, int32_t* out_status,
                hipStream_t stream);
 
+/*
+ * Plans: one population shape evaluated generation after generation (the
+ * paper's loop uploads a new population each generation and scores it,
+ * Sec. "Dividing Tasks Between CPU and GPU").  A plan owns its workspace,
+ * captures the whole pipeline (validation and staging, the partition by
+ * stack depth class and program length -- longest first --, the persistent
+ * per-class evaluation kernels and the fp64 reduction) into a hipGraph
+ * once, and replays it with gp_plan_launch.  The caller rewrites the
+ * program/data buffers in place between launches (same pointers, same
+ * sizes) or calls gp_plan_update for new pointers or sizes (re-capture).
+ *
+ * gp_tuning holds scheduling knobs only; none of them changes any result
+ * (a program's summation order depends on n_cases, n_vars and its own
+ * stack depth, never on these).  0 fields mean defaults.  With autotune
+ * != 0, gp_plan_create times candidate knobs on the given inputs (this
+ * runs the evaluation several times and synchronizes `stream`) and keeps
+ * the fastest; results are cached per workload shape in the process and,
+ * if the environment variable GPEVAL_TUNE_CACHE names a file, there too.
+ */
+typedef struct {
+    const uint32_t* nodes; const int64_t* offsets; int64_t n_programs; int64_t n_nodes;
+    const float* consts; int64_t n_consts;
+    const float* X; int32_t n_vars; int64_t ld_x;
+    const float* y; int64_t n_cases;
+    double tax_on_length; uint32_t allowed_op_mask;
+    double* out_fitness; int32_t* out_status;       /* out_status may be NULL */
+} gp_problem;                                       /* same meaning as gp_eval's arguments */
+
+typedef struct {
+    int32_t programs_per_item;   /* programs per work item, 1..64 (default 8) */
+    int32_t wg_per_cu;           /* persistent workgroups per CU, 0 = occupancy limit */
+    int32_t concurrent_classes;  /* 1: depth classes run on forked streams */
+} gp_tuning;
+
+typedef struct gp_plan gp_plan;
+
+/* Create (and capture) a plan; tuning may be NULL.  GP_E_* on failure. */
+int gp_plan_create(gp_plan** plan, const gp_problem* problem, const gp_tuning* tuning,
+                   int autotune, hipStream_t stream);
+/* Replay the captured evaluation on `stream` (asynchronous). */
+int gp_plan_launch(gp_plan* plan, hipStream_t stream);
+/* Point the plan at new buffers/sizes and re-capture (synchronous). */
+int gp_plan_update(gp_plan* plan, const gp_problem* problem);
+/* The scheduling knobs the plan uses (after autotuning, if requested). */
+int gp_plan_get_tuning(const gp_plan* plan, gp_tuning* out);
+/* Waits for outstanding work and frees the plan.  NULL is ignored. */
+void gp_plan_destroy(gp_plan* plan);
+
 /* Release every cached workspace of the calling process (all devices). */
 void gp_release_workspaces(void);
+
+/* ---------------------------------------------------------------- serving
+ * gp_server -- a scoring service shared by many concurrent evolutionary
+ * runs.  The paper scores each generation's whole population in one
+ * device pass and splits populations into batches that fit device memory
+ * (Sec. "Hardware Optimized"); here many runs share one device:
+ *   - datasets are uploaded once (gp_server_add_dataset) and stay resident;
+ *   - a request (one population, host arrays) is admitted when the device
+ *     budget covers its program and output buffers, then uploaded through
+ *     pinned staging on a copy stream;
+ *   - requests are split into chunks (program ranges) of bounded work and
+ *     workspace, and every admitted chunk goes into the next
+ *     gp_eval_batched launch; up to n_streams launches are in flight, so
+ *     requests that arrive while others run join the next launch
+ *     (continuous batching);
+ *   - results are copied back per request; latency is measured from
+ *     gp_server_submit to the moment the results are in the caller's
+ *     arrays.
+ * Each program's result is bit-identical to gp_eval of its population
+ * alone.  A scheduler thread owned by the server does all device work; the
+ * functions below may be called from any thread.
+ */
+typedef struct gp_server gp_server;
+
+typedef struct {
+    int64_t device_budget_bytes;    /* datasets + requests + launch workspaces
+                                       (0: 8 GiB) */
+    int64_t pinned_bytes;           /* host staging (0: min(budget, 1 GiB)) */
+    int64_t chunk_node_evals;       /* work per chunk, in length x cases
+                                       (0: 2^33) */
+    int64_t batch_node_evals;       /* work per launch (0: 4 chunks); a launch
+                                       takes at least one chunk */
+    int32_t n_streams;              /* launches in flight, 1..8 (0: 2) */
+    int32_t max_batch_chunks;       /* chunks per launch, 1..4096 (0: 1024) */
+    int32_t one_launch_per_request; /* 1: FIFO, one gp_eval per request on one
+                                       stream, no chunking (comparison mode) */
+    uint32_t allowed_op_mask;       /* 0: GP_ALL_OPS */
+} gp_server_config;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t launches, chunks_launched;
+    double node_evals;              /* sum of length x n_cases, completed requests */
+    double latency_p50_ms, latency_p99_ms, latency_max_ms, latency_mean_ms;
+    double busy_ms;                 /* wall time with >= 1 launch in flight */
+    double wall_ms;                 /* since creation or the last reset */
+    int64_t device_bytes_in_use, device_bytes_peak;
+    int32_t waiting, in_flight;     /* requests not admitted / admitted, not done */
+} gp_server_stats;
+
+/* Creates the server, its streams (default priority), device arena and
+ * pinned staging, and its scheduler thread on the current device.
+ * GP_E_NO_MEMORY if the budget cannot be allocated. */
+int gp_server_create(gp_server** server, const gp_server_config* config);
+
+/* Uploads X (host, X[v * ld_x + i]) and y (host, n_cases) into the
+ * server's arena; synchronous.  *dataset_id names it in submits.
+ * GP_E_NO_MEMORY if the arena cannot hold it now. */
+int gp_server_add_dataset(gp_server* server, const float* X, int32_t n_vars, int64_t ld_x,
+                          const float* y, int64_t n_cases, double tax_on_length,
+                          int32_t* dataset_id);
+
+/* Frees a dataset; GP_E_INVALID_ARG while requests on it are pending. */
+int gp_server_remove_dataset(gp_server* server, int32_t dataset_id);
+
+/* Queues a scoring request.  Host arrays as in gp_eval (nodes[n_nodes],
+ * offsets[n_programs + 1], consts[n_consts]); offsets must be
+ * non-decreasing within [0, n_nodes] (GP_E_INVALID_ARG otherwise).  The
+ * server reads the program arrays until the request completes and then
+ * writes out_fitness[n_programs] and, if not NULL, out_status[n_programs];
+ * the caller keeps all of them alive and unchanged until then.
+ * GP_E_TOO_LARGE if the request could never fit the budget. */
+int gp_server_submit(gp_server* server, int32_t dataset_id, const uint32_t* nodes,
+                     int64_t n_nodes, const int64_t* offsets, int64_t n_programs,
+                     const float* consts, int64_t n_consts, double* out_fitness,
+                     int32_t* out_status, int64_t* ticket);
+
+/* Waits up to timeout_ms (< 0: no limit, 0: just look) for completed
+ * requests and returns up to max_n of them (ticket and result code, GP_OK
+ * or the error that failed the request), each once. */
+int gp_server_poll(gp_server* server, double timeout_ms, int64_t* tickets, int32_t* results,
+                   int32_t max_n, int32_t* n_done);
+
+/* Waits up to timeout_ms for one ticket; *done = 1 and *result set once it
+ * has completed (the ticket is then consumed).  GP_E_INVALID_ARG for a
+ * ticket that is unknown or already consumed. */
+int gp_server_wait(gp_server* server, int64_t ticket, double timeout_ms, int32_t* done,
+                   int32_t* result);
+
+int gp_server_get_stats(gp_server* server, gp_server_stats* out);
+int gp_server_reset_stats(gp_server* server);
+
+/* Completes every submitted request, then frees everything. */
+void gp_server_destroy(gp_server* server);
+
+/*
+ * gp_workspace_size -- device bytes the library may hold for one stream
+ * after a gp_eval / gp_eval_batched call of this shape (its cached
+ * workspace, growth slack included).  Pure host arithmetic: no device
+ * call.  For admission control by callers that budget device memory.
+ * Returns GP_E_INVALID_ARG for sizes out of range.
+ */
+int gp_workspace_size(int64_t n_programs, int64_t n_nodes, int32_t n_requests,
+                      int32_t n_datasets, int32_t max_n_vars, int64_t max_n_cases,
+                      size_t* bytes);
 
 /*
  * Phase timing (the paper's console reports GPU kernel time per generation,

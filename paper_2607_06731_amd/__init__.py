@@ -5,9 +5,12 @@ PyTorch provides device memory and streams.  If the library has not been
 built, every entry point raises -- there is no CPU fallback.
 
 Entry points mirror ``include/gpeval.h``:
-    gp_eval(...)       score a population held in device tensors
-    gp_validate(...)   host-side structural check of a population
-    evaluate(...)      convenience: numpy in, upload, gp_eval, numpy out
+    gp_eval(...)          score a population held in device tensors
+    gp_eval_batched(...)  score several requests, each on its own dataset
+    gp_predict(...)       per-case outputs of every program
+    Plan                  a captured (hipGraph) evaluation, optionally autotuned
+    gp_validate(...)      host-side structural check of a population
+    evaluate(...)         convenience: numpy in, upload, gp_eval, numpy out
 """
 from __future__ import annotations
 
@@ -25,6 +28,59 @@ GP_OK, GP_E_INVALID_ARG, GP_E_BAD_PROGRAM, GP_E_TOO_LARGE, GP_E_NO_MEMORY, GP_E_
 GP_ALL_OPS = (1 << 12) - 1
 
 _lib = None
+
+
+class GPProblem(ctypes.Structure):
+    """struct gp_problem of include/gpeval.h"""
+    _fields_ = [("nodes", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("n_programs", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("consts", ctypes.c_void_p), ("n_consts", ctypes.c_int64),
+                ("X", ctypes.c_void_p), ("n_vars", ctypes.c_int32), ("ld_x", ctypes.c_int64),
+                ("y", ctypes.c_void_p), ("n_cases", ctypes.c_int64),
+                ("tax_on_length", ctypes.c_double), ("allowed_op_mask", ctypes.c_uint32),
+                ("out_fitness", ctypes.c_void_p), ("out_status", ctypes.c_void_p)]
+
+
+class GPDataset(ctypes.Structure):
+    """struct gp_dataset of include/gpeval.h"""
+    _fields_ = [("X", ctypes.c_void_p), ("y", ctypes.c_void_p), ("ld_x", ctypes.c_int64),
+                ("n_cases", ctypes.c_int64), ("tax_on_length", ctypes.c_double),
+                ("n_vars", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class GPRequest(ctypes.Structure):
+    """struct gp_request of include/gpeval.h"""
+    _fields_ = [("nodes", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("consts", ctypes.c_void_p), ("n_programs", ctypes.c_int64),
+                ("n_nodes", ctypes.c_int64), ("n_consts", ctypes.c_int64),
+                ("out_fitness", ctypes.c_void_p), ("out_status", ctypes.c_void_p),
+                ("dataset", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class GPTuning(ctypes.Structure):
+    """struct gp_tuning of include/gpeval.h"""
+    _fields_ = [("programs_per_item", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("concurrent_classes", ctypes.c_int32)]
+
+
+class GPServerConfig(ctypes.Structure):
+    """struct gp_server_config of include/gpeval.h"""
+    _fields_ = [("device_budget_bytes", ctypes.c_int64), ("pinned_bytes", ctypes.c_int64),
+                ("chunk_node_evals", ctypes.c_int64), ("batch_node_evals", ctypes.c_int64),
+                ("n_streams", ctypes.c_int32), ("max_batch_chunks", ctypes.c_int32),
+                ("one_launch_per_request", ctypes.c_int32), ("allowed_op_mask", ctypes.c_uint32)]
+
+
+class GPServerStats(ctypes.Structure):
+    """struct gp_server_stats of include/gpeval.h"""
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("chunks_launched", ctypes.c_int64), ("node_evals", ctypes.c_double),
+                ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+                ("latency_max_ms", ctypes.c_double), ("latency_mean_ms", ctypes.c_double),
+                ("busy_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
+                ("device_bytes_in_use", ctypes.c_int64), ("device_bytes_peak", ctypes.c_int64),
+                ("waiting", ctypes.c_int32), ("in_flight", ctypes.c_int32)]
 
 
 class GPError(RuntimeError):
@@ -50,9 +106,48 @@ def lib():
         L.gp_eval.argtypes = [vp, vp, i64, i64, vp, i64, vp, i32, i64, vp, i64,
                               ctypes.c_double, u32, vp, vp, vp]
         L.gp_eval.restype = ctypes.c_int
+        L.gp_eval_batched.argtypes = [vp, i32, vp, i32, i64, i64, i32, i64, u32, vp]
+        L.gp_eval_batched.restype = ctypes.c_int
         L.gp_predict.argtypes = [vp, vp, i64, i64, vp, i64, vp, i32, i64, i64, u32, vp, i64,
                                  vp, vp]
         L.gp_predict.restype = ctypes.c_int
+        L.gp_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(GPProblem),
+                                     ctypes.POINTER(GPTuning), ctypes.c_int, vp]
+        L.gp_plan_create.restype = ctypes.c_int
+        L.gp_plan_launch.argtypes = [vp, vp]
+        L.gp_plan_launch.restype = ctypes.c_int
+        L.gp_plan_update.argtypes = [vp, ctypes.POINTER(GPProblem)]
+        L.gp_plan_update.restype = ctypes.c_int
+        L.gp_plan_get_tuning.argtypes = [vp, ctypes.POINTER(GPTuning)]
+        L.gp_plan_get_tuning.restype = ctypes.c_int
+        L.gp_plan_destroy.argtypes = [vp]
+        L.gp_plan_destroy.restype = None
+        L.gp_workspace_size.argtypes = [i64, i64, i32, i32, i32, i64,
+                                        ctypes.POINTER(ctypes.c_size_t)]
+        L.gp_workspace_size.restype = ctypes.c_int
+        L.gp_server_create.argtypes = [ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(GPServerConfig)]
+        L.gp_server_create.restype = ctypes.c_int
+        L.gp_server_add_dataset.argtypes = [vp, vp, i32, i64, vp, i64, ctypes.c_double,
+                                            ctypes.POINTER(ctypes.c_int32)]
+        L.gp_server_add_dataset.restype = ctypes.c_int
+        L.gp_server_remove_dataset.argtypes = [vp, i32]
+        L.gp_server_remove_dataset.restype = ctypes.c_int
+        L.gp_server_submit.argtypes = [vp, i32, vp, i64, vp, i64, vp, i64, vp, vp,
+                                       ctypes.POINTER(ctypes.c_int64)]
+        L.gp_server_submit.restype = ctypes.c_int
+        L.gp_server_poll.argtypes = [vp, ctypes.c_double, vp, vp, i32,
+                                     ctypes.POINTER(ctypes.c_int32)]
+        L.gp_server_poll.restype = ctypes.c_int
+        L.gp_server_wait.argtypes = [vp, i64, ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]
+        L.gp_server_wait.restype = ctypes.c_int
+        L.gp_server_get_stats.argtypes = [vp, ctypes.POINTER(GPServerStats)]
+        L.gp_server_get_stats.restype = ctypes.c_int
+        L.gp_server_reset_stats.argtypes = [vp]
+        L.gp_server_reset_stats.restype = ctypes.c_int
+        L.gp_server_destroy.argtypes = [vp]
+        L.gp_server_destroy.restype = None
         L.gp_release_workspaces.argtypes = []
         L.gp_release_workspaces.restype = None
         L.gp_timing_enable.argtypes = [ctypes.c_int]
@@ -156,6 +251,55 @@ def gp_eval(nodes, offsets, consts, X, y, tax_on_length, out_fitness,
     return out_fitness
 
 
+def table_tensor(entries, device="cuda"):
+    """Pack ctypes structures into a device byte tensor (the dataset and
+    request tables of gp_eval_batched)."""
+    import torch
+    if not entries:
+        return torch.zeros(0, dtype=torch.uint8, device=device)
+    raw = b"".join(bytes(e) for e in entries)
+    host = torch.frombuffer(bytearray(raw), dtype=torch.uint8)
+    return host.to(device)
+
+
+def dataset_entry(data, tax_on_length=0.0):
+    """GPDataset for a resident dataset (X [n_vars, ld], y [n_cases])."""
+    import torch
+    return GPDataset(_dev_ptr(data.X, torch.float32, "X"), _dev_ptr(data.y, torch.float32, "y"),
+                     data.X.shape[1], data.n_cases, float(tax_on_length), data.n_vars, 0)
+
+
+def request_entry(pop, dataset, out_fitness, out_status=None):
+    """GPRequest for a resident population scored against table entry
+    `dataset`, writing into out_fitness (float64[P]) / out_status."""
+    import torch
+    if out_fitness.numel() < pop.n_programs:
+        raise ValueError("out_fitness holds fewer than n_programs values")
+    if out_status is not None and out_status.numel() < pop.n_programs:
+        raise ValueError("out_status holds fewer than n_programs values")
+    return GPRequest(_dev_ptr(pop.nodes, torch.uint32, "nodes"),
+                     _dev_ptr(pop.offsets, torch.int64, "offsets"),
+                     _dev_ptr(pop.consts, torch.float32, "consts"), pop.n_programs,
+                     pop.nodes.numel(), pop.consts.numel(),
+                     _dev_ptr(out_fitness, torch.float64, "out_fitness"),
+                     _dev_ptr(out_status, torch.int32, "out_status"), int(dataset), 0)
+
+
+def gp_eval_batched(requests, datasets, total_programs, total_nodes, max_n_vars, max_n_cases,
+                    allowed_op_mask=0, stream=None):
+    """Score many requests in one launch.  requests / datasets: uint8 device
+    tensors holding packed GPRequest / GPDataset entries (see table_tensor);
+    the totals and bounds are the host's view of those tables."""
+    import torch
+    n_req = requests.numel() // ctypes.sizeof(GPRequest)
+    n_ds = datasets.numel() // ctypes.sizeof(GPDataset)
+    rc = lib().gp_eval_batched(_dev_ptr(requests, torch.uint8, "requests"), n_req,
+                               _dev_ptr(datasets, torch.uint8, "datasets"), n_ds,
+                               int(total_programs), int(total_nodes), int(max_n_vars),
+                               int(max_n_cases), int(allowed_op_mask), _stream_handle(stream))
+    _check(rc)
+
+
 def gp_predict(nodes, offsets, consts, X, out, out_status=None, allowed_op_mask=0,
                n_cases=None, stream=None):
     """Per-case outputs into out float32[P, ld_out] (device tensors)."""
@@ -188,6 +332,62 @@ def predict(nodes, offsets, consts, X, allowed_op_mask=0, device="cuda"):
     gp_predict(pop.nodes, pop.offsets, pop.consts, Xd, out, allowed_op_mask=allowed_op_mask)
     torch.cuda.synchronize()
     return out.cpu().numpy()
+
+
+def _problem(pop, data, tax, out, status, allowed_op_mask):
+    import torch
+    return GPProblem(_dev_ptr(pop.nodes, torch.uint32, "nodes"),
+                     _dev_ptr(pop.offsets, torch.int64, "offsets"), pop.n_programs,
+                     pop.nodes.numel(), _dev_ptr(pop.consts, torch.float32, "consts"),
+                     pop.consts.numel(), _dev_ptr(data.X, torch.float32, "X"), data.n_vars,
+                     data.X.shape[1], _dev_ptr(data.y, torch.float32, "y"), data.n_cases,
+                     float(tax), int(allowed_op_mask), _dev_ptr(out, torch.float64, "out"),
+                     _dev_ptr(status, torch.int32, "status"))
+
+
+class Plan:
+    """A captured evaluation (hipGraph) of one population shape; relaunch it
+    after rewriting the population/data tensors in place."""
+
+    def __init__(self, pop, data, tax_on_length, out, status=None, allowed_op_mask=0,
+                 tuning=None, autotune=False, stream=None):
+        self._keep = (pop, data, out, status)
+        pb = _problem(pop, data, tax_on_length, out, status, allowed_op_mask)
+        tu = None
+        if tuning is not None:
+            tu = GPTuning(int(tuning.get("programs_per_item", 0)), int(tuning.get("wg_per_cu", 0)),
+                          int(tuning.get("concurrent_classes", 0)))
+        h = ctypes.c_void_p()
+        _check(lib().gp_plan_create(ctypes.byref(h), ctypes.byref(pb),
+                                    ctypes.byref(tu) if tu is not None else None,
+                                    1 if autotune else 0, _stream_handle(stream)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().gp_plan_launch(self._h, _stream_handle(stream)))
+
+    def update(self, pop, data, tax_on_length, out, status=None, allowed_op_mask=0):
+        self._keep = (pop, data, out, status)
+        pb = _problem(pop, data, tax_on_length, out, status, allowed_op_mask)
+        _check(lib().gp_plan_update(self._h, ctypes.byref(pb)))
+
+    @property
+    def tuning(self):
+        t = GPTuning()
+        _check(lib().gp_plan_get_tuning(self._h, ctypes.byref(t)))
+        return {"programs_per_item": t.programs_per_item, "wg_per_cu": t.wg_per_cu,
+                "concurrent_classes": t.concurrent_classes}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class DevicePopulation:
@@ -231,3 +431,110 @@ def evaluate(nodes, offsets, consts, X, y, tax_on_length=0.0, allowed_op_mask=0,
     if return_status:
         return out.cpu().numpy(), st.cpu().numpy()
     return out.cpu().numpy()
+
+
+def workspace_size(n_programs, n_nodes, n_requests=1, n_datasets=1, max_n_vars=1,
+                   max_n_cases=1):
+    """gp_workspace_size: device bytes one call of this shape may hold."""
+    b = ctypes.c_size_t()
+    _check(lib().gp_workspace_size(int(n_programs), int(n_nodes), int(n_requests),
+                                   int(n_datasets), int(max_n_vars), int(max_n_cases),
+                                   ctypes.byref(b)))
+    return b.value
+
+
+class Server:
+    """gp_server: resident datasets, admission by device budget, chunking and
+    continuous batching on the library's scheduler thread.  Requests take
+    host (numpy) arrays; this wrapper keeps them alive until their ticket
+    completes and returns the result arrays."""
+
+    def __init__(self, device_budget_bytes=0, pinned_bytes=0, chunk_node_evals=0,
+                 batch_node_evals=0, n_streams=0, max_batch_chunks=0,
+                 one_launch_per_request=False, allowed_op_mask=0):
+        cfg = GPServerConfig(int(device_budget_bytes), int(pinned_bytes), int(chunk_node_evals),
+                             int(batch_node_evals), int(n_streams), int(max_batch_chunks),
+                             1 if one_launch_per_request else 0, int(allowed_op_mask))
+        h = ctypes.c_void_p()
+        _check(lib().gp_server_create(ctypes.byref(h), ctypes.byref(cfg)))
+        self._h = h
+        self._pending = {}          # ticket -> (arrays kept alive, fitness, status)
+
+    def add_dataset(self, X, y, tax_on_length=0.0):
+        X = np.ascontiguousarray(X, np.float32)
+        if X.ndim == 1:
+            X = X.reshape(1, -1)
+        y = np.ascontiguousarray(y, np.float32)
+        i = ctypes.c_int32()
+        _check(lib().gp_server_add_dataset(self._h, X.ctypes.data, X.shape[0], X.shape[1],
+                                           y.ctypes.data, y.size, float(tax_on_length),
+                                           ctypes.byref(i)))
+        return i.value
+
+    def remove_dataset(self, dataset_id):
+        _check(lib().gp_server_remove_dataset(self._h, int(dataset_id)))
+
+    def submit(self, dataset_id, nodes, offsets, consts):
+        nodes = np.ascontiguousarray(nodes, np.uint32)
+        offsets = np.ascontiguousarray(offsets, np.int64)
+        consts = np.ascontiguousarray(consts, np.float32)
+        P = offsets.size - 1
+        fit = np.empty(P, np.float64)
+        st = np.empty(P, np.int32)
+        t = ctypes.c_int64()
+        _check(lib().gp_server_submit(self._h, int(dataset_id),
+                                      nodes.ctypes.data if nodes.size else None, nodes.size,
+                                      offsets.ctypes.data, P,
+                                      consts.ctypes.data if consts.size else None, consts.size,
+                                      fit.ctypes.data, st.ctypes.data, ctypes.byref(t)))
+        self._pending[t.value] = ((nodes, offsets, consts), fit, st)
+        return t.value
+
+    def poll(self, timeout_ms=0.0, max_n=256):
+        """Completed requests: list of (ticket, result code, fitness, status)."""
+        tk = np.empty(max_n, np.int64)
+        rc = np.empty(max_n, np.int32)
+        n = ctypes.c_int32()
+        _check(lib().gp_server_poll(self._h, float(timeout_ms), tk.ctypes.data, rc.ctypes.data,
+                                    max_n, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            _, fit, st = self._pending.pop(int(tk[i]))
+            out.append((int(tk[i]), int(rc[i]), fit, st))
+        return out
+
+    def wait(self, ticket, timeout_ms=-1.0):
+        """(result code, fitness, status) of one ticket, or None on timeout."""
+        done, res = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().gp_server_wait(self._h, int(ticket), float(timeout_ms), ctypes.byref(done),
+                                    ctypes.byref(res)))
+        if not done.value:
+            return None
+        _, fit, st = self._pending.pop(int(ticket))
+        return res.value, fit, st
+
+    def stats(self):
+        s = GPServerStats()
+        _check(lib().gp_server_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in GPServerStats._fields_}
+
+    def reset_stats(self):
+        _check(lib().gp_server_reset_stats(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gp_server_destroy(self._h)
+            self._h = None
+            self._pending.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

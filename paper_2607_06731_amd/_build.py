@@ -6,7 +6,7 @@ import subprocess
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "gpeval.hip")
+SRCS = [os.path.join(PKG, "csrc", "gpeval.hip"), os.path.join(PKG, "csrc", "server.cpp")]
 LIB = os.path.join(PKG, "libgpeval.so")
 INCLUDE = os.path.join(ROOT, "include")
 
@@ -32,7 +32,7 @@ def hipcc():
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-o", tmp, SRC]
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-o", tmp] + SRCS + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)

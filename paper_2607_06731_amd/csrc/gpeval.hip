@@ -6,9 +6,11 @@
 //                    stage each node as 8 bytes {op | read-slot | write-slot,
 //                    var index or constant bits}, record length, maximum
 //                    depth and depth class.
-//   k_class_count /  stable partition of program ids by depth class
-//   k_class_scan /   (max depth <= 8, <= 16, <= 32), so each class runs a
-//   k_class_scatter  kernel whose register stack is only as deep as needed.
+//   k_class_count /  stable partition of program ids by (depth class, length
+//   k_class_scan /   bucket): each depth class (max depth <= 8, <= 16, <= 32)
+//   k_class_scatter  runs a kernel whose register stack is only as deep as
+//                    needed, and within a class the longest programs come
+//                    first (longest-processing-time order for the work queue).
 //   k_eval<MAXD,K>   persistent workgroups pull (program group, case tile)
 //                    items from an atomic counter; the case tile's inputs
 //                    are staged in LDS; each wavefront runs one program at a
@@ -34,6 +36,8 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <array>
 #include <map>
@@ -58,6 +62,17 @@ int set_error(int code, const char* fmt, ...)
     return code;
 }
 
+}  // namespace
+
+// Shared with the other translation units of the library (not exported).
+__attribute__((visibility("hidden"))) void gp_internal_set_error(int code, const char* msg)
+{
+    (void)code;
+    g_last_error = msg;
+}
+
+namespace {
+
 #define GP_HIP_TRY(expr)                                                      \
     do {                                                                      \
         hipError_t e_ = (expr);                                               \
@@ -70,13 +85,16 @@ int set_error(int code, const char* fmt, ...)
 constexpr int kWG = 256;                 // 4 wavefronts of 64
 constexpr int kWaves = kWG / 64;
 constexpr int kClasses = 3;              // max depth <= 8, <= 16, <= 32
+constexpr int kLenBuckets = 8;           // staged length 1, 2-3, ..., 64-127, 128+
+constexpr int kKeys = kClasses * kLenBuckets;
 constexpr int kMaxTiles = 32;            // case tiles per program (cap)
 constexpr uint32_t kNoSlot = 0xFFu;      // staged write slot: nothing to save
 constexpr int kBucketBlock = 1024;       // programs per partition block
+constexpr int kMaxRequests = 4096;       // requests per batched call (tables are scanned by one workgroup)
 
 // Per-program record written by k_prepare.
 struct ProgMeta {
-    int64_t start;      // first node (original and staged code share it)
+    int64_t start;      // first staged slot (request node base + program offset)
     int32_t len;        // node count (the length taxed)
     int32_t slen;       // staged instruction count (<= len)
 };
@@ -101,7 +119,7 @@ __host__ __device__ inline int depth_class(int maxd)
 // per lane for the shallow class measured slower on gfx950: occupancy drops
 // from 5 to 3 waves per SIMD and LDS input reads are exposed.)  Depends only
 // on the class and the dataset, never on the rest of the population.
-int class_k(int c, int n_vars)
+__host__ __device__ inline int class_k(int c, int n_vars)
 {
     if (c == 0) return 4;
     return c == 1 ? 4 : 2;
@@ -119,7 +137,7 @@ struct TileShape {
     int32_t n_tiles;    // tiles covering n_cases
 };
 
-TileShape tile_shape(int64_t n_cases, int k)
+__host__ __device__ inline TileShape tile_shape(int64_t n_cases, int k)
 {
     TileShape t;
     t.sub = kWG * k;
@@ -134,11 +152,142 @@ TileShape tile_shape(int64_t n_cases, int k)
 // Power-of-two pre-scale s = 2^-e with 4^e >= n: every scaled partial sum
 // of squared residuals is then <= MSE, so it overflows fp32 only when the
 // MSE itself is beyond FLT_MAX.
-int scale_exponent(int64_t n)
+__host__ __device__ inline int scale_exponent(int64_t n)
 {
     int e = 0;
     while ((int64_t(1) << (2 * e)) < n) ++e;
     return e;
+}
+
+// ---------------------------------------------------- datasets, segments
+// Dataset entry as the kernels use it (derived on the device each call).
+struct DevDataset {
+    const float* X;
+    const float* y;
+    int64_t ld_x;
+    int64_t n_cases;
+    double tax;
+    double unscale;                 // 4^e / n_cases
+    float scale;                    // 2^-e
+    int32_t n_vars;
+    int32_t passes[kClasses];
+    int32_t n_tiles[kClasses];
+};
+
+// Request entry as the kernels use it: the caller's entry with its
+// program and node offsets inside the whole call (derived each call).
+struct DevRequest {
+    const uint32_t* nodes;
+    const int64_t* offsets;
+    const float* consts;
+    int64_t n_programs;
+    int64_t n_nodes;
+    int64_t n_consts;
+    int64_t node_base;              // first staged slot of this request
+    double* out;
+    int32_t* out_status;
+    int32_t dataset;
+};
+
+// One workgroup: check the dataset and request tables, derive each
+// dataset's tile shapes and scales, and lay the requests out one after the
+// other (program starts seg_start[], staged-node bases).  With ds_in == NULL
+// the single dataset `one` is used; with req_in == NULL the single request
+// `one_req`.  *bad becomes 1 for inconsistent tables; then no program is
+// staged and sizes are clamped so that every later index stays in range.
+__global__ __launch_bounds__(256) void k_tables(
+    const gp_dataset* __restrict__ ds_in, int32_t n_ds, gp_dataset one,
+    const gp_request* __restrict__ req_in, int32_t n_req, gp_request one_req,
+    int64_t n_programs, int64_t n_nodes, int32_t max_vars, int64_t max_cases, int32_t need_out,
+    DevDataset* __restrict__ ds_out, DevRequest* __restrict__ req_out,
+    int32_t* __restrict__ seg_ds, int64_t* __restrict__ seg_start, int32_t* __restrict__ bad)
+{
+    __shared__ int s_bad;
+    __shared__ int64_t s_prog[256], s_node[256];
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    for (int d = threadIdx.x; d < n_ds; d += blockDim.x) {
+        const gp_dataset in = ds_in ? ds_in[d] : one;
+        DevDataset o;
+        const bool ok = in.n_cases >= 1 && in.n_cases <= max_cases && in.n_vars >= 0 &&
+                        in.n_vars <= max_vars && in.y != nullptr &&
+                        (in.n_vars == 0 || (in.X != nullptr && in.ld_x >= in.n_cases)) &&
+                        __builtin_isfinite(in.tax_on_length);
+        if (!ok) atomicOr(&s_bad, 1);
+        const int64_t n = ok ? in.n_cases : 1;
+        const int e = scale_exponent(n);
+        o.X = in.X;
+        o.y = in.y;
+        o.ld_x = in.ld_x;
+        o.n_cases = n;
+        o.tax = in.tax_on_length;
+        o.unscale = ldexp(1.0, 2 * e) / (double)n;
+        o.scale = ldexpf(1.0f, -e);
+        o.n_vars = ok ? in.n_vars : 0;
+        for (int c = 0; c < kClasses; ++c) {
+            const TileShape t = tile_shape(n, class_k(c, o.n_vars));
+            o.passes[c] = t.passes;
+            o.n_tiles[c] = t.n_tiles;
+        }
+        ds_out[d] = o;
+    }
+    // each thread takes a contiguous chunk of requests: check, clamp, sum
+    const int chunk = (n_req + 255) / 256;
+    const int r0 = min(n_req, (int)threadIdx.x * chunk), r1 = min(n_req, r0 + chunk);
+    int64_t sp = 0, sn = 0;
+    for (int r = r0; r < r1; ++r) {
+        const gp_request q = req_in ? req_in[r] : one_req;
+        const bool ok = q.n_programs >= 0 && q.n_programs <= n_programs && q.n_nodes >= 0 &&
+                        q.n_nodes <= n_nodes && q.n_consts >= 0 && q.n_consts <= GP_MAX_CONSTS &&
+                        (q.n_programs == 0 || q.offsets != nullptr) &&
+                        (q.n_nodes == 0 || q.nodes != nullptr) &&
+                        (q.n_consts == 0 || q.consts != nullptr) &&
+                        (!need_out || q.n_programs == 0 || q.out_fitness != nullptr) &&
+                        q.dataset >= 0 && q.dataset < n_ds;
+        if (!ok) atomicOr(&s_bad, 1);
+        sp += q.n_programs >= 0 && q.n_programs <= n_programs ? q.n_programs : 0;
+        sn += q.n_nodes >= 0 && q.n_nodes <= n_nodes ? q.n_nodes : 0;
+    }
+    s_prog[threadIdx.x] = sp;
+    s_node[threadIdx.x] = sn;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the chunk sums
+    for (int off = 1; off < 256; off <<= 1) {
+        const int64_t vp = threadIdx.x >= off ? s_prog[threadIdx.x - off] : 0;
+        const int64_t vn = threadIdx.x >= off ? s_node[threadIdx.x - off] : 0;
+        __syncthreads();
+        s_prog[threadIdx.x] += vp;
+        s_node[threadIdx.x] += vn;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && (s_prog[255] != n_programs || s_node[255] != n_nodes))
+        atomicOr(&s_bad, 1);
+    int64_t pp = s_prog[threadIdx.x] - sp, pn = s_node[threadIdx.x] - sn;
+    for (int r = r0; r < r1; ++r) {
+        const gp_request q = req_in ? req_in[r] : one_req;
+        const int64_t np = q.n_programs >= 0 && q.n_programs <= n_programs ? q.n_programs : 0;
+        const int64_t nn = q.n_nodes >= 0 && q.n_nodes <= n_nodes ? q.n_nodes : 0;
+        DevRequest o;
+        o.nodes = q.nodes;
+        o.offsets = q.offsets;
+        o.consts = q.consts;
+        o.n_programs = np;
+        o.n_nodes = nn;
+        o.n_consts = q.n_consts;
+        o.node_base = pn;
+        o.out = q.out_fitness;
+        o.out_status = q.out_status;
+        o.dataset = q.dataset >= 0 && q.dataset < n_ds ? q.dataset : 0;
+        req_out[r] = o;
+        seg_ds[r] = o.dataset;
+        // starts beyond the call's programs are clamped: such a table is bad
+        seg_start[r] = pp < n_programs ? pp : n_programs;
+        pp += np;
+        pn += nn;
+    }
+    if (threadIdx.x == 0) seg_start[n_req] = n_programs;
+    __syncthreads();
+    if (threadIdx.x == 0) *bad = s_bad;
 }
 
 // ------------------------------------------------------------- k_prepare
@@ -148,19 +297,35 @@ int scale_exponent(int64_t n)
 __host__ __device__ constexpr int class_depth(int c) { return c == 0 ? 8 : (c == 1 ? 16 : 32); }
 
 __global__ __launch_bounds__(256) void k_prepare(
-    const uint32_t* __restrict__ nodes, const int64_t* __restrict__ offsets,
-    int64_t n_programs, int64_t n_nodes, const float* __restrict__ consts,
-    int64_t n_consts, int32_t n_vars, uint32_t allowed,
-    uint2* __restrict__ code, ProgMeta* __restrict__ meta,
-    uint8_t* __restrict__ cls, int32_t* __restrict__ out_status)
+    int64_t n_programs, uint32_t allowed, const DevDataset* __restrict__ ds,
+    const DevRequest* __restrict__ reqs, const int64_t* __restrict__ seg_start, int32_t n_seg,
+    const int32_t* __restrict__ tables_bad, int32_t lpt,
+    uint2* __restrict__ code, ProgMeta* __restrict__ meta, uint8_t* __restrict__ cls,
+    int32_t* __restrict__ pds)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_programs) return;
-    const int64_t s = offsets[p], e = offsets[p + 1];
+    // the segment holding p: last segment whose start is <= p
+    int lo_s = 0, hi_s = n_seg - 1;
+    while (lo_s < hi_s) {
+        const int mid = (lo_s + hi_s + 1) >> 1;
+        if (seg_start[mid] <= p) lo_s = mid; else hi_s = mid - 1;
+    }
+    const DevRequest R = reqs[lo_s];
+    const int64_t q = p - seg_start[lo_s];        // index inside the request
+    pds[p] = lo_s;
+    const uint32_t* __restrict__ nodes = R.nodes;
+    const float* __restrict__ consts = R.consts;
+    const int64_t n_consts = R.n_consts;
+    const int32_t n_vars = ds[R.dataset].n_vars;
+    const bool tab_ok = *tables_bad == 0;
+    const int64_t s = tab_ok ? R.offsets[q] : 0, e = tab_ok ? R.offsets[q + 1] : 0;
     int status = GP_PROG_OK;
     int depth = 0, maxd = 0;
     // pass 1: validate (GCL stack discipline, operand ranges, allowed ops)
-    if (s < 0 || e < s || e > n_nodes || e - s > INT32_MAX) {
+    if (!tab_ok) {
+        status = GP_PROG_BAD_TABLE;
+    } else if (s < 0 || e < s || e > R.n_nodes || e - s > INT32_MAX) {
         status = GP_PROG_BAD_OFFSETS;
     } else if (e == s) {
         status = GP_PROG_EMPTY;
@@ -183,7 +348,7 @@ __global__ __launch_bounds__(256) void k_prepare(
     // pass 2: stage 8-byte instructions {op | read index << 8 | write index
     // << 16, variable index or constant bits}, folding a leaf into the op
     // that directly follows it
-    int64_t sk = s;                              // next staged slot
+    int64_t sk = R.node_base + s;                // next staged slot
     if (c >= 0) {
         const uint32_t J = 32u / (uint32_t)class_depth(c);
         const uint32_t dummy = 32u - J;          // slot MAXD-1: never live
@@ -225,42 +390,48 @@ __global__ __launch_bounds__(256) void k_prepare(
         }
     }
     ProgMeta m;
-    m.start = s;
+    m.start = R.node_base + s;
     m.len = (int32_t)(status == GP_PROG_BAD_OFFSETS ? 0 : e - s);
-    m.slen = (int32_t)(sk - s);
+    m.slen = (int32_t)(sk - m.start);
     meta[p] = m;
-    cls[p] = c >= 0 ? (uint8_t)c : (uint8_t)0xFF;
-    if (out_status) out_status[p] = status;
+    // partition key: depth class, then (single-segment calls) length bucket
+    // from longest to shortest; with several segments the order inside a
+    // class stays the input order, so each segment's programs stay together
+    int lb = 31 - __clz((uint32_t)(m.slen > 0 ? m.slen : 1));
+    lb = lb < kLenBuckets - 1 ? lb : kLenBuckets - 1;
+    const int sub_key = lpt ? (kLenBuckets - 1 - lb) : 0;
+    cls[p] = c >= 0 ? (uint8_t)(c * kLenBuckets + sub_key) : (uint8_t)0xFF;
+    if (R.out_status && q < R.n_programs) R.out_status[q] = status;
 }
 
 // --------------------------------------------------- depth-class partition
-// blk_counts[c * n_blk + b] = programs of class c in block b.
+// blk_counts[k * n_blk + b] = programs with partition key k in block b.
 __global__ __launch_bounds__(kBucketBlock) void k_class_count(
     const uint8_t* __restrict__ cls, int64_t n_programs, int32_t n_blk,
     int32_t* __restrict__ blk_counts)
 {
-    __shared__ int cnt[kClasses];
-    if (threadIdx.x < kClasses) cnt[threadIdx.x] = 0;
+    __shared__ int cnt[kKeys];
+    if (threadIdx.x < kKeys) cnt[threadIdx.x] = 0;
     __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * kBucketBlock + threadIdx.x;
     if (p < n_programs) {
         const int c = cls[p];
-        if (c < kClasses) atomicAdd(&cnt[c], 1);
+        if (c < kKeys) atomicAdd(&cnt[c], 1);
     }
     __syncthreads();
-    if (threadIdx.x < kClasses) blk_counts[threadIdx.x * n_blk + blockIdx.x] = cnt[threadIdx.x];
+    if (threadIdx.x < kKeys) blk_counts[threadIdx.x * n_blk + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// One workgroup: exclusive scan of blk_counts in class-major order into
-// blk_base; class_info[2c] = first position of class c, [2c+1] = its size;
-// also clears the per-class work counters of k_eval.
+// One workgroup: exclusive scan of blk_counts in key-major order into
+// blk_base; class_info[2c] = first position of depth class c, [2c+1] = its
+// size (its keys are contiguous); also clears the per-class work counters.
 __global__ __launch_bounds__(1024) void k_class_scan(
     const int32_t* __restrict__ blk_counts, int32_t n_blk,
     int32_t* __restrict__ blk_base, int32_t* __restrict__ class_info,
     uint32_t* __restrict__ work_counters)
 {
     __shared__ int part[1024];
-    const int total = kClasses * n_blk;
+    const int total = kKeys * n_blk;
     const int chunk = (total + 1023) / 1024;
     const int t = threadIdx.x;
     const int lo = t * chunk, hi = min(total, lo + chunk);
@@ -281,39 +452,96 @@ __global__ __launch_bounds__(1024) void k_class_scan(
         run += blk_counts[i];
     }
     if (t < kClasses) {
-        // class t starts after every program of the classes before it
-        int start = 0, size = 0;
-        for (int i = 0; i < t * n_blk; ++i) start += blk_counts[i];
-        for (int i = t * n_blk; i < (t + 1) * n_blk; ++i) size += blk_counts[i];
+        // exclusive prefix of entry i from the scanned chunk sums (LDS)
+        auto prefix = [&](int i) {
+            if (i >= total) return part[1023];
+            const int owner = i / chunk;
+            int b = owner > 0 ? part[owner - 1] : 0;
+            for (int j = owner * chunk; j < i; ++j) b += blk_counts[j];
+            return b;
+        };
+        const int start = prefix(t * kLenBuckets * n_blk);
+        const int end = prefix((t + 1) * kLenBuckets * n_blk);
         class_info[2 * t] = start;
-        class_info[2 * t + 1] = size;
+        class_info[2 * t + 1] = end - start;
         work_counters[t] = 0u;
     }
 }
 
-// Stable scatter: order[blk_base[c, b] + rank of p among class-c programs
-// of block b] = p.
+// Stable scatter: order[blk_base[k, b] + rank of p among key-k programs of
+// block b] = p.
 __global__ __launch_bounds__(kBucketBlock) void k_class_scatter(
     const uint8_t* __restrict__ cls, int64_t n_programs, int32_t n_blk,
     const int32_t* __restrict__ blk_base, int32_t* __restrict__ order)
 {
     constexpr int kW = kBucketBlock / 64;
-    __shared__ int wcnt[kW][kClasses];
+    __shared__ int wcnt[kW][kKeys];
     const int64_t p = (int64_t)blockIdx.x * kBucketBlock + threadIdx.x;
     const int c = p < n_programs ? (int)cls[p] : 0xFF;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int rank = 0;
-    for (int cc = 0; cc < kClasses; ++cc) {
+    for (int cc = 0; cc < kKeys; ++cc) {
         const uint64_t m = __ballot(c == cc);
         if (lane == 0) wcnt[wave][cc] = __popcll(m);
         if (c == cc) rank = __popcll(m & below);
     }
     __syncthreads();
-    if (c < kClasses) {
+    if (c < kKeys) {
         for (int w = 0; w < wave; ++w) rank += wcnt[w][c];
         order[blk_base[c * n_blk + blockIdx.x] + rank] = (int32_t)p;
     }
+}
+
+// Programs of each depth class inside each segment: seg_cnt[c * n_seg + s].
+// (Segment bounds are only trusted after k_tables accepted the table; they
+// are clamped to the program range regardless.)
+__global__ __launch_bounds__(256) void k_seg_count(const uint8_t* __restrict__ cls,
+                                                   const int64_t* __restrict__ seg_start,
+                                                   int32_t n_seg, int64_t n_programs,
+                                                   const int32_t* __restrict__ tables_bad,
+                                                   int32_t* __restrict__ seg_cnt)
+{
+    __shared__ int cnt[kClasses];
+    const int sgi = blockIdx.x;
+    if (threadIdx.x < kClasses) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int local[kClasses] = {0, 0, 0};
+    int64_t p0 = seg_start[sgi], p1 = seg_start[sgi + 1];
+    if (*tables_bad) p0 = p1 = 0;
+    p0 = p0 < 0 ? 0 : (p0 > n_programs ? n_programs : p0);
+    p1 = p1 < p0 ? p0 : (p1 > n_programs ? n_programs : p1);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const int k = cls[p];
+        if (k < kKeys) local[k / kLenBuckets] += 1;
+    }
+    for (int c = 0; c < kClasses; ++c)
+        if (local[c]) atomicAdd(&cnt[c], local[c]);
+    __syncthreads();
+    if (threadIdx.x < kClasses) seg_cnt[threadIdx.x * n_seg + sgi] = cnt[threadIdx.x];
+}
+
+// Per class (one thread each): where each segment's programs start inside
+// the class's range of `order`, and the prefix of work items (G-program
+// groups times the segment dataset's case tiles) over segments.
+__global__ __launch_bounds__(64) void k_seg_scan(const int32_t* __restrict__ seg_cnt,
+                                                 const int32_t* __restrict__ seg_ds,
+                                                 const DevDataset* __restrict__ ds, int32_t n_seg,
+                                                 int32_t G, int32_t* __restrict__ seg_pos,
+                                                 uint32_t* __restrict__ item_pre)
+{
+    const int c = threadIdx.x;
+    if (c >= kClasses) return;
+    int32_t pos = 0;
+    uint32_t items = 0;
+    for (int s = 0; s < n_seg; ++s) {
+        const int32_t n = seg_cnt[c * n_seg + s];
+        seg_pos[c * n_seg + s] = pos;
+        item_pre[c * (n_seg + 1) + s] = items;
+        pos += n;
+        items += (uint32_t)((n + G - 1) / G) * (uint32_t)ds[seg_ds[s]].n_tiles[c];
+    }
+    item_pre[c * (n_seg + 1) + n_seg] = items;
 }
 
 // ------------------------------------------------------------ evaluation
@@ -321,15 +549,15 @@ __global__ __launch_bounds__(kBucketBlock) void k_class_scatter(
 // parameters so that uniform loads of programs and metadata become scalar
 // memory loads).
 struct EvalConst {
+    int32_t cls;
+    int32_t G;              // programs per work item
+    int32_t part_stride;
+    int32_t max_vars;       // LDS input tile rows
+    int32_t n_seg;
+    // single-dataset form (gp_predict)
     int64_t ld_x;
     int64_t n_cases;
-    int32_t cls;
     int32_t n_vars;
-    int32_t G;              // programs per work item
-    int32_t passes;
-    int32_t n_tiles;
-    int32_t part_stride;
-    float scale;            // 2^-e
 };
 
 // Error-free sum: s + e == a + b exactly (Knuth's TwoSum).
@@ -604,9 +832,10 @@ template <int MAXD, int K>
 __global__ __launch_bounds__(kWG) void k_eval(
     const uint2* __restrict__ code, const ProgMeta* __restrict__ meta,
     const int32_t* __restrict__ order, const int32_t* __restrict__ class_info,
-    uint32_t* __restrict__ work_counter, const float* __restrict__ X,
-    const float* __restrict__ y, float2* __restrict__ part,
-    uint8_t* __restrict__ part_bad, EvalConst a)
+    uint32_t* __restrict__ work_counter, const DevDataset* __restrict__ ds,
+    const int32_t* __restrict__ seg_ds, const int32_t* __restrict__ seg_cnt,
+    const int32_t* __restrict__ seg_pos, const uint32_t* __restrict__ item_pre,
+    float2* __restrict__ part, uint8_t* __restrict__ part_bad, EvalConst a)
 {
     static_assert(K == 2 || K == 4 || K == 8, "cases per lane");
     static_assert(MAXD == 8 || MAXD == 16 || MAXD == 32, "stack class");
@@ -614,20 +843,23 @@ __global__ __launch_bounds__(kWG) void k_eval(
     static_assert(K % J == 0 && K / J <= 4, "chunking");
     constexpr int SUB = kWG * K;                  // cases per sub-tile
     extern __shared__ float lds[];
-    float* xt = lds;                              // [n_vars][SUB]
-    float2* wpart = reinterpret_cast<float2*>(lds + (size_t)a.n_vars * SUB);  // [G][kWaves]
-    uint32_t* wbad = reinterpret_cast<uint32_t*>(wpart + a.G * kWaves);        // [G]
+    float* xt = lds;                              // [max_vars][SUB]
+    float2* wpart = reinterpret_cast<float2*>(lds + (size_t)a.max_vars * SUB);  // [G][kWaves]
+    uint32_t* wbad = reinterpret_cast<uint32_t*>(wpart + a.G * kWaves);          // [G]
     __shared__ uint32_t s_item;
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int lo = tid;                           // this lane's first case in a sub-tile
-    const int start = class_info[2 * a.cls];
-    const int count = class_info[2 * a.cls + 1];
-    const int n_groups = (count + a.G - 1) / a.G;
-    const uint32_t n_items = (uint32_t)n_groups * (uint32_t)a.n_tiles;
-    int64_t staged = -1;                          // sub-tile currently in LDS
+    const int c = a.cls;
+    const int cstart = class_info[2 * c];
+    const int32_t* __restrict__ cnt_c = seg_cnt + c * a.n_seg;
+    const int32_t* __restrict__ pos_c = seg_pos + c * a.n_seg;
+    const uint32_t* __restrict__ pre_c = item_pre + c * (a.n_seg + 1);
+    const uint32_t n_items = pre_c[a.n_seg];
+    int staged_d = -1;                            // dataset and sub-tile in LDS
+    int64_t staged = -1;
 
     for (;;) {
         if (tid == 0) s_item = atomicAdd(work_counter, 1u);
@@ -635,23 +867,37 @@ __global__ __launch_bounds__(kWG) void k_eval(
         __syncthreads();
         const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= n_items) break;
-        const int tile = (int)(item / (uint32_t)n_groups);
-        const int grp = (int)(item % (uint32_t)n_groups);
+        // segment of this item: last s with pre_c[s] <= item
+        int sl = 0, sh = a.n_seg - 1;
+        while (sl < sh) {
+            const int mid = (sl + sh + 1) >> 1;
+            if (pre_c[mid] <= item) sl = mid; else sh = mid - 1;
+        }
+        const int d = seg_ds[sl];
+        const DevDataset D = ds[d];
+        const int count = cnt_c[sl];
+        const int n_groups = (count + a.G - 1) / a.G;
+        const uint32_t local = item - pre_c[sl];
+        const int tile = (int)(local / (uint32_t)n_groups);
+        const int grp = (int)(local % (uint32_t)n_groups);
         const int g0 = grp * a.G;
         const int gn = min(a.G, count - g0);
+        const int obase = cstart + pos_c[sl] + g0;
+        const int passes = D.passes[c];
 
-        for (int pass = 0; pass < a.passes; ++pass) {
-            const int64_t sub_idx = (int64_t)tile * a.passes + pass;
+        for (int pass = 0; pass < passes; ++pass) {
+            const int64_t sub_idx = (int64_t)tile * passes + pass;
             const int64_t base = sub_idx * SUB;
-            if (base >= a.n_cases) break;
-            if (sub_idx != staged) {
+            if (base >= D.n_cases) break;
+            if (sub_idx != staged || d != staged_d) {
                 __syncthreads();
-                for (int i = tid; i < a.n_vars * SUB; i += kWG) {
-                    const int v = i / SUB, c = i - v * SUB;
-                    const int64_t gi = base + c;
-                    xt[i] = gi < a.n_cases ? X[(int64_t)v * a.ld_x + gi] : 0.f;
+                for (int i = tid; i < D.n_vars * SUB; i += kWG) {
+                    const int v = i / SUB, cc = i - v * SUB;
+                    const int64_t gi = base + cc;
+                    xt[i] = gi < D.n_cases ? D.X[(int64_t)v * D.ld_x + gi] : 0.f;
                 }
                 staged = sub_idx;
+                staged_d = d;
                 __syncthreads();
             }
             float yv[K];
@@ -659,12 +905,12 @@ __global__ __launch_bounds__(kWG) void k_eval(
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int64_t gi = base + lo + j * kWG;
-                live[j] = gi < a.n_cases;
-                yv[j] = live[j] ? y[gi] : 0.f;
+                live[j] = gi < D.n_cases;
+                yv[j] = live[j] ? D.y[gi] : 0.f;
             }
 
             for (int g = 0; g < gn; ++g) {
-                const int pid = order[start + g0 + g];
+                const int pid = order[obase + g];
                 const ProgMeta m = meta[pid];
                 float tos[K];
                 run_program<MAXD, K, SUB>(code + m.start, code + m.start + m.slen, xt + lo, tos);
@@ -677,7 +923,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
                     if (live[j]) {
                         const float f = tos[j];
                         bad |= !__builtin_isfinite(f);
-                        const float r = (f - yv[j]) * a.scale;
+                        const float r = (f - yv[j]) * D.scale;
                         float s, e;
                         two_sum(hi, r * r, s, e);
                         hi = s;
@@ -708,7 +954,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
         }
         // combine the wavefronts in fixed order and store the tile partial
         if (tid < gn) {
-            const int pid = order[start + g0 + tid];
+            const int pid = order[obase + tid];
             float h = wpart[tid * kWaves].x, l = wpart[tid * kWaves].y;
 #pragma unroll
             for (int w = 1; w < kWaves; ++w) acc_pair(h, l, wpart[tid * kWaves + w].x, wpart[tid * kWaves + w].y);
@@ -778,7 +1024,7 @@ __global__ __launch_bounds__(256) void k_fill_invalid(const uint8_t* __restrict_
                                                       int64_t ld_out)
 {
     const int64_t p = blockIdx.x;
-    if (cls[p] < kClasses) return;
+    if (cls[p] < kKeys) return;
     for (int64_t i = threadIdx.x; i < n_cases; i += 256) out[p * ld_out + i] = __builtin_nanf("");
 }
 
@@ -786,24 +1032,29 @@ __global__ __launch_bounds__(256) void k_fill_invalid(const uint8_t* __restrict_
 struct ReduceArgs {
     const ProgMeta* meta;
     const uint8_t* cls;
+    const int32_t* pds;             // request of each program
+    const DevRequest* reqs;
+    const int64_t* seg_start;
+    const DevDataset* ds;
     const float2* part;
     const uint8_t* part_bad;
-    double* out;
     int64_t n_programs;
     int32_t part_stride;
-    int32_t n_tiles[kClasses];
-    double unscale;         // 4^e / n_cases
-    double tax;
 };
 
 __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n_programs) return;
+    const int r = a.pds[p];
+    const DevRequest& R = a.reqs[r];
+    const int64_t q = p - a.seg_start[r];
+    if (!R.out || q >= R.n_programs) return;     // only for inconsistent tables
     const int c = a.cls[p];
-    if (c >= kClasses) { a.out[p] = __builtin_nan(""); return; }
+    if (c >= kKeys) { R.out[q] = __builtin_nan(""); return; }
     const ProgMeta m = a.meta[p];
-    const int nt = a.n_tiles[c];
+    const DevDataset& D = a.ds[R.dataset];
+    const int nt = D.n_tiles[c / kLenBuckets];
     double s = 0.0;
     bool bad = false;
     for (int t = 0; t < nt; ++t) {
@@ -811,26 +1062,20 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
         s += (double)v.x + (double)v.y;
         bad |= a.part_bad[p * a.part_stride + t] != 0;
     }
-    const double mse = s * a.unscale;
-    a.out[p] = (bad || !(mse <= (double)FLT_MAX)) ? __builtin_inf() : mse + a.tax * (double)m.len;
+    const double mse = s * D.unscale;
+    R.out[q] = (bad || !(mse <= (double)FLT_MAX)) ? __builtin_inf() : mse + D.tax * (double)m.len;
 }
 
 // ----------------------------------------------------------- workspaces
-struct Workspace {
-    void* ptr = nullptr;
-    size_t bytes = 0;
-};
-
-std::mutex g_ws_mutex;
-std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
-
 struct Layout {
-    size_t code, meta, cls, order, blk_counts, blk_base, class_info, counters, part, part_bad, total;
+    size_t code, meta, cls, order, blk_counts, blk_base, class_info, counters, part, part_bad;
+    size_t ds, req, seg_ds, seg_start, seg_cnt, seg_pos, item_pre, pds, bad, total;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride)
+Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride, int32_t n_ds,
+                   int32_t n_seg)
 {
     Layout L;
     const int64_t n_blk = (n_programs + kBucketBlock - 1) / kBucketBlock;
@@ -839,22 +1084,116 @@ Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride)
     L.meta = off;       off = align_up(off + (size_t)n_programs * sizeof(ProgMeta));
     L.cls = off;        off = align_up(off + (size_t)n_programs);
     L.order = off;      off = align_up(off + (size_t)n_programs * 4);
-    L.blk_counts = off; off = align_up(off + (size_t)kClasses * n_blk * 4);
-    L.blk_base = off;   off = align_up(off + (size_t)kClasses * n_blk * 4);
+    L.blk_counts = off; off = align_up(off + (size_t)kKeys * n_blk * 4);
+    L.blk_base = off;   off = align_up(off + (size_t)kKeys * n_blk * 4);
     L.class_info = off; off = align_up(off + 2 * kClasses * 4);
     L.counters = off;   off = align_up(off + kClasses * 4);
     L.part = off;       off = align_up(off + (size_t)n_programs * part_stride * sizeof(float2));
     L.part_bad = off;   off = align_up(off + (size_t)n_programs * part_stride);
+    L.ds = off;         off = align_up(off + (size_t)n_ds * sizeof(DevDataset));
+    L.req = off;        off = align_up(off + (size_t)n_seg * sizeof(DevRequest));
+    L.seg_ds = off;     off = align_up(off + (size_t)n_seg * 4);
+    L.seg_start = off;  off = align_up(off + (size_t)(n_seg + 1) * 8);
+    L.seg_cnt = off;    off = align_up(off + (size_t)kClasses * n_seg * 4);
+    L.seg_pos = off;    off = align_up(off + (size_t)kClasses * n_seg * 4);
+    L.item_pre = off;   off = align_up(off + (size_t)kClasses * (n_seg + 1) * 4);
+    L.pds = off;        off = align_up(off + (size_t)n_programs * 4);
+    L.bad = off;        off = align_up(off + 4);
     L.total = off;
     return L;
 }
 
-int get_workspace(hipStream_t stream, size_t bytes, void** out)
+// Device views of one call's workspace.
+struct Staged {
+    uint2* code;
+    ProgMeta* meta;
+    uint8_t* cls;
+    int32_t* order;
+    int32_t* blk_counts;
+    int32_t* blk_base;
+    int32_t* class_info;
+    uint32_t* counters;
+    float2* part;
+    uint8_t* part_bad;
+    DevDataset* ds;
+    DevRequest* req;
+    int32_t* seg_ds;
+    int64_t* seg_start;
+    int32_t* seg_cnt;
+    int32_t* seg_pos;
+    uint32_t* item_pre;
+    int32_t* pds;
+    int32_t* bad;
+};
+
+Staged carve(void* base, const Layout& L)
+{
+    char* ws = static_cast<char*>(base);
+    Staged st;
+    st.code = reinterpret_cast<uint2*>(ws + L.code);
+    st.meta = reinterpret_cast<ProgMeta*>(ws + L.meta);
+    st.cls = reinterpret_cast<uint8_t*>(ws + L.cls);
+    st.order = reinterpret_cast<int32_t*>(ws + L.order);
+    st.blk_counts = reinterpret_cast<int32_t*>(ws + L.blk_counts);
+    st.blk_base = reinterpret_cast<int32_t*>(ws + L.blk_base);
+    st.class_info = reinterpret_cast<int32_t*>(ws + L.class_info);
+    st.counters = reinterpret_cast<uint32_t*>(ws + L.counters);
+    st.part = reinterpret_cast<float2*>(ws + L.part);
+    st.part_bad = reinterpret_cast<uint8_t*>(ws + L.part_bad);
+    st.ds = reinterpret_cast<DevDataset*>(ws + L.ds);
+    st.req = reinterpret_cast<DevRequest*>(ws + L.req);
+    st.seg_ds = reinterpret_cast<int32_t*>(ws + L.seg_ds);
+    st.seg_start = reinterpret_cast<int64_t*>(ws + L.seg_start);
+    st.seg_cnt = reinterpret_cast<int32_t*>(ws + L.seg_cnt);
+    st.seg_pos = reinterpret_cast<int32_t*>(ws + L.seg_pos);
+    st.item_pre = reinterpret_cast<uint32_t*>(ws + L.item_pre);
+    st.pds = reinterpret_cast<int32_t*>(ws + L.pds);
+    st.bad = reinterpret_cast<int32_t*>(ws + L.bad);
+    return st;
+}
+
+// Side streams and fork/join events used when depth classes run
+// concurrently.  Default priority, non-blocking.
+struct SideStreams {
+    hipStream_t s[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    int create()
+    {
+        for (auto& x : s) GP_HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        GP_HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        for (auto& e : join) GP_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        return GP_OK;
+    }
+    void destroy()
+    {
+        for (auto& x : s) if (x) (void)hipStreamDestroy(x);
+        if (fork) (void)hipEventDestroy(fork);
+        for (auto& e : join) if (e) (void)hipEventDestroy(e);
+        s[0] = s[1] = nullptr;
+        fork = join[0] = join[1] = nullptr;
+    }
+};
+
+// Per-(device, caller stream) state of gp_eval / gp_predict.
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    SideStreams side;
+};
+
+std::mutex g_ws_mutex;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+int get_workspace(hipStream_t stream, size_t bytes, Workspace** out)
 {
     int dev = 0;
     GP_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_ws_mutex);
     Workspace& w = g_ws[std::make_pair(dev, stream)];
+    if (!w.side.s[0]) {
+        int rc = w.side.create();
+        if (rc != GP_OK) return rc;
+    }
     if (w.bytes < bytes) {
         if (w.ptr) {
             // earlier work on this stream may still use the old buffer
@@ -871,58 +1210,31 @@ int get_workspace(hipStream_t stream, size_t bytes, void** out)
         }
         w.bytes = want;
     }
-    *out = w.ptr;
+    *out = &w;
     return GP_OK;
 }
 
 struct DeviceInfo {
     int cus = 0;
-    int occ[kClasses] = {0, 0, 0};
 };
 std::mutex g_dev_mutex;
 std::map<int, DeviceInfo> g_dev;
 
-template <int MAXD, int K>
-size_t eval_lds_bytes(int n_vars, int G)
+int device_cus(int* cus)
 {
-    return (size_t)n_vars * kWG * K * sizeof(float) + (size_t)G * kWaves * sizeof(float2) +
-           (size_t)G * sizeof(uint32_t);
-}
-
-struct EvalPtrs {
-    const uint2* code;
-    const ProgMeta* meta;
-    const int32_t* order;
-    const int32_t* class_info;
-    uint32_t* work_counter;
-    const float* X;
-    const float* y;
-    float2* part;
-    uint8_t* part_bad;
-};
-
-template <int MAXD, int K>
-int launch_eval(const EvalPtrs& p, const EvalConst& args, hipStream_t stream, int cus)
-{
-    const size_t lds = eval_lds_bytes<MAXD, K>(args.n_vars, args.G);
-    if (lds > 64 * 1024) {
-        GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval<MAXD, K>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    }
-    int per_cu = 0;
-    GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval<MAXD, K>, kWG, lds));
-    if (per_cu < 1) return set_error(GP_E_TOO_LARGE, "n_vars=%d needs %zu bytes of LDS per workgroup", args.n_vars, lds);
-    const int grid = cus * per_cu;
-    hipLaunchKernelGGL((k_eval<MAXD, K>), dim3(grid), dim3(kWG), lds, stream, p.code, p.meta,
-                       p.order, p.class_info, p.work_counter, p.X, p.y, p.part, p.part_bad, args);
-    GP_HIP_TRY(hipGetLastError());
+    int dev = 0;
+    GP_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_dev_mutex);
+    DeviceInfo& di = g_dev[dev];
+    if (di.cus == 0) GP_HIP_TRY(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    *cus = di.cus;
     return GP_OK;
 }
 
 // ---------------------------------------------------------------- timing
 struct Timing {
     bool on = false;
-    // events of calls not yet read: kPhases + 1 boundaries per call
+    // events of calls not yet read: GP_TIMING_PHASES boundaries per call
     std::vector<std::array<hipEvent_t, GP_TIMING_PHASES>> pending;
     double ms[GP_TIMING_PHASES] = {0, 0, 0, 0, 0, 0};
     int64_t calls = 0;
@@ -934,9 +1246,9 @@ thread_local Timing g_timing;
 struct CallEvents {
     std::array<hipEvent_t, GP_TIMING_PHASES> ev{};
     bool on = false;
-    int begin()
+    int begin(bool enable)
     {
-        on = g_timing.on;
+        on = enable && g_timing.on;
         if (!on) return GP_OK;
         for (auto& e : ev) GP_HIP_TRY(hipEventCreate(&e));
         return GP_OK;
@@ -952,23 +1264,24 @@ struct CallEvents {
     }
 };
 
-template <int MAXD, int K>
-int launch_predict(const EvalPtrs& p, float* out, int64_t ld_out, const EvalConst& args,
-                   hipStream_t stream, int cus)
-{
-    const size_t lds = (size_t)args.n_vars * kWG * K * sizeof(float);
-    if (lds > 64 * 1024) {
-        GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_predict<MAXD, K>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    }
-    int per_cu = 0;
-    GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_predict<MAXD, K>, kWG, lds));
-    if (per_cu < 1) return set_error(GP_E_TOO_LARGE, "n_vars=%d needs %zu bytes of LDS per workgroup", args.n_vars, lds);
-    hipLaunchKernelGGL((k_predict<MAXD, K>), dim3(cus * per_cu), dim3(kWG), lds, stream, p.code,
-                       p.meta, p.order, p.class_info, p.work_counter, p.X, out, ld_out, args);
-    GP_HIP_TRY(hipGetLastError());
-    return GP_OK;
-}
+// ------------------------------------------------------------- problem
+// Everything one evaluation needs (device pointers, sizes, scoring).  A
+// single-population call carries its request and dataset inline (req_dev
+// and ds_dev NULL); a batched call points at device tables.
+struct Problem {
+    gp_request one_req;             // inline request ...
+    const gp_request* req_dev;      // ... or a device table of n_req
+    int32_t n_req;
+    gp_dataset one;                 // inline dataset ...
+    const gp_dataset* ds_dev;       // ... or a device table of n_ds
+    int32_t n_ds;
+    int64_t n_programs;             // over all requests
+    int64_t n_nodes;
+    int32_t max_vars;
+    int64_t max_cases;
+    uint32_t allowed;
+    int32_t need_out;               // fitness outputs required (not for gp_predict)
+};
 
 int check_common(int64_t n_programs, int64_t n_nodes, int64_t n_consts, int32_t n_vars,
                  int64_t ld_x, int64_t n_cases)
@@ -996,67 +1309,415 @@ int check_pointers(const uint32_t* nodes, int64_t n_nodes, const float* consts, 
     return GP_OK;
 }
 
-int device_cus(int* cus)
+int check_problem(const Problem& pb)
 {
-    int dev = 0;
-    GP_HIP_TRY(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lk(g_dev_mutex);
-    DeviceInfo& di = g_dev[dev];
-    if (di.cus == 0) GP_HIP_TRY(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
-    *cus = di.cus;
+    const bool batched = pb.req_dev != nullptr;
+    int rc = check_common(pb.n_programs, pb.n_nodes, batched ? 0 : pb.one_req.n_consts,
+                          pb.max_vars, batched ? pb.max_cases : pb.one.ld_x, pb.max_cases);
+    if (rc != GP_OK) return rc;
+    if (batched) {
+        if (!pb.ds_dev) return set_error(GP_E_INVALID_ARG, "datasets_dev is NULL");
+        if (pb.n_ds < 1) return set_error(GP_E_INVALID_ARG, "n_datasets < 1");
+        if (pb.n_req < 1) return set_error(GP_E_INVALID_ARG, "n_requests < 1");
+        if (pb.n_req > kMaxRequests) return set_error(GP_E_TOO_LARGE, "more than %d requests", kMaxRequests);
+        return GP_OK;
+    }
+    if (pb.n_programs == 0) return GP_OK;
+    const gp_request& q = pb.one_req;
+    if (!q.offsets) return set_error(GP_E_INVALID_ARG, "offsets is NULL");
+    if (pb.need_out && !q.out_fitness) return set_error(GP_E_INVALID_ARG, "out_fitness is NULL");
+    if ((rc = check_pointers(q.nodes, q.n_nodes, q.consts, q.n_consts, nullptr, 0)) != GP_OK) return rc;
+    if (!pb.one.y) return set_error(GP_E_INVALID_ARG, "y is NULL");
+    if (pb.one.n_vars > 0 && !pb.one.X) return set_error(GP_E_INVALID_ARG, "X is NULL");
+    if (!std::isfinite(pb.one.tax_on_length)) return set_error(GP_E_INVALID_ARG, "tax_on_length is not finite");
     return GP_OK;
 }
 
-// Device views of one call's workspace.
-struct Staged {
-    uint2* code;
-    ProgMeta* meta;
-    uint8_t* cls;
-    int32_t* order;
-    int32_t* class_info;
-    uint32_t* counters;
+// --------------------------------------------------- launch configuration
+// Scheduling knobs.  None of them changes a result: a program's summation
+// order is fixed by (n_cases, its depth class, n_vars) alone.
+struct Tuning {
+    int G = 8;              // programs per work item
+    int wg_per_cu = 0;      // persistent workgroups per CU (0: occupancy limit)
+    int concurrent = 0;     // depth classes on forked streams
+};
+
+struct EvalPtrs {
+    const uint2* code;
+    const ProgMeta* meta;
+    const int32_t* order;
+    const int32_t* class_info;
+    uint32_t* work_counter;
+    const float* X;
+    const float* y;
     float2* part;
     uint8_t* part_bad;
 };
 
-// Validation, staging and the stable depth-class partition, on `stream`.
-int stage_population(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
-                     int64_t n_nodes, const float* consts, int64_t n_consts, int32_t n_vars,
-                     uint32_t allowed_op_mask, int32_t* out_status, int32_t part_stride,
-                     hipStream_t stream, Staged* st)
+template <int MAXD, int K>
+size_t eval_lds_bytes(int n_vars, int G)
 {
-    const uint32_t allowed = allowed_op_mask ? allowed_op_mask : GP_ALL_OPS;
-    const Layout L = make_layout(n_programs, n_nodes, part_stride);
-    void* wsv = nullptr;
-    int rc = get_workspace(stream, L.total, &wsv);
-    if (rc != GP_OK) return rc;
-    char* ws = static_cast<char*>(wsv);
-    st->code = reinterpret_cast<uint2*>(ws + L.code);
-    st->meta = reinterpret_cast<ProgMeta*>(ws + L.meta);
-    st->cls = reinterpret_cast<uint8_t*>(ws + L.cls);
-    st->order = reinterpret_cast<int32_t*>(ws + L.order);
-    int32_t* blk_counts = reinterpret_cast<int32_t*>(ws + L.blk_counts);
-    int32_t* blk_base = reinterpret_cast<int32_t*>(ws + L.blk_base);
-    st->class_info = reinterpret_cast<int32_t*>(ws + L.class_info);
-    st->counters = reinterpret_cast<uint32_t*>(ws + L.counters);
-    st->part = reinterpret_cast<float2*>(ws + L.part);
-    st->part_bad = reinterpret_cast<uint8_t*>(ws + L.part_bad);
+    return (size_t)n_vars * kWG * K * sizeof(float) + (size_t)G * kWaves * sizeof(float2) +
+           (size_t)G * sizeof(uint32_t);
+}
 
-    const int32_t n_blk = (int32_t)((n_programs + kBucketBlock - 1) / kBucketBlock);
-    const unsigned grid_p = (unsigned)((n_programs + 255) / 256);
-    hipLaunchKernelGGL(k_prepare, dim3(grid_p), dim3(256), 0, stream, nodes, offsets, n_programs,
-                       n_nodes, consts, n_consts, n_vars, allowed, st->code, st->meta, st->cls,
-                       out_status);
+// Grid size of one class kernel (LDS attribute set outside any capture).
+template <int MAXD, int K>
+int eval_grid(int n_vars, int G, int wg_per_cu, int cus, int* grid, size_t* lds_out)
+{
+    const size_t lds = eval_lds_bytes<MAXD, K>(n_vars, G);
+    if (lds > 64 * 1024) {
+        GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval<MAXD, K>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    int per_cu = 0;
+    GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval<MAXD, K>, kWG, lds));
+    if (per_cu < 1) return set_error(GP_E_TOO_LARGE, "n_vars=%d needs %zu bytes of LDS per workgroup", n_vars, lds);
+    if (wg_per_cu > 0 && wg_per_cu < per_cu) per_cu = wg_per_cu;
+    *grid = cus * per_cu;
+    *lds_out = lds;
+    return GP_OK;
+}
+
+struct EvalLaunch {
+    int32_t stride = 1;
+    int grid[kClasses] = {0, 0, 0};
+    size_t lds[kClasses] = {0, 0, 0};
+    Layout layout;
+};
+
+int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
+{
+    int cus = 0;
+    int rc = device_cus(&cus);
+    if (rc != GP_OK) return rc;
+    el->stride = 1;
+    for (int c = 0; c < kClasses; ++c) {
+        // tile counts grow with n_cases, so the largest dataset sizes the
+        // partial buffer
+        const TileShape t = tile_shape(pb.max_cases, class_k(c, pb.max_vars));
+        if (t.n_tiles > el->stride) el->stride = t.n_tiles;
+    }
+    if ((rc = eval_grid<8, 4>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
+    if ((rc = eval_grid<16, 4>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
+    if ((rc = eval_grid<32, 2>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2])) != GP_OK) return rc;
+    el->layout = make_layout(pb.n_programs, pb.n_nodes, el->stride, pb.n_ds, pb.n_req);
+    return GP_OK;
+}
+
+// Dataset/segment tables, validation, staging and the stable (depth class,
+// length) partition.
+int enqueue_stage(const Problem& pb, const Staged& st, hipStream_t stream)
+{
+    const int32_t n_blk = (int32_t)((pb.n_programs + kBucketBlock - 1) / kBucketBlock);
+    const unsigned grid_p = (unsigned)((pb.n_programs + 255) / 256);
+    hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, stream, pb.ds_dev, pb.n_ds, pb.one,
+                       pb.req_dev, pb.n_req, pb.one_req, pb.n_programs, pb.n_nodes, pb.max_vars,
+                       pb.max_cases, pb.need_out, st.ds, st.req, st.seg_ds, st.seg_start, st.bad);
     GP_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_class_count, dim3(n_blk), dim3(kBucketBlock), 0, stream, st->cls,
-                       n_programs, n_blk, blk_counts);
+    const int32_t lpt = pb.n_req == 1 ? 1 : 0;
+    hipLaunchKernelGGL(k_prepare, dim3(grid_p), dim3(256), 0, stream, pb.n_programs, pb.allowed,
+                       st.ds, st.req, st.seg_start, pb.n_req, st.bad, lpt, st.code, st.meta,
+                       st.cls, st.pds);
     GP_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_class_scan, dim3(1), dim3(1024), 0, stream, blk_counts, n_blk, blk_base,
-                       st->class_info, st->counters);
+    hipLaunchKernelGGL(k_class_count, dim3(n_blk), dim3(kBucketBlock), 0, stream, st.cls,
+                       pb.n_programs, n_blk, st.blk_counts);
     GP_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_class_scatter, dim3(n_blk), dim3(kBucketBlock), 0, stream, st->cls,
-                       n_programs, n_blk, blk_base, st->order);
+    hipLaunchKernelGGL(k_class_scan, dim3(1), dim3(1024), 0, stream, st.blk_counts, n_blk,
+                       st.blk_base, st.class_info, st.counters);
     GP_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_class_scatter, dim3(n_blk), dim3(kBucketBlock), 0, stream, st.cls,
+                       pb.n_programs, n_blk, st.blk_base, st.order);
+    GP_HIP_TRY(hipGetLastError());
+    return GP_OK;
+}
+
+// The whole evaluation as stream work (no allocation, no synchronization:
+// safe to capture into a graph).
+int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, const Staged& st,
+                 SideStreams& side, hipStream_t stream, CallEvents& ce)
+{
+    int rc;
+    if ((rc = ce.mark(0, stream)) != GP_OK) return rc;
+    if ((rc = enqueue_stage(pb, st, stream)) != GP_OK) return rc;
+    hipLaunchKernelGGL(k_seg_count, dim3((unsigned)pb.n_req), dim3(256), 0, stream, st.cls,
+                       st.seg_start, pb.n_req, pb.n_programs, st.bad, st.seg_cnt);
+    GP_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(64), 0, stream, st.seg_cnt, st.seg_ds, st.ds,
+                       pb.n_req, tu.G, st.seg_pos, st.item_pre);
+    GP_HIP_TRY(hipGetLastError());
+
+    EvalConst ea{};
+    ea.G = tu.G;
+    ea.part_stride = el.stride;
+    ea.max_vars = pb.max_vars;
+    ea.n_seg = pb.n_req;
+    if (tu.concurrent) {
+        GP_HIP_TRY(hipEventRecord(side.fork, stream));
+        for (auto& x : side.s) GP_HIP_TRY(hipStreamWaitEvent(x, side.fork, 0));
+    }
+    for (int c = 0; c < kClasses; ++c) {
+        if ((rc = ce.mark(1 + c, stream)) != GP_OK) return rc;
+        const hipStream_t sc = (tu.concurrent && c > 0) ? side.s[c - 1] : stream;
+        ea.cls = c;
+        const dim3 g(el.grid[c]), b(kWG);
+#define GP_LAUNCH_EVAL(MD, KK)                                                                 \
+        hipLaunchKernelGGL((k_eval<MD, KK>), g, b, el.lds[c], sc, st.code, st.meta, st.order,  \
+                           st.class_info, st.counters + c, st.ds, st.seg_ds, st.seg_cnt,       \
+                           st.seg_pos, st.item_pre, st.part, st.part_bad, ea)
+        if (c == 0) GP_LAUNCH_EVAL(8, 4);
+        else if (c == 1) GP_LAUNCH_EVAL(16, 4);
+        else GP_LAUNCH_EVAL(32, 2);
+#undef GP_LAUNCH_EVAL
+        GP_HIP_TRY(hipGetLastError());
+    }
+    if (tu.concurrent) {
+        for (int i = 0; i < 2; ++i) {
+            GP_HIP_TRY(hipEventRecord(side.join[i], side.s[i]));
+            GP_HIP_TRY(hipStreamWaitEvent(stream, side.join[i], 0));
+        }
+    }
+    ReduceArgs ra{};
+    ra.meta = st.meta; ra.cls = st.cls; ra.pds = st.pds; ra.reqs = st.req;
+    ra.seg_start = st.seg_start; ra.ds = st.ds;
+    ra.part = st.part; ra.part_bad = st.part_bad;
+    ra.n_programs = pb.n_programs; ra.part_stride = el.stride;
+    if ((rc = ce.mark(4, stream)) != GP_OK) return rc;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((pb.n_programs + 255) / 256)), dim3(256), 0,
+                       stream, ra);
+    GP_HIP_TRY(hipGetLastError());
+    if ((rc = ce.mark(5, stream)) != GP_OK) return rc;
+    return GP_OK;
+}
+
+template <int MAXD, int K>
+int launch_predict(const EvalPtrs& p, float* out, int64_t ld_out, const EvalConst& args,
+                   hipStream_t stream, int cus)
+{
+    const size_t lds = (size_t)args.n_vars * kWG * K * sizeof(float);
+    if (lds > 64 * 1024) {
+        GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_predict<MAXD, K>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    int per_cu = 0;
+    GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_predict<MAXD, K>, kWG, lds));
+    if (per_cu < 1) return set_error(GP_E_TOO_LARGE, "n_vars=%d needs %zu bytes of LDS per workgroup", args.n_vars, lds);
+    hipLaunchKernelGGL((k_predict<MAXD, K>), dim3(cus * per_cu), dim3(kWG), lds, stream, p.code,
+                       p.meta, p.order, p.class_info, p.work_counter, p.X, out, ld_out, args);
+    GP_HIP_TRY(hipGetLastError());
+    return GP_OK;
+}
+
+// ----------------------------------------------------------------- autotune
+// In-process cache of tuned scheduling knobs, optionally mirrored in a
+// text file named by GPEVAL_TUNE_CACHE (one "key G wg_per_cu concurrent"
+// line per entry).  Keys describe the workload shape, not its values.
+std::mutex g_tune_mutex;
+std::map<std::string, Tuning> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const Problem& pb)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    char name[64] = {0};
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) snprintf(name, sizeof name, "%s", prop.gcnArchName);
+    for (char* c = name; *c; ++c) if (*c == ' ' || *c == ':') *c = '_';
+    const double mean_len = pb.n_programs ? (double)pb.n_nodes / (double)pb.n_programs : 0.0;
+    int lp = 0;
+    while ((int64_t(1) << (lp + 1)) <= pb.n_programs) ++lp;
+    int lc = 0;
+    while ((int64_t(1) << (lc + 1)) <= pb.max_cases) ++lc;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s/cases2^%d/vars%d/progs2^%d/len%d/reqs%d", name, lc,
+             pb.max_vars, lp, (int)(mean_len + 0.5), pb.n_req);
+    return buf;
+}
+
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("GPEVAL_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char key[200];
+    Tuning t;
+    while (fscanf(f, "%199s %d %d %d", key, &t.G, &t.wg_per_cu, &t.concurrent) == 4)
+        g_tune[key] = t;
+    fclose(f);
+}
+
+void tune_store_locked(const std::string& key, const Tuning& t)
+{
+    g_tune[key] = t;
+    const char* path = getenv("GPEVAL_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d\n", key.c_str(), t.G, t.wg_per_cu, t.concurrent);
+    fclose(f);
+}
+
+}  // namespace
+
+// ================================================================== plans
+struct gp_plan {
+    Problem pb;
+    Tuning tu;
+    EvalLaunch el;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    Staged st;
+    SideStreams side;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+    double tuned_ms = 0.0;
+};
+
+namespace {
+
+void plan_release_graph(gp_plan* p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+// (Re)size the plan's workspace and capture its graph.
+int plan_build(gp_plan* p)
+{
+    int rc = configure_eval(p->pb, p->tu, &p->el);
+    if (rc != GP_OK) return rc;
+    if (p->ws_bytes < p->el.layout.total) {
+        if (p->ws) {
+            GP_HIP_TRY(hipDeviceSynchronize());
+            GP_HIP_TRY(hipFree(p->ws));
+            p->ws = nullptr;
+            p->ws_bytes = 0;
+        }
+        if (hipMalloc(&p->ws, p->el.layout.total) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(GP_E_NO_MEMORY, "plan workspace of %zu bytes", p->el.layout.total);
+        }
+        p->ws_bytes = p->el.layout.total;
+    }
+    p->st = carve(p->ws, p->el.layout);
+    plan_release_graph(p);
+    GP_HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    CallEvents none;
+    (void)none.begin(false);
+    rc = enqueue_eval(p->pb, p->tu, p->el, p->st, p->side, p->cap, none);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->cap, &g);
+    if (rc != GP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (ec != hipSuccess) return set_error(GP_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+    p->graph = g;
+    GP_HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    return GP_OK;
+}
+
+// Time candidate scheduling knobs on the real inputs; keep the fastest.
+int plan_autotune(gp_plan* p, hipStream_t stream)
+{
+    const std::string key = tune_key(p->pb);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            p->tu = it->second;
+            return GP_OK;
+        }
+    }
+    const int Gs[] = {2, 4, 8, 16, 32};
+    hipEvent_t e0, e1;
+    GP_HIP_TRY(hipEventCreate(&e0));
+    GP_HIP_TRY(hipEventCreate(&e1));
+    Tuning best = p->tu;
+    float best_ms = 1e30f;
+    int rc = GP_OK;
+    for (int conc = 0; conc < 2 && rc == GP_OK; ++conc) {
+        for (int G : Gs) {
+            Tuning t;
+            t.G = G;
+            t.concurrent = conc;
+            EvalLaunch el;
+            if ((rc = configure_eval(p->pb, t, &el)) != GP_OK) break;
+            if (el.layout.total > p->ws_bytes) continue;
+            const Staged st = carve(p->ws, el.layout);
+            CallEvents none;
+            (void)none.begin(false);
+            // one warm-up, then the median of three
+            float ms3[3];
+            if ((rc = enqueue_eval(p->pb, t, el, st, p->side, stream, none)) != GP_OK) break;
+            for (int r = 0; r < 3 && rc == GP_OK; ++r) {
+                if (hipEventRecord(e0, stream) != hipSuccess) { rc = set_error(GP_E_HIP, "event"); break; }
+                rc = enqueue_eval(p->pb, t, el, st, p->side, stream, none);
+                if (rc != GP_OK) break;
+                if (hipEventRecord(e1, stream) != hipSuccess) { rc = set_error(GP_E_HIP, "event"); break; }
+                if (hipEventSynchronize(e1) != hipSuccess) { rc = set_error(GP_E_HIP, "sync"); break; }
+                (void)hipEventElapsedTime(&ms3[r], e0, e1);
+            }
+            if (rc != GP_OK) break;
+            std::sort(ms3, ms3 + 3);
+            if (ms3[1] < best_ms) {
+                best_ms = ms3[1];
+                best = t;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != GP_OK) return rc;
+    p->tu = best;
+    p->tuned_ms = best_ms;
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    tune_store_locked(key, best);
+    return GP_OK;
+}
+
+Problem make_problem(const gp_problem* d)
+{
+    Problem pb{};
+    pb.one_req.nodes = d->nodes; pb.one_req.offsets = d->offsets; pb.one_req.consts = d->consts;
+    pb.one_req.n_programs = d->n_programs; pb.one_req.n_nodes = d->n_nodes;
+    pb.one_req.n_consts = d->n_consts;
+    pb.one_req.out_fitness = d->out_fitness; pb.one_req.out_status = d->out_status;
+    pb.one_req.dataset = 0;
+    pb.req_dev = nullptr; pb.n_req = 1;
+    pb.one.X = d->X; pb.one.y = d->y; pb.one.ld_x = d->ld_x; pb.one.n_cases = d->n_cases;
+    pb.one.tax_on_length = d->tax_on_length; pb.one.n_vars = d->n_vars; pb.one.reserved = 0;
+    pb.ds_dev = nullptr; pb.n_ds = 1;
+    pb.n_programs = d->n_programs; pb.n_nodes = d->n_nodes;
+    pb.max_vars = d->n_vars; pb.max_cases = d->n_cases;
+    pb.allowed = d->allowed_op_mask ? d->allowed_op_mask : GP_ALL_OPS;
+    pb.need_out = 1;
+    return pb;
+}
+
+int eval_problem(const Problem& pb, hipStream_t stream)
+{
+    int rc = check_problem(pb);
+    if (rc != GP_OK || pb.n_programs == 0) return rc;
+    Tuning tu;
+    EvalLaunch el;
+    if ((rc = configure_eval(pb, tu, &el)) != GP_OK) return rc;
+    Workspace* w = nullptr;
+    if ((rc = get_workspace(stream, el.layout.total, &w)) != GP_OK) return rc;
+    const Staged st = carve(w->ptr, el.layout);
+    CallEvents ce;
+    if ((rc = ce.begin(true)) != GP_OK) return rc;
+    if ((rc = enqueue_eval(pb, tu, el, st, w->side, stream, ce)) != GP_OK) return rc;
+    ce.commit();
     return GP_OK;
 }
 
@@ -1115,60 +1776,26 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
             double tax_on_length, uint32_t allowed_op_mask,
             double* out_fitness, int32_t* out_status, hipStream_t stream)
 {
-    int rc = check_common(n_programs, n_nodes, n_consts, n_vars, ld_x, n_cases);
-    if (rc != GP_OK) return rc;
-    if (n_programs == 0) return GP_OK;
-    if (!offsets || !out_fitness || !y) return set_error(GP_E_INVALID_ARG, "NULL offsets, y or out_fitness");
-    if ((rc = check_pointers(nodes, n_nodes, consts, n_consts, X, n_vars)) != GP_OK) return rc;
-    if (!std::isfinite(tax_on_length)) return set_error(GP_E_INVALID_ARG, "tax_on_length is not finite");
+    const gp_problem d{nodes, offsets, n_programs, n_nodes, consts, n_consts, X, n_vars, ld_x,
+                       y, n_cases, tax_on_length, allowed_op_mask, out_fitness, out_status};
+    return eval_problem(make_problem(&d), stream);
+}
 
-    int cus = 0;
-    if ((rc = device_cus(&cus)) != GP_OK) return rc;
-    TileShape ts[kClasses];
-    int32_t stride = 1;
-    for (int c = 0; c < kClasses; ++c) {
-        ts[c] = tile_shape(n_cases, class_k(c, n_vars));
-        if (ts[c].n_tiles > stride) stride = ts[c].n_tiles;
-    }
-    CallEvents ce;
-    if ((rc = ce.begin()) != GP_OK) return rc;
-    if ((rc = ce.mark(0, stream)) != GP_OK) return rc;
-    Staged st;
-    rc = stage_population(nodes, offsets, n_programs, n_nodes, consts, n_consts, n_vars,
-                          allowed_op_mask, out_status, stride, stream, &st);
-    if (rc != GP_OK) return rc;
-
-    const int e = scale_exponent(n_cases);
-    EvalPtrs ep{st.code, st.meta, st.order, st.class_info, nullptr, X, y, st.part, st.part_bad};
-    EvalConst ea{};
-    ea.ld_x = ld_x; ea.n_cases = n_cases; ea.n_vars = n_vars; ea.G = 8;
-    ea.part_stride = stride;
-    ea.scale = ldexpf(1.0f, -e);
-    for (int c = 0; c < kClasses; ++c) {
-        if ((rc = ce.mark(1 + c, stream)) != GP_OK) return rc;
-        ea.cls = c;
-        ep.work_counter = st.counters + c;
-        ea.passes = ts[c].passes;
-        ea.n_tiles = ts[c].n_tiles;
-        if (c == 0) rc = launch_eval<8, 4>(ep, ea, stream, cus);
-        else if (c == 1) rc = launch_eval<16, 4>(ep, ea, stream, cus);
-        else rc = launch_eval<32, 2>(ep, ea, stream, cus);
-        if (rc != GP_OK) return rc;
-    }
-
-    ReduceArgs ra{};
-    ra.meta = st.meta; ra.cls = st.cls; ra.part = st.part; ra.part_bad = st.part_bad;
-    ra.out = out_fitness;
-    ra.n_programs = n_programs; ra.part_stride = stride;
-    for (int c = 0; c < kClasses; ++c) ra.n_tiles[c] = ts[c].n_tiles;
-    ra.unscale = ldexp(1.0, 2 * e) / (double)n_cases;
-    ra.tax = tax_on_length;
-    if ((rc = ce.mark(4, stream)) != GP_OK) return rc;
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((n_programs + 255) / 256)), dim3(256), 0, stream, ra);
-    GP_HIP_TRY(hipGetLastError());
-    if ((rc = ce.mark(5, stream)) != GP_OK) return rc;
-    ce.commit();
-    return GP_OK;
+int gp_eval_batched(const gp_request* requests_dev, int32_t n_requests,
+                    const gp_dataset* datasets_dev, int32_t n_datasets,
+                    int64_t total_programs, int64_t total_nodes,
+                    int32_t max_n_vars, int64_t max_n_cases, uint32_t allowed_op_mask,
+                    hipStream_t stream)
+{
+    if (!requests_dev) return set_error(GP_E_INVALID_ARG, "requests_dev is NULL");
+    Problem pb{};
+    pb.req_dev = requests_dev; pb.n_req = n_requests;
+    pb.ds_dev = datasets_dev; pb.n_ds = n_datasets;
+    pb.n_programs = total_programs; pb.n_nodes = total_nodes;
+    pb.max_vars = max_n_vars; pb.max_cases = max_n_cases;
+    pb.allowed = allowed_op_mask ? allowed_op_mask : GP_ALL_OPS;
+    pb.need_out = 1;
+    return eval_problem(pb, stream);
 }
 
 int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
@@ -1188,10 +1815,24 @@ int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs
         return set_error(GP_E_TOO_LARGE, "n_programs * n_cases too large for one gp_predict call");
     int cus = 0;
     if ((rc = device_cus(&cus)) != GP_OK) return rc;
-    Staged st;
-    rc = stage_population(nodes, offsets, n_programs, n_nodes, consts, n_consts, n_vars,
-                          allowed_op_mask, out_status, 0, stream, &st);
-    if (rc != GP_OK) return rc;
+    Problem pb{};
+    pb.one_req.nodes = nodes; pb.one_req.offsets = offsets; pb.one_req.consts = consts;
+    pb.one_req.n_programs = n_programs; pb.one_req.n_nodes = n_nodes;
+    pb.one_req.n_consts = n_consts; pb.one_req.out_status = out_status;
+    pb.n_req = 1;
+    pb.one.X = X; pb.one.y = reinterpret_cast<const float*>(out);   // any non-null: unused
+    pb.one.ld_x = ld_x; pb.one.n_cases = n_cases; pb.one.tax_on_length = 0.0;
+    pb.one.n_vars = n_vars;
+    pb.n_ds = 1;
+    pb.n_programs = n_programs; pb.n_nodes = n_nodes;
+    pb.max_vars = n_vars; pb.max_cases = n_cases;
+    pb.allowed = allowed_op_mask ? allowed_op_mask : GP_ALL_OPS;
+    pb.need_out = 0;
+    const Layout L = make_layout(n_programs, n_nodes, 0, 1, 1);
+    Workspace* w = nullptr;
+    if ((rc = get_workspace(stream, L.total, &w)) != GP_OK) return rc;
+    const Staged st = carve(w->ptr, L);
+    if ((rc = enqueue_stage(pb, st, stream)) != GP_OK) return rc;
     EvalPtrs ep{st.code, st.meta, st.order, st.class_info, nullptr, X, nullptr, nullptr, nullptr};
     EvalConst ea{};
     ea.ld_x = ld_x; ea.n_cases = n_cases; ea.n_vars = n_vars;
@@ -1207,6 +1848,94 @@ int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs
                        n_cases, out, ld_out);
     GP_HIP_TRY(hipGetLastError());
     return GP_OK;
+}
+
+int gp_plan_create(gp_plan** plan, const gp_problem* problem, const gp_tuning* tuning,
+                   int autotune, hipStream_t stream)
+{
+    if (!plan || !problem) return set_error(GP_E_INVALID_ARG, "NULL plan or problem");
+    *plan = nullptr;
+    const Problem pb = make_problem(problem);
+    int rc = check_problem(pb);
+    if (rc != GP_OK) return rc;
+    if (pb.n_programs == 0) return set_error(GP_E_INVALID_ARG, "a plan needs n_programs >= 1");
+    gp_plan* p = new gp_plan();
+    p->pb = pb;
+    if (tuning) {
+        if (tuning->programs_per_item < 0 || tuning->programs_per_item > 64 || tuning->wg_per_cu < 0) {
+            delete p;
+            return set_error(GP_E_INVALID_ARG, "tuning out of range");
+        }
+        if (tuning->programs_per_item > 0) p->tu.G = tuning->programs_per_item;
+        p->tu.wg_per_cu = tuning->wg_per_cu;
+        p->tu.concurrent = tuning->concurrent_classes != 0;
+    }
+    if (hipGetDevice(&p->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess ||
+        p->side.create() != GP_OK) {
+        gp_plan_destroy(p);
+        return set_error(GP_E_HIP, "plan stream setup failed");
+    }
+    // workspace for the largest candidate configuration
+    EvalLaunch el;
+    Tuning big = p->tu;
+    big.G = 32;
+    if ((rc = configure_eval(pb, big, &el)) != GP_OK ||
+        hipMalloc(&p->ws, el.layout.total) != hipSuccess) {
+        (void)hipGetLastError();
+        gp_plan_destroy(p);
+        return rc != GP_OK ? rc : set_error(GP_E_NO_MEMORY, "plan workspace");
+    }
+    p->ws_bytes = el.layout.total;
+    if (autotune && (rc = plan_autotune(p, stream)) != GP_OK) {
+        gp_plan_destroy(p);
+        return rc;
+    }
+    if ((rc = plan_build(p)) != GP_OK) {
+        gp_plan_destroy(p);
+        return rc;
+    }
+    *plan = p;
+    return GP_OK;
+}
+
+int gp_plan_launch(gp_plan* plan, hipStream_t stream)
+{
+    if (!plan || !plan->exec) return set_error(GP_E_INVALID_ARG, "plan is not built");
+    GP_HIP_TRY(hipGraphLaunch(plan->exec, stream));
+    return GP_OK;
+}
+
+int gp_plan_update(gp_plan* plan, const gp_problem* problem)
+{
+    if (!plan || !problem) return set_error(GP_E_INVALID_ARG, "NULL plan or problem");
+    const Problem pb = make_problem(problem);
+    int rc = check_problem(pb);
+    if (rc != GP_OK) return rc;
+    if (pb.n_programs == 0) return set_error(GP_E_INVALID_ARG, "a plan needs n_programs >= 1");
+    plan->pb = pb;
+    return plan_build(plan);
+}
+
+int gp_plan_get_tuning(const gp_plan* plan, gp_tuning* out)
+{
+    if (!plan || !out) return set_error(GP_E_INVALID_ARG, "NULL plan or out");
+    out->programs_per_item = plan->tu.G;
+    out->wg_per_cu = plan->tu.wg_per_cu;
+    out->concurrent_classes = plan->tu.concurrent;
+    return GP_OK;
+}
+
+void gp_plan_destroy(gp_plan* plan)
+{
+    if (!plan) return;
+    if (plan->cap) (void)hipStreamSynchronize(plan->cap);
+    (void)hipDeviceSynchronize();
+    plan_release_graph(plan);
+    plan->side.destroy();
+    if (plan->cap) (void)hipStreamDestroy(plan->cap);
+    if (plan->ws) (void)hipFree(plan->ws);
+    delete plan;
 }
 
 int gp_timing_enable(int on)
@@ -1249,14 +1978,50 @@ int gp_timing_read(double* ms, int64_t* n_calls)
     return rc;
 }
 
+int gp_workspace_size(int64_t n_programs, int64_t n_nodes, int32_t n_requests,
+                      int32_t n_datasets, int32_t max_n_vars, int64_t max_n_cases,
+                      size_t* bytes)
+{
+    if (!bytes) return set_error(GP_E_INVALID_ARG, "bytes is NULL");
+    if (n_programs < 0 || n_nodes < 0 || n_requests < 1 || n_datasets < 1 || max_n_vars < 0 ||
+        max_n_cases < 1)
+        return set_error(GP_E_INVALID_ARG, "sizes out of range");
+    int32_t stride = 1;
+    for (int c = 0; c < kClasses; ++c) {
+        const TileShape t = tile_shape(max_n_cases, class_k(c, max_n_vars));
+        if (t.n_tiles > stride) stride = t.n_tiles;
+    }
+    const size_t need = make_layout(n_programs, n_nodes, stride, n_datasets, n_requests).total;
+    *bytes = need + need / 4;      // the growth slack get_workspace adds
+    return GP_OK;
+}
+
+}  // extern "C"
+
+// Drops the cached workspace of one stream (the server calls it before it
+// destroys its streams).  Not exported.
+__attribute__((visibility("hidden"))) void gp_internal_release_stream_workspace(hipStream_t stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_ws_mutex);
+    auto it = g_ws.find(std::make_pair(dev, stream));
+    if (it == g_ws.end()) return;
+    (void)hipStreamSynchronize(stream);
+    if (it->second.ptr) (void)hipFree(it->second.ptr);
+    it->second.side.destroy();
+    g_ws.erase(it);
+}
+
+extern "C" {
+
 void gp_release_workspaces(void)
 {
     std::lock_guard<std::mutex> lk(g_ws_mutex);
     for (auto& kv : g_ws) {
-        if (kv.second.ptr) {
-            (void)hipStreamSynchronize(kv.first.second);
-            (void)hipFree(kv.second.ptr);
-        }
+        (void)hipStreamSynchronize(kv.first.second);
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+        kv.second.side.destroy();
     }
     g_ws.clear();
 }

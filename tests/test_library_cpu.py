@@ -104,3 +104,34 @@ def test_no_oracle_in_product_path():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "gp_oracle" not in text, fn
+
+
+def test_workspace_size_model(L):
+    ws = gp.workspace_size
+    base = ws(0, 0)
+    assert ws(1000, 0) > base and ws(0, 100000) > base
+    # more programs and nodes never need less
+    assert ws(2000, 50000) >= ws(1000, 50000) >= ws(1000, 40000)
+    # more cases means more tiles per program (at most 32)
+    assert ws(1000, 0, max_n_cases=1 << 20) > ws(1000, 0, max_n_cases=1024)
+    assert ws(1000, 0, max_n_cases=1 << 30) == ws(1000, 0, max_n_cases=1 << 20)
+    b = ctypes.c_size_t()
+    assert L.gp_workspace_size(-1, 0, 1, 1, 1, 1, ctypes.byref(b)) == gp.GP_E_INVALID_ARG
+    assert L.gp_workspace_size(1, 0, 0, 1, 1, 1, ctypes.byref(b)) == gp.GP_E_INVALID_ARG
+
+
+def test_batched_and_server_reject_bad_arguments(L):
+    c = ctypes.c_void_p(1)
+    # NULL tables / counts < 1 fail before any device work
+    assert L.gp_eval_batched(None, 1, c, 1, 1, 1, 1, 1, 0, None) == gp.GP_E_INVALID_ARG
+    assert L.gp_eval_batched(c, 1, None, 1, 1, 1, 1, 1, 0, None) == gp.GP_E_INVALID_ARG
+    assert L.gp_eval_batched(c, 0, c, 1, 1, 1, 1, 1, 0, None) == gp.GP_E_INVALID_ARG
+    assert L.gp_eval_batched(c, 5000, c, 1, 1, 1, 1, 1, 0, None) == gp.GP_E_TOO_LARGE
+    h = ctypes.c_void_p()
+    cfg = gp.GPServerConfig(1 << 20, 0, 0, 0, 0, 0, 0, 0)          # budget below 16 MiB
+    assert L.gp_server_create(ctypes.byref(h), ctypes.byref(cfg)) == gp.GP_E_INVALID_ARG
+    cfg = gp.GPServerConfig(0, 0, 0, 0, 9, 0, 0, 0)                # too many streams
+    assert L.gp_server_create(ctypes.byref(h), ctypes.byref(cfg)) == gp.GP_E_INVALID_ARG
+    t = ctypes.c_int64()
+    assert L.gp_server_submit(None, 0, None, 0, c, 0, None, 0, None, None,
+                              ctypes.byref(t)) == gp.GP_E_INVALID_ARG
