@@ -494,31 +494,40 @@ __global__ __launch_bounds__(kBucketBlock) void k_class_scatter(
 }
 
 // Programs of each depth class inside each segment: seg_cnt[c * n_seg + s].
-// (Segment bounds are only trusted after k_tables accepted the table; they
-// are clamped to the program range regardless.)
-__global__ __launch_bounds__(256) void k_seg_count(const uint8_t* __restrict__ cls,
+// One thread per (class, segment).  With several segments the partition
+// keeps each class in program order, so a segment's programs of class c are
+// the class's entries between two lower bounds of the segment's program
+// range; a single segment holds the whole class.
+__global__ __launch_bounds__(256) void k_seg_count(const int32_t* __restrict__ order,
+                                                   const int32_t* __restrict__ class_info,
                                                    const int64_t* __restrict__ seg_start,
-                                                   int32_t n_seg, int64_t n_programs,
+                                                   int32_t n_seg,
                                                    const int32_t* __restrict__ tables_bad,
                                                    int32_t* __restrict__ seg_cnt)
 {
-    __shared__ int cnt[kClasses];
-    const int sgi = blockIdx.x;
-    if (threadIdx.x < kClasses) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    int local[kClasses] = {0, 0, 0};
-    int64_t p0 = seg_start[sgi], p1 = seg_start[sgi + 1];
-    if (*tables_bad) p0 = p1 = 0;
-    p0 = p0 < 0 ? 0 : (p0 > n_programs ? n_programs : p0);
-    p1 = p1 < p0 ? p0 : (p1 > n_programs ? n_programs : p1);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        const int k = cls[p];
-        if (k < kKeys) local[k / kLenBuckets] += 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kClasses * n_seg) return;
+    const int c = i / n_seg, sg = i - c * n_seg;
+    const int32_t* __restrict__ ord = order + class_info[2 * c];
+    const int n = class_info[2 * c + 1];
+    int cnt;
+    if (*tables_bad) {
+        cnt = 0;                         // no program was staged
+    } else if (n_seg == 1) {
+        cnt = n;
+    } else {
+        // first position whose program id is >= v
+        auto lower = [&](int64_t v) {
+            int lo = 0, hi = n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((int64_t)ord[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            return lo;
+        };
+        cnt = lower(seg_start[sg + 1]) - lower(seg_start[sg]);
     }
-    for (int c = 0; c < kClasses; ++c)
-        if (local[c]) atomicAdd(&cnt[c], local[c]);
-    __syncthreads();
-    if (threadIdx.x < kClasses) seg_cnt[threadIdx.x * n_seg + sgi] = cnt[threadIdx.x];
+    seg_cnt[i] = cnt;
 }
 
 // Per class (one thread each): where each segment's programs start inside
@@ -874,7 +883,16 @@ __global__ __launch_bounds__(kWG) void k_eval(
             if (pre_c[mid] <= item) sl = mid; else sh = mid - 1;
         }
         const int d = seg_ds[sl];
-        const DevDataset D = ds[d];
+        // fields one by one: a struct copy indexed by the class would live
+        // in scratch memory
+        const DevDataset* __restrict__ Dp = ds + d;
+        const float* __restrict__ Xd = Dp->X;
+        const float* __restrict__ yd = Dp->y;
+        const int64_t ld_x = Dp->ld_x;
+        const int64_t n_cases = Dp->n_cases;
+        const int n_vars = Dp->n_vars;
+        const float scale = Dp->scale;
+        const int passes = Dp->passes[c];
         const int count = cnt_c[sl];
         const int n_groups = (count + a.G - 1) / a.G;
         const uint32_t local = item - pre_c[sl];
@@ -883,18 +901,17 @@ __global__ __launch_bounds__(kWG) void k_eval(
         const int g0 = grp * a.G;
         const int gn = min(a.G, count - g0);
         const int obase = cstart + pos_c[sl] + g0;
-        const int passes = D.passes[c];
 
         for (int pass = 0; pass < passes; ++pass) {
             const int64_t sub_idx = (int64_t)tile * passes + pass;
             const int64_t base = sub_idx * SUB;
-            if (base >= D.n_cases) break;
+            if (base >= n_cases) break;
             if (sub_idx != staged || d != staged_d) {
                 __syncthreads();
-                for (int i = tid; i < D.n_vars * SUB; i += kWG) {
+                for (int i = tid; i < n_vars * SUB; i += kWG) {
                     const int v = i / SUB, cc = i - v * SUB;
                     const int64_t gi = base + cc;
-                    xt[i] = gi < D.n_cases ? D.X[(int64_t)v * D.ld_x + gi] : 0.f;
+                    xt[i] = gi < n_cases ? Xd[(int64_t)v * ld_x + gi] : 0.f;
                 }
                 staged = sub_idx;
                 staged_d = d;
@@ -905,8 +922,8 @@ __global__ __launch_bounds__(kWG) void k_eval(
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int64_t gi = base + lo + j * kWG;
-                live[j] = gi < D.n_cases;
-                yv[j] = live[j] ? D.y[gi] : 0.f;
+                live[j] = gi < n_cases;
+                yv[j] = live[j] ? yd[gi] : 0.f;
             }
 
             for (int g = 0; g < gn; ++g) {
@@ -923,7 +940,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
                     if (live[j]) {
                         const float f = tos[j];
                         bad |= !__builtin_isfinite(f);
-                        const float r = (f - yv[j]) * D.scale;
+                        const float r = (f - yv[j]) * scale;
                         float s, e;
                         two_sum(hi, r * r, s, e);
                         hi = s;
@@ -1440,8 +1457,9 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
     int rc;
     if ((rc = ce.mark(0, stream)) != GP_OK) return rc;
     if ((rc = enqueue_stage(pb, st, stream)) != GP_OK) return rc;
-    hipLaunchKernelGGL(k_seg_count, dim3((unsigned)pb.n_req), dim3(256), 0, stream, st.cls,
-                       st.seg_start, pb.n_req, pb.n_programs, st.bad, st.seg_cnt);
+    hipLaunchKernelGGL(k_seg_count, dim3((unsigned)((kClasses * pb.n_req + 255) / 256)), dim3(256),
+                       0, stream, st.order, st.class_info, st.seg_start, pb.n_req, st.bad,
+                       st.seg_cnt);
     GP_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(64), 0, stream, st.seg_cnt, st.seg_ds, st.ds,
                        pb.n_req, tu.G, st.seg_pos, st.item_pre);
