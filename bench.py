@@ -1,15 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of batched fitness evaluation on one MI355X.
 
-Workload (default): the full-generation configuration -- 100,000 random
-postfix programs (lengths uniform 3..64, ops + - * protected-/ sin cos exp
-protected-log sqrt|.| abs), 5 input variables, 4,096 fitness cases, MSE plus
-a 1e-3 per-node length tax.  Inputs are resident in HBM before the timed
-region; one step = one complete gp_eval call (device-side validation and
-staging, depth-class partition, evaluation, fp64 reduction).
+Workloads (seeded synthetic inputs, recipes in paper_2607_06731_amd/synth.py):
+  plain       1,000 programs (len U{3..32}) x 1,024 cases, 3 vars
+  generation  100,000 programs (len U{3..64}) x 4,096 cases, 5 vars,
+              ops + - * protected-/ sin cos exp protected-log sqrt|.| abs,
+              MSE + 1e-3 per-node length tax                    (default)
+  uneven      1,000,000 programs (len clip(Geom(1/24), 3, 128)) x 16,384
+              cases, 10 vars
+  precision   50,000 programs (len U{3..64}) x 1,048,576 cases, 3 vars
+  serving     64 evolutionary runs as closed-loop clients of the scoring
+              server (populations log-U[1k, 200k], len U{3..128}, datasets
+              of 256..65,536 cases and 1..20 vars), continuous batching
+              against one launch per request
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one
-GPU only.
+Inputs are resident in HBM before the timed region; one step = one complete
+gp_eval call (device-side validation and staging, depth-class partition,
+evaluation, fp64 reduction).  Prints one JSON line.  --gpus above 1 is
+refused: this build runs on one GPU only.
+
+--copy-bytes N runs only a plain device-to-device copy of N bytes (the
+calibration kernel for the HBM traffic counters) and exits.
 """
 import argparse
 import json
@@ -22,6 +33,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_LANE_OPS = 256 * 64 * 2.4e9      # fp32 VALU lane-slots per second (non-packed)
+WORKLOADS = {"plain": 1, "generation": 2, "uneven": 3, "precision": 4}
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -61,33 +73,33 @@ def cpu_baseline(w, budget_s=15.0):
                       % (sub.n_programs, P, w.data.n_cases, node_evals, dt)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); "
-              "got --gpus %d" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def copy_calibration(n_bytes):
+    import torch
+    a = torch.empty(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel() * 4}), flush=True)
 
+
+def describe(name, w):
+    lens = w.pop.lengths
+    return ("%s: %d programs (mean length %.1f) x %d cases, %d vars"
+            % (name, w.pop.n_programs, lens.mean(), w.data.n_cases, w.data.n_vars))
+
+
+def throughput(args):
     import numpy as np
     import torch
 
     import paper_2607_06731_amd as gp
     from paper_2607_06731_amd import synth
 
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        sys.exit(1)
     gp.lib()
-    w = synth.make_config(args.config)
-    print("[bench] config %d: %d programs, %d nodes, %d cases, %d vars"
-          % (args.config, w.pop.n_programs, int(w.pop.offsets[-1]), w.data.n_cases,
-             w.data.n_vars), file=sys.stderr, flush=True)
+    w = synth.make_config(WORKLOADS[args.workload])
+    print("[bench] %s" % describe(args.workload, w), file=sys.stderr, flush=True)
     pop = gp.DevicePopulation(w.pop.nodes, w.pop.offsets, w.pop.consts)
     data = gp.DeviceDataset(w.data.X, w.data.y)
     out = torch.empty(pop.n_programs, dtype=torch.float64, device="cuda")
@@ -149,10 +161,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "config%d: %d programs x %d cases, %d vars, mean len %.1f"
-                               % (args.config, w.pop.n_programs, w.data.n_cases,
-                                  w.data.n_vars, lens.mean()),
-                   "node_evals_per_step": node_evals},
+        "config": {"workload": describe(args.workload, w), "node_evals_per_step": node_evals},
         "frac_of_fp32_valu_lane_peak": round(gpops * 1e9 / PEAK_LANE_OPS, 4),
         "phase_ms": phase_ms,
         "roofline": roofline,
@@ -162,6 +171,171 @@ def main():
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)
+
+
+# ------------------------------------------------------------------ serving
+def serving_workload(n_runs=64, seed=0):
+    """Datasets of the runs and one population per run.  Populations are
+    slices of one master population (len U{3..128}, 20 variables) with
+    variable indices folded into each run's range; only their shapes matter
+    for timing."""
+    import numpy as np
+
+    from paper_2607_06731_amd import synth
+    runs = synth.make_serving_runs(n_runs, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    P_max = 200_000
+    master = synth.sample_programs(rng, rng.integers(3, 129, P_max), 20, synth.UNARY_2)
+    pops = []
+    for r in runs:
+        P = int(np.exp(rng.uniform(np.log(1000), np.log(P_max + 1))))
+        P = min(max(P, 1000), P_max)
+        start = int(rng.integers(0, P_max - P + 1))
+        sub = master.take(np.arange(start, start + P))
+        nodes = sub.nodes.copy()
+        is_load = (nodes & 0xFF) == synth.LOAD
+        nodes[is_load] = synth.LOAD | (((nodes[is_load] >> 8) % r.data.n_vars) << 8)
+        pops.append(synth.Population(nodes, sub.offsets, sub.consts))
+    return runs, pops
+
+
+def drive(srv, ids, pops, think_ms, warmup_s, run_s, seed):
+    """Closed-loop clients: each run has one request outstanding; after its
+    result returns it waits Exp(think_ms) (breeding on the host) and
+    submits again.  Statistics cover the run_s window after warm-up."""
+    import heapq
+
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    n = len(pops)
+    now = time.perf_counter()
+    due = [(now + (rng.exponential(think_ms) * 1e-3 if think_ms > 0 else 0.0), r)
+           for r in range(n)]
+    heapq.heapify(due)
+    owner = {}
+    t_warm = now + warmup_s
+    t_end = t_warm + run_s
+    reset = False
+    while True:
+        now = time.perf_counter()
+        if not reset and now >= t_warm:
+            srv.reset_stats()
+            reset = True
+        if now >= t_end:
+            break
+        while due and due[0][0] <= now:
+            _, r = heapq.heappop(due)
+            p = pops[r]
+            owner[srv.submit(ids[r], p.nodes, p.offsets, p.consts)] = r
+        wait_ms = 5.0
+        if due:
+            wait_ms = min(wait_ms, max(0.0, (due[0][0] - now) * 1e3))
+        for t, rc, _, _ in srv.poll(timeout_ms=wait_ms):
+            if rc != 0:
+                raise RuntimeError("request failed with %d" % rc)
+            r = owner.pop(t)
+            nxt = time.perf_counter() + (rng.exponential(think_ms) * 1e-3 if think_ms > 0 else 0.0)
+            heapq.heappush(due, (nxt, r))
+    st = srv.stats()
+    # let outstanding requests finish before the server goes away
+    while owner:
+        for t, _, _, _ in srv.poll(timeout_ms=100.0):
+            owner.pop(t, None)
+    return st
+
+
+def serving(args):
+    import paper_2607_06731_amd as gp
+
+    gp.lib()
+    t0 = time.perf_counter()
+    runs, pops = serving_workload()
+    print("[bench] serving: %d runs, %d programs in flight at most, built in %.1f s"
+          % (len(runs), sum(p.n_programs for p in pops), time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    tax = 1e-3
+    modes = {"batched": {}, "one_launch_per_request": {"one_launch_per_request": True}}
+
+    def summary(st):
+        w = st["wall_ms"] * 1e-3
+        return {"gpops": round(st["node_evals"] / w / 1e9, 3),
+                "requests_per_s": round(st["completed"] / w, 2),
+                "p50_ms": round(st["latency_p50_ms"], 3), "p99_ms": round(st["latency_p99_ms"], 3),
+                "max_ms": round(st["latency_max_ms"], 3), "completed": st["completed"],
+                "launches": st["launches"], "chunks": st["chunks_launched"],
+                "gpu_busy_frac": round(st["busy_ms"] / st["wall_ms"], 3)}
+
+    res = {}
+    cap = {}
+    for name, kw in modes.items():
+        with gp.Server(device_budget_bytes=args.serve_budget_mib << 20, **kw) as srv:
+            ids = [srv.add_dataset(r.data.X, r.data.y, tax) for r in runs]
+            st = drive(srv, ids, pops, 0.0, 2.0, args.serve_seconds, seed=11)
+            res[name] = {"saturated": summary(st)}
+            cap[name] = st["completed"] / (st["wall_ms"] * 1e-3)
+            print("[bench] %s saturated: %s" % (name, res[name]["saturated"]),
+                  file=sys.stderr, flush=True)
+    # offered load: a fraction of the batched capacity (requests/s), the same
+    # seeded think times for both modes
+    think_ms = len(runs) / (args.serve_load * cap["batched"]) * 1e3
+    for name, kw in modes.items():
+        with gp.Server(device_budget_bytes=args.serve_budget_mib << 20, **kw) as srv:
+            ids = [srv.add_dataset(r.data.X, r.data.y, tax) for r in runs]
+            st = drive(srv, ids, pops, think_ms, 2.0, args.serve_seconds, seed=12)
+            res[name]["load_%.1f" % args.serve_load] = summary(st)
+            print("[bench] %s at load %.1f: %s" % (name, args.serve_load,
+                                                  res[name]["load_%.1f" % args.serve_load]),
+                  file=sys.stderr, flush=True)
+    b = res["batched"]["saturated"]["gpops"]
+    o = res["one_launch_per_request"]["saturated"]["gpops"]
+    rec = {
+        "metric": "serving throughput (GPOPs) with p50/p99 scoring latency",
+        "value": b,
+        "unit": "GPOPs",
+        "n_gpus": 1,
+        "steps": None,
+        "warmup": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving: %d closed-loop runs, %.0f s per point, budget %d MiB"
+                               % (len(runs), args.serve_seconds, args.serve_budget_mib),
+                   "think_ms_at_load": round(think_ms, 2)},
+        "batched_over_one_launch_per_request": round(b / o, 3) if o else None,
+        "serving": res,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="generation", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-load", type=float, default=0.6)
+    ap.add_argument("--serve-budget-mib", type=int, default=8192)
+    ap.add_argument("--copy-bytes", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); "
+              "got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes)
+    elif args.workload == "serving":
+        serving(args)
+    else:
+        throughput(args)
 
 
 if __name__ == "__main__":

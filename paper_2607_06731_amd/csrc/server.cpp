@@ -283,8 +283,35 @@ void complete(gp_server* s, const ReqPtr& R, int rc)
     s->done_rc[R->ticket] = rc;
 }
 
-// Stage and upload every waiting request that fits, oldest first.
-int admit(gp_server* s, bool* progress)
+// Copy a request's programs into its pinned block (offsets rebased per
+// chunk) and queue the upload on the copy stream.  Scheduler thread only.
+int stage(gp_server* s, Request& R)
+{
+    char* h = s->h_arena + R.host_off;
+    std::memcpy(h, R.nodes, (size_t)R.n_nodes * 4);
+    int64_t* ho = reinterpret_cast<int64_t*>(h + R.o_offs);
+    size_t k = 0;
+    for (const Chunk& c : R.chunks) {
+        const int64_t base = R.offsets[c.b];
+        for (int64_t p = c.b; p <= c.e; ++p) ho[k++] = R.offsets[p] - base;
+    }
+    if (R.n_consts) std::memcpy(h + R.o_consts, R.consts, (size_t)R.n_consts * 4);
+    SRV_HIP(hipMemcpyAsync(s->d_arena + R.dev_off, h, R.o_out, hipMemcpyHostToDevice, s->up));
+    if (s->free_events.empty()) {
+        hipEvent_t e = nullptr;
+        SRV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        s->free_events.push_back(e);
+    }
+    R.uploaded = s->free_events.back();
+    s->free_events.pop_back();
+    SRV_HIP(hipEventRecord(R.uploaded, s->up));
+    return GP_OK;
+}
+
+// Admit every waiting request that fits, oldest first.  The staging copy
+// runs with the lock released: only this thread touches the arenas, the
+// ready list and admitted requests.
+int admit(gp_server* s, std::unique_lock<std::mutex>& lk, bool* progress)
 {
     while (!s->waiting.empty()) {
         const ReqPtr R = s->waiting.front();
@@ -297,26 +324,12 @@ int admit(gp_server* s, bool* progress)
         R->dev_off = od;
         R->host_off = oh;
         R->admitted = true;
-        char* h = s->h_arena + oh;
-        std::memcpy(h, R->nodes, (size_t)R->n_nodes * 4);
-        int64_t* ho = reinterpret_cast<int64_t*>(h + R->o_offs);
-        size_t k = 0;
-        for (const Chunk& c : R->chunks) {
-            const int64_t base = R->offsets[c.b];
-            for (int64_t p = c.b; p <= c.e; ++p) ho[k++] = R->offsets[p] - base;
-        }
-        if (R->n_consts) std::memcpy(h + R->o_consts, R->consts, (size_t)R->n_consts * 4);
-        SRV_HIP(hipMemcpyAsync(s->d_arena + od, h, R->o_out, hipMemcpyHostToDevice, s->up));
-        if (s->free_events.empty()) {
-            hipEvent_t e = nullptr;
-            SRV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-            s->free_events.push_back(e);
-        }
-        R->uploaded = s->free_events.back();
-        s->free_events.pop_back();
-        SRV_HIP(hipEventRecord(R->uploaded, s->up));
         s->waiting.pop_front();
-        s->ready.push_back(R);
+        lk.unlock();
+        const int rc = stage(s, *R);
+        lk.lock();
+        s->ready.push_back(R);          // on failure the server fails it below
+        if (rc != GP_OK) return rc;
         *progress = true;
     }
     return GP_OK;
@@ -525,7 +538,7 @@ void scheduler(gp_server* s)
                     rc = fail(GP_E_HIP, "launch failed: %s", hipGetErrorString(q));
                 }
             }
-            if (rc == GP_OK) rc = admit(s, &progress);
+            if (rc == GP_OK) rc = admit(s, lk, &progress);
             for (int i = 0; i < (int)s->slots.size() && rc == GP_OK; ++i) {
                 if (s->slots[i].busy || s->ready.empty()) continue;
                 rc = launch(s, i);
