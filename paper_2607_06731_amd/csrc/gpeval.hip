@@ -1,23 +1,30 @@
 // gpeval.hip -- gfx950 kernels and C ABI of the batched fitness evaluator.
 //
 // Path of one gp_eval call (all on the caller's stream):
-//   k_prepare        one thread per program: validate (GCL stack discipline,
+//   k_tables         one workgroup: check the dataset and request tables, lay
+//                    the requests out back to back, derive tile shapes.
+//   k_validate       one thread per program: validate (GCL stack discipline,
 //                    32-element limit, opcode/operand ranges, allowed ops),
-//                    stage each node as 8 bytes {op | read-slot | write-slot,
-//                    var index or constant bits}, record length, maximum
-//                    depth and depth class.
-//   k_class_count /  stable partition of program ids by (depth class, length
-//   k_class_scan /   bucket): each depth class (max depth <= 8, <= 16, <= 32)
-//   k_class_scatter  runs a kernel whose register stack is only as deep as
-//                    needed, and within a class the longest programs come
-//                    first (longest-processing-time order for the work queue).
+//                    count staged instructions, depth class and partition
+//                    key; per-block key counts and staged sizes.
+//   k_class_scan     one workgroup: scans of both; class ranges.
+//   k_stage          one thread per program: stage each instruction as 16
+//                    bytes {flags | op, payload, read slot or leaf kind,
+//                    write slot} at a range of its own, folding a leaf into
+//                    the operator after it; stable scatter of program ids by
+//                    (depth class, length band): each depth class (max
+//                    depth <= 8, <= 16, <= 32) runs a kernel whose register
+//                    stack is only as deep as needed, longest programs first.
+//   k_seg_count /    per (class, request): program counts, positions and
+//   k_seg_scan       work-item prefixes.
 //   k_eval<MAXD,K>   persistent workgroups pull (program group, case tile)
-//                    items from an atomic counter; the case tile's inputs
-//                    are staged in LDS; each wavefront runs one program at a
-//                    time over K cases per lane with the value stack in
-//                    VGPRs; residual, scaled square and compensated (TwoSum)
-//                    accumulation are fused; wave shuffles then LDS reduce
-//                    to one {hi, lo, bad} partial per (program, tile).
+//                    items from an atomic counter; the tile's inputs and
+//                    targets are staged in LDS; each wavefront takes the
+//                    group's programs one at a time and runs one over the
+//                    64*K cases of the sub-tile (K per lane) with the value
+//                    stack in VGPRs; residual, scaled square and compensated
+//                    (TwoSum) accumulation are fused; a wave shuffle tree
+//                    gives one {hi, lo, bad} partial per (program, tile).
 //   k_reduce         one thread per program: fp64 sum of its tile partials
 //                    in fixed order, unscaling, tax, classification.
 //
@@ -92,22 +99,23 @@ constexpr uint32_t kNoSlot = 0xFFu;      // staged write slot: nothing to save
 constexpr int kBucketBlock = 1024;       // programs per partition block
 constexpr int kMaxRequests = 4096;       // requests per batched call (tables are scanned by one workgroup)
 
-// Per-program record written by k_prepare.
+// Per-program record written by the staging passes.
 struct ProgMeta {
-    int64_t start;      // first staged slot (request node base + program offset)
+    int64_t start;      // first staged instruction
     int32_t len;        // node count (the length taxed)
-    int32_t slen;       // staged instruction count (<= len)
+    int32_t slen;       // staged instructions (0: not staged)
 };
 static_assert(sizeof(ProgMeta) == 16, "ProgMeta layout");
 
-// Staged-only opcodes (superinstructions).  A leaf directly followed by a
+// Staged instruction flags (see k_stage).  A leaf directly followed by a
 // binary op folds into "top = top OP leaf"; a leaf directly followed by a
 // unary op folds into "save top; top = f(leaf)".  The leaf's load and the
 // op still run for every case: only the push/pop and one dispatch go.
-constexpr uint32_t kOpBinVar = 12;      // 12..15: ADD..DIV, leaf = X[var]
-constexpr uint32_t kOpBinConst = 16;    // 16..19: ADD..DIV, leaf = constant
-constexpr uint32_t kOpUnVar = 20;       // 20..25: SIN..ABS of X[var]
-constexpr uint32_t kOpUnConst = 26;     // 26..31: SIN..ABS of a constant
+constexpr uint32_t kFPush = 1u;
+constexpr uint32_t kFUn = 2u;
+constexpr uint32_t kFSBin = 4u;
+constexpr uint32_t kFLBin = 8u;
+constexpr uint32_t kFLast = 16u;        // the program's last instruction
 
 __host__ __device__ inline int depth_class(int maxd)
 {
@@ -125,29 +133,56 @@ __host__ __device__ inline int class_k(int c, int n_vars)
     return c == 1 ? 4 : 2;
 }
 
-// Tile geometry for one class: a tile is `passes` consecutive sub-tiles of
-// 256*K cases; a work item covers one tile of G programs.  Up to 32 tiles
-// per program keep enough work items for small depth classes (larger
-// tiles were measured slower: too few items to fill 256 CUs).  Depends
-// only on (n_cases, K), so a program's summation order never depends on
-// the rest of the population.
+// Tile geometry for one class.  A sub-tile is 64*K cases (one wavefront, K
+// per lane).  The inputs and targets of `window` sub-tiles fit the LDS tile
+// budget together ((n_vars + 1) rows of 64*K floats each), so a wavefront
+// runs a program over a whole window without a barrier.  A tile is `passes`
+// consecutive sub-tiles (a whole number of windows where the case count
+// allows, at most 32 tiles per program); a work item covers one tile of G
+// programs.  Depends only on (n_cases, K, n_vars) -- the dataset -- so a
+// program's summation order never depends on the rest of the population or
+// the batch.
+constexpr int kTileLds = 24 * 1024;      // LDS bytes for input windows (6 workgroups per CU)
+constexpr int kMaxWindow = 8;
+
 struct TileShape {
-    int32_t sub;        // cases per sub-tile (256 * K)
+    int32_t sub;        // cases per sub-tile (64 * K)
     int32_t passes;     // sub-tiles per tile
     int32_t n_tiles;    // tiles covering n_cases
+    int32_t window;     // sub-tiles staged in LDS at once
 };
 
-__host__ __device__ inline TileShape tile_shape(int64_t n_cases, int k)
+__host__ __device__ inline int32_t tile_window(int k, int n_vars)
+{
+    const int64_t block = (int64_t)(n_vars + 1) * 64 * k * 4;
+    int64_t w = kTileLds / block;
+    return (int32_t)(w < 1 ? 1 : (w > kMaxWindow ? kMaxWindow : w));
+}
+
+__host__ __device__ inline TileShape tile_shape(int64_t n_cases, int k, int n_vars)
 {
     TileShape t;
-    t.sub = kWG * k;
-    int64_t n_sub = (n_cases + t.sub - 1) / t.sub;
+    t.sub = 64 * k;
+    const int64_t n_sub = (n_cases + t.sub - 1) / t.sub;
+    t.window = tile_window(k, n_vars);
     int64_t passes = (n_sub + kMaxTiles - 1) / kMaxTiles;
+    if (passes < t.window) passes = t.window < n_sub ? t.window : n_sub;
     if (passes < 1) passes = 1;
     t.passes = (int32_t)passes;
     t.n_tiles = (int32_t)((n_sub + passes - 1) / passes);
     return t;
 }
+
+// Partial slots per program that any dataset of at most max_cases cases
+// can need: n_tiles never exceeds kMaxTiles or the sub-tile count, and the
+// sub-tile count grows with n_cases, so a smaller dataset can need more
+// tiles than the largest one (33 sub-tiles make 17 tiles, 32 make 32).
+__host__ __device__ inline int32_t max_tiles(int64_t max_cases, int k)
+{
+    const int64_t n_sub = (max_cases + 64 * k - 1) / (64 * k);
+    return (int32_t)(n_sub < kMaxTiles ? (n_sub < 1 ? 1 : n_sub) : kMaxTiles);
+}
+
 
 // Power-of-two pre-scale s = 2^-e with 4^e >= n: every scaled partial sum
 // of squared residuals is then <= MSE, so it overflows fp32 only when the
@@ -172,6 +207,7 @@ struct DevDataset {
     int32_t n_vars;
     int32_t passes[kClasses];
     int32_t n_tiles[kClasses];
+    int32_t window[kClasses];
 };
 
 // Request entry as the kernels use it: the caller's entry with its
@@ -225,9 +261,10 @@ __global__ __launch_bounds__(256) void k_tables(
         o.scale = ldexpf(1.0f, -e);
         o.n_vars = ok ? in.n_vars : 0;
         for (int c = 0; c < kClasses; ++c) {
-            const TileShape t = tile_shape(n, class_k(c, o.n_vars));
+            const TileShape t = tile_shape(n, class_k(c, o.n_vars), o.n_vars);
             o.passes[c] = t.passes;
             o.n_tiles[c] = t.n_tiles;
+            o.window[c] = t.window;
         }
         ds_out[d] = o;
     }
@@ -288,302 +325,6 @@ __global__ __launch_bounds__(256) void k_tables(
     if (threadIdx.x == 0) seg_start[n_req] = n_programs;
     __syncthreads();
     if (threadIdx.x == 0) *bad = s_bad;
-}
-
-// ------------------------------------------------------------- k_prepare
-// Stack slots are stored pre-scaled: element `slot` of a class with maximum
-// depth MAXD lives at index slot * (32 / MAXD) of each 32-float VGPR chunk,
-// so the kernel uses a 5-bit field directly (always inside the chunk).
-__host__ __device__ constexpr int class_depth(int c) { return c == 0 ? 8 : (c == 1 ? 16 : 32); }
-
-__global__ __launch_bounds__(256) void k_prepare(
-    int64_t n_programs, uint32_t allowed, const DevDataset* __restrict__ ds,
-    const DevRequest* __restrict__ reqs, const int64_t* __restrict__ seg_start, int32_t n_seg,
-    const int32_t* __restrict__ tables_bad, int32_t lpt,
-    uint2* __restrict__ code, ProgMeta* __restrict__ meta, uint8_t* __restrict__ cls,
-    int32_t* __restrict__ pds)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_programs) return;
-    // the segment holding p: last segment whose start is <= p
-    int lo_s = 0, hi_s = n_seg - 1;
-    while (lo_s < hi_s) {
-        const int mid = (lo_s + hi_s + 1) >> 1;
-        if (seg_start[mid] <= p) lo_s = mid; else hi_s = mid - 1;
-    }
-    const DevRequest R = reqs[lo_s];
-    const int64_t q = p - seg_start[lo_s];        // index inside the request
-    pds[p] = lo_s;
-    const uint32_t* __restrict__ nodes = R.nodes;
-    const float* __restrict__ consts = R.consts;
-    const int64_t n_consts = R.n_consts;
-    const int32_t n_vars = ds[R.dataset].n_vars;
-    const bool tab_ok = *tables_bad == 0;
-    const int64_t s = tab_ok ? R.offsets[q] : 0, e = tab_ok ? R.offsets[q + 1] : 0;
-    int status = GP_PROG_OK;
-    int depth = 0, maxd = 0;
-    // pass 1: validate (GCL stack discipline, operand ranges, allowed ops)
-    if (!tab_ok) {
-        status = GP_PROG_BAD_TABLE;
-    } else if (s < 0 || e < s || e > R.n_nodes || e - s > INT32_MAX) {
-        status = GP_PROG_BAD_OFFSETS;
-    } else if (e == s) {
-        status = GP_PROG_EMPTY;
-    } else {
-        for (int64_t k = s; k < e; ++k) {
-            const uint32_t w = nodes[k];
-            const uint32_t op = w & 0xFFu, arg = w >> 8;
-            if (op >= GP_N_OPS || !((allowed >> op) & 1u)) { status = GP_PROG_BAD_OP; break; }
-            if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) { status = GP_PROG_BAD_VAR; break; }
-            if (op == GP_CONST && (int64_t)arg >= n_consts) { status = GP_PROG_BAD_CONST; break; }
-            const int need = op <= GP_CONST ? 0 : (op <= GP_DIV ? 2 : 1);
-            if (depth < need) { status = GP_PROG_UNDERFLOW; break; }
-            depth += op <= GP_CONST ? 1 : (op <= GP_DIV ? -1 : 0);
-            if (depth > GP_MAX_STACK) { status = GP_PROG_TOO_DEEP; break; }
-            if (depth > maxd) maxd = depth;
-        }
-        if (status == GP_PROG_OK && depth != 1) status = GP_PROG_FINAL_DEPTH;
-    }
-    const int c = status == GP_PROG_OK ? depth_class(maxd) : -1;
-    // pass 2: stage 8-byte instructions {op | read index << 8 | write index
-    // << 16, variable index or constant bits}, folding a leaf into the op
-    // that directly follows it
-    int64_t sk = R.node_base + s;                // next staged slot
-    if (c >= 0) {
-        const uint32_t J = 32u / (uint32_t)class_depth(c);
-        const uint32_t dummy = 32u - J;          // slot MAXD-1: never live
-        depth = 0;
-        for (int64_t k = s; k < e; ++k) {
-            const uint32_t w = nodes[k];
-            const uint32_t op = w & 0xFFu, arg = w >> 8;
-            uint2 cw;
-            if (op <= GP_CONST) {
-                const uint32_t payload = op == GP_LOAD ? arg : __float_as_uint(consts[arg]);
-                // the old top (element depth-1) would move into slot depth-1
-                const uint32_t wr = depth >= 1 ? (uint32_t)(depth - 1) * J : dummy;
-                const uint32_t nx = k + 1 < e ? (nodes[k + 1] & 0xFFu) : 0xFFu;
-                if (depth >= 1 && nx >= GP_ADD && nx <= GP_DIV) {
-                    // top = top OP leaf: no push, no pop
-                    cw.x = (op == GP_LOAD ? kOpBinVar : kOpBinConst) + (nx - GP_ADD);
-                    cw.y = payload;
-                    ++k;                         // the binary node is consumed
-                } else if (nx >= GP_SIN && nx < GP_N_OPS) {
-                    cw.x = ((op == GP_LOAD ? kOpUnVar : kOpUnConst) + (nx - GP_SIN)) | (wr << 16);
-                    cw.y = payload;
-                    ++depth;
-                    ++k;                         // the unary node is consumed
-                } else {
-                    cw.x = op | (wr << 16);
-                    cw.y = payload;
-                    ++depth;
-                }
-            } else if (op <= GP_DIV) {
-                // second from top (element depth-2) is read from slot depth-2
-                cw.x = op | (((uint32_t)(depth - 2) * J) << 8);
-                cw.y = 0;
-                --depth;
-            } else {
-                cw.x = op;
-                cw.y = 0;
-            }
-            code[sk++] = cw;
-        }
-    }
-    ProgMeta m;
-    m.start = R.node_base + s;
-    m.len = (int32_t)(status == GP_PROG_BAD_OFFSETS ? 0 : e - s);
-    m.slen = (int32_t)(sk - m.start);
-    meta[p] = m;
-    // partition key: depth class, then (single-segment calls) length bucket
-    // from longest to shortest; with several segments the order inside a
-    // class stays the input order, so each segment's programs stay together
-    int lb = 31 - __clz((uint32_t)(m.slen > 0 ? m.slen : 1));
-    lb = lb < kLenBuckets - 1 ? lb : kLenBuckets - 1;
-    const int sub_key = lpt ? (kLenBuckets - 1 - lb) : 0;
-    cls[p] = c >= 0 ? (uint8_t)(c * kLenBuckets + sub_key) : (uint8_t)0xFF;
-    if (R.out_status && q < R.n_programs) R.out_status[q] = status;
-}
-
-// --------------------------------------------------- depth-class partition
-// blk_counts[k * n_blk + b] = programs with partition key k in block b.
-__global__ __launch_bounds__(kBucketBlock) void k_class_count(
-    const uint8_t* __restrict__ cls, int64_t n_programs, int32_t n_blk,
-    int32_t* __restrict__ blk_counts)
-{
-    __shared__ int cnt[kKeys];
-    if (threadIdx.x < kKeys) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t p = (int64_t)blockIdx.x * kBucketBlock + threadIdx.x;
-    if (p < n_programs) {
-        const int c = cls[p];
-        if (c < kKeys) atomicAdd(&cnt[c], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x < kKeys) blk_counts[threadIdx.x * n_blk + blockIdx.x] = cnt[threadIdx.x];
-}
-
-// One workgroup: exclusive scan of blk_counts in key-major order into
-// blk_base; class_info[2c] = first position of depth class c, [2c+1] = its
-// size (its keys are contiguous); also clears the per-class work counters.
-__global__ __launch_bounds__(1024) void k_class_scan(
-    const int32_t* __restrict__ blk_counts, int32_t n_blk,
-    int32_t* __restrict__ blk_base, int32_t* __restrict__ class_info,
-    uint32_t* __restrict__ work_counters)
-{
-    __shared__ int part[1024];
-    const int total = kKeys * n_blk;
-    const int chunk = (total + 1023) / 1024;
-    const int t = threadIdx.x;
-    const int lo = t * chunk, hi = min(total, lo + chunk);
-    int sum = 0;
-    for (int i = lo; i < hi; ++i) sum += blk_counts[i];
-    part[t] = sum;
-    __syncthreads();
-    // inclusive Hillis-Steele scan of the 1024 chunk sums
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int run = part[t] - sum;
-    for (int i = lo; i < hi; ++i) {
-        blk_base[i] = run;
-        run += blk_counts[i];
-    }
-    if (t < kClasses) {
-        // exclusive prefix of entry i from the scanned chunk sums (LDS)
-        auto prefix = [&](int i) {
-            if (i >= total) return part[1023];
-            const int owner = i / chunk;
-            int b = owner > 0 ? part[owner - 1] : 0;
-            for (int j = owner * chunk; j < i; ++j) b += blk_counts[j];
-            return b;
-        };
-        const int start = prefix(t * kLenBuckets * n_blk);
-        const int end = prefix((t + 1) * kLenBuckets * n_blk);
-        class_info[2 * t] = start;
-        class_info[2 * t + 1] = end - start;
-        work_counters[t] = 0u;
-    }
-}
-
-// Stable scatter: order[blk_base[k, b] + rank of p among key-k programs of
-// block b] = p.
-__global__ __launch_bounds__(kBucketBlock) void k_class_scatter(
-    const uint8_t* __restrict__ cls, int64_t n_programs, int32_t n_blk,
-    const int32_t* __restrict__ blk_base, int32_t* __restrict__ order)
-{
-    constexpr int kW = kBucketBlock / 64;
-    __shared__ int wcnt[kW][kKeys];
-    const int64_t p = (int64_t)blockIdx.x * kBucketBlock + threadIdx.x;
-    const int c = p < n_programs ? (int)cls[p] : 0xFF;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int rank = 0;
-    for (int cc = 0; cc < kKeys; ++cc) {
-        const uint64_t m = __ballot(c == cc);
-        if (lane == 0) wcnt[wave][cc] = __popcll(m);
-        if (c == cc) rank = __popcll(m & below);
-    }
-    __syncthreads();
-    if (c < kKeys) {
-        for (int w = 0; w < wave; ++w) rank += wcnt[w][c];
-        order[blk_base[c * n_blk + blockIdx.x] + rank] = (int32_t)p;
-    }
-}
-
-// Programs of each depth class inside each segment: seg_cnt[c * n_seg + s].
-// One thread per (class, segment).  With several segments the partition
-// keeps each class in program order, so a segment's programs of class c are
-// the class's entries between two lower bounds of the segment's program
-// range; a single segment holds the whole class.
-__global__ __launch_bounds__(256) void k_seg_count(const int32_t* __restrict__ order,
-                                                   const int32_t* __restrict__ class_info,
-                                                   const int64_t* __restrict__ seg_start,
-                                                   int32_t n_seg,
-                                                   const int32_t* __restrict__ tables_bad,
-                                                   int32_t* __restrict__ seg_cnt)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kClasses * n_seg) return;
-    const int c = i / n_seg, sg = i - c * n_seg;
-    const int32_t* __restrict__ ord = order + class_info[2 * c];
-    const int n = class_info[2 * c + 1];
-    int cnt;
-    if (*tables_bad) {
-        cnt = 0;                         // no program was staged
-    } else if (n_seg == 1) {
-        cnt = n;
-    } else {
-        // first position whose program id is >= v
-        auto lower = [&](int64_t v) {
-            int lo = 0, hi = n;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if ((int64_t)ord[mid] < v) lo = mid + 1; else hi = mid;
-            }
-            return lo;
-        };
-        cnt = lower(seg_start[sg + 1]) - lower(seg_start[sg]);
-    }
-    seg_cnt[i] = cnt;
-}
-
-// Per class (one thread each): where each segment's programs start inside
-// the class's range of `order`, and the prefix of work items (G-program
-// groups times the segment dataset's case tiles) over segments.
-__global__ __launch_bounds__(64) void k_seg_scan(const int32_t* __restrict__ seg_cnt,
-                                                 const int32_t* __restrict__ seg_ds,
-                                                 const DevDataset* __restrict__ ds, int32_t n_seg,
-                                                 int32_t G, int32_t* __restrict__ seg_pos,
-                                                 uint32_t* __restrict__ item_pre)
-{
-    const int c = threadIdx.x;
-    if (c >= kClasses) return;
-    int32_t pos = 0;
-    uint32_t items = 0;
-    for (int s = 0; s < n_seg; ++s) {
-        const int32_t n = seg_cnt[c * n_seg + s];
-        seg_pos[c * n_seg + s] = pos;
-        item_pre[c * (n_seg + 1) + s] = items;
-        pos += n;
-        items += (uint32_t)((n + G - 1) / G) * (uint32_t)ds[seg_ds[s]].n_tiles[c];
-    }
-    item_pre[c * (n_seg + 1) + n_seg] = items;
-}
-
-// ------------------------------------------------------------ evaluation
-// Scalars of one class launch (pointers travel as restrict-qualified kernel
-// parameters so that uniform loads of programs and metadata become scalar
-// memory loads).
-struct EvalConst {
-    int32_t cls;
-    int32_t G;              // programs per work item
-    int32_t part_stride;
-    int32_t max_vars;       // LDS input tile rows
-    int32_t n_seg;
-    // single-dataset form (gp_predict)
-    int64_t ld_x;
-    int64_t n_cases;
-    int32_t n_vars;
-};
-
-// Error-free sum: s + e == a + b exactly (Knuth's TwoSum).
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
-{
-    s = a + b;
-    const float bp = s - a;
-    e = (a - (s - bp)) + (b - bp);
-}
-
-// Compensated pair (hi, lo) += (h2, l2).
-__device__ __forceinline__ void acc_pair(float& hi, float& lo, float h2, float l2)
-{
-    float s, e;
-    two_sum(hi, h2, s, e);
-    hi = s;
-    lo = (lo + l2) + e;
 }
 
 // ------------------------------------------------------------------ sin/cos
@@ -668,6 +409,469 @@ __device__ __forceinline__ float log_protected(float a)
     return x <= 0.001f ? 0.f : ln;
 }
 
+// ------------------------------------------------------ scalar op values
+// Protected division (the divisor threshold is fp32(0.001)); shared by the
+// interpreter and by constant folding, so both give the same bits.
+__device__ __forceinline__ float div_protected(float a, float b)
+{
+    return fabsf(b) <= 0.001f ? 1.f : a / b;
+}
+
+// One operator on one value, exactly as the interpreter computes it for a
+// case (used to fold constant subtrees while staging).
+__device__ __forceinline__ float binary_value(uint32_t bop, float a, float b)
+{
+    switch (bop) {
+    case GP_ADD: return a + b;
+    case GP_SUB: return a - b;
+    case GP_MUL: return a * b;
+    default: return div_protected(a, b);
+    }
+}
+
+__device__ __forceinline__ float unary_value(uint32_t uop, float x)
+{
+    switch (uop) {
+    case GP_SIN: return fabsf(x) <= kTrigFastLimit ? sin_fast(x) : sinf(x);
+    case GP_COS: return fabsf(x) <= kTrigFastLimit ? cos_fast(x) : cosf(x);
+    case GP_EXP: return expf(x);
+    case GP_LOG: return log_protected(x);
+    case GP_SQRT: return sqrt_abs(x);
+    default: return fabsf(x);
+    }
+}
+
+// ------------------------------------------------------------- staging
+// Stack slots are stored pre-scaled: element `slot` of a class with maximum
+// depth MAXD lives at index slot * (32 / MAXD) of each 32-float VGPR chunk,
+// so the kernel uses the index directly (always inside the chunk).
+__host__ __device__ constexpr int class_depth(int c) { return c == 0 ? 8 : (c == 1 ? 16 : 32); }
+
+// Request of program p: the last request whose first program is <= p.
+__device__ __forceinline__ int request_of(const int64_t* __restrict__ seg_start, int32_t n_seg,
+                                          int64_t p)
+{
+    int lo = 0, hi = n_seg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_start[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Emits the staged instructions of one valid program (EMIT) or only counts
+// them.  Constants are held back on a shadow stack and folded: an operator
+// whose operands are all held-back constants is computed here, once, with
+// the interpreter's own scalar arithmetic (the same bits every case would
+// get), and only its value travels on.  Held-back constants always sit on
+// top of the runtime stack; they are pushed ("flushed") before a variable is
+// pushed above them, combined with the runtime top as "top = top OP c", or
+// pushed at the end when the whole program is constant.  A variable directly
+// followed by an operator folds into it (top OP x, or save + f(x)).  What is
+// folded depends only on the node kinds, never on values, so counting and
+// emitting agree.
+template <bool EMIT>
+__device__ int64_t stage_walk(const uint32_t* __restrict__ nodes, int64_t s, int64_t e,
+                              const float* __restrict__ consts, uint32_t J, uint32_t row_bytes,
+                              uint4* __restrict__ out)
+{
+    const uint32_t dummy = 32u - J;              // slot MAXD-1: never live
+    float pv[GP_MAX_STACK];                      // held-back constant values
+    int rt = 0;                                  // runtime stack depth
+    int np = 0;                                  // held-back constants
+    int64_t n = 0;                               // emitted instructions
+    for (int64_t k = s; k < e; ++k) {
+        const uint32_t w = nodes[k];
+        const uint32_t op = w & 0xFFu, arg = w >> 8;
+        if (op == GP_CONST) {
+            if (EMIT) pv[np] = consts[arg];
+            ++np;
+            continue;
+        }
+        if (op == GP_LOAD) {
+            // flush: held-back constants become runtime elements, bottom up
+            for (int i = 0; i < np; ++i) {
+                if (EMIT) {
+                    const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
+                    out[n] = make_uint4(kFPush, __float_as_uint(pv[i]), 1u, wr);
+                }
+                ++n;
+                ++rt;
+            }
+            np = 0;
+            const uint32_t payload = arg * row_bytes;
+            const uint32_t nx = k + 1 < e ? (nodes[k + 1] & 0xFFu) : 0xFFu;
+            const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
+            if (nx >= GP_ADD && nx <= GP_DIV) {
+                // top = top OP x (the binary op has a runtime element below)
+                if (EMIT) out[n] = make_uint4(kFLBin | ((nx - GP_ADD) << 8), payload, 0u, 0u);
+                ++k;
+            } else if (nx >= GP_SIN && nx < GP_N_OPS) {
+                if (EMIT) out[n] = make_uint4(kFPush | kFUn | ((nx - GP_SIN) << 8), payload, 0u, wr);
+                ++rt;
+                ++k;
+            } else {
+                if (EMIT) out[n] = make_uint4(kFPush, payload, 0u, wr);
+                ++rt;
+            }
+            ++n;
+            continue;
+        }
+        if (op <= GP_DIV) {
+            const uint32_t bop = op - GP_ADD;
+            if (np >= 2) {
+                --np;
+                if (EMIT) pv[np - 1] = binary_value(op, pv[np - 1], pv[np]);
+            } else if (np == 1) {
+                // top = top OP c: the runtime top is the left operand
+                --np;
+                if (EMIT) out[n] = make_uint4(kFLBin | (bop << 8), __float_as_uint(pv[0]), 1u, 0u);
+                ++n;
+            } else {
+                // second from top (element rt-2) is read from slot rt-2
+                if (EMIT) out[n] = make_uint4(kFSBin | (bop << 8), 0u, (uint32_t)(rt - 2) * J, 0u);
+                ++n;
+                --rt;
+            }
+            continue;
+        }
+        if (np >= 1) {
+            if (EMIT) pv[np - 1] = unary_value(op, pv[np - 1]);
+        } else {
+            if (EMIT) out[n] = make_uint4(kFUn | ((op - GP_SIN) << 8), 0u, 0u, 0u);
+            ++n;
+        }
+    }
+    // a constant program: its value is pushed
+    for (int i = 0; i < np; ++i) {
+        if (EMIT) {
+            const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
+            out[n] = make_uint4(kFPush, __float_as_uint(pv[i]), 1u, wr);
+        }
+        ++n;
+        ++rt;
+    }
+    if (EMIT && n > 0) out[n - 1].x |= kFLast;
+    return n;
+}
+
+// Pass 1, one thread per program (blocks of kBucketBlock): validate (GCL
+// stack discipline, operand ranges, allowed ops), count the staged
+// instructions the program needs (a leaf directly followed by an operator
+// folds into it), derive the depth
+// class and the partition key, and accumulate per-block key counts and
+// staged sizes for the scans that follow.
+__global__ __launch_bounds__(kBucketBlock) void k_validate(
+    int64_t n_programs, uint32_t allowed, const DevDataset* __restrict__ ds,
+    const DevRequest* __restrict__ reqs, const int64_t* __restrict__ seg_start, int32_t n_seg,
+    const int32_t* __restrict__ tables_bad, int32_t lpt, int32_t n_blk,
+    ProgMeta* __restrict__ meta, uint8_t* __restrict__ cls, int32_t* __restrict__ pds,
+    int32_t* __restrict__ blk_counts, int64_t* __restrict__ blk_slen)
+{
+    __shared__ int cnt[kKeys];
+    __shared__ unsigned long long s_slen;
+    if (threadIdx.x < kKeys) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_slen = 0ull;
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * kBucketBlock + threadIdx.x;
+    if (p < n_programs) {
+        const int r = request_of(seg_start, n_seg, p);
+        const DevRequest R = reqs[r];
+        const int64_t q = p - seg_start[r];           // index inside the request
+        pds[p] = r;
+        const uint32_t* __restrict__ nodes = R.nodes;
+        const int32_t n_vars = ds[R.dataset].n_vars;
+        const bool tab_ok = *tables_bad == 0;
+        const int64_t s = tab_ok ? R.offsets[q] : 0, e = tab_ok ? R.offsets[q + 1] : 0;
+        int status = GP_PROG_OK;
+        int depth = 0, maxd = 0;
+        if (!tab_ok) {
+            status = GP_PROG_BAD_TABLE;
+        } else if (s < 0 || e < s || e > R.n_nodes || e - s > INT32_MAX - 1) {
+            status = GP_PROG_BAD_OFFSETS;
+        } else if (e == s) {
+            status = GP_PROG_EMPTY;
+        } else {
+            for (int64_t k = s; k < e; ++k) {
+                const uint32_t w = nodes[k];
+                const uint32_t op = w & 0xFFu, arg = w >> 8;
+                if (op >= GP_N_OPS || !((allowed >> op) & 1u)) { status = GP_PROG_BAD_OP; break; }
+                if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) { status = GP_PROG_BAD_VAR; break; }
+                if (op == GP_CONST && (int64_t)arg >= R.n_consts) { status = GP_PROG_BAD_CONST; break; }
+                const int need = op <= GP_CONST ? 0 : (op <= GP_DIV ? 2 : 1);
+                if (depth < need) { status = GP_PROG_UNDERFLOW; break; }
+                depth += op <= GP_CONST ? 1 : (op <= GP_DIV ? -1 : 0);
+                if (depth > GP_MAX_STACK) { status = GP_PROG_TOO_DEEP; break; }
+                if (depth > maxd) maxd = depth;
+            }
+            if (status == GP_PROG_OK && depth != 1) status = GP_PROG_FINAL_DEPTH;
+        }
+        const int c = status == GP_PROG_OK ? depth_class(maxd) : -1;
+        ProgMeta m;
+        m.start = 0;
+        m.len = (int32_t)(status == GP_PROG_BAD_OFFSETS || status == GP_PROG_BAD_TABLE ? 0 : e - s);
+        m.slen = c >= 0 ? (int32_t)stage_walk<false>(nodes, s, e, nullptr, 0u, 0u, nullptr) : 0;
+        meta[p] = m;
+        // partition key: depth class, then (single-request calls) length
+        // band from longest to shortest; with several requests the order
+        // inside a class stays the input order, so each request's programs
+        // stay together
+        int lb = 31 - __clz((uint32_t)(m.slen > 0 ? m.slen : 1));
+        lb = lb < kLenBuckets - 1 ? lb : kLenBuckets - 1;
+        const int key = c >= 0 ? c * kLenBuckets + (lpt ? kLenBuckets - 1 - lb : 0) : 0xFF;
+        cls[p] = (uint8_t)key;
+        if (key < kKeys) atomicAdd(&cnt[key], 1);
+        if (m.slen) atomicAdd(&s_slen, (unsigned long long)m.slen);
+        if (R.out_status && q < R.n_programs) R.out_status[q] = status;
+    }
+    __syncthreads();
+    if (threadIdx.x < kKeys) blk_counts[threadIdx.x * n_blk + blockIdx.x] = cnt[threadIdx.x];
+    if (threadIdx.x == 0) blk_slen[blockIdx.x] = (int64_t)s_slen;
+}
+
+// One workgroup: exclusive scans of the per-block key counts (key-major
+// order) into blk_base and of the per-block staged sizes into blk_code;
+// class_info[2c] = first position of depth class c, [2c+1] = its size (its
+// keys are contiguous); also clears the per-class work counters.  Staged
+// code never exceeds the call's node count unless programs' node ranges
+// overlap; then *overflow is set, nothing is staged and every class is
+// left empty.
+__global__ __launch_bounds__(1024) void k_class_scan(
+    const int32_t* __restrict__ blk_counts, const int64_t* __restrict__ blk_slen, int32_t n_blk,
+    int64_t code_capacity, int32_t* __restrict__ blk_base, int64_t* __restrict__ blk_code,
+    int32_t* __restrict__ class_info, uint32_t* __restrict__ work_counters,
+    int32_t* __restrict__ overflow)
+{
+    __shared__ int part[1024];
+    __shared__ long long lpart[1024];
+    const int t = threadIdx.x;
+    const int total = kKeys * n_blk;
+    const int chunk = (total + 1023) / 1024;
+    const int lo = t * chunk, hi = min(total, lo + chunk);
+    int sum = 0;
+    for (int i = lo; i < hi; ++i) sum += blk_counts[i];
+    part[t] = sum;
+    const int chunk2 = (n_blk + 1023) / 1024;
+    const int lo2 = t * chunk2, hi2 = min(n_blk, lo2 + chunk2);
+    long long sum2 = 0;
+    for (int i = lo2; i < hi2; ++i) sum2 += blk_slen[i];
+    lpart[t] = sum2;
+    __syncthreads();
+    // inclusive Hillis-Steele scans of the chunk sums
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = t >= off ? part[t - off] : 0;
+        const long long v2 = t >= off ? lpart[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        lpart[t] += v2;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+    for (int i = lo; i < hi; ++i) {
+        blk_base[i] = run;
+        run += blk_counts[i];
+    }
+    long long run2 = lpart[t] - sum2;
+    for (int i = lo2; i < hi2; ++i) {
+        blk_code[i] = run2;
+        run2 += blk_slen[i];
+    }
+    if (t < kClasses) {
+        // exclusive prefix of entry i from the scanned chunk sums (LDS)
+        auto prefix = [&](int i) {
+            if (i >= total) return part[1023];
+            const int owner = i / chunk;
+            int b = owner > 0 ? part[owner - 1] : 0;
+            for (int j = owner * chunk; j < i; ++j) b += blk_counts[j];
+            return b;
+        };
+        const bool ovf = lpart[1023] > code_capacity;
+        const int start = prefix(t * kLenBuckets * n_blk);
+        const int end = prefix((t + 1) * kLenBuckets * n_blk);
+        class_info[2 * t] = start;
+        class_info[2 * t + 1] = ovf ? 0 : end - start;
+        work_counters[t] = 0u;
+        if (t == 0) *overflow = ovf ? 1 : 0;
+    }
+}
+
+// Pass 2, same blocks as pass 1: each program's staged range starts at its
+// block's base plus the exclusive scan of staged sizes inside the block, so
+// ranges never overlap whatever the offsets; the program is staged there
+// and its id is scattered (stably) into the partition order.
+//
+// Staged instruction (16 bytes, one scalar load):
+//   x = flags | sel << 8, y = payload, z = rd or leaf-is-constant, w = wr
+//   kFPush  save the top into stack slot w, then the top = leaf
+//   kFUn    the top = unary sel (SIN..ABS as 0..5) of the top
+//   kFSBin  the top = stack slot z  OP_sel  top  (ADD..DIV as 0..3)
+//   kFLBin  the top = top  OP_sel  leaf
+//   kFLast  (with any of the above) the program's last instruction
+// A leaf is the constant with bits y when z != 0, else the input row at LDS
+// byte offset y (variable index * sub-tile cases * 4).
+__global__ __launch_bounds__(kBucketBlock) void k_stage(
+    int64_t n_programs, const DevDataset* __restrict__ ds, const DevRequest* __restrict__ reqs,
+    const int64_t* __restrict__ seg_start, const int32_t* __restrict__ pds, int32_t n_blk,
+    const int64_t* __restrict__ blk_code, const int32_t* __restrict__ blk_base,
+    const int32_t* __restrict__ overflow, uint8_t* __restrict__ cls,
+    ProgMeta* __restrict__ meta, uint4* __restrict__ code, int32_t* __restrict__ order)
+{
+    __shared__ long long sc[kBucketBlock];
+    constexpr int kW = kBucketBlock / 64;
+    __shared__ int wcnt[kW][kKeys];
+    const int t = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * kBucketBlock + t;
+    int key = p < n_programs ? (int)cls[p] : 0xFF;
+    if (*overflow) {
+        // overlapping node ranges: no program of this call is staged
+        if (key < kKeys) {
+            cls[p] = 0xFF;
+            const int r = pds[p];
+            const DevRequest& R = reqs[r];
+            const int64_t q = p - seg_start[r];
+            if (R.out_status && q < R.n_programs) R.out_status[q] = GP_PROG_BAD_OFFSETS;
+        }
+        return;
+    }
+    ProgMeta m;
+    m.start = 0;
+    m.len = 0;
+    m.slen = 0;
+    if (p < n_programs) m = meta[p];
+    // inclusive scan of staged sizes inside the block
+    sc[t] = m.slen;
+    __syncthreads();
+    for (int off = 1; off < kBucketBlock; off <<= 1) {
+        const long long v = t >= off ? sc[t - off] : 0;
+        __syncthreads();
+        sc[t] += v;
+        __syncthreads();
+    }
+    const int64_t start = blk_code[blockIdx.x] + sc[t] - m.slen;
+    if (key < kKeys) {
+        const int c = key / kLenBuckets;
+        const int r = pds[p];
+        const DevRequest R = reqs[r];
+        const int64_t q = p - seg_start[r];
+        const uint32_t* __restrict__ nodes = R.nodes;
+        const float* __restrict__ consts = R.consts;
+        const int64_t s = R.offsets[q], e = R.offsets[q + 1];
+        const uint32_t J = 32u / (uint32_t)class_depth(c);
+        const uint32_t row_bytes = (uint32_t)(64 * class_k(c, ds[R.dataset].n_vars)) * 4u;
+        stage_walk<true>(nodes, s, e, consts, J, row_bytes, code + start);
+        m.start = start;
+        meta[p].start = start;
+    }
+    // stable scatter into the partition order
+    const int wave = t >> 6, lane = t & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int rank = 0;
+    for (int kk = 0; kk < kKeys; ++kk) {
+        const uint64_t bm = __ballot(key == kk);
+        if (lane == 0) wcnt[wave][kk] = __popcll(bm);
+        if (key == kk) rank = __popcll(bm & below);
+    }
+    __syncthreads();
+    if (key < kKeys) {
+        for (int w2 = 0; w2 < wave; ++w2) rank += wcnt[w2][key];
+        order[blk_base[key * n_blk + blockIdx.x] + rank] = (int32_t)p;
+    }
+}
+
+// Programs of each depth class inside each segment: seg_cnt[c * n_seg + s].
+// One thread per (class, segment).  With several segments the partition
+// keeps each class in program order, so a segment's programs of class c are
+// the class's entries between two lower bounds of the segment's program
+// range; a single segment holds the whole class.
+__global__ __launch_bounds__(256) void k_seg_count(const int32_t* __restrict__ order,
+                                                   const int32_t* __restrict__ class_info,
+                                                   const int64_t* __restrict__ seg_start,
+                                                   int32_t n_seg,
+                                                   const int32_t* __restrict__ tables_bad,
+                                                   int32_t* __restrict__ seg_cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kClasses * n_seg) return;
+    const int c = i / n_seg, sg = i - c * n_seg;
+    const int32_t* __restrict__ ord = order + class_info[2 * c];
+    const int n = class_info[2 * c + 1];
+    int cnt;
+    if (*tables_bad) {
+        cnt = 0;                         // no program was staged
+    } else if (n_seg == 1) {
+        cnt = n;
+    } else {
+        // first position whose program id is >= v
+        auto lower = [&](int64_t v) {
+            int lo = 0, hi = n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((int64_t)ord[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            return lo;
+        };
+        cnt = lower(seg_start[sg + 1]) - lower(seg_start[sg]);
+    }
+    seg_cnt[i] = cnt;
+}
+
+// Per class (one thread each): where each segment's programs start inside
+// the class's range of `order`, and the prefix of work items (G-program
+// groups times the segment dataset's case tiles) over segments.
+__global__ __launch_bounds__(64) void k_seg_scan(const int32_t* __restrict__ seg_cnt,
+                                                 const int32_t* __restrict__ seg_ds,
+                                                 const DevDataset* __restrict__ ds, int32_t n_seg,
+                                                 int32_t G, int32_t* __restrict__ seg_pos,
+                                                 uint32_t* __restrict__ item_pre)
+{
+    const int c = threadIdx.x;
+    if (c >= kClasses) return;
+    int32_t pos = 0;
+    uint32_t items = 0;
+    for (int s = 0; s < n_seg; ++s) {
+        const int32_t n = seg_cnt[c * n_seg + s];
+        seg_pos[c * n_seg + s] = pos;
+        item_pre[c * (n_seg + 1) + s] = items;
+        pos += n;
+        items += (uint32_t)((n + G - 1) / G) * (uint32_t)ds[seg_ds[s]].n_tiles[c];
+    }
+    item_pre[c * (n_seg + 1) + n_seg] = items;
+}
+
+// ------------------------------------------------------------ evaluation
+// Scalars of one class launch (pointers travel as restrict-qualified kernel
+// parameters so that uniform loads of programs and metadata become scalar
+// memory loads).
+struct EvalConst {
+    int32_t cls;
+    int32_t G;              // programs per work item
+    int32_t part_stride;
+    int32_t max_vars;       // largest n_vars of the call
+    int32_t n_seg;
+    int32_t tile_floats;    // LDS floats for input windows
+    // single-dataset form (gp_predict)
+    int64_t ld_x;
+    int64_t n_cases;
+    int32_t n_vars;
+};
+
+// Error-free sum: s + e == a + b exactly (Knuth's TwoSum).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e)
+{
+    s = a + b;
+    const float bp = s - a;
+    e = (a - (s - bp)) + (b - bp);
+}
+
+// Compensated pair (hi, lo) += (h2, l2).
+__device__ __forceinline__ void acc_pair(float& hi, float& lo, float h2, float l2)
+{
+    float s, e;
+    two_sum(hi, h2, s, e);
+    hi = s;
+    lo = (lo + l2) + e;
+}
+
 // The value stack below the top lives in VGPR arrays of 32 floats ("chunks"):
 // chunk c holds cases [c*J, (c+1)*J) of every slot, element index
 // slot*J + (case mod J), J = 32 / MAXD.  A uniform dynamic index into a
@@ -703,7 +907,7 @@ __device__ __forceinline__ float log_protected(float a)
             break;                                                                 \
         default:                                                                   \
             _Pragma("unroll") for (int j = 0; j < K; ++j)                          \
-                out[j] = fabsf(b[j]) <= 0.001f ? 1.f : a[j] / b[j];                \
+                out[j] = div_protected(a[j], b[j]);                                \
             break;                                                                 \
         }                                                                          \
     } while (0)
@@ -714,9 +918,22 @@ __device__ __forceinline__ float log_protected(float a)
 // major: case j of lane t is element j*256 + t of a variable's row (row
 // stride SUB), so each of the K reads of a LOAD is a conflict-free,
 // lane-contiguous LDS access.  The top of the stack is returned in tos[].
-template <int MAXD, int K, int SUB>
-__device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
-                                            const uint2* __restrict__ pend,
+// Loads a leaf for K cases: the constant with bits `payload` when is_const,
+// else the input row at LDS byte offset `payload` from this lane's base.
+#define GP_LEAF(is_const, payload, out)                                            \
+    do {                                                                           \
+        if (is_const) {                                                            \
+            const float c_ = __uint_as_float(payload);                             \
+            _Pragma("unroll") for (int j = 0; j < K; ++j) out[j] = c_;             \
+        } else {                                                                   \
+            const float* xp_ = reinterpret_cast<const float*>(                     \
+                reinterpret_cast<const char*>(xl) + (payload));                    \
+            _Pragma("unroll") for (int j = 0; j < K; ++j) out[j] = xp_[j * 64];    \
+        }                                                                          \
+    } while (0)
+
+template <int MAXD, int K>
+__device__ __forceinline__ void run_program(const uint4* __restrict__ pc,
                                             const float* __restrict__ xl, float (&tos)[K])
 {
     constexpr int J = 32 / MAXD;                  // cases per 32-float chunk
@@ -725,70 +942,42 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
 #pragma unroll
     for (int j = 0; j < K; ++j) tos[j] = 0.f;
 
-    // the staging buffer has one padding node after the last
-    // program, so fetching one node ahead never leaves it
-    uint2 w_next = *pc;
+    // Dispatch on flag bits; the program's last instruction carries kFLast
+    // (no separate trip count).  Stack indices are masked to the 32-element
+    // chunk: the register index can never leave the chunk, whatever the
+    // staged word says.
+    uint32_t f;
     do {
-        const uint2 w = w_next;
+        const uint4 w = *pc;
         ++pc;
-        w_next = *pc;
-        const uint32_t op = w.x & 0xFFu;
-        const uint32_t rd = (w.x >> 8) & 31u;
-        const uint32_t wr = (w.x >> 16) & 31u;
-        if (op <= GP_CONST) {
-            // leaf: the old top moves into the stack (slot MAXD-1
-            // never holds a live element, so a push onto an empty
-            // stack writes there), the new value becomes the top
-#pragma unroll
-            for (int j = 0; j < K; ++j) GP_CHUNK_PUT(wr, j, tos[j]);
-            if (op == GP_LOAD) {
-                const float* xp = xl + (size_t)w.y * SUB;
-#pragma unroll
-                for (int j = 0; j < K; ++j) tos[j] = xp[j * kWG];
-            } else {
-                const float c = __uint_as_float(w.y);
-#pragma unroll
-                for (int j = 0; j < K; ++j) tos[j] = c;
-            }
-        } else if (op <= GP_DIV) {
-            // binary: a = second from top (stack slot rd), b = top
+        f = w.x;
+        if (f & kFSBin) {
+            // a = second from top (stack slot z), b = top
             float sv[K];
 #pragma unroll
-            for (int j = 0; j < K; ++j) sv[j] = GP_CHUNK_GET(rd, j);
-            GP_BINARY(op, sv, tos);
-        } else if (op >= kOpBinVar && op < kOpUnVar) {
-            // top = top OP leaf
+            for (int j = 0; j < K; ++j) sv[j] = GP_CHUNK_GET(w.z & 31u, j);
+            GP_BINARY(GP_ADD + (f >> 8), sv, tos);
+        } else if (f & kFLBin) {
             float lv[K];
-            if (op < kOpBinConst) {
-                const float* xp = xl + (size_t)w.y * SUB;
+            GP_LEAF(w.z, w.y, lv);
+            GP_BINARY_AB(GP_ADD + (f >> 8), tos, lv, tos);
+        } else if (!(f & kFUn)) {
+            // the old top moves into the stack (slot MAXD-1 never holds a
+            // live element, so a push onto an empty stack writes there),
+            // the leaf becomes the top
 #pragma unroll
-                for (int j = 0; j < K; ++j) lv[j] = xp[j * kWG];
-            } else {
-                const float c = __uint_as_float(w.y);
-#pragma unroll
-                for (int j = 0; j < K; ++j) lv[j] = c;
-            }
-            const uint32_t bop = GP_ADD + ((op - kOpBinVar) & 3u);
-            GP_BINARY_AB(bop, tos, lv, tos);
+            for (int j = 0; j < K; ++j) GP_CHUNK_PUT(w.w & 31u, j, tos[j]);
+            GP_LEAF(w.z, w.y, tos);
         } else {
-            uint32_t uop = op;
-            if (op >= kOpUnVar) {
+            if (f & kFPush) {
                 // f(leaf): the old top is saved first
 #pragma unroll
-                for (int j = 0; j < K; ++j) GP_CHUNK_PUT(wr, j, tos[j]);
-                if (op < kOpUnConst) {
-                    const float* xp = xl + (size_t)w.y * SUB;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) tos[j] = xp[j * kWG];
-                    uop = op - kOpUnVar + GP_SIN;
-                } else {
-                    const float c = __uint_as_float(w.y);
-#pragma unroll
-                    for (int j = 0; j < K; ++j) tos[j] = c;
-                    uop = op - kOpUnConst + GP_SIN;
-                }
+                for (int j = 0; j < K; ++j) GP_CHUNK_PUT(w.w & 31u, j, tos[j]);
+                GP_LEAF(w.z, w.y, tos);
             }
-            // unary: replaces the top
+        // unary: replaces the top
+        const uint32_t uop = GP_SIN + (f >> 8);
+        {
             switch (uop) {
             case GP_SIN:
             case GP_COS: {
@@ -798,13 +987,20 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
 #pragma unroll
                 for (int j = 0; j < K; ++j) big |= !(fabsf(tos[j]) <= kTrigFastLimit);
                 if (__builtin_expect(__ballot(big) != 0ull, 0)) {
+                    // rare: cases beyond the fast range take the library
+                    // function (with its large-argument reduction)
+                    if (uop == GP_SIN) {
 #pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        const float x = tos[j];
-                        if (fabsf(x) <= kTrigFastLimit)
-                            tos[j] = uop == GP_SIN ? sin_fast(x) : cos_fast(x);
-                        else
-                            tos[j] = uop == GP_SIN ? sinf(x) : cosf(x);
+                        for (int j = 0; j < K; ++j) {
+                            const float x = tos[j];
+                            tos[j] = fabsf(x) <= kTrigFastLimit ? sin_fast(x) : sinf(x);
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < K; ++j) {
+                            const float x = tos[j];
+                            tos[j] = fabsf(x) <= kTrigFastLimit ? cos_fast(x) : cosf(x);
+                        }
                     }
                 } else if (uop == GP_SIN) {
 #pragma unroll
@@ -832,14 +1028,14 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                 for (int j = 0; j < K; ++j) tos[j] = fabsf(tos[j]);
                 break;
             }
+            }
         }
-    } while (pc != pend);
-
+    } while (!(f & kFLast));
 }
 
 template <int MAXD, int K>
 __global__ __launch_bounds__(kWG) void k_eval(
-    const uint2* __restrict__ code, const ProgMeta* __restrict__ meta,
+    const uint4* __restrict__ code, const ProgMeta* __restrict__ meta,
     const int32_t* __restrict__ order, const int32_t* __restrict__ class_info,
     uint32_t* __restrict__ work_counter, const DevDataset* __restrict__ ds,
     const int32_t* __restrict__ seg_ds, const int32_t* __restrict__ seg_cnt,
@@ -850,29 +1046,30 @@ __global__ __launch_bounds__(kWG) void k_eval(
     static_assert(MAXD == 8 || MAXD == 16 || MAXD == 32, "stack class");
     constexpr int J = 32 / MAXD;                  // cases per 32-float chunk
     static_assert(K % J == 0 && K / J <= 4, "chunking");
-    constexpr int SUB = kWG * K;                  // cases per sub-tile
+    constexpr int SUB = 64 * K;                   // cases per sub-tile
     extern __shared__ float lds[];
-    float* xt = lds;                              // [max_vars][SUB]
-    float2* wpart = reinterpret_cast<float2*>(lds + (size_t)a.max_vars * SUB);  // [G][kWaves]
-    uint32_t* wbad = reinterpret_cast<uint32_t*>(wpart + a.G * kWaves);          // [G]
-    __shared__ uint32_t s_item;
+    float* xt = lds;                              // window: [W][n_vars + 1][SUB]
+    float2* acc = reinterpret_cast<float2*>(lds + a.tile_floats);            // [G]
+    uint32_t* accbad = reinterpret_cast<uint32_t*>(acc + a.G);               // [G]
+    __shared__ uint32_t s_item, s_next;
 
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
     const int lane = tid & 63;
-    const int lo = tid;                           // this lane's first case in a sub-tile
     const int c = a.cls;
     const int cstart = class_info[2 * c];
     const int32_t* __restrict__ cnt_c = seg_cnt + c * a.n_seg;
     const int32_t* __restrict__ pos_c = seg_pos + c * a.n_seg;
     const uint32_t* __restrict__ pre_c = item_pre + c * (a.n_seg + 1);
     const uint32_t n_items = pre_c[a.n_seg];
-    int staged_d = -1;                            // dataset and sub-tile in LDS
+    int staged_d = -1;                            // dataset and first sub-tile in LDS
     int64_t staged = -1;
 
     for (;;) {
         if (tid == 0) s_item = atomicAdd(work_counter, 1u);
-        if (tid < a.G) wbad[tid] = 0u;
+        if (tid < a.G) {
+            acc[tid] = make_float2(0.f, 0.f);
+            accbad[tid] = 0u;
+        }
         __syncthreads();
         const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= n_items) break;
@@ -893,6 +1090,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
         const int n_vars = Dp->n_vars;
         const float scale = Dp->scale;
         const int passes = Dp->passes[c];
+        const int window = Dp->window[c];
         const int count = cnt_c[sl];
         const int n_groups = (count + a.G - 1) / a.G;
         const uint32_t local = item - pre_c[sl];
@@ -901,50 +1099,59 @@ __global__ __launch_bounds__(kWG) void k_eval(
         const int g0 = grp * a.G;
         const int gn = min(a.G, count - g0);
         const int obase = cstart + pos_c[sl] + g0;
+        const int64_t n_sub = (n_cases + SUB - 1) / SUB;
+        const int rows = n_vars + 1;              // inputs, then the targets
 
-        for (int pass = 0; pass < passes; ++pass) {
-            const int64_t sub_idx = (int64_t)tile * passes + pass;
-            const int64_t base = sub_idx * SUB;
-            if (base >= n_cases) break;
-            if (sub_idx != staged || d != staged_d) {
-                __syncthreads();
-                for (int i = tid; i < n_vars * SUB; i += kWG) {
-                    const int v = i / SUB, cc = i - v * SUB;
-                    const int64_t gi = base + cc;
-                    xt[i] = gi < n_cases ? Xd[(int64_t)v * ld_x + gi] : 0.f;
+        for (int w0 = 0; w0 < passes; w0 += window) {
+            const int64_t first = (int64_t)tile * passes + w0;      // first sub-tile
+            if (first >= n_sub) break;
+            const int nw = (int)min((int64_t)min(window, passes - w0), n_sub - first);
+            if (first != staged || d != staged_d) {
+                // lane t's case j of a sub-tile is element j*64 + t of a
+                // row: conflict-free, lane-contiguous reads
+                for (int i = tid; i < nw * rows * SUB; i += kWG) {
+                    const int blk = i / (rows * SUB);
+                    const int r = i - blk * rows * SUB;
+                    const int v = r / SUB, cc = r - v * SUB;
+                    const int64_t gi = (first + blk) * SUB + cc;
+                    float val = 0.f;
+                    if (gi < n_cases) val = v < n_vars ? Xd[(int64_t)v * ld_x + gi] : yd[gi];
+                    xt[i] = val;
                 }
-                staged = sub_idx;
+                staged = first;
                 staged_d = d;
-                __syncthreads();
             }
-            float yv[K];
-            bool live[K];
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const int64_t gi = base + lo + j * kWG;
-                live[j] = gi < n_cases;
-                yv[j] = live[j] ? yd[gi] : 0.f;
-            }
-
-            for (int g = 0; g < gn; ++g) {
+            if (tid == 0) s_next = 0u;
+            __syncthreads();
+            // each wavefront takes the group's programs one at a time and
+            // runs each over the whole window
+            for (;;) {
+                uint32_t gq = 0u;
+                if (lane == 0) gq = atomicAdd(&s_next, 1u);
+                const int g = (int)__builtin_amdgcn_readfirstlane(gq);
+                if (g >= gn) break;
                 const int pid = order[obase + g];
                 const ProgMeta m = meta[pid];
-                float tos[K];
-                run_program<MAXD, K, SUB>(code + m.start, code + m.start + m.slen, xt + lo, tos);
-
                 // fused residual, validity and scaled compensated square sum
                 float hi = 0.f, lo_ = 0.f;
                 bool bad = false;
+                for (int b = 0; b < nw; ++b) {
+                    const float* blk = xt + b * rows * SUB;
+                    float tos[K];
+                    run_program<MAXD, K>(code + m.start, blk + lane, tos);
+                    const int64_t base = (first + b) * SUB;
+                    const float* yt = blk + n_vars * SUB;
 #pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    if (live[j]) {
-                        const float f = tos[j];
-                        bad |= !__builtin_isfinite(f);
-                        const float r = (f - yv[j]) * scale;
-                        float s, e;
-                        two_sum(hi, r * r, s, e);
-                        hi = s;
-                        lo_ += e;
+                    for (int j = 0; j < K; ++j) {
+                        if (base + lane + j * 64 < n_cases) {
+                            const float f = tos[j];
+                            bad |= !__builtin_isfinite(f);
+                            const float r = (f - yt[lane + j * 64]) * scale;
+                            float s, e;
+                            two_sum(hi, r * r, s, e);
+                            hi = s;
+                            lo_ += e;
+                        }
                     }
                 }
                 // wavefront tree: every lane ends with the same pair
@@ -955,29 +1162,22 @@ __global__ __launch_bounds__(kWG) void k_eval(
                     acc_pair(hi, lo_, h2, l2);
                 }
                 const bool wave_bad = __ballot(bad) != 0ull;
+                // one wavefront per program and window: the windows add up
+                // in order, whichever wavefront ran them
                 if (lane == 0) {
-                    float2 v = make_float2(hi, lo_);
-                    if (pass > 0) {
-                        float2 o = wpart[g * kWaves + wave];
-                        float h = o.x, l = o.y;
-                        acc_pair(h, l, v.x, v.y);
-                        v = make_float2(h, l);
-                    }
-                    wpart[g * kWaves + wave] = v;
+                    float h = acc[g].x, l = acc[g].y;
+                    acc_pair(h, l, hi, lo_);
+                    acc[g] = make_float2(h, l);
+                    if (wave_bad) accbad[g] = 1u;
                 }
-                if (wave_bad && lane == 0) atomicOr(&wbad[g], 1u);
             }
             __syncthreads();
         }
-        // combine the wavefronts in fixed order and store the tile partial
         if (tid < gn) {
             const int pid = order[obase + tid];
-            float h = wpart[tid * kWaves].x, l = wpart[tid * kWaves].y;
-#pragma unroll
-            for (int w = 1; w < kWaves; ++w) acc_pair(h, l, wpart[tid * kWaves + w].x, wpart[tid * kWaves + w].y);
             const int64_t slot = (int64_t)pid * a.part_stride + tile;
-            part[slot] = make_float2(h, l);
-            part_bad[slot] = (uint8_t)(wbad[tid] != 0u);
+            part[slot] = acc[tid];
+            part_bad[slot] = (uint8_t)(accbad[tid] != 0u);
         }
         __syncthreads();
     }
@@ -985,33 +1185,35 @@ __global__ __launch_bounds__(kWG) void k_eval(
 
 // ------------------------------------------------------------ k_predict
 // Per-case outputs f_p(x_i) of the programs of one depth class: persistent
-// workgroups pull (program, sub-tile) items; each lane writes its K values.
+// workgroups pull (group of four programs, sub-tile) items; each wavefront
+// runs one program of the group and each lane writes its K values.
 template <int MAXD, int K>
 __global__ __launch_bounds__(kWG) void k_predict(
-    const uint2* __restrict__ code, const ProgMeta* __restrict__ meta,
+    const uint4* __restrict__ code, const ProgMeta* __restrict__ meta,
     const int32_t* __restrict__ order, const int32_t* __restrict__ class_info,
     uint32_t* __restrict__ work_counter, const float* __restrict__ X,
     float* __restrict__ out, int64_t ld_out, EvalConst a)
 {
-    constexpr int SUB = kWG * K;
+    constexpr int SUB = 64 * K;
     extern __shared__ float lds[];
     float* xt = lds;                              // [n_vars][SUB]
     __shared__ uint32_t s_item;
     const int tid = threadIdx.x;
-    const int lo = tid;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
     const int start = class_info[2 * a.cls];
     const int count = class_info[2 * a.cls + 1];
+    const int n_groups = (count + kWaves - 1) / kWaves;
     const int64_t n_sub = (a.n_cases + SUB - 1) / SUB;
-    const uint64_t n_items = (uint64_t)count * (uint64_t)n_sub;
+    const uint64_t n_items = (uint64_t)n_groups * (uint64_t)n_sub;
     int64_t staged = -1;
     for (;;) {
         if (tid == 0) s_item = atomicAdd(work_counter, 1u);
         __syncthreads();
         const uint64_t item = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
         if (item >= n_items) break;
-        const int64_t sub = (int64_t)(item / (uint64_t)count);
-        const int g = (int)(item % (uint64_t)count);
+        const int64_t sub = (int64_t)(item / (uint64_t)n_groups);
+        const int grp = (int)(item % (uint64_t)n_groups);
         const int64_t base = sub * SUB;
         if (sub != staged) {
             for (int i = tid; i < a.n_vars * SUB; i += kWG) {
@@ -1020,16 +1222,19 @@ __global__ __launch_bounds__(kWG) void k_predict(
                 xt[i] = gi < a.n_cases ? X[(int64_t)v * a.ld_x + gi] : 0.f;
             }
             staged = sub;
-            __syncthreads();
         }
-        const int pid = order[start + g];
-        const ProgMeta m = meta[pid];
-        float tos[K];
-        run_program<MAXD, K, SUB>(code + m.start, code + m.start + m.slen, xt + lo, tos);
+        __syncthreads();
+        const int g = grp * kWaves + wave;
+        if (g < count) {
+            const int pid = order[start + g];
+            const ProgMeta m = meta[pid];
+            float tos[K];
+            run_program<MAXD, K>(code + m.start, xt + lane, tos);
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int64_t gi = base + lo + j * kWG;
-            if (gi < a.n_cases) out[(int64_t)pid * ld_out + gi] = tos[j];
+            for (int j = 0; j < K; ++j) {
+                const int64_t gi = base + lane + j * 64;
+                if (gi < a.n_cases) out[(int64_t)pid * ld_out + gi] = tos[j];
+            }
         }
         __syncthreads();
     }
@@ -1085,8 +1290,9 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
 
 // ----------------------------------------------------------- workspaces
 struct Layout {
-    size_t code, meta, cls, order, blk_counts, blk_base, class_info, counters, part, part_bad;
-    size_t ds, req, seg_ds, seg_start, seg_cnt, seg_pos, item_pre, pds, bad, total;
+    size_t code, meta, cls, order, blk_counts, blk_base, blk_slen, blk_code, class_info, counters;
+    size_t part, part_bad;
+    size_t ds, req, seg_ds, seg_start, seg_cnt, seg_pos, item_pre, pds, bad, overflow, total;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
@@ -1097,12 +1303,15 @@ Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride, int
     Layout L;
     const int64_t n_blk = (n_programs + kBucketBlock - 1) / kBucketBlock;
     size_t off = 0;
-    L.code = off;       off = align_up(off + (size_t)(n_nodes + 1) * sizeof(uint2));
+    // a staged program never holds more instructions than nodes
+    L.code = off;       off = align_up(off + (size_t)(n_nodes + 1) * sizeof(uint4));
     L.meta = off;       off = align_up(off + (size_t)n_programs * sizeof(ProgMeta));
     L.cls = off;        off = align_up(off + (size_t)n_programs);
     L.order = off;      off = align_up(off + (size_t)n_programs * 4);
     L.blk_counts = off; off = align_up(off + (size_t)kKeys * n_blk * 4);
     L.blk_base = off;   off = align_up(off + (size_t)kKeys * n_blk * 4);
+    L.blk_slen = off;   off = align_up(off + (size_t)n_blk * 8);
+    L.blk_code = off;   off = align_up(off + (size_t)n_blk * 8);
     L.class_info = off; off = align_up(off + 2 * kClasses * 4);
     L.counters = off;   off = align_up(off + kClasses * 4);
     L.part = off;       off = align_up(off + (size_t)n_programs * part_stride * sizeof(float2));
@@ -1116,18 +1325,21 @@ Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride, int
     L.item_pre = off;   off = align_up(off + (size_t)kClasses * (n_seg + 1) * 4);
     L.pds = off;        off = align_up(off + (size_t)n_programs * 4);
     L.bad = off;        off = align_up(off + 4);
+    L.overflow = off;   off = align_up(off + 4);
     L.total = off;
     return L;
 }
 
 // Device views of one call's workspace.
 struct Staged {
-    uint2* code;
+    uint4* code;
     ProgMeta* meta;
     uint8_t* cls;
     int32_t* order;
     int32_t* blk_counts;
     int32_t* blk_base;
+    int64_t* blk_slen;
+    int64_t* blk_code;
     int32_t* class_info;
     uint32_t* counters;
     float2* part;
@@ -1141,18 +1353,21 @@ struct Staged {
     uint32_t* item_pre;
     int32_t* pds;
     int32_t* bad;
+    int32_t* overflow;
 };
 
 Staged carve(void* base, const Layout& L)
 {
     char* ws = static_cast<char*>(base);
     Staged st;
-    st.code = reinterpret_cast<uint2*>(ws + L.code);
+    st.code = reinterpret_cast<uint4*>(ws + L.code);
     st.meta = reinterpret_cast<ProgMeta*>(ws + L.meta);
     st.cls = reinterpret_cast<uint8_t*>(ws + L.cls);
     st.order = reinterpret_cast<int32_t*>(ws + L.order);
     st.blk_counts = reinterpret_cast<int32_t*>(ws + L.blk_counts);
     st.blk_base = reinterpret_cast<int32_t*>(ws + L.blk_base);
+    st.blk_slen = reinterpret_cast<int64_t*>(ws + L.blk_slen);
+    st.blk_code = reinterpret_cast<int64_t*>(ws + L.blk_code);
     st.class_info = reinterpret_cast<int32_t*>(ws + L.class_info);
     st.counters = reinterpret_cast<uint32_t*>(ws + L.counters);
     st.part = reinterpret_cast<float2*>(ws + L.part);
@@ -1166,6 +1381,7 @@ Staged carve(void* base, const Layout& L)
     st.item_pre = reinterpret_cast<uint32_t*>(ws + L.item_pre);
     st.pds = reinterpret_cast<int32_t*>(ws + L.pds);
     st.bad = reinterpret_cast<int32_t*>(ws + L.bad);
+    st.overflow = reinterpret_cast<int32_t*>(ws + L.overflow);
     return st;
 }
 
@@ -1360,7 +1576,7 @@ struct Tuning {
 };
 
 struct EvalPtrs {
-    const uint2* code;
+    const uint4* code;
     const ProgMeta* meta;
     const int32_t* order;
     const int32_t* class_info;
@@ -1372,9 +1588,19 @@ struct EvalPtrs {
 };
 
 template <int MAXD, int K>
+size_t eval_tile_floats(int n_vars)
+{
+    // every dataset's window fits the budget; a single sub-tile of a dataset
+    // with very many variables may need more
+    const size_t one = (size_t)(n_vars + 1) * 64 * K;
+    const size_t budget = kTileLds / sizeof(float);
+    return one > budget ? one : budget;
+}
+
+template <int MAXD, int K>
 size_t eval_lds_bytes(int n_vars, int G)
 {
-    return (size_t)n_vars * kWG * K * sizeof(float) + (size_t)G * kWaves * sizeof(float2) +
+    return eval_tile_floats<MAXD, K>(n_vars) * sizeof(float) + (size_t)G * sizeof(float2) +
            (size_t)G * sizeof(uint32_t);
 }
 
@@ -1412,8 +1638,8 @@ int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
     for (int c = 0; c < kClasses; ++c) {
         // tile counts grow with n_cases, so the largest dataset sizes the
         // partial buffer
-        const TileShape t = tile_shape(pb.max_cases, class_k(c, pb.max_vars));
-        if (t.n_tiles > el->stride) el->stride = t.n_tiles;
+        const int32_t t = max_tiles(pb.max_cases, class_k(c, pb.max_vars));
+        if (t > el->stride) el->stride = t;
     }
     if ((rc = eval_grid<8, 4>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
     if ((rc = eval_grid<16, 4>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
@@ -1427,24 +1653,22 @@ int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
 int enqueue_stage(const Problem& pb, const Staged& st, hipStream_t stream)
 {
     const int32_t n_blk = (int32_t)((pb.n_programs + kBucketBlock - 1) / kBucketBlock);
-    const unsigned grid_p = (unsigned)((pb.n_programs + 255) / 256);
     hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, stream, pb.ds_dev, pb.n_ds, pb.one,
                        pb.req_dev, pb.n_req, pb.one_req, pb.n_programs, pb.n_nodes, pb.max_vars,
                        pb.max_cases, pb.need_out, st.ds, st.req, st.seg_ds, st.seg_start, st.bad);
     GP_HIP_TRY(hipGetLastError());
     const int32_t lpt = pb.n_req == 1 ? 1 : 0;
-    hipLaunchKernelGGL(k_prepare, dim3(grid_p), dim3(256), 0, stream, pb.n_programs, pb.allowed,
-                       st.ds, st.req, st.seg_start, pb.n_req, st.bad, lpt, st.code, st.meta,
-                       st.cls, st.pds);
+    hipLaunchKernelGGL(k_validate, dim3(n_blk), dim3(kBucketBlock), 0, stream, pb.n_programs,
+                       pb.allowed, st.ds, st.req, st.seg_start, pb.n_req, st.bad, lpt, n_blk,
+                       st.meta, st.cls, st.pds, st.blk_counts, st.blk_slen);
     GP_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_class_count, dim3(n_blk), dim3(kBucketBlock), 0, stream, st.cls,
-                       pb.n_programs, n_blk, st.blk_counts);
+    hipLaunchKernelGGL(k_class_scan, dim3(1), dim3(1024), 0, stream, st.blk_counts, st.blk_slen,
+                       n_blk, pb.n_nodes, st.blk_base, st.blk_code, st.class_info, st.counters,
+                       st.overflow);
     GP_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_class_scan, dim3(1), dim3(1024), 0, stream, st.blk_counts, n_blk,
-                       st.blk_base, st.class_info, st.counters);
-    GP_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_class_scatter, dim3(n_blk), dim3(kBucketBlock), 0, stream, st.cls,
-                       pb.n_programs, n_blk, st.blk_base, st.order);
+    hipLaunchKernelGGL(k_stage, dim3(n_blk), dim3(kBucketBlock), 0, stream, pb.n_programs, st.ds,
+                       st.req, st.seg_start, st.pds, n_blk, st.blk_code, st.blk_base, st.overflow,
+                       st.cls, st.meta, st.code, st.order);
     GP_HIP_TRY(hipGetLastError());
     return GP_OK;
 }
@@ -1483,9 +1707,16 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
         hipLaunchKernelGGL((k_eval<MD, KK>), g, b, el.lds[c], sc, st.code, st.meta, st.order,  \
                            st.class_info, st.counters + c, st.ds, st.seg_ds, st.seg_cnt,       \
                            st.seg_pos, st.item_pre, st.part, st.part_bad, ea)
-        if (c == 0) GP_LAUNCH_EVAL(8, 4);
-        else if (c == 1) GP_LAUNCH_EVAL(16, 4);
-        else GP_LAUNCH_EVAL(32, 2);
+        if (c == 0) {
+            ea.tile_floats = (int32_t)eval_tile_floats<8, 4>(pb.max_vars);
+            GP_LAUNCH_EVAL(8, 4);
+        } else if (c == 1) {
+            ea.tile_floats = (int32_t)eval_tile_floats<16, 4>(pb.max_vars);
+            GP_LAUNCH_EVAL(16, 4);
+        } else {
+            ea.tile_floats = (int32_t)eval_tile_floats<32, 2>(pb.max_vars);
+            GP_LAUNCH_EVAL(32, 2);
+        }
 #undef GP_LAUNCH_EVAL
         GP_HIP_TRY(hipGetLastError());
     }
@@ -1512,7 +1743,7 @@ template <int MAXD, int K>
 int launch_predict(const EvalPtrs& p, float* out, int64_t ld_out, const EvalConst& args,
                    hipStream_t stream, int cus)
 {
-    const size_t lds = (size_t)args.n_vars * kWG * K * sizeof(float);
+    const size_t lds = (size_t)args.n_vars * 64 * K * sizeof(float);
     if (lds > 64 * 1024) {
         GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_predict<MAXD, K>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -2006,8 +2237,8 @@ int gp_workspace_size(int64_t n_programs, int64_t n_nodes, int32_t n_requests,
         return set_error(GP_E_INVALID_ARG, "sizes out of range");
     int32_t stride = 1;
     for (int c = 0; c < kClasses; ++c) {
-        const TileShape t = tile_shape(max_n_cases, class_k(c, max_n_vars));
-        if (t.n_tiles > stride) stride = t.n_tiles;
+        const int32_t t = max_tiles(max_n_cases, class_k(c, max_n_vars));
+        if (t > stride) stride = t;
     }
     const size_t need = make_layout(n_programs, n_nodes, stride, n_datasets, n_requests).total;
     *bytes = need + need / 4;      // the growth slack get_workspace adds

@@ -145,3 +145,26 @@ def test_batched_rejects_bad_table():
     with pytest.raises(gp.GPError):
         gp.gp_eval_batched(gp.table_tensor([good]), gp.table_tensor([]), P, pop.nodes.numel(),
                            d.n_vars, d.n_cases)
+
+
+def test_batched_tile_counts_of_mixed_sizes():
+    """A smaller dataset can need more case tiles than the largest one of
+    the call (33 sub-tiles make 17 tiles, 32 make 32): partial rows must be
+    sized for both, and results stay equal to scoring alone."""
+    gp = _gp()
+    from paper_2607_06731_amd import synth
+    rng = np.random.default_rng(77)
+    runs = []
+    for n in (33 * 256 - 5, 32 * 256 - 7, 65 * 128 + 3):
+        X = rng.standard_normal((3, n)).astype(np.float32)
+        y = (X[0] * X[1] + rng.normal(0, 0.05, n)).astype(np.float32)
+        runs.append(synth.ServingRun(len(runs), synth.Dataset(X, y)))
+    reqs = [(i, synth.make_serving_request(rng, runs[i], min_pop=300, max_pop=600))
+            for i in (0, 1, 2, 1)]
+    _say("batched mixed tile counts")
+    got = _run_batched(gp, runs, reqs, 1e-3)
+    for (i, pop), (F, st) in zip(reqs, got):
+        alone = gp.evaluate(pop.nodes, pop.offsets, pop.consts, runs[i].data.X, runs[i].data.y,
+                            1e-3, 0)
+        assert (st == 0).all()
+        assert np.array_equal(F, alone, equal_nan=True)

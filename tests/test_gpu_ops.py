@@ -164,3 +164,70 @@ def test_predict_agrees_with_eval():
     both = np.isfinite(Fp)
     assert np.array_equal(both, np.isfinite(F))
     assert np.all(np.abs(F[both] - Fp[both]) <= 1e-6 * np.abs(Fp[both]) + 1e-12)
+
+
+def test_overlapping_node_ranges():
+    """Programs may share nodes through their offsets; each staged program
+    gets its own range.  If the staged programs together would need more
+    than n_nodes entries, no program of the call is evaluated and all get
+    GP_PROG_BAD_OFFSETS (never a write outside the staging buffer)."""
+    gp = _gp()
+    v = lambda j: LOAD | (j << 8)
+    nodes = np.array([v(0), v(1), ADD, v(0), MUL], np.uint32)
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-2, 2, (2, 700)).astype(np.float32)
+    y = rng.uniform(-2, 2, 700).astype(np.float32)
+    consts = np.zeros(0, np.float32)
+    _say("overlapping node ranges")
+    # p0 = nodes[0:3], p1 = nodes[3:0] (decreasing), p2 = nodes[0:5]: 5 staged entries fit
+    off = np.array([0, 3, 0, 5], np.int64)
+    F, st = gp.evaluate(nodes, off, consts, X, y, 0.0, 0, return_status=True)
+    assert st.tolist() == [0, 8, 0] and np.isnan(F[1])
+    for p in (0, 2):
+        sn, so = oracle.subset(nodes, off, [p])
+        ref, _, _ = oracle.fitness(sn, so, consts, X, y)
+        assert abs(F[p] - ref[0]) <= 1e-4 * abs(ref[0]) + 1e-12
+    # p0 = p2 = nodes[0:5]: 6 staged entries > 5 nodes
+    off = np.array([0, 5, 0, 5], np.int64)
+    F, st = gp.evaluate(nodes, off, consts, X, y, 0.0, 0, return_status=True)
+    assert st.tolist() == [8, 8, 8] and np.isnan(F).all()
+
+
+def test_constant_subtrees_fold_to_the_same_bits():
+    """Constant subtrees are computed once while staging, with the
+    interpreter's own arithmetic: every per-case output must equal, bit for
+    bit, the same program with each constant read from an input row that
+    holds that constant in every case (which the interpreter evaluates per
+    case)."""
+    gp = _gp()
+    c = lambda j: CONST | (j << 8)
+    v = lambda j: LOAD | (j << 8)
+    consts = np.array([0.75, -2.5, 1e-4, 3e5, 88.5, -0.0, 1e30], np.float32)
+    n_c = consts.size
+    shapes = [
+        [c(0), SIN], [c(3), COS, c(1), MUL], [c(4), EXP, c(6), MUL], [c(2), LOG],
+        [c(1), SQRT, c(0), DIV], [c(5), ABS, c(1), ADD], [c(0), c(1), DIV, SIN, v(0), ADD],
+        [v(0), c(0), c(1), MUL, SUB], [c(0), v(0), c(1), MUL, ADD],
+        [c(1), c(2), DIV, v(0), MUL, c(3), SIN, c(4), COS, MUL, SUB],
+        [c(6), c(6), MUL, v(0), ADD],                    # overflow in the folded part
+        [v(0), c(2), c(5), SUB, DIV],                    # protected division by a small constant
+        [c(0), EXP, EXP, EXP, LOG, c(1), COS, ADD],
+    ]
+    # the same programs with constant j read from input row 1 + j
+    as_vars = [[v(1 + (t >> 8)) if (t & 0xFF) == CONST else t for t in prog] for prog in shapes]
+    rng = np.random.default_rng(9)
+    X = np.empty((1 + n_c, 3000), np.float32)
+    X[0] = rng.uniform(-4, 4, 3000)
+    X[1:] = consts[:, None]
+    for group in (shapes, as_vars):
+        lens = [len(p) for p in group]
+        assert max(lens) <= 64
+    flat = lambda g: (np.array([t for p in g for t in p], np.uint32),
+                      np.concatenate([[0], np.cumsum([len(p) for p in g])]).astype(np.int64))
+    n1, o1 = flat(shapes)
+    n2, o2 = flat(as_vars)
+    _say("constant folding bit identity")
+    got = gp.predict(n1, o1, consts, X)
+    ref = gp.predict(n2, o2, consts, X)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), \
+        np.nonzero(got.view(np.uint32) != ref.view(np.uint32))
