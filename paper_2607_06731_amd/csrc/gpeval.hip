@@ -39,6 +39,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -96,7 +97,8 @@ constexpr int kLenBuckets = 8;           // staged length 1, 2-3, ..., 64-127, 1
 constexpr int kKeys = kClasses * kLenBuckets;
 constexpr int kMaxTiles = 32;            // case tiles per program (cap)
 constexpr uint32_t kNoSlot = 0xFFu;      // staged write slot: nothing to save
-constexpr int kBucketBlock = 1024;       // programs per partition block
+constexpr int kBucketBlock = 256;        // programs per staging/partition block
+constexpr int kStageNodes = 12288;       // LDS node cache of a staging block (48 KB)
 constexpr int kMaxRequests = 4096;       // requests per batched call (tables are scanned by one workgroup)
 
 // Per-program record written by the staging passes.
@@ -459,8 +461,59 @@ __device__ __forceinline__ int request_of(const int64_t* __restrict__ seg_start,
     return lo;
 }
 
-// Emits the staged instructions of one valid program (EMIT) or only counts
-// them.  Constants are held back on a shadow stack and folded: an operator
+// Node readers for the staging passes: straight from the request's array,
+// or from the block's LDS copy of its node range.
+struct GlobalNodes {
+    const uint32_t* __restrict__ p;
+    __device__ uint32_t operator()(int64_t k) const { return p[k]; }
+};
+struct LdsNodes {
+    const uint32_t* p;          // LDS
+    int64_t lo;                 // first cached node
+    __device__ uint32_t operator()(int64_t k) const { return p[k - lo]; }
+};
+
+// Cooperative, coalesced copy of the node range [min s, max e) of the
+// block's programs into LDS, when they all belong to one request and the
+// range fits.  `mine`: this thread has a program with a valid node range.
+// Every thread of the block must call it.  Returns true when the copy is
+// used (then *lo is the first cached node).
+__device__ bool cache_block_nodes(bool mine, int r, int64_t s, int64_t e,
+                                  const DevRequest* __restrict__ reqs, uint32_t* cache,
+                                  int64_t* lo)
+{
+    __shared__ long long s_lo, s_hi;
+    __shared__ int s_r, s_mixed, s_any;
+    if (threadIdx.x == 0) {
+        s_lo = LLONG_MAX;
+        s_hi = LLONG_MIN;
+        s_r = -1;
+        s_mixed = 0;
+        s_any = 0;
+    }
+    __syncthreads();
+    if (mine) {
+        atomicMin(&s_lo, (long long)s);
+        atomicMax(&s_hi, (long long)e);
+        atomicMax(&s_r, r);
+        s_any = 1;
+    }
+    __syncthreads();
+    if (mine && r != s_r) s_mixed = 1;
+    __syncthreads();
+    const bool use = s_any && !s_mixed && s_hi - s_lo <= kStageNodes;
+    if (use) {
+        const uint32_t* __restrict__ src = reqs[s_r].nodes + s_lo;
+        const int n = (int)(s_hi - s_lo);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) cache[i] = src[i];
+        *lo = s_lo;
+    }
+    __syncthreads();
+    return use;
+}
+
+// Emits the staged instructions of one valid program (k_validate counts
+// them with the same rules as it validates).  Constants are held back on a shadow stack and folded: an operator
 // whose operands are all held-back constants is computed here, once, with
 // the interpreter's own scalar arithmetic (the same bits every case would
 // get), and only its value travels on.  Held-back constants always sit on
@@ -470,48 +523,50 @@ __device__ __forceinline__ int request_of(const int64_t* __restrict__ seg_start,
 // followed by an operator folds into it (top OP x, or save + f(x)).  What is
 // folded depends only on the node kinds, never on values, so counting and
 // emitting agree.
-template <bool EMIT>
-__device__ int64_t stage_walk(const uint32_t* __restrict__ nodes, int64_t s, int64_t e,
+template <class Nodes>
+__device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e,
                               const float* __restrict__ consts, uint32_t J, uint32_t row_bytes,
-                              uint4* __restrict__ out)
+                              uint4* __restrict__ out, int64_t cap)
 {
+    // never writes past the range k_validate sized (`cap` entries)
+    auto put = [&](int64_t i, uint4 v) {
+        if (i < cap) out[i] = v;
+    };
     const uint32_t dummy = 32u - J;              // slot MAXD-1: never live
     float pv[GP_MAX_STACK];                      // held-back constant values
     int rt = 0;                                  // runtime stack depth
     int np = 0;                                  // held-back constants
     int64_t n = 0;                               // emitted instructions
     for (int64_t k = s; k < e; ++k) {
-        const uint32_t w = nodes[k];
+        const uint32_t w = nodes(k);
         const uint32_t op = w & 0xFFu, arg = w >> 8;
         if (op == GP_CONST) {
-            if (EMIT) pv[np] = consts[arg];
+            pv[np & (GP_MAX_STACK - 1)] = consts[arg];   // np < 32 in a valid program
             ++np;
             continue;
         }
         if (op == GP_LOAD) {
             // flush: held-back constants become runtime elements, bottom up
             for (int i = 0; i < np; ++i) {
-                if (EMIT) {
-                    const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
-                    out[n] = make_uint4(kFPush, __float_as_uint(pv[i]), 1u, wr);
-                }
+                const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
+                put(n, make_uint4(kFPush, __float_as_uint(pv[i]), 1u, wr));
                 ++n;
                 ++rt;
             }
             np = 0;
             const uint32_t payload = arg * row_bytes;
-            const uint32_t nx = k + 1 < e ? (nodes[k + 1] & 0xFFu) : 0xFFu;
+            const uint32_t nx = k + 1 < e ? (nodes(k + 1) & 0xFFu) : 0xFFu;
             const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
             if (nx >= GP_ADD && nx <= GP_DIV) {
                 // top = top OP x (the binary op has a runtime element below)
-                if (EMIT) out[n] = make_uint4(kFLBin | ((nx - GP_ADD) << 8), payload, 0u, 0u);
+                put(n, make_uint4(kFLBin | ((nx - GP_ADD) << 8), payload, 0u, 0u));
                 ++k;
             } else if (nx >= GP_SIN && nx < GP_N_OPS) {
-                if (EMIT) out[n] = make_uint4(kFPush | kFUn | ((nx - GP_SIN) << 8), payload, 0u, wr);
+                put(n, make_uint4(kFPush | kFUn | ((nx - GP_SIN) << 8), payload, 0u, wr));
                 ++rt;
                 ++k;
             } else {
-                if (EMIT) out[n] = make_uint4(kFPush, payload, 0u, wr);
+                put(n, make_uint4(kFPush, payload, 0u, wr));
                 ++rt;
             }
             ++n;
@@ -521,46 +576,86 @@ __device__ int64_t stage_walk(const uint32_t* __restrict__ nodes, int64_t s, int
             const uint32_t bop = op - GP_ADD;
             if (np >= 2) {
                 --np;
-                if (EMIT) pv[np - 1] = binary_value(op, pv[np - 1], pv[np]);
+                pv[np - 1] = binary_value(op, pv[np - 1], pv[np]);
             } else if (np == 1) {
                 // top = top OP c: the runtime top is the left operand
                 --np;
-                if (EMIT) out[n] = make_uint4(kFLBin | (bop << 8), __float_as_uint(pv[0]), 1u, 0u);
+                put(n, make_uint4(kFLBin | (bop << 8), __float_as_uint(pv[0]), 1u, 0u));
                 ++n;
             } else {
                 // second from top (element rt-2) is read from slot rt-2
-                if (EMIT) out[n] = make_uint4(kFSBin | (bop << 8), 0u, (uint32_t)(rt - 2) * J, 0u);
+                put(n, make_uint4(kFSBin | (bop << 8), 0u, (uint32_t)(rt - 2) * J, 0u));
                 ++n;
                 --rt;
             }
             continue;
         }
         if (np >= 1) {
-            if (EMIT) pv[np - 1] = unary_value(op, pv[np - 1]);
+            pv[np - 1] = unary_value(op, pv[np - 1]);
         } else {
-            if (EMIT) out[n] = make_uint4(kFUn | ((op - GP_SIN) << 8), 0u, 0u, 0u);
+            put(n, make_uint4(kFUn | ((op - GP_SIN) << 8), 0u, 0u, 0u));
             ++n;
         }
     }
     // a constant program: its value is pushed
     for (int i = 0; i < np; ++i) {
-        if (EMIT) {
-            const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
-            out[n] = make_uint4(kFPush, __float_as_uint(pv[i]), 1u, wr);
-        }
+        const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
+        put(n, make_uint4(kFPush, __float_as_uint(pv[i]), 1u, wr));
         ++n;
         ++rt;
     }
-    if (EMIT && n > 0) out[n - 1].x |= kFLast;
+    if (n > 0 && n <= cap) out[n - 1].x |= kFLast;
     return n;
 }
 
-// Pass 1, one thread per program (blocks of kBucketBlock): validate (GCL
-// stack discipline, operand ranges, allowed ops), count the staged
-// instructions the program needs (a leaf directly followed by an operator
-// folds into it), derive the depth
-// class and the partition key, and accumulate per-block key counts and
-// staged sizes for the scans that follow.
+// Validation of one program (GCL stack discipline, operand ranges,
+// allowed ops) and the count of staged instructions, by the same rules
+// stage_walk emits them: held-back constants (np), a variable folding into
+// the operator after it.
+template <class Nodes>
+__device__ void check_program(Nodes nodes, int64_t s, int64_t e, uint32_t allowed,
+                              int32_t n_vars, int64_t n_consts, int& status, int& maxd,
+                              int64_t& n_staged)
+{
+    int depth = 0;
+    int64_t n_st = 0;
+    int np = 0;
+    bool taken = false;
+    for (int64_t k = s; k < e; ++k) {
+        const uint32_t w = nodes(k);
+        const uint32_t op = w & 0xFFu, arg = w >> 8;
+        if (op >= GP_N_OPS || !((allowed >> op) & 1u)) { status = GP_PROG_BAD_OP; break; }
+        if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) { status = GP_PROG_BAD_VAR; break; }
+        if (op == GP_CONST && (int64_t)arg >= n_consts) { status = GP_PROG_BAD_CONST; break; }
+        const int need = op <= GP_CONST ? 0 : (op <= GP_DIV ? 2 : 1);
+        if (depth < need) { status = GP_PROG_UNDERFLOW; break; }
+        depth += op <= GP_CONST ? 1 : (op <= GP_DIV ? -1 : 0);
+        if (depth > GP_MAX_STACK) { status = GP_PROG_TOO_DEEP; break; }
+        if (depth > maxd) maxd = depth;
+        if (op == GP_CONST) {
+            ++np;
+        } else if (op == GP_LOAD) {
+            n_st += np + 1;                   // flush, then the variable
+            np = 0;
+            taken = k + 1 < e && (nodes(k + 1) & 0xFFu) > GP_CONST;
+        } else if (taken) {
+            taken = false;                    // folded into the variable
+        } else if (op <= GP_DIV) {
+            if (np >= 2) --np;
+            else if (np == 1) { np = 0; ++n_st; }
+            else ++n_st;
+        } else if (np == 0) {
+            ++n_st;
+        }
+    }
+    if (status == GP_PROG_OK && depth != 1) status = GP_PROG_FINAL_DEPTH;
+    n_staged = n_st + np;
+}
+
+// Pass 1, one thread per program (blocks of kBucketBlock): validate, count
+// staged instructions, derive the depth class and the partition key, and
+// accumulate per-block key counts and staged sizes for the scans that
+// follow.  The block's nodes are read from an LDS copy when they fit.
 __global__ __launch_bounds__(kBucketBlock) void k_validate(
     int64_t n_programs, uint32_t allowed, const DevDataset* __restrict__ ds,
     const DevRequest* __restrict__ reqs, const int64_t* __restrict__ seg_start, int32_t n_seg,
@@ -570,47 +665,53 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
 {
     __shared__ int cnt[kKeys];
     __shared__ unsigned long long s_slen;
+    __shared__ uint32_t cache[kStageNodes];
     if (threadIdx.x < kKeys) cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_slen = 0ull;
-    __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * kBucketBlock + threadIdx.x;
-    if (p < n_programs) {
-        const int r = request_of(seg_start, n_seg, p);
-        const DevRequest R = reqs[r];
-        const int64_t q = p - seg_start[r];           // index inside the request
+    const bool have = p < n_programs;
+    const bool tab_ok = *tables_bad == 0;
+    int r = 0;
+    int64_t q = 0, s = 0, e = 0;
+    DevRequest R{};
+    if (have) {
+        r = request_of(seg_start, n_seg, p);
+        R = reqs[r];
+        q = p - seg_start[r];                 // index inside the request
         pds[p] = r;
-        const uint32_t* __restrict__ nodes = R.nodes;
-        const int32_t n_vars = ds[R.dataset].n_vars;
-        const bool tab_ok = *tables_bad == 0;
-        const int64_t s = tab_ok ? R.offsets[q] : 0, e = tab_ok ? R.offsets[q + 1] : 0;
+        if (tab_ok) {
+            s = R.offsets[q];
+            e = R.offsets[q + 1];
+        }
+    }
+    const bool range_ok = s >= 0 && e >= s && e <= R.n_nodes && e - s <= INT32_MAX - 1;
+    int64_t lo = 0;
+    const bool cached = cache_block_nodes(have && tab_ok && range_ok && e > s, r, s, e, reqs,
+                                          cache, &lo);
+    if (have) {
         int status = GP_PROG_OK;
-        int depth = 0, maxd = 0;
+        int maxd = 0;
+        int64_t n_staged = 0;
         if (!tab_ok) {
             status = GP_PROG_BAD_TABLE;
-        } else if (s < 0 || e < s || e > R.n_nodes || e - s > INT32_MAX - 1) {
+        } else if (!range_ok) {
             status = GP_PROG_BAD_OFFSETS;
         } else if (e == s) {
             status = GP_PROG_EMPTY;
         } else {
-            for (int64_t k = s; k < e; ++k) {
-                const uint32_t w = nodes[k];
-                const uint32_t op = w & 0xFFu, arg = w >> 8;
-                if (op >= GP_N_OPS || !((allowed >> op) & 1u)) { status = GP_PROG_BAD_OP; break; }
-                if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) { status = GP_PROG_BAD_VAR; break; }
-                if (op == GP_CONST && (int64_t)arg >= R.n_consts) { status = GP_PROG_BAD_CONST; break; }
-                const int need = op <= GP_CONST ? 0 : (op <= GP_DIV ? 2 : 1);
-                if (depth < need) { status = GP_PROG_UNDERFLOW; break; }
-                depth += op <= GP_CONST ? 1 : (op <= GP_DIV ? -1 : 0);
-                if (depth > GP_MAX_STACK) { status = GP_PROG_TOO_DEEP; break; }
-                if (depth > maxd) maxd = depth;
-            }
-            if (status == GP_PROG_OK && depth != 1) status = GP_PROG_FINAL_DEPTH;
+            const int32_t n_vars = ds[R.dataset].n_vars;
+            if (cached)
+                check_program(LdsNodes{cache, lo}, s, e, allowed, n_vars, R.n_consts, status, maxd,
+                              n_staged);
+            else
+                check_program(GlobalNodes{R.nodes}, s, e, allowed, n_vars, R.n_consts, status,
+                              maxd, n_staged);
         }
         const int c = status == GP_PROG_OK ? depth_class(maxd) : -1;
         ProgMeta m;
         m.start = 0;
         m.len = (int32_t)(status == GP_PROG_BAD_OFFSETS || status == GP_PROG_BAD_TABLE ? 0 : e - s);
-        m.slen = c >= 0 ? (int32_t)stage_walk<false>(nodes, s, e, nullptr, 0u, 0u, nullptr) : 0;
+        m.slen = c >= 0 ? (int32_t)n_staged : 0;
         meta[p] = m;
         // partition key: depth class, then (single-request calls) length
         // band from longest to shortest; with several requests the order
@@ -719,6 +820,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_stage(
     __shared__ long long sc[kBucketBlock];
     constexpr int kW = kBucketBlock / 64;
     __shared__ int wcnt[kW][kKeys];
+    __shared__ uint32_t cache[kStageNodes];
     const int t = threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * kBucketBlock + t;
     int key = p < n_programs ? (int)cls[p] : 0xFF;
@@ -748,18 +850,26 @@ __global__ __launch_bounds__(kBucketBlock) void k_stage(
         __syncthreads();
     }
     const int64_t start = blk_code[blockIdx.x] + sc[t] - m.slen;
+    int r = 0;
+    int64_t s = 0, e = 0;
+    DevRequest R{};
+    if (key < kKeys) {
+        r = pds[p];
+        R = reqs[r];
+        const int64_t q = p - seg_start[r];
+        s = R.offsets[q];
+        e = R.offsets[q + 1];
+    }
+    int64_t lo = 0;
+    const bool cached = cache_block_nodes(key < kKeys, r, s, e, reqs, cache, &lo);
     if (key < kKeys) {
         const int c = key / kLenBuckets;
-        const int r = pds[p];
-        const DevRequest R = reqs[r];
-        const int64_t q = p - seg_start[r];
-        const uint32_t* __restrict__ nodes = R.nodes;
-        const float* __restrict__ consts = R.consts;
-        const int64_t s = R.offsets[q], e = R.offsets[q + 1];
         const uint32_t J = 32u / (uint32_t)class_depth(c);
         const uint32_t row_bytes = (uint32_t)(64 * class_k(c, ds[R.dataset].n_vars)) * 4u;
-        stage_walk<true>(nodes, s, e, consts, J, row_bytes, code + start);
-        m.start = start;
+        if (cached)
+            stage_walk(LdsNodes{cache, lo}, s, e, R.consts, J, row_bytes, code + start, m.slen);
+        else
+            stage_walk(GlobalNodes{R.nodes}, s, e, R.consts, J, row_bytes, code + start, m.slen);
         meta[p].start = start;
     }
     // stable scatter into the partition order
