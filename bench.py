@@ -73,6 +73,28 @@ def cpu_baseline(w, budget_s=15.0):
                       % (sub.n_programs, P, w.data.n_cases, node_evals, dt)}
 
 
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel, from the committed counter
+    summary, while the kernel source is the one the counters were taken on;
+    None otherwise."""
+    import hashlib
+    import re
+    if workload != "generation":
+        return None
+    summary = os.path.join(ROOT, "profiles", "k_eval_generation_counters.md")
+    src = os.path.join(ROOT, "paper_2607_06731_amd", "csrc", "gpeval.hip")
+    try:
+        text = open(summary).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)
+    t = re.search(r"traffic_bytes_per_launch: ([0-9]+)", text)
+    if not m or not t or m.group(1) != digest:
+        return None
+    return int(t.group(1))
+
+
 def copy_calibration(n_bytes):
     import torch
     a = torch.empty(n_bytes // 4, dtype=torch.float32, device="cuda")
@@ -144,7 +166,8 @@ def throughput(args):
     roofline = {"bound": "alu", "kernel": "k_eval<8,4> (depth<=8 class)",
                 "achieved": round(achieved, 4), "peak": round(PEAK_LANE_OPS / 1e12, 4),
                 "unit": "T node-evals/s vs T fp32 VALU lane-ops/s",
-                "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4), "traffic": None,
+                "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4),
+                "traffic": measured_traffic(args.workload),
                 "kernel_ms": round(ms0, 4), "node_evals_per_launch": evals0}
     phase_ms = {k: round(v / max(n_calls, 1), 4) for k, v in phases.items()}
 
