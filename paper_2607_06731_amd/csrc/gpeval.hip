@@ -95,6 +95,7 @@ constexpr int kWaves = kWG / 64;
 constexpr int kClasses = 3;              // max depth <= 8, <= 16, <= 32
 constexpr int kLenBuckets = 8;           // staged length 1, 2-3, ..., 64-127, 128+
 constexpr int kKeys = kClasses * kLenBuckets;
+constexpr int kK1 = 4;                  // cases per lane of the depth <= 16 class
 constexpr int kMaxTiles = 32;            // case tiles per program (cap)
 constexpr uint32_t kNoSlot = 0xFFu;      // staged write slot: nothing to save
 constexpr int kBucketBlock = 256;        // programs per staging/partition block
@@ -132,7 +133,7 @@ __host__ __device__ inline int depth_class(int maxd)
 __host__ __device__ inline int class_k(int c, int n_vars)
 {
     if (c == 0) return 4;
-    return c == 1 ? 4 : 2;
+    return c == 1 ? kK1 : 2;
 }
 
 // Tile geometry for one class.  A sub-tile is 64*K cases (one wavefront, K
@@ -1752,7 +1753,7 @@ int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
         if (t > el->stride) el->stride = t;
     }
     if ((rc = eval_grid<8, 4>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
-    if ((rc = eval_grid<16, 4>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
+    if ((rc = eval_grid<16, kK1>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
     if ((rc = eval_grid<32, 2>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2])) != GP_OK) return rc;
     el->layout = make_layout(pb.n_programs, pb.n_nodes, el->stride, pb.n_ds, pb.n_req);
     return GP_OK;
@@ -1821,8 +1822,8 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
             ea.tile_floats = (int32_t)eval_tile_floats<8, 4>(pb.max_vars);
             GP_LAUNCH_EVAL(8, 4);
         } else if (c == 1) {
-            ea.tile_floats = (int32_t)eval_tile_floats<16, 4>(pb.max_vars);
-            GP_LAUNCH_EVAL(16, 4);
+            ea.tile_floats = (int32_t)eval_tile_floats<16, kK1>(pb.max_vars);
+            GP_LAUNCH_EVAL(16, kK1);
         } else {
             ea.tile_floats = (int32_t)eval_tile_floats<32, 2>(pb.max_vars);
             GP_LAUNCH_EVAL(32, 2);
@@ -2199,7 +2200,7 @@ int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs
         ea.cls = c;
         ep.work_counter = st.counters + c;
         if (c == 0) rc = launch_predict<8, 4>(ep, out, ld_out, ea, stream, cus);
-        else if (c == 1) rc = launch_predict<16, 4>(ep, out, ld_out, ea, stream, cus);
+        else if (c == 1) rc = launch_predict<16, kK1>(ep, out, ld_out, ea, stream, cus);
         else rc = launch_predict<32, 2>(ep, out, ld_out, ea, stream, cus);
         if (rc != GP_OK) return rc;
     }

@@ -76,6 +76,37 @@ def test_config2_full_size_sampled():
     assert not np.isnan(F).any()
 
 
+def _full_size_sampled(gp, k, per_len, cap, seed):
+    """Workload k at full size in the launch configuration bench.py times,
+    gated on a seeded sample stratified by program length."""
+    from paper_2607_06731_amd import synth
+    w = synth.make_config(k)
+    _say("workload %d full size: %d programs x %d cases" % (k, w.pop.n_programs, w.data.n_cases))
+    F = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
+             w.allowed_mask)
+    rng = np.random.default_rng(seed)
+    L = w.pop.lengths
+    idx = []
+    for l in np.unique(L):
+        pool = np.nonzero(L == l)[0]
+        idx.append(rng.choice(pool, min(per_len, pool.size), replace=False))
+    idx = rng.permutation(np.concatenate(idx))[:cap]
+    sub = w.pop.take(idx)
+    _gate(F[idx], sub.nodes, sub.offsets, sub.consts, w.data.X, w.data.y, w.tax,
+          w.allowed_mask, "workload %d full (sampled %d)" % (k, idx.size))
+    assert not np.isnan(F).any()
+
+
+def test_uneven_full_size_sampled():
+    """1,000,000 programs (lengths 3..128) x 16,384 cases, 10 variables."""
+    _full_size_sampled(_need_gpu(), 3, per_len=4, cap=400, seed=43)
+
+
+def test_precision_full_size_sampled():
+    """50,000 programs x 1,048,576 cases, |y| up to 1e4."""
+    _full_size_sampled(_need_gpu(), 4, per_len=1, cap=62, seed=44)
+
+
 # ------------------------------------------------------------ pins on GPU
 def test_brute_force_special_values():
     gp = _need_gpu()
