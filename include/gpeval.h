@@ -218,7 +218,8 @@ typedef struct {
 } gp_problem;                                       /* same meaning as gp_eval's arguments */
 
 typedef struct {
-    int32_t programs_per_item;   /* programs per work item, 1..64 (default 8) */
+    int32_t programs_per_item;   /* most programs per work item, 1..128 (default 64);
+                                    a depth class with few programs uses fewer */
     int32_t wg_per_cu;           /* persistent workgroups per CU, 0 = occupancy limit */
     int32_t concurrent_classes;  /* 1: depth classes run on forked streams */
 } gp_tuning;

@@ -98,8 +98,8 @@ constexpr int kKeys = kClasses * kLenBuckets;
 constexpr int kK1 = 4;                  // cases per lane of the depth <= 16 class
 constexpr int kMaxTiles = 32;            // case tiles per program (cap)
 constexpr uint32_t kNoSlot = 0xFFu;      // staged write slot: nothing to save
-constexpr int kBucketBlock = 256;        // programs per staging/partition block
-constexpr int kStageNodes = 12288;       // LDS node cache of a staging block (48 KB)
+constexpr int kBucketBlock = 128;        // programs per staging/partition block
+constexpr int kStageNodes = 8192;        // LDS node cache of a staging block (32 KB)
 constexpr int kMaxRequests = 4096;       // requests per batched call (tables are scanned by one workgroup)
 
 // Per-program record written by the staging passes.
@@ -462,6 +462,10 @@ __device__ __forceinline__ int request_of(const int64_t* __restrict__ seg_start,
     return lo;
 }
 
+// LDS-qualified pointers (per-lane LDS addressing without generic loads).
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) float lds_f32;
+
 // Node readers for the staging passes: straight from the request's array,
 // or from the block's LDS copy of its node range.
 struct GlobalNodes {
@@ -469,9 +473,14 @@ struct GlobalNodes {
     __device__ uint32_t operator()(int64_t k) const { return p[k]; }
 };
 struct LdsNodes {
-    const uint32_t* p;          // LDS
+    const lds_u32* p;           // the block's node cache
     int64_t lo;                 // first cached node
     __device__ uint32_t operator()(int64_t k) const { return p[k - lo]; }
+};
+// Constant reader.
+struct GlobalConsts {
+    const float* __restrict__ p;
+    __device__ float operator()(uint32_t j) const { return p[j]; }
 };
 
 // Cooperative, coalesced copy of the node range [min s, max e) of the
@@ -480,7 +489,7 @@ struct LdsNodes {
 // Every thread of the block must call it.  Returns true when the copy is
 // used (then *lo is the first cached node).
 __device__ bool cache_block_nodes(bool mine, int r, int64_t s, int64_t e,
-                                  const DevRequest* __restrict__ reqs, uint32_t* cache,
+                                  const DevRequest* __restrict__ reqs, lds_u32* cache,
                                   int64_t* lo)
 {
     __shared__ long long s_lo, s_hi;
@@ -504,9 +513,25 @@ __device__ bool cache_block_nodes(bool mine, int r, int64_t s, int64_t e,
     __syncthreads();
     const bool use = s_any && !s_mixed && s_hi - s_lo <= kStageNodes;
     if (use) {
+        // 16 independent loads in flight per thread and round: a plain copy
+        // loop would wait out the memory latency once per element
+        constexpr int kU = 16;
         const uint32_t* __restrict__ src = reqs[s_r].nodes + s_lo;
         const int n = (int)(s_hi - s_lo);
-        for (int i = threadIdx.x; i < n; i += blockDim.x) cache[i] = src[i];
+        const int step = (int)blockDim.x * kU;
+        for (int i0 = 0; i0 < n; i0 += step) {
+            uint32_t v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                v[u] = i < n ? src[i] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                if (i < n) cache[i] = v[u];
+            }
+        }
         *lo = s_lo;
     }
     __syncthreads();
@@ -524,17 +549,19 @@ __device__ bool cache_block_nodes(bool mine, int r, int64_t s, int64_t e,
 // followed by an operator folds into it (top OP x, or save + f(x)).  What is
 // folded depends only on the node kinds, never on values, so counting and
 // emitting agree.
-template <class Nodes>
-__device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e,
-                              const float* __restrict__ consts, uint32_t J, uint32_t row_bytes,
-                              uint4* __restrict__ out, int64_t cap)
+template <class Nodes, class Consts>
+__device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, uint32_t J,
+                              uint32_t row_bytes, uint4* __restrict__ out, int64_t cap,
+                              lds_f32* pvs)
 {
+    // held-back constant i of this thread is pvs[i * kBucketBlock] (LDS:
+    // a per-lane index into a register array would become a select chain)
+#define pv(i) pvs[(i) * kBucketBlock]
     // never writes past the range k_validate sized (`cap` entries)
     auto put = [&](int64_t i, uint4 v) {
         if (i < cap) out[i] = v;
     };
     const uint32_t dummy = 32u - J;              // slot MAXD-1: never live
-    float pv[GP_MAX_STACK];                      // held-back constant values
     int rt = 0;                                  // runtime stack depth
     int np = 0;                                  // held-back constants
     int64_t n = 0;                               // emitted instructions
@@ -542,7 +569,7 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e,
         const uint32_t w = nodes(k);
         const uint32_t op = w & 0xFFu, arg = w >> 8;
         if (op == GP_CONST) {
-            pv[np & (GP_MAX_STACK - 1)] = consts[arg];   // np < 32 in a valid program
+            pv(np & (GP_MAX_STACK - 1)) = consts(arg);   // np < 32 in a valid program
             ++np;
             continue;
         }
@@ -550,7 +577,7 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e,
             // flush: held-back constants become runtime elements, bottom up
             for (int i = 0; i < np; ++i) {
                 const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
-                put(n, make_uint4(kFPush, __float_as_uint(pv[i]), 1u, wr));
+                put(n, make_uint4(kFPush, __float_as_uint(pv(i)), 1u, wr));
                 ++n;
                 ++rt;
             }
@@ -577,11 +604,11 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e,
             const uint32_t bop = op - GP_ADD;
             if (np >= 2) {
                 --np;
-                pv[np - 1] = binary_value(op, pv[np - 1], pv[np]);
+                pv(np - 1) = binary_value(op, pv(np - 1), pv(np));
             } else if (np == 1) {
                 // top = top OP c: the runtime top is the left operand
                 --np;
-                put(n, make_uint4(kFLBin | (bop << 8), __float_as_uint(pv[0]), 1u, 0u));
+                put(n, make_uint4(kFLBin | (bop << 8), __float_as_uint(pv(0)), 1u, 0u));
                 ++n;
             } else {
                 // second from top (element rt-2) is read from slot rt-2
@@ -592,7 +619,7 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e,
             continue;
         }
         if (np >= 1) {
-            pv[np - 1] = unary_value(op, pv[np - 1]);
+            pv(np - 1) = unary_value(op, pv(np - 1));
         } else {
             put(n, make_uint4(kFUn | ((op - GP_SIN) << 8), 0u, 0u, 0u));
             ++n;
@@ -601,12 +628,13 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e,
     // a constant program: its value is pushed
     for (int i = 0; i < np; ++i) {
         const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
-        put(n, make_uint4(kFPush, __float_as_uint(pv[i]), 1u, wr));
+        put(n, make_uint4(kFPush, __float_as_uint(pv(i)), 1u, wr));
         ++n;
         ++rt;
     }
     if (n > 0 && n <= cap) out[n - 1].x |= kFLast;
     return n;
+#undef pv
 }
 
 // Validation of one program (GCL stack discipline, operand ranges,
@@ -666,7 +694,8 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
 {
     __shared__ int cnt[kKeys];
     __shared__ unsigned long long s_slen;
-    __shared__ uint32_t cache[kStageNodes];
+    __shared__ uint32_t cache_mem[kStageNodes];
+    lds_u32* cache = (lds_u32*)cache_mem;
     if (threadIdx.x < kKeys) cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_slen = 0ull;
     const int64_t p = (int64_t)blockIdx.x * kBucketBlock + threadIdx.x;
@@ -821,7 +850,9 @@ __global__ __launch_bounds__(kBucketBlock) void k_stage(
     __shared__ long long sc[kBucketBlock];
     constexpr int kW = kBucketBlock / 64;
     __shared__ int wcnt[kW][kKeys];
-    __shared__ uint32_t cache[kStageNodes];
+    __shared__ uint32_t cache_mem[kStageNodes];
+    __shared__ float pv_mem[GP_MAX_STACK * kBucketBlock];
+    lds_u32* cache = (lds_u32*)cache_mem;
     const int t = threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * kBucketBlock + t;
     int key = p < n_programs ? (int)cls[p] : 0xFF;
@@ -867,10 +898,13 @@ __global__ __launch_bounds__(kBucketBlock) void k_stage(
         const int c = key / kLenBuckets;
         const uint32_t J = 32u / (uint32_t)class_depth(c);
         const uint32_t row_bytes = (uint32_t)(64 * class_k(c, ds[R.dataset].n_vars)) * 4u;
+        lds_f32* pvs = (lds_f32*)pv_mem + t;
         if (cached)
-            stage_walk(LdsNodes{cache, lo}, s, e, R.consts, J, row_bytes, code + start, m.slen);
+            stage_walk(LdsNodes{cache, lo}, s, e, GlobalConsts{R.consts}, J, row_bytes,
+                       code + start, m.slen, pvs);
         else
-            stage_walk(GlobalNodes{R.nodes}, s, e, R.consts, J, row_bytes, code + start, m.slen);
+            stage_walk(GlobalNodes{R.nodes}, s, e, GlobalConsts{R.consts}, J, row_bytes,
+                       code + start, m.slen, pvs);
         meta[p].start = start;
     }
     // stable scatter into the partition order
@@ -926,17 +960,30 @@ __global__ __launch_bounds__(256) void k_seg_count(const int32_t* __restrict__ o
     seg_cnt[i] = cnt;
 }
 
-// Per class (one thread each): where each segment's programs start inside
-// the class's range of `order`, and the prefix of work items (G-program
-// groups times the segment dataset's case tiles) over segments.
+// Per class (one thread each): the group size (programs per work item) and,
+// per segment, where its programs start inside the class's range of
+// `order` and the prefix of work items (groups times the segment dataset's
+// case tiles).  Groups are as large as g_max allows while the class still
+// has about target_items items (a small class gets smaller groups, so its
+// few programs still spread over the GPU); never below 4, one program per
+// wavefront of a workgroup.  Grouping never changes a result.
 __global__ __launch_bounds__(64) void k_seg_scan(const int32_t* __restrict__ seg_cnt,
                                                  const int32_t* __restrict__ seg_ds,
                                                  const DevDataset* __restrict__ ds, int32_t n_seg,
-                                                 int32_t G, int32_t* __restrict__ seg_pos,
-                                                 uint32_t* __restrict__ item_pre)
+                                                 int32_t g_max, int32_t target_items,
+                                                 int32_t* __restrict__ seg_pos,
+                                                 uint32_t* __restrict__ item_pre,
+                                                 int32_t* __restrict__ class_g)
 {
     const int c = threadIdx.x;
     if (c >= kClasses) return;
+    double prog_tiles = 0.0;
+    for (int s = 0; s < n_seg; ++s)
+        prog_tiles += (double)seg_cnt[c * n_seg + s] * (double)ds[seg_ds[s]].n_tiles[c];
+    int G = g_max;
+    while (G > 4 && prog_tiles / G < (double)target_items) G >>= 1;
+    if (G < 1) G = 1;
+    class_g[c] = G;
     int32_t pos = 0;
     uint32_t items = 0;
     for (int s = 0; s < n_seg; ++s) {
@@ -1151,7 +1198,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
     uint32_t* __restrict__ work_counter, const DevDataset* __restrict__ ds,
     const int32_t* __restrict__ seg_ds, const int32_t* __restrict__ seg_cnt,
     const int32_t* __restrict__ seg_pos, const uint32_t* __restrict__ item_pre,
-    float2* __restrict__ part, uint8_t* __restrict__ part_bad, EvalConst a)
+    const int32_t* __restrict__ class_g, float2* __restrict__ part, uint8_t* __restrict__ part_bad, EvalConst a)
 {
     static_assert(K == 2 || K == 4 || K == 8, "cases per lane");
     static_assert(MAXD == 8 || MAXD == 16 || MAXD == 32, "stack class");
@@ -1167,6 +1214,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int c = a.cls;
+    const int G = class_g[c];                     // <= a.G, the accumulators' capacity
     const int cstart = class_info[2 * c];
     const int32_t* __restrict__ cnt_c = seg_cnt + c * a.n_seg;
     const int32_t* __restrict__ pos_c = seg_pos + c * a.n_seg;
@@ -1177,7 +1225,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
 
     for (;;) {
         if (tid == 0) s_item = atomicAdd(work_counter, 1u);
-        if (tid < a.G) {
+        if (tid < G) {
             acc[tid] = make_float2(0.f, 0.f);
             accbad[tid] = 0u;
         }
@@ -1203,12 +1251,12 @@ __global__ __launch_bounds__(kWG) void k_eval(
         const int passes = Dp->passes[c];
         const int window = Dp->window[c];
         const int count = cnt_c[sl];
-        const int n_groups = (count + a.G - 1) / a.G;
+        const int n_groups = (count + G - 1) / G;
         const uint32_t local = item - pre_c[sl];
         const int tile = (int)(local / (uint32_t)n_groups);
         const int grp = (int)(local % (uint32_t)n_groups);
-        const int g0 = grp * a.G;
-        const int gn = min(a.G, count - g0);
+        const int g0 = grp * G;
+        const int gn = min(G, count - g0);
         const int obase = cstart + pos_c[sl] + g0;
         const int64_t n_sub = (n_cases + SUB - 1) / SUB;
         const int rows = n_vars + 1;              // inputs, then the targets
@@ -1401,7 +1449,8 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
 
 // ----------------------------------------------------------- workspaces
 struct Layout {
-    size_t code, meta, cls, order, blk_counts, blk_base, blk_slen, blk_code, class_info, counters;
+    size_t code, meta, cls, order, blk_counts, blk_base, blk_slen, blk_code, class_info, class_g;
+    size_t counters;
     size_t part, part_bad;
     size_t ds, req, seg_ds, seg_start, seg_cnt, seg_pos, item_pre, pds, bad, overflow, total;
 };
@@ -1424,6 +1473,7 @@ Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride, int
     L.blk_slen = off;   off = align_up(off + (size_t)n_blk * 8);
     L.blk_code = off;   off = align_up(off + (size_t)n_blk * 8);
     L.class_info = off; off = align_up(off + 2 * kClasses * 4);
+    L.class_g = off;    off = align_up(off + kClasses * 4);
     L.counters = off;   off = align_up(off + kClasses * 4);
     L.part = off;       off = align_up(off + (size_t)n_programs * part_stride * sizeof(float2));
     L.part_bad = off;   off = align_up(off + (size_t)n_programs * part_stride);
@@ -1452,6 +1502,7 @@ struct Staged {
     int64_t* blk_slen;
     int64_t* blk_code;
     int32_t* class_info;
+    int32_t* class_g;
     uint32_t* counters;
     float2* part;
     uint8_t* part_bad;
@@ -1480,6 +1531,7 @@ Staged carve(void* base, const Layout& L)
     st.blk_slen = reinterpret_cast<int64_t*>(ws + L.blk_slen);
     st.blk_code = reinterpret_cast<int64_t*>(ws + L.blk_code);
     st.class_info = reinterpret_cast<int32_t*>(ws + L.class_info);
+    st.class_g = reinterpret_cast<int32_t*>(ws + L.class_g);
     st.counters = reinterpret_cast<uint32_t*>(ws + L.counters);
     st.part = reinterpret_cast<float2*>(ws + L.part);
     st.part_bad = reinterpret_cast<uint8_t*>(ws + L.part_bad);
@@ -1681,7 +1733,7 @@ int check_problem(const Problem& pb)
 // Scheduling knobs.  None of them changes a result: a program's summation
 // order is fixed by (n_cases, its depth class, n_vars) alone.
 struct Tuning {
-    int G = 8;              // programs per work item
+    int G = 64;             // programs per work item, at most (small classes use fewer)
     int wg_per_cu = 0;      // persistent workgroups per CU (0: occupancy limit)
     int concurrent = 0;     // depth classes on forked streams
 };
@@ -1735,6 +1787,7 @@ int eval_grid(int n_vars, int G, int wg_per_cu, int cus, int* grid, size_t* lds_
 
 struct EvalLaunch {
     int32_t stride = 1;
+    int32_t target_items = 1;   // work items per class worth keeping large groups for
     int grid[kClasses] = {0, 0, 0};
     size_t lds[kClasses] = {0, 0, 0};
     Layout layout;
@@ -1752,6 +1805,7 @@ int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
         const int32_t t = max_tiles(pb.max_cases, class_k(c, pb.max_vars));
         if (t > el->stride) el->stride = t;
     }
+    el->target_items = 4 * 6 * cus;     // ~4 items per workgroup slot
     if ((rc = eval_grid<8, 4>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
     if ((rc = eval_grid<16, kK1>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
     if ((rc = eval_grid<32, 2>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2])) != GP_OK) return rc;
@@ -1797,7 +1851,7 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
                        st.seg_cnt);
     GP_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(64), 0, stream, st.seg_cnt, st.seg_ds, st.ds,
-                       pb.n_req, tu.G, st.seg_pos, st.item_pre);
+                       pb.n_req, tu.G, el.target_items, st.seg_pos, st.item_pre, st.class_g);
     GP_HIP_TRY(hipGetLastError());
 
     EvalConst ea{};
@@ -1817,7 +1871,7 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
 #define GP_LAUNCH_EVAL(MD, KK)                                                                 \
         hipLaunchKernelGGL((k_eval<MD, KK>), g, b, el.lds[c], sc, st.code, st.meta, st.order,  \
                            st.class_info, st.counters + c, st.ds, st.seg_ds, st.seg_cnt,       \
-                           st.seg_pos, st.item_pre, st.part, st.part_bad, ea)
+                           st.seg_pos, st.item_pre, st.class_g, st.part, st.part_bad, ea)
         if (c == 0) {
             ea.tile_floats = (int32_t)eval_tile_floats<8, 4>(pb.max_vars);
             GP_LAUNCH_EVAL(8, 4);
@@ -1998,7 +2052,7 @@ int plan_autotune(gp_plan* p, hipStream_t stream)
             return GP_OK;
         }
     }
-    const int Gs[] = {2, 4, 8, 16, 32};
+    const int Gs[] = {16, 32, 64, 128};
     hipEvent_t e0, e1;
     GP_HIP_TRY(hipEventCreate(&e0));
     GP_HIP_TRY(hipEventCreate(&e1));
@@ -2222,7 +2276,7 @@ int gp_plan_create(gp_plan** plan, const gp_problem* problem, const gp_tuning* t
     gp_plan* p = new gp_plan();
     p->pb = pb;
     if (tuning) {
-        if (tuning->programs_per_item < 0 || tuning->programs_per_item > 64 || tuning->wg_per_cu < 0) {
+        if (tuning->programs_per_item < 0 || tuning->programs_per_item > 128 || tuning->wg_per_cu < 0) {
             delete p;
             return set_error(GP_E_INVALID_ARG, "tuning out of range");
         }
@@ -2239,7 +2293,7 @@ int gp_plan_create(gp_plan** plan, const gp_problem* problem, const gp_tuning* t
     // workspace for the largest candidate configuration
     EvalLaunch el;
     Tuning big = p->tu;
-    big.G = 32;
+    big.G = 128;
     if ((rc = configure_eval(pb, big, &el)) != GP_OK ||
         hipMalloc(&p->ws, el.layout.total) != hipSuccess) {
         (void)hipGetLastError();
