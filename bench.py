@@ -309,7 +309,11 @@ def serving(args):
           % (len(runs), sum(p.n_programs for p in pops), time.perf_counter() - t0),
           file=sys.stderr, flush=True)
     tax = 1e-3
-    modes = {"batched": {}, "one_launch_per_request": {"one_launch_per_request": True}}
+    batched = {"chunk_node_evals": 1 << args.serve_chunk_log2,
+               "batch_node_evals": args.serve_batch_chunks << args.serve_chunk_log2}
+    modes = {"batched": batched, "one_launch_per_request": {"one_launch_per_request": True}}
+    if args.serve_batched_only:
+        del modes["one_launch_per_request"]
 
     def summary(st):
         w = st["wall_ms"] * 1e-3
@@ -342,7 +346,7 @@ def serving(args):
                                                   res[name]["load_%.1f" % args.serve_load]),
                   file=sys.stderr, flush=True)
     b = res["batched"]["saturated"]["gpops"]
-    o = res["one_launch_per_request"]["saturated"]["gpops"]
+    o = res.get("one_launch_per_request", {}).get("saturated", {}).get("gpops")
     rec = {
         "metric": "serving throughput (GPOPs) with p50/p99 scoring latency",
         "value": b,
@@ -357,7 +361,9 @@ def serving(args):
         "data": "synthetic",
         "config": {"workload": "serving: %d closed-loop runs, %.0f s per point, budget %d MiB"
                                % (len(runs), args.serve_seconds, args.serve_budget_mib),
-                   "think_ms_at_load": round(think_ms, 2)},
+                   "think_ms_at_load": round(think_ms, 2),
+                   "chunk_node_evals": batched["chunk_node_evals"],
+                   "batch_node_evals": batched["batch_node_evals"]},
         "batched_over_one_launch_per_request": round(b / o, 3) if o else None,
         "serving": res,
     }
@@ -378,6 +384,11 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--serve-load", type=float, default=0.6)
     ap.add_argument("--serve-budget-mib", type=int, default=8192)
+    ap.add_argument("--serve-chunk-log2", type=int, default=35,
+                    help="work per chunk, log2 of length x cases")
+    ap.add_argument("--serve-batch-chunks", type=int, default=4,
+                    help="work per launch, in chunks")
+    ap.add_argument("--serve-batched-only", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -269,7 +269,7 @@ typedef struct {
                                        (0: 8 GiB) */
     int64_t pinned_bytes;           /* host staging (0: min(budget, 1 GiB)) */
     int64_t chunk_node_evals;       /* work per chunk, in length x cases
-                                       (0: 2^33) */
+                                       (0: 2^35) */
     int64_t batch_node_evals;       /* work per launch (0: 4 chunks); a launch
                                        takes at least one chunk */
     int32_t n_streams;              /* launches in flight, 1..8 (0: 2) */

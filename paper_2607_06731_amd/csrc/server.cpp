@@ -598,7 +598,7 @@ int gp_server_create(gp_server** server, const gp_server_config* config)
         return fail(GP_E_INVALID_ARG, "server configuration out of range");
     if (!c.device_budget_bytes) c.device_budget_bytes = int64_t(8) << 30;
     if (!c.pinned_bytes) c.pinned_bytes = std::min<int64_t>(c.device_budget_bytes, int64_t(1) << 30);
-    if (!c.chunk_node_evals) c.chunk_node_evals = int64_t(1) << 33;
+    if (!c.chunk_node_evals) c.chunk_node_evals = int64_t(1) << 35;
     if (!c.batch_node_evals) c.batch_node_evals = 4 * c.chunk_node_evals;
     if (!c.n_streams) c.n_streams = 2;
     if (!c.max_batch_chunks) c.max_batch_chunks = 1024;
