@@ -78,26 +78,32 @@ def cpu_baseline(w, budget_s=15.0):
                       % (sub.n_programs, P, w.data.n_cases, node_evals, dt)}
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the dominant kernel, from the committed counter
+def measured_counters(workload):
+    """Counter figures of the dominant kernel (HBM bytes per launch, VALU busy
+    fraction, VALU lane-slots per node evaluation) from the committed counter
     summary, while the kernel source is the one the counters were taken on;
-    None otherwise."""
+    an empty dict otherwise."""
     import hashlib
     import re
     if workload != "generation":
-        return None
+        return {}
     summary = os.path.join(ROOT, "profiles", "k_eval_generation_counters.md")
     src = os.path.join(ROOT, "paper_2607_06731_amd", "csrc", "gpeval.hip")
     try:
         text = open(summary).read()
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
-        return None
+        return {}
     m = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)
-    t = re.search(r"traffic_bytes_per_launch: ([0-9]+)", text)
-    if not m or not t or m.group(1) != digest:
-        return None
-    return int(t.group(1))
+    if not m or m.group(1) != digest:
+        return {}
+    out = {}
+    for key, cast in (("traffic_bytes_per_launch", int), ("valu_busy", float),
+                      ("valu_lane_slots_per_node_eval", float)):
+        v = re.search(r"%s: ([0-9.]+)" % key, text)
+        if v:
+            out[key] = cast(v.group(1))
+    return out
 
 
 def copy_calibration(n_bytes):
@@ -192,12 +198,15 @@ def throughput(args):
     cls0 = (status == 0) & (maxd <= 8)
     evals0 = int(lens[cls0].sum()) * w.data.n_cases
     ms0 = phases["eval_d8"] / max(n_calls, 1)
+    counters = measured_counters(args.workload)
     achieved = evals0 / (ms0 * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_eval<8,4> (depth<=8 class)",
                 "achieved": round(achieved, 4), "peak": round(PEAK_LANE_OPS / 1e12, 4),
                 "unit": "T node-evals/s vs T fp32 VALU lane-ops/s",
                 "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4),
-                "traffic": measured_traffic(args.workload),
+                "traffic": counters.get("traffic_bytes_per_launch"),
+                "valu_busy": counters.get("valu_busy"),
+                "valu_lane_slots_per_node_eval": counters.get("valu_lane_slots_per_node_eval"),
                 "kernel_ms": round(ms0, 4), "node_evals_per_launch": evals0}
     phase_ms = {k: round(v / max(n_calls, 1), 4) for k, v in phases.items()}
 

@@ -45,16 +45,19 @@ class GateReport:
     n_class_flip_certified: int = 0
     n_fail: int = 0
     max_rel_err: float = 0.0          # over passing finite programs
+    median_rel_err: float = 0.0
+    p99_rel_err: float = 0.0
     failures: list = field(default_factory=list)
 
     def ok(self):
         return self.n_fail == 0
 
     def summary(self):
-        return ("n=%d pass=%d ill=%d chaotic=%d flip=%d fail=%d invalid=%d max_rel=%.3g"
+        return ("n=%d pass=%d ill=%d chaotic=%d flip=%d fail=%d invalid=%d "
+                "rel_err median=%.2g p99=%.2g max=%.3g"
                 % (self.n, self.n_pass, self.n_ill_conditioned, self.n_chaotic,
                    self.n_class_flip_certified, self.n_fail, self.n_invalid_programs,
-                   self.max_rel_err))
+                   self.median_rel_err, self.p99_rel_err, self.max_rel_err))
 
 
 def _close(a, b, rel=REL, abs_=ABS):
@@ -85,6 +88,8 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
     if both.any():
         rel = np.abs(F_dev[both] - F64[both]) / np.maximum(np.abs(F64[both]), 1e-300)
         rep.max_rel_err = float(rel.max())
+        rep.median_rel_err = float(np.median(rel))
+        rep.p99_rel_err = float(np.quantile(rel, 0.99))
 
     sus = np.nonzero(valid & ~good)[0]
     if sus.size:
