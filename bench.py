@@ -38,7 +38,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_LANE_OPS = 256 * 64 * 2.4e9      # fp32 VALU lane-slots per second (non-packed)
-WORKLOADS = {"plain": 1, "generation": 2, "uneven": 3, "precision": 4}
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -131,7 +130,7 @@ def throughput(args):
     from paper_2607_06731_amd import synth
 
     gp.lib()
-    w = synth.make_config(WORKLOADS[args.workload])
+    w = synth.make_workload(args.workload)
     print("[bench] %s" % describe(args.workload, w), file=sys.stderr, flush=True)
     pop = gp.DevicePopulation(w.pop.nodes, w.pop.offsets, w.pop.consts)
     data = gp.DeviceDataset(w.data.X, w.data.y)
@@ -384,7 +383,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="generation", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--workload", default="generation", choices=sorted(synth.WORKLOADS) + ["serving"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="time plain gp_eval calls only (default: an autotuned, graph-captured "

@@ -16,24 +16,25 @@ EXP 8, LOG 9, SQRT 10, ABS 11.
 
 Workload recipes (fixed for this project; the paper benchmarks on data it
 does not ship, so these stand in for it):
-  1 plain eval      1,000 programs, len U{3..32}, {+,-,*,/,sin,cos,exp,log},
+  plain             1,000 programs, len U{3..32}, {+,-,*,/,sin,cos,exp,log},
                     3 vars, 1,024 cases, X ~ U(-1,1),
                     y = x0^2 + sin(x1) x2 + N(0, sd 0.01), tax 0
-  2 full generation 100,000 programs, len U{3..64}, set 1 + {sqrt, abs},
+  generation        100,000 programs, len U{3..64}, set 1 + {sqrt, abs},
                     5 vars, 4,096 cases, X ~ U(-3,3), y = dense degree<=3
                     polynomial (56 monomials, coef U(-1,1)) + N(0, 0.05),
                     tax 1e-3
-  3 batched uneven  1,000,000 programs, len clip(Geom(1/24), 3, 128), set 2,
-                    10 vars, 16,384 cases, X ~ N(0,1), y as 2 (286 monomials)
-  4 precision       50,000 programs, len U{3..64}, set 2, 3 vars,
+  uneven            1,000,000 programs, len clip(Geom(1/24), 3, 128), set 2,
+                    10 vars, 16,384 cases, X ~ N(0,1), y as generation (286
+                    monomials)
+  precision         50,000 programs, len U{3..64}, set 2, 3 vars,
                     1,048,576 cases, X ~ U(-10,10), y = degree-3 polynomial
                     (20 monomials) scaled to max|y| = 1e4, no noise
-  5 serving         64 runs, each n_vars U{1..20}, cases log-U[256, 65536],
+  serving           64 runs, each n_vars U{1..20}, cases log-U[256, 65536],
                     X ~ N(0,1), y = <=32 random degree<=3 monomials + N(0,
                     0.05); requests of log-U[1k, 200k] programs, len
                     U{3..128}, set 2
 
-Program sampler: length L from the config's law; tokens left to right with
+Program sampler: length L from the workload's length law; tokens left to right with
 current depth d and r tokens still to come after this one.  A class is
 feasible when: leaf d+1 <= 32 and d <= r; unary d >= 1 and d-1 <= r; binary
 d >= 2 and d-2 <= r.  A feasible class is picked uniformly, then an op
@@ -131,7 +132,13 @@ class Workload:
         return int(self.pop.offsets[-1]) * int(self.data.n_cases)
 
 
-def _rngs(k, seed=None):
+# Each workload draws from its own seed stream (default entropy 1000 + id).
+WORKLOAD_IDS = {"plain": 1, "generation": 2, "uneven": 3, "precision": 4, "serving": 5}
+WORKLOADS = ("plain", "generation", "uneven", "precision")
+
+
+def _rngs(name, seed=None):
+    k = WORKLOAD_IDS[name]
     ss = np.random.SeedSequence(1000 + k if seed is None else seed)
     kids = ss.spawn(5)
     return [np.random.Generator(np.random.PCG64(s)) for s in kids]
@@ -217,61 +224,64 @@ def poly_eval(X64, terms, coefs):
     return y
 
 
-def length_law(k, rng, n):
-    if k == 1:
+def length_law(name, rng, n):
+    if name == "plain":
         return rng.integers(3, 33, n)
-    if k in (2, 4):
+    if name in ("generation", "precision"):
         return rng.integers(3, 65, n)
-    if k == 3:
+    if name == "uneven":
         return np.clip(rng.geometric(1.0 / 24.0, n), 3, 128)
-    if k == 5:
+    if name == "serving":
         return rng.integers(3, 129, n)
-    raise ValueError(k)
+    raise ValueError(name)
 
 
-CONFIG_SIZES = {1: (1_000, 1_024, 3), 2: (100_000, 4_096, 5),
-                3: (1_000_000, 16_384, 10), 4: (50_000, 1_048_576, 3)}
+# programs, cases, variables at full size
+SIZES = {"plain": (1_000, 1_024, 3), "generation": (100_000, 4_096, 5),
+         "uneven": (1_000_000, 16_384, 10), "precision": (50_000, 1_048_576, 3)}
 
 
-def make_dataset(k, n_cases=None, seed=None):
-    rp, rx, rpoly, rnoise, _ = _rngs(k, seed)
-    _, n_default, n_vars = CONFIG_SIZES[k]
+def make_dataset(name, n_cases=None, seed=None):
+    rp, rx, rpoly, rnoise, _ = _rngs(name, seed)
+    _, n_default, n_vars = SIZES[name]
     n = n_default if n_cases is None else int(n_cases)
-    if k == 1:
+    if name == "plain":
         X = rx.uniform(-1, 1, (n_vars, n)).astype(np.float32)
         X64 = X.astype(np.float64)
         y = X64[0] ** 2 + np.sin(X64[1]) * X64[2] + rnoise.normal(0, 0.01, n)
-    elif k == 2:
+    elif name == "generation":
         X = rx.uniform(-3, 3, (n_vars, n)).astype(np.float32)
         terms = monomials(n_vars)
         y = poly_eval(X.astype(np.float64), terms, rpoly.uniform(-1, 1, len(terms)))
         y += rnoise.normal(0, 0.05, n)
-    elif k == 3:
+    elif name == "uneven":
         X = rx.standard_normal((n_vars, n)).astype(np.float32)
         terms = monomials(n_vars)
         y = poly_eval(X.astype(np.float64), terms, rpoly.uniform(-1, 1, len(terms)))
         y += rnoise.normal(0, 0.05, n)
-    elif k == 4:
+    elif name == "precision":
         X = rx.uniform(-10, 10, (n_vars, n)).astype(np.float32)
         terms = monomials(n_vars)
         y = poly_eval(X.astype(np.float64), terms, rpoly.uniform(-1, 1, len(terms)))
         y *= 1e4 / np.max(np.abs(y))
     else:
-        raise ValueError(k)
+        raise ValueError(name)
     return Dataset(np.ascontiguousarray(X), y.astype(np.float32))
 
 
-def make_config(k, n_programs=None, n_cases=None, seed=None):
-    """Workload k (1..4) at its full size, or with sizes overridden."""
-    rp = _rngs(k, seed)[0]
-    P_default, _, n_vars = CONFIG_SIZES[k]
+def make_workload(name, n_programs=None, n_cases=None, seed=None):
+    """Workload ``name`` (one of WORKLOADS) at its full size, or with sizes
+    overridden."""
+    rp = _rngs(name, seed)[0]
+    P_default, _, n_vars = SIZES[name]
     P = P_default if n_programs is None else int(n_programs)
-    unary = UNARY_1 if k == 1 else UNARY_2
-    pop = sample_programs(rp, length_law(k, rp, P), n_vars, unary)
-    data = make_dataset(k, n_cases, seed)
-    tax = 0.0 if k == 1 else 1e-3
-    mask = MASK_1 if k == 1 else MASK_2
-    return Workload("config%d" % k, pop, data, tax, mask)
+    plain = name == "plain"
+    unary = UNARY_1 if plain else UNARY_2
+    pop = sample_programs(rp, length_law(name, rp, P), n_vars, unary)
+    data = make_dataset(name, n_cases, seed)
+    tax = 0.0 if plain else 1e-3
+    mask = MASK_1 if plain else MASK_2
+    return Workload(name, pop, data, tax, mask)
 
 
 # ---------------------------------------------------------------- serving
@@ -282,8 +292,8 @@ class ServingRun:
 
 
 def make_serving_runs(n_runs=64, seed=None, max_cases=65536):
-    """Config 5 datasets: one resident dataset per evolutionary run."""
-    _, rx, rpoly, rnoise, _ = _rngs(5, seed)
+    """Serving datasets: one resident dataset per evolutionary run."""
+    _, rx, rpoly, rnoise, _ = _rngs("serving", seed)
     runs = []
     for r in range(n_runs):
         n_vars = int(rx.integers(1, 21))

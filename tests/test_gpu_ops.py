@@ -153,7 +153,7 @@ def test_predict_agrees_with_eval():
     within the compensated-sum error."""
     gp = _gp()
     from paper_2607_06731_amd import synth
-    w = synth.make_config(2, n_programs=300, n_cases=2000)
+    w = synth.make_workload("generation", n_programs=300, n_cases=2000)
     _say("predict vs eval")
     f = gp.predict(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X).astype(np.float64)
     F = gp.evaluate(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,

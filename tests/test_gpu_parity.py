@@ -43,26 +43,28 @@ def _gate(F, nodes, offsets, consts, X, y, tax, mask, label):
 
 
 # ------------------------------------------------------------ workloads
-@pytest.mark.parametrize("k,P,n", [(1, None, None), (2, 4000, None), (3, 3000, 4000),
-                                   (4, 48, 1 << 20), (2, 2000, 1025), (2, 2000, 7)])
-def test_config_parity(k, P, n):
+@pytest.mark.parametrize("name,P,n", [("plain", None, None), ("generation", 4000, None),
+                                      ("uneven", 3000, 4000), ("precision", 48, 1 << 20),
+                                      ("generation", 2000, 1025), ("generation", 2000, 7)])
+def test_workload_parity(name, P, n):
     gp = _need_gpu()
     from paper_2607_06731_amd import synth
-    w = synth.make_config(k, n_programs=P, n_cases=n)
-    _say("config %d P=%d n=%d" % (k, w.pop.n_programs, w.data.n_cases))
+    w = synth.make_workload(name, n_programs=P, n_cases=n)
+    label = "%s P=%d n=%d" % (name, w.pop.n_programs, w.data.n_cases)
+    _say(label)
     F = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
              w.allowed_mask)
     _gate(F, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
-          w.allowed_mask, "config %d" % k)
+          w.allowed_mask, label)
 
 
-def test_config2_full_size_sampled():
-    """Full config-2 launch (100,000 programs x 4,096 cases) gated on a
+def test_generation_full_size_sampled():
+    """Full generation launch (100,000 programs x 4,096 cases) gated on a
     seeded sample of 400 programs, stratified by length."""
     gp = _need_gpu()
     from paper_2607_06731_amd import synth
-    w = synth.make_config(2)
-    _say("config 2 full size")
+    w = synth.make_workload("generation")
+    _say("generation full size")
     F = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
              w.allowed_mask)
     rng = np.random.default_rng(42)
@@ -71,17 +73,17 @@ def test_config2_full_size_sampled():
                           for l in range(3, 65)])[:400]
     sub = w.pop.take(idx)
     _gate(F[idx], sub.nodes, sub.offsets, sub.consts, w.data.X, w.data.y, w.tax,
-          w.allowed_mask, "config 2 full (sampled)")
+          w.allowed_mask, "generation full (sampled)")
     # every structurally valid program got a number or +inf, never NaN
     assert not np.isnan(F).any()
 
 
-def _full_size_sampled(gp, k, per_len, cap, seed):
-    """Workload k at full size in the launch configuration bench.py times,
+def _full_size_sampled(gp, name, per_len, cap, seed):
+    """Workload ``name`` at full size in the launch configuration bench.py times,
     gated on a seeded sample stratified by program length."""
     from paper_2607_06731_amd import synth
-    w = synth.make_config(k)
-    _say("workload %d full size: %d programs x %d cases" % (k, w.pop.n_programs, w.data.n_cases))
+    w = synth.make_workload(name)
+    _say("%s full size: %d programs x %d cases" % (name, w.pop.n_programs, w.data.n_cases))
     F = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
              w.allowed_mask)
     rng = np.random.default_rng(seed)
@@ -93,18 +95,18 @@ def _full_size_sampled(gp, k, per_len, cap, seed):
     idx = rng.permutation(np.concatenate(idx))[:cap]
     sub = w.pop.take(idx)
     _gate(F[idx], sub.nodes, sub.offsets, sub.consts, w.data.X, w.data.y, w.tax,
-          w.allowed_mask, "workload %d full (sampled %d)" % (k, idx.size))
+          w.allowed_mask, "%s full (sampled %d)" % (name, idx.size))
     assert not np.isnan(F).any()
 
 
 def test_uneven_full_size_sampled():
     """1,000,000 programs (lengths 3..128) x 16,384 cases, 10 variables."""
-    _full_size_sampled(_need_gpu(), 3, per_len=4, cap=400, seed=43)
+    _full_size_sampled(_need_gpu(), "uneven", per_len=4, cap=400, seed=43)
 
 
 def test_precision_full_size_sampled():
     """50,000 programs x 1,048,576 cases, |y| up to 1e4."""
-    _full_size_sampled(_need_gpu(), 4, per_len=1, cap=62, seed=44)
+    _full_size_sampled(_need_gpu(), "precision", per_len=1, cap=62, seed=44)
 
 
 # ------------------------------------------------------------ pins on GPU
@@ -270,7 +272,7 @@ def test_empty_population():
 def test_deterministic_and_batch_independent():
     gp = _need_gpu()
     from paper_2607_06731_amd import synth
-    w = synth.make_config(2, n_programs=6000, n_cases=4096)
+    w = synth.make_workload("generation", n_programs=6000, n_cases=4096)
     _say("determinism")
     F1 = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax, w.allowed_mask)
     F2 = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax, w.allowed_mask)
@@ -285,7 +287,7 @@ def test_commutativity_bitwise():
     gp = _need_gpu()
     from oracle import ADD, MUL
     from paper_2607_06731_amd import synth
-    w = synth.make_config(2, n_programs=200, n_cases=2048)
+    w = synth.make_workload("generation", n_programs=200, n_cases=2048)
     pop = w.pop
     progs = []
     for p in range(0, 100, 2):

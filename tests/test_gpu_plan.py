@@ -27,7 +27,7 @@ def test_plan_matches_eval_for_every_tuning():
     gp = _gp()
     import torch
     from paper_2607_06731_amd import synth
-    w = synth.make_config(3, n_programs=20000, n_cases=3000)
+    w = synth.make_workload("uneven", n_programs=20000, n_cases=3000)
     pop = gp.DevicePopulation(w.pop.nodes, w.pop.offsets, w.pop.consts)
     data = gp.DeviceDataset(w.data.X, w.data.y)
     ref = torch.empty(pop.n_programs, dtype=torch.float64, device="cuda")
@@ -53,7 +53,7 @@ def test_plan_autotune_and_inplace_update():
     gp = _gp()
     import torch
     from paper_2607_06731_amd import synth
-    w = synth.make_config(2, n_programs=30000, n_cases=4096)
+    w = synth.make_workload("generation", n_programs=30000, n_cases=4096)
     pop = gp.DevicePopulation(w.pop.nodes, w.pop.offsets, w.pop.consts)
     data = gp.DeviceDataset(w.data.X, w.data.y)
     out = torch.empty(pop.n_programs, dtype=torch.float64, device="cuda")
@@ -68,7 +68,7 @@ def test_plan_autotune_and_inplace_update():
                         w.allowed_mask)
     assert np.array_equal(F1, F_ref, equal_nan=True)
     # next generation: same shape, new programs written in place
-    w2 = synth.make_config(2, n_programs=30000, n_cases=4096, seed=77)
+    w2 = synth.make_workload("generation", n_programs=30000, n_cases=4096, seed=77)
     same = w2.pop.nodes.size == w.pop.nodes.size and w2.pop.consts.size == w.pop.consts.size
     if same:
         pop.nodes.copy_(torch.from_numpy(w2.pop.nodes).cuda())
@@ -81,7 +81,7 @@ def test_plan_autotune_and_inplace_update():
                              w.tax, w.allowed_mask)
         assert np.array_equal(F2, F2_ref, equal_nan=True)
     # different size: update re-captures
-    w3 = synth.make_config(2, n_programs=11111, n_cases=4096, seed=78)
+    w3 = synth.make_workload("generation", n_programs=11111, n_cases=4096, seed=78)
     pop3 = gp.DevicePopulation(w3.pop.nodes, w3.pop.offsets, w3.pop.consts)
     out3 = torch.empty(pop3.n_programs, dtype=torch.float64, device="cuda")
     plan.update(pop3, data, w.tax, out3, allowed_op_mask=w.allowed_mask)

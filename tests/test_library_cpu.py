@@ -62,7 +62,7 @@ def test_host_validate_matches_oracle_on_brute_force():
 
 def test_host_validate_status_codes():
     rng = np.random.default_rng(1)
-    w = synth.make_config(2, n_programs=2000, n_cases=64)
+    w = synth.make_workload("generation", n_programs=2000, n_cases=64)
     nodes = w.pop.nodes.copy()
     # mutate: random opcodes, operand indices and truncations
     idx = rng.choice(nodes.size, 300, replace=False)

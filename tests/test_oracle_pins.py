@@ -468,7 +468,7 @@ class TestInvariants:
 
     def setup_method(self):
         from paper_2607_06731_amd import synth
-        self.w = synth.make_config(2, n_programs=300, n_cases=512)
+        self.w = synth.make_workload("generation", n_programs=300, n_cases=512)
 
     def test_commutative_ops_bitwise(self):
         pop = self.w.pop

@@ -7,31 +7,33 @@ import oracle
 from paper_2607_06731_amd import synth
 
 
-@pytest.mark.parametrize("k,P", [(1, 1000), (2, 5000), (3, 20000), (4, 2000)])
-def test_programs_valid_and_lengths(k, P):
-    w = synth.make_config(k, n_programs=P, n_cases=256)
+@pytest.mark.parametrize("name,P", [("plain", 1000), ("generation", 5000), ("uneven", 20000),
+                                    ("precision", 2000)])
+def test_programs_valid_and_lengths(name, P):
+    w = synth.make_workload(name, n_programs=P, n_cases=256)
     st, md = oracle.validate(w.pop.nodes, w.pop.offsets, w.pop.consts.size,
                              w.data.n_vars, w.allowed_mask)
     assert np.all(st == 0)
     assert md.max() <= 32
     L = w.pop.lengths
-    lo, hi = {1: (3, 32), 2: (3, 64), 3: (3, 128), 4: (3, 64)}[k]
+    lo, hi = {"plain": (3, 32), "generation": (3, 64), "uneven": (3, 128),
+              "precision": (3, 64)}[name]
     assert L.min() >= lo and L.max() <= hi
-    if k == 3:
+    if name == "uneven":
         # clip(Geom(1/24), 3, 128): mean about 24, ~12% at the lower clip
         assert 22.5 < L.mean() < 25.5
         assert 0.10 < np.mean(L == 3) < 0.14
 
 
 def test_deterministic():
-    a = synth.make_config(2, n_programs=500, n_cases=64)
-    b = synth.make_config(2, n_programs=500, n_cases=64)
+    a = synth.make_workload("generation", n_programs=500, n_cases=64)
+    b = synth.make_workload("generation", n_programs=500, n_cases=64)
     assert np.array_equal(a.pop.nodes, b.pop.nodes)
     assert np.array_equal(a.data.X, b.data.X) and np.array_equal(a.data.y, b.data.y)
 
 
 def test_take_reindexes_constants():
-    w = synth.make_config(2, n_programs=200, n_cases=64)
+    w = synth.make_workload("generation", n_programs=200, n_cases=64)
     idx = np.array([5, 17, 3, 199])
     sub = w.pop.take(idx)
     F_all, _, _ = oracle.fitness(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X,
@@ -41,8 +43,8 @@ def test_take_reindexes_constants():
     assert np.array_equal(F_all[idx], F_sub, equal_nan=True)
 
 
-def test_config_shapes():
-    d = synth.make_dataset(4, n_cases=4096)
+def test_workload_shapes():
+    d = synth.make_dataset("precision", n_cases=4096)
     assert d.X.shape == (3, 4096) and d.X.dtype == np.float32
     assert np.abs(d.y).max() == pytest.approx(1e4, rel=1e-6)
     runs = synth.make_serving_runs(8)
