@@ -379,6 +379,7 @@ def serving(args):
 
 
 def main():
+    from paper_2607_06731_amd import synth
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -400,7 +401,7 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
               "got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Generate the fp32 coefficients of the device sine kernel.
 
-sin(r) ~= r + r^3 * (c0 + c1 u + c2 u^2 + c3 u^3 + c4 u^4),  u = r^2,
+sin(r) ~= r + r^3 * (c0 + c1 u + c2 u^2 + c3 u^3),  u = r^2  (odd degree 9),
 on |r| <= pi/2 + 0.01, minimising the maximum *relative* error (Lawson's
 iteratively reweighted least squares, which converges to the minimax
 solution), then rounding the coefficients to fp32 and re-fitting the
@@ -18,7 +18,7 @@ import numpy as np
 # pi to 60 significant digits (enough for the three-part fp32 split below)
 PI_DIGITS = "3.14159265358979323846264338327950288419716939937510582097494"
 
-DEG = 5              # number of coefficients c0..c4 (odd degree 11)
+DEG = 4              # number of coefficients c0..c3 (odd degree 9)
 HALF_PI = np.pi / 2 + 0.01   # margin: k = rint(x / pi) is computed in fp32
 
 

@@ -119,6 +119,13 @@ constexpr uint32_t kFUn = 2u;
 constexpr uint32_t kFSBin = 4u;
 constexpr uint32_t kFLBin = 8u;
 constexpr uint32_t kFLast = 16u;        // the program's last instruction
+constexpr uint32_t kFConst = 32u;       // the leaf is a constant
+
+__host__ __device__ inline uint2 staged_word(uint32_t flags, uint32_t sel, uint32_t slot,
+                                             uint32_t payload)
+{
+    return make_uint2(flags | (sel << 8) | (slot << 16), payload);
+}
 
 __host__ __device__ inline int depth_class(int maxd)
 {
@@ -331,29 +338,30 @@ __global__ __launch_bounds__(256) void k_tables(
 }
 
 // ------------------------------------------------------------------ sin/cos
-// Constants from gen_sin_poly.py: minimax odd polynomial for sin on
-// |r| <= pi/2 + 0.01 (relative error 5.7e-10 before fp32 evaluation) and a
-// three-part fp32 split of pi for Cody-Waite reduction.  Measured against
+// Constants from gen_sin_poly.py: minimax odd polynomial of degree 9 for sin
+// on |r| <= pi/2 + 0.01 (relative error 6.8e-9 before fp32 evaluation) and
+// a three-part fp32 split of pi for Cody-Waite reduction.  Measured against
 // correctly rounded results: <= 1.75 ulp for |x| <= 2^17, including inputs
 // next to multiples of pi; larger or non-finite inputs take the library
 // path (which carries a Payne-Hanek reduction).
-constexpr float kSinC0 = -1.666666716e-01f;
-constexpr float kSinC1 = 8.333351463e-03f;
-constexpr float kSinC2 = -1.984328410e-04f;
-constexpr float kSinC3 = 2.763883458e-06f;
-constexpr float kSinC4 = -2.573010249e-08f;
+constexpr float kSinC0 = -1.666665971e-01f;
+constexpr float kSinC1 = 8.333066478e-03f;
+constexpr float kSinC2 = -1.980943489e-04f;
+constexpr float kSinC3 = 2.605112741e-06f;
 constexpr float kPiA = 3.141592741e+00f;
 constexpr float kPiB = -8.742277657e-08f;
 constexpr float kPiC = -3.430249020e-15f;
 constexpr float kInvPi = 3.183098733e-01f;
 constexpr float kTrigFastLimit = 131072.0f;
+// 1.5 * 2^23: adding it to |v| < 2^22 rounds v to an integer n (the value's
+// spacing there is 1) and leaves n's parity in the lowest significand bit.
+constexpr float kRoundInt = 12582912.0f;
 
 // sin(r) for |r| <= pi/2 (+ margin)
 __device__ __forceinline__ float sin_poly(float r)
 {
     const float u = r * r;
-    float q = fmaf(u, kSinC4, kSinC3);
-    q = fmaf(u, q, kSinC2);
+    float q = fmaf(u, kSinC3, kSinC2);
     q = fmaf(u, q, kSinC1);
     q = fmaf(u, q, kSinC0);
     return fmaf(u * r, q, r);
@@ -367,32 +375,57 @@ __device__ __forceinline__ float reduce_pi(float x, float kh)
     return fmaf(-kh, kPiC, r);
 }
 
-// sin x = (-1)^k sin(x - k pi), k = rint(x / pi)
-__device__ __forceinline__ float sin_fast(float x)
+// Flips the sign of s when the integer held in the low bit of t's
+// significand is odd (adding the bit at position 31 flips the sign bit).
+__device__ __forceinline__ float flip_if_odd(float s, float t)
 {
-    const float k = rintf(x * kInvPi);
-    const float s = sin_poly(reduce_pi(x, k));
-    const int ki = (int)k;
-    return __int_as_float(__float_as_int(s) ^ (ki << 31));
+    return __uint_as_float(__float_as_uint(s) + (__float_as_uint(t) << 31));
 }
 
-// cos x = -(-1)^k sin(x - (k + 1/2) pi), k = rint(x / pi - 1/2)
+// sin x = (-1)^k sin(x - k pi), k = the integer nearest x / pi
+__device__ __forceinline__ float sin_fast(float x)
+{
+    const float t = fmaf(x, kInvPi, kRoundInt);
+    const float k = t - kRoundInt;
+    return flip_if_odd(sin_poly(reduce_pi(x, k)), t);
+}
+
+// cos x = (-1)^(k+1) sin(x - (k + 1/2) pi), k = the integer nearest
+// x / pi - 1/2; t carries k + 1 (the offset is odd, so the parity is k+1's)
 __device__ __forceinline__ float cos_fast(float x)
 {
-    const float k = rintf(fmaf(x, kInvPi, -0.5f));
-    const float s = sin_poly(reduce_pi(x, k + 0.5f));
-    const int ki = (int)k;
-    return __int_as_float(__float_as_int(s) ^ ((ki + 1) << 31));
+    const float t = fmaf(x, kInvPi, -0.5f) + (kRoundInt + 1.0f);
+    const float k = t - (kRoundInt + 1.0f);
+    return flip_if_odd(sin_poly(reduce_pi(x, k + 0.5f)), t);
+}
+
+// ---------------------------------------------------------------------- exp
+// e^x = 2^(x log2 e): h = fp32(x log2 e), n = the integer nearest h, and
+// 2^((h - n) + (x log2 e - h)) from the hardware exp2 on |f| <= 1/2 + tiny,
+// scaled by 2^n; log2 e is split into an fp32 head and tail so the product
+// keeps about 48 bits.  For |x| <= 87 no step overflows or underflows (the
+// scaled result stays a normal number); other inputs take ROCm's expf.
+constexpr float kLog2eHi = 1.442695022e+00f;   // fp32(log2 e), 0x3fb8aa3b
+constexpr float kLog2eLo = 1.925963034e-08f;   // fp32(log2 e - kLog2eHi), 0x32a57060
+constexpr float kExpFastLimit = 87.0f;
+
+__device__ __forceinline__ float exp_fast(float x)
+{
+    const float h = x * kLog2eHi;
+    const float n = rintf(h);
+    const float f = (h - n) + fmaf(x, kLog2eLo, fmaf(x, kLog2eHi, -h));
+    return ldexpf(__builtin_amdgcn_exp2f(f), (int)n);
 }
 
 // --------------------------------------------------------- sqrt|a|, ln|a|
 // sqrt|a| with the hardware square root (faithful, <= 1 ulp); magnitudes
 // below 2^-100 are scaled by 2^64 first (and the root by 2^-32 after), so
 // no denormal reaches the instruction.
+constexpr float kSqrtTiny = 0x1p-100f;
 __device__ __forceinline__ float sqrt_abs(float a)
 {
     const float x = fabsf(a);
-    const bool tiny = x < 0x1p-100f;
+    const bool tiny = x < kSqrtTiny;
     const float r = __builtin_amdgcn_sqrtf(tiny ? x * 0x1p64f : x);
     return tiny ? r * 0x1p-32f : r;
 }
@@ -420,6 +453,28 @@ __device__ __forceinline__ float div_protected(float a, float b)
     return fabsf(b) <= 0.001f ? 1.f : a / b;
 }
 
+// Per-case values of the elementary functions: the fast formula inside its
+// range, the library function outside.  The interpreter calls these only
+// when some case of a wavefront is outside a fast range (it takes the fast
+// formulas directly otherwise), and constant folding always; they stay out
+// of line so that their per-case range tests are not merged into the
+// interpreter's wavefront-wide tests (which would keep the per-case results
+// live across the branch) and their library reductions do not raise the
+// interpreter's register count.
+__attribute__((noinline)) __device__ float sin_value(float x)
+{
+    return fabsf(x) <= kTrigFastLimit ? sin_fast(x) : sinf(x);
+}
+__attribute__((noinline)) __device__ float cos_value(float x)
+{
+    return fabsf(x) <= kTrigFastLimit ? cos_fast(x) : cosf(x);
+}
+__attribute__((noinline)) __device__ float exp_value(float x)
+{
+    return fabsf(x) <= kExpFastLimit ? exp_fast(x) : expf(x);
+}
+__attribute__((noinline)) __device__ float sqrt_value(float x) { return sqrt_abs(x); }
+
 // One operator on one value, exactly as the interpreter computes it for a
 // case (used to fold constant subtrees while staging).
 __device__ __forceinline__ float binary_value(uint32_t bop, float a, float b)
@@ -435,11 +490,11 @@ __device__ __forceinline__ float binary_value(uint32_t bop, float a, float b)
 __device__ __forceinline__ float unary_value(uint32_t uop, float x)
 {
     switch (uop) {
-    case GP_SIN: return fabsf(x) <= kTrigFastLimit ? sin_fast(x) : sinf(x);
-    case GP_COS: return fabsf(x) <= kTrigFastLimit ? cos_fast(x) : cosf(x);
-    case GP_EXP: return expf(x);
+    case GP_SIN: return sin_value(x);
+    case GP_COS: return cos_value(x);
+    case GP_EXP: return exp_value(x);
     case GP_LOG: return log_protected(x);
-    case GP_SQRT: return sqrt_abs(x);
+    case GP_SQRT: return sqrt_value(x);
     default: return fabsf(x);
     }
 }
@@ -551,14 +606,14 @@ __device__ bool cache_block_nodes(bool mine, int r, int64_t s, int64_t e,
 // emitting agree.
 template <class Nodes, class Consts>
 __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, uint32_t J,
-                              uint32_t row_bytes, uint4* __restrict__ out, int64_t cap,
+                              uint32_t row_bytes, uint2* __restrict__ out, int64_t cap,
                               lds_f32* pvs)
 {
     // held-back constant i of this thread is pvs[i * kBucketBlock] (LDS:
     // a per-lane index into a register array would become a select chain)
 #define pv(i) pvs[(i) * kBucketBlock]
     // never writes past the range k_validate sized (`cap` entries)
-    auto put = [&](int64_t i, uint4 v) {
+    auto put = [&](int64_t i, uint2 v) {
         if (i < cap) out[i] = v;
     };
     const uint32_t dummy = 32u - J;              // slot MAXD-1: never live
@@ -577,7 +632,7 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
             // flush: held-back constants become runtime elements, bottom up
             for (int i = 0; i < np; ++i) {
                 const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
-                put(n, make_uint4(kFPush, __float_as_uint(pv(i)), 1u, wr));
+                put(n, staged_word(kFPush | kFConst, 0u, wr, __float_as_uint(pv(i))));
                 ++n;
                 ++rt;
             }
@@ -587,14 +642,14 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
             const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
             if (nx >= GP_ADD && nx <= GP_DIV) {
                 // top = top OP x (the binary op has a runtime element below)
-                put(n, make_uint4(kFLBin | ((nx - GP_ADD) << 8), payload, 0u, 0u));
+                put(n, staged_word(kFLBin, nx - GP_ADD, 0u, payload));
                 ++k;
             } else if (nx >= GP_SIN && nx < GP_N_OPS) {
-                put(n, make_uint4(kFPush | kFUn | ((nx - GP_SIN) << 8), payload, 0u, wr));
+                put(n, staged_word(kFPush | kFUn, nx - GP_SIN, wr, payload));
                 ++rt;
                 ++k;
             } else {
-                put(n, make_uint4(kFPush, payload, 0u, wr));
+                put(n, staged_word(kFPush, 0u, wr, payload));
                 ++rt;
             }
             ++n;
@@ -608,11 +663,11 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
             } else if (np == 1) {
                 // top = top OP c: the runtime top is the left operand
                 --np;
-                put(n, make_uint4(kFLBin | (bop << 8), __float_as_uint(pv(0)), 1u, 0u));
+                put(n, staged_word(kFLBin | kFConst, bop, 0u, __float_as_uint(pv(0))));
                 ++n;
             } else {
                 // second from top (element rt-2) is read from slot rt-2
-                put(n, make_uint4(kFSBin | (bop << 8), 0u, (uint32_t)(rt - 2) * J, 0u));
+                put(n, staged_word(kFSBin, bop, (uint32_t)(rt - 2) * J, 0u));
                 ++n;
                 --rt;
             }
@@ -621,14 +676,14 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
         if (np >= 1) {
             pv(np - 1) = unary_value(op, pv(np - 1));
         } else {
-            put(n, make_uint4(kFUn | ((op - GP_SIN) << 8), 0u, 0u, 0u));
+            put(n, staged_word(kFUn, op - GP_SIN, 0u, 0u));
             ++n;
         }
     }
     // a constant program: its value is pushed
     for (int i = 0; i < np; ++i) {
         const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
-        put(n, make_uint4(kFPush, __float_as_uint(pv(i)), 1u, wr));
+        put(n, staged_word(kFPush | kFConst, 0u, wr, __float_as_uint(pv(i))));
         ++n;
         ++rt;
     }
@@ -831,21 +886,24 @@ __global__ __launch_bounds__(1024) void k_class_scan(
 // ranges never overlap whatever the offsets; the program is staged there
 // and its id is scattered (stably) into the partition order.
 //
-// Staged instruction (16 bytes, one scalar load):
-//   x = flags | sel << 8, y = payload, z = rd or leaf-is-constant, w = wr
-//   kFPush  save the top into stack slot w, then the top = leaf
+// Staged instruction (8 bytes, one scalar load):
+//   x = flags | sel << 8 | slot << 16, y = payload
+//   kFPush  save the top into stack slot `slot`, then the top = leaf
 //   kFUn    the top = unary sel (SIN..ABS as 0..5) of the top
-//   kFSBin  the top = stack slot z  OP_sel  top  (ADD..DIV as 0..3)
+//   kFSBin  the top = stack slot `slot`  OP_sel  top  (ADD..DIV as 0..3)
 //   kFLBin  the top = top  OP_sel  leaf
 //   kFLast  (with any of the above) the program's last instruction
-// A leaf is the constant with bits y when z != 0, else the input row at LDS
-// byte offset y (variable index * sub-tile cases * 4).
+// A leaf is the constant with bits y when kFConst is set, else the input
+// row at LDS byte offset y (variable index * sub-tile cases * 4).  Eight
+// bytes (not sixteen) keep the code of the programs that the resident
+// wavefronts run at once small enough to stay in the scalar cache while
+// each program passes over its window.
 __global__ __launch_bounds__(kBucketBlock) void k_stage(
     int64_t n_programs, const DevDataset* __restrict__ ds, const DevRequest* __restrict__ reqs,
     const int64_t* __restrict__ seg_start, const int32_t* __restrict__ pds, int32_t n_blk,
     const int64_t* __restrict__ blk_code, const int32_t* __restrict__ blk_base,
     const int32_t* __restrict__ overflow, uint8_t* __restrict__ cls,
-    ProgMeta* __restrict__ meta, uint4* __restrict__ code, int32_t* __restrict__ order)
+    ProgMeta* __restrict__ meta, uint2* __restrict__ code, int32_t* __restrict__ order)
 {
     __shared__ long long sc[kBucketBlock];
     constexpr int kW = kBucketBlock / 64;
@@ -1090,8 +1148,20 @@ __device__ __forceinline__ void acc_pair(float& hi, float& lo, float h2, float l
         }                                                                          \
     } while (0)
 
+// Whether any lane of the wavefront holds, among its K values, one with
+// |v| > limit or a NaN: one compare per value into a lane mask, the masks
+// OR-ed on the scalar unit.
+template <int K>
+__device__ __forceinline__ bool wave_any_above(const float (&v)[K], float limit)
+{
+    uint64_t m = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) m |= __ballot(!(fabsf(v[j]) <= limit));
+    return m != 0ull;
+}
+
 template <int MAXD, int K>
-__device__ __forceinline__ void run_program(const uint4* __restrict__ pc,
+__device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                                             const float* __restrict__ xl, float (&tos)[K])
 {
     constexpr int J = 32 / MAXD;                  // cases per 32-float chunk
@@ -1106,59 +1176,61 @@ __device__ __forceinline__ void run_program(const uint4* __restrict__ pc,
     // staged word says.
     uint32_t f;
     do {
-        const uint4 w = *pc;
+        const uint2 w = *pc;
         ++pc;
         f = w.x;
+        const uint32_t sel = (f >> 8) & 0xFu;
+        const uint32_t slot = (f >> 16) & 31u;
         if (f & kFSBin) {
-            // a = second from top (stack slot z), b = top
+            // a = second from top (stack slot `slot`), b = top
             float sv[K];
 #pragma unroll
-            for (int j = 0; j < K; ++j) sv[j] = GP_CHUNK_GET(w.z & 31u, j);
-            GP_BINARY(GP_ADD + (f >> 8), sv, tos);
+            for (int j = 0; j < K; ++j) sv[j] = GP_CHUNK_GET(slot, j);
+            GP_BINARY(GP_ADD + sel, sv, tos);
         } else if (f & kFLBin) {
-            float lv[K];
-            GP_LEAF(w.z, w.y, lv);
-            GP_BINARY_AB(GP_ADD + (f >> 8), tos, lv, tos);
+            // top OP leaf; a constant leaf gets its own copy of the op
+            // switch so the constant stays a scalar operand instead of
+            // being broadcast into registers first
+            if (f & kFConst) {
+                float cv[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) cv[j] = __uint_as_float(w.y);
+                GP_BINARY_AB(GP_ADD + sel, tos, cv, tos);
+            } else {
+                float lv[K];
+                GP_LEAF(false, w.y, lv);
+                GP_BINARY_AB(GP_ADD + sel, tos, lv, tos);
+            }
         } else if (!(f & kFUn)) {
             // the old top moves into the stack (slot MAXD-1 never holds a
             // live element, so a push onto an empty stack writes there),
             // the leaf becomes the top
 #pragma unroll
-            for (int j = 0; j < K; ++j) GP_CHUNK_PUT(w.w & 31u, j, tos[j]);
-            GP_LEAF(w.z, w.y, tos);
+            for (int j = 0; j < K; ++j) GP_CHUNK_PUT(slot, j, tos[j]);
+            GP_LEAF(f & kFConst, w.y, tos);
         } else {
             if (f & kFPush) {
                 // f(leaf): the old top is saved first
 #pragma unroll
-                for (int j = 0; j < K; ++j) GP_CHUNK_PUT(w.w & 31u, j, tos[j]);
-                GP_LEAF(w.z, w.y, tos);
+                for (int j = 0; j < K; ++j) GP_CHUNK_PUT(slot, j, tos[j]);
+                GP_LEAF(f & kFConst, w.y, tos);
             }
         // unary: replaces the top
-        const uint32_t uop = GP_SIN + (f >> 8);
+        const uint32_t uop = GP_SIN + sel;
         {
             switch (uop) {
             case GP_SIN:
             case GP_COS: {
-                // fast path for |x| <= 2^17; the library function (with a
-                // large-argument reduction) for the rest
-                bool big = false;
-#pragma unroll
-                for (int j = 0; j < K; ++j) big |= !(fabsf(tos[j]) <= kTrigFastLimit);
-                if (__builtin_expect(__ballot(big) != 0ull, 0)) {
-                    // rare: cases beyond the fast range take the library
-                    // function (with its large-argument reduction)
+                // fast path when every case of the wavefront has |x| <= 2^17;
+                // otherwise per case, the library function (with its
+                // large-argument reduction) beyond the fast range
+                if (__builtin_expect(wave_any_above<K>(tos, kTrigFastLimit), 0)) {
                     if (uop == GP_SIN) {
 #pragma unroll
-                        for (int j = 0; j < K; ++j) {
-                            const float x = tos[j];
-                            tos[j] = fabsf(x) <= kTrigFastLimit ? sin_fast(x) : sinf(x);
-                        }
+                        for (int j = 0; j < K; ++j) tos[j] = sin_value(tos[j]);
                     } else {
 #pragma unroll
-                        for (int j = 0; j < K; ++j) {
-                            const float x = tos[j];
-                            tos[j] = fabsf(x) <= kTrigFastLimit ? cos_fast(x) : cosf(x);
-                        }
+                        for (int j = 0; j < K; ++j) tos[j] = cos_value(tos[j]);
                     }
                 } else if (uop == GP_SIN) {
 #pragma unroll
@@ -1170,17 +1242,36 @@ __device__ __forceinline__ void run_program(const uint4* __restrict__ pc,
                 break;
             }
             case GP_EXP:
+                // same split as sin/cos, at |x| <= 87 (per case values equal
+                // exp_value's either way)
+                if (__builtin_expect(wave_any_above<K>(tos, kExpFastLimit), 0)) {
 #pragma unroll
-                for (int j = 0; j < K; ++j) tos[j] = expf(tos[j]);
+                    for (int j = 0; j < K; ++j) tos[j] = exp_value(tos[j]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) tos[j] = exp_fast(tos[j]);
+                }
                 break;
             case GP_LOG:
 #pragma unroll
                 for (int j = 0; j < K; ++j) tos[j] = log_protected(tos[j]);
                 break;
-            case GP_SQRT:
+            case GP_SQRT: {
+                // the hardware root directly unless some case of the
+                // wavefront is below the scaling threshold (or NaN);
+                // sqrt_abs gives the same value for the others
+                uint64_t tiny = 0;
 #pragma unroll
-                for (int j = 0; j < K; ++j) tos[j] = sqrt_abs(tos[j]);
+                for (int j = 0; j < K; ++j) tiny |= __ballot(!(fabsf(tos[j]) >= kSqrtTiny));
+                if (__builtin_expect(tiny != 0ull, 0)) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) tos[j] = sqrt_value(tos[j]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) tos[j] = __builtin_amdgcn_sqrtf(fabsf(tos[j]));
+                }
                 break;
+            }
             default:
 #pragma unroll
                 for (int j = 0; j < K; ++j) tos[j] = fabsf(tos[j]);
@@ -1193,7 +1284,7 @@ __device__ __forceinline__ void run_program(const uint4* __restrict__ pc,
 
 template <int MAXD, int K>
 __global__ __launch_bounds__(kWG) void k_eval(
-    const uint4* __restrict__ code, const ProgMeta* __restrict__ meta,
+    const uint2* __restrict__ code, const ProgMeta* __restrict__ meta,
     const int32_t* __restrict__ order, const int32_t* __restrict__ class_info,
     uint32_t* __restrict__ work_counter, const DevDataset* __restrict__ ds,
     const int32_t* __restrict__ seg_ds, const int32_t* __restrict__ seg_cnt,
@@ -1348,7 +1439,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
 // runs one program of the group and each lane writes its K values.
 template <int MAXD, int K>
 __global__ __launch_bounds__(kWG) void k_predict(
-    const uint4* __restrict__ code, const ProgMeta* __restrict__ meta,
+    const uint2* __restrict__ code, const ProgMeta* __restrict__ meta,
     const int32_t* __restrict__ order, const int32_t* __restrict__ class_info,
     uint32_t* __restrict__ work_counter, const float* __restrict__ X,
     float* __restrict__ out, int64_t ld_out, EvalConst a)
@@ -1464,7 +1555,7 @@ Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride, int
     const int64_t n_blk = (n_programs + kBucketBlock - 1) / kBucketBlock;
     size_t off = 0;
     // a staged program never holds more instructions than nodes
-    L.code = off;       off = align_up(off + (size_t)(n_nodes + 1) * sizeof(uint4));
+    L.code = off;       off = align_up(off + (size_t)(n_nodes + 1) * sizeof(uint2));
     L.meta = off;       off = align_up(off + (size_t)n_programs * sizeof(ProgMeta));
     L.cls = off;        off = align_up(off + (size_t)n_programs);
     L.order = off;      off = align_up(off + (size_t)n_programs * 4);
@@ -1493,7 +1584,7 @@ Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride, int
 
 // Device views of one call's workspace.
 struct Staged {
-    uint4* code;
+    uint2* code;
     ProgMeta* meta;
     uint8_t* cls;
     int32_t* order;
@@ -1522,7 +1613,7 @@ Staged carve(void* base, const Layout& L)
 {
     char* ws = static_cast<char*>(base);
     Staged st;
-    st.code = reinterpret_cast<uint4*>(ws + L.code);
+    st.code = reinterpret_cast<uint2*>(ws + L.code);
     st.meta = reinterpret_cast<ProgMeta*>(ws + L.meta);
     st.cls = reinterpret_cast<uint8_t*>(ws + L.cls);
     st.order = reinterpret_cast<int32_t*>(ws + L.order);
@@ -1739,7 +1830,7 @@ struct Tuning {
 };
 
 struct EvalPtrs {
-    const uint4* code;
+    const uint2* code;
     const ProgMeta* meta;
     const int32_t* order;
     const int32_t* class_info;
