@@ -454,25 +454,29 @@ __device__ __forceinline__ float div_protected(float a, float b)
 }
 
 // Per-case values of the elementary functions: the fast formula inside its
-// range, the library function outside.  The interpreter calls these only
-// when some case of a wavefront is outside a fast range (it takes the fast
-// formulas directly otherwise), and constant folding always; they stay out
-// of line so that their per-case range tests are not merged into the
-// interpreter's wavefront-wide tests (which would keep the per-case results
-// live across the branch) and their library reductions do not raise the
-// interpreter's register count.
-__attribute__((noinline)) __device__ float sin_value(float x)
+// range, the library function outside.  Constant folding uses the inline
+// forms.  The interpreter calls the out-of-line forms, only when some case
+// of a wavefront is outside a fast range (it takes the fast formulas
+// directly otherwise): out of line, their per-case range tests are not
+// merged into the interpreter's wavefront-wide tests (which would keep the
+// per-case results live across the branch) and their library reductions
+// do not raise the interpreter's register count.  Both forms run the same
+// arithmetic, so they give the same bits.
+__device__ __forceinline__ float sin_value_inl(float x)
 {
     return fabsf(x) <= kTrigFastLimit ? sin_fast(x) : sinf(x);
 }
-__attribute__((noinline)) __device__ float cos_value(float x)
+__device__ __forceinline__ float cos_value_inl(float x)
 {
     return fabsf(x) <= kTrigFastLimit ? cos_fast(x) : cosf(x);
 }
-__attribute__((noinline)) __device__ float exp_value(float x)
+__device__ __forceinline__ float exp_value_inl(float x)
 {
     return fabsf(x) <= kExpFastLimit ? exp_fast(x) : expf(x);
 }
+__attribute__((noinline)) __device__ float sin_value(float x) { return sin_value_inl(x); }
+__attribute__((noinline)) __device__ float cos_value(float x) { return cos_value_inl(x); }
+__attribute__((noinline)) __device__ float exp_value(float x) { return exp_value_inl(x); }
 __attribute__((noinline)) __device__ float sqrt_value(float x) { return sqrt_abs(x); }
 
 // One operator on one value, exactly as the interpreter computes it for a
@@ -490,11 +494,11 @@ __device__ __forceinline__ float binary_value(uint32_t bop, float a, float b)
 __device__ __forceinline__ float unary_value(uint32_t uop, float x)
 {
     switch (uop) {
-    case GP_SIN: return sin_value(x);
-    case GP_COS: return cos_value(x);
-    case GP_EXP: return exp_value(x);
+    case GP_SIN: return sin_value_inl(x);
+    case GP_COS: return cos_value_inl(x);
+    case GP_EXP: return exp_value_inl(x);
     case GP_LOG: return log_protected(x);
-    case GP_SQRT: return sqrt_value(x);
+    case GP_SQRT: return sqrt_abs(x);
     default: return fabsf(x);
     }
 }
@@ -834,8 +838,19 @@ __global__ __launch_bounds__(1024) void k_class_scan(
     const int total = kKeys * n_blk;
     const int chunk = (total + 1023) / 1024;
     const int lo = t * chunk, hi = min(total, lo + chunk);
+    // loads in batches of 8, so that a thread's loads are in flight together
     int sum = 0;
-    for (int i = lo; i < hi; ++i) sum += blk_counts[i];
+    {
+        int i = lo;
+        for (; i + 8 <= hi; i += 8) {
+            int v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = blk_counts[i + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) sum += v[u];
+        }
+        for (; i < hi; ++i) sum += blk_counts[i];
+    }
     part[t] = sum;
     const int chunk2 = (n_blk + 1023) / 1024;
     const int lo2 = t * chunk2, hi2 = min(n_blk, lo2 + chunk2);
@@ -853,9 +868,22 @@ __global__ __launch_bounds__(1024) void k_class_scan(
         __syncthreads();
     }
     int run = part[t] - sum;
-    for (int i = lo; i < hi; ++i) {
-        blk_base[i] = run;
-        run += blk_counts[i];
+    {
+        int i = lo;
+        for (; i + 8 <= hi; i += 8) {
+            int v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = blk_counts[i + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                blk_base[i + u] = run;
+                run += v[u];
+            }
+        }
+        for (; i < hi; ++i) {
+            blk_base[i] = run;
+            run += blk_counts[i];
+        }
     }
     long long run2 = lpart[t] - sum2;
     for (int i = lo2; i < hi2; ++i) {
