@@ -99,7 +99,11 @@ constexpr int kK1 = 4;                  // cases per lane of the depth <= 16 cla
 constexpr int kMaxTiles = 32;            // case tiles per program (cap)
 constexpr uint32_t kNoSlot = 0xFFu;      // staged write slot: nothing to save
 constexpr int kBucketBlock = 128;        // programs per staging/partition block
-constexpr int kStageNodes = 8192;        // LDS node cache of a staging block (32 KB)
+constexpr int kStageNodes = 6656;        // LDS node cache of a staging block (26 KB, 52 per program)
+// Constants held back for folding per program while staging: a longer run
+// of constants is pushed (as runtime values) before the next one is held.
+// 16 keeps the staging block at four per CU (with the node cache).
+constexpr int kHeldConsts = 16;
 constexpr int kMaxRequests = 4096;       // requests per batched call (tables are scanned by one workgroup)
 
 // Per-program record written by the staging passes.
@@ -627,13 +631,8 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
     for (int64_t k = s; k < e; ++k) {
         const uint32_t w = nodes(k);
         const uint32_t op = w & 0xFFu, arg = w >> 8;
-        if (op == GP_CONST) {
-            pv(np & (GP_MAX_STACK - 1)) = consts(arg);   // np < 32 in a valid program
-            ++np;
-            continue;
-        }
-        if (op == GP_LOAD) {
-            // flush: held-back constants become runtime elements, bottom up
+        // held-back constants become runtime elements, bottom up
+        auto flush = [&]() {
             for (int i = 0; i < np; ++i) {
                 const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
                 put(n, staged_word(kFPush | kFConst, 0u, wr, __float_as_uint(pv(i))));
@@ -641,6 +640,15 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
                 ++rt;
             }
             np = 0;
+        };
+        if (op == GP_CONST) {
+            if (np == kHeldConsts) flush();
+            pv(np & (kHeldConsts - 1)) = consts(arg);
+            ++np;
+            continue;
+        }
+        if (op == GP_LOAD) {
+            flush();
             const uint32_t payload = arg * row_bytes;
             const uint32_t nx = k + 1 < e ? (nodes(k + 1) & 0xFFu) : 0xFFu;
             const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
@@ -721,6 +729,7 @@ __device__ void check_program(Nodes nodes, int64_t s, int64_t e, uint32_t allowe
         if (depth > GP_MAX_STACK) { status = GP_PROG_TOO_DEEP; break; }
         if (depth > maxd) maxd = depth;
         if (op == GP_CONST) {
+            if (np == kHeldConsts) { n_st += np; np = 0; }   // pushed, as in staging
             ++np;
         } else if (op == GP_LOAD) {
             n_st += np + 1;                   // flush, then the variable
@@ -937,7 +946,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_stage(
     constexpr int kW = kBucketBlock / 64;
     __shared__ int wcnt[kW][kKeys];
     __shared__ uint32_t cache_mem[kStageNodes];
-    __shared__ float pv_mem[GP_MAX_STACK * kBucketBlock];
+    __shared__ float pv_mem[kHeldConsts * kBucketBlock];
     lds_u32* cache = (lds_u32*)cache_mem;
     const int t = threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * kBucketBlock + t;

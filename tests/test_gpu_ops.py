@@ -212,6 +212,12 @@ def test_constant_subtrees_fold_to_the_same_bits():
         [c(6), c(6), MUL, v(0), ADD],                    # overflow in the folded part
         [v(0), c(2), c(5), SUB, DIV],                    # protected division by a small constant
         [c(0), EXP, EXP, EXP, LOG, c(1), COS, ADD],
+        # runs of constants longer than staging holds back (16): the
+        # excess is pushed as runtime values and still computes the same
+        [c(j % 5) for j in range(20)] + [ADD, SUB] * 9 + [MUL, v(0), ADD],
+        [c(j % 3) for j in range(24)] + [SIN] + [ADD] * 23 + [v(0), MUL],
+        [c(0)] * 17 + [v(0)] + [c(1)] * 14 + [SUB] * 31 + [COS],
+        [v(0)] + [c(j % 4) for j in range(31)] + [DIV, ADD] * 15 + [ADD],
     ]
     # the same programs with constant j read from input row 1 + j
     as_vars = [[v(1 + (t >> 8)) if (t & 0xFF) == CONST else t for t in prog] for prog in shapes]
