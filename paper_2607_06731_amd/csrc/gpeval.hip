@@ -1511,7 +1511,9 @@ __global__ __launch_bounds__(kWG) void k_predict(
             staged = sub;
         }
         __syncthreads();
-        const int g = grp * kWaves + wave;
+        // wave-uniform (readfirstlane tells the compiler), so the
+        // interpreter below keeps its scalar branches
+        const int g = __builtin_amdgcn_readfirstlane(grp * kWaves + wave);
         if (g < count) {
             const int pid = order[start + g];
             const ProgMeta m = meta[pid];
