@@ -79,9 +79,10 @@ def cpu_baseline(w, budget_s=15.0):
 
 def measured_counters(workload):
     """Counter figures of the dominant kernel (HBM bytes per launch, VALU busy
-    fraction, VALU lane-slots per node evaluation) from the committed counter
-    summary, while the kernel source is the one the counters were taken on;
-    an empty dict otherwise."""
+    fraction, VALU lane-slots per node evaluation, scalar instructions per
+    interpreted instruction, scalar-cache miss rate) from the committed
+    counter summary, while the kernel source is the one the counters were
+    taken on; an empty dict otherwise."""
     import hashlib
     import re
     if workload != "generation":
@@ -98,7 +99,8 @@ def measured_counters(workload):
         return {}
     out = {}
     for key, cast in (("traffic_bytes_per_launch", int), ("valu_busy", float),
-                      ("valu_lane_slots_per_node_eval", float)):
+                      ("valu_lane_slots_per_node_eval", float),
+                      ("salu_per_dispatch", float), ("scalar_cache_miss_rate", float)):
         v = re.search(r"%s: ([0-9.]+)" % key, text)
         if v:
             out[key] = cast(v.group(1))
@@ -206,6 +208,8 @@ def throughput(args):
                 "traffic": counters.get("traffic_bytes_per_launch"),
                 "valu_busy": counters.get("valu_busy"),
                 "valu_lane_slots_per_node_eval": counters.get("valu_lane_slots_per_node_eval"),
+                "salu_per_dispatch": counters.get("salu_per_dispatch"),
+                "scalar_cache_miss_rate": counters.get("scalar_cache_miss_rate"),
                 "kernel_ms": round(ms0, 4), "node_evals_per_launch": evals0}
     phase_ms = {k: round(v / max(n_calls, 1), 4) for k, v in phases.items()}
 

@@ -122,7 +122,7 @@ constexpr uint32_t kFPush = 1u;
 constexpr uint32_t kFUn = 2u;
 constexpr uint32_t kFSBin = 4u;
 constexpr uint32_t kFLBin = 8u;
-constexpr uint32_t kFLast = 16u;        // the program's last instruction
+constexpr uint32_t kFLast = 0x80000000u;  // the program's last instruction (sign bit)
 constexpr uint32_t kFConst = 32u;       // the leaf is a constant
 
 __host__ __device__ inline uint2 staged_word(uint32_t flags, uint32_t sel, uint32_t slot,
@@ -1191,10 +1191,12 @@ __device__ __forceinline__ void acc_pair(float& hi, float& lo, float h2, float l
 template <int K>
 __device__ __forceinline__ bool wave_any_above(const float (&v)[K], float limit)
 {
-    uint64_t m = 0;
+    // the largest magnitude on the vector unit (a NaN drops out of the
+    // maximum: the fast formulas propagate it), one compare into a mask
+    float m = fabsf(v[0]);
 #pragma unroll
-    for (int j = 0; j < K; ++j) m |= __ballot(!(fabsf(v[j]) <= limit));
-    return m != 0ull;
+    for (int j = 1; j < K; ++j) m = __builtin_fmaxf(m, fabsf(v[j]));
+    return __ballot(m > limit) != 0ull;
 }
 
 template <int MAXD, int K>
@@ -1207,45 +1209,23 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
 #pragma unroll
     for (int j = 0; j < K; ++j) tos[j] = 0.f;
 
-    // Dispatch on flag bits; the program's last instruction carries kFLast
-    // (no separate trip count).  Stack indices are masked to the 32-element
-    // chunk: the register index can never leave the chunk, whatever the
-    // staged word says.
+    // Dispatch on flag bits, unary forms first (the most frequent); the
+    // program's last instruction carries kFLast in the sign bit (no separate
+    // trip count).  The loop is bound by scalar instructions per dispatch,
+    // so the word is fetched with a 32-bit offset (one add per step) and
+    // range tests run on the vector unit.  Stack indices are masked to the
+    // 32-element chunk: the register index can never leave the chunk,
+    // whatever the staged word says.
     uint32_t f;
+    uint32_t off = 0;                          // byte offset of the next word
     do {
-        const uint2 w = *pc;
-        ++pc;
+        const uint2 w = *reinterpret_cast<const uint2*>(
+            reinterpret_cast<const char*>(pc) + off);
+        off += 8u;
         f = w.x;
         const uint32_t sel = (f >> 8) & 0xFu;
         const uint32_t slot = (f >> 16) & 31u;
-        if (f & kFSBin) {
-            // a = second from top (stack slot `slot`), b = top
-            float sv[K];
-#pragma unroll
-            for (int j = 0; j < K; ++j) sv[j] = GP_CHUNK_GET(slot, j);
-            GP_BINARY(GP_ADD + sel, sv, tos);
-        } else if (f & kFLBin) {
-            // top OP leaf; a constant leaf gets its own copy of the op
-            // switch so the constant stays a scalar operand instead of
-            // being broadcast into registers first
-            if (f & kFConst) {
-                float cv[K];
-#pragma unroll
-                for (int j = 0; j < K; ++j) cv[j] = __uint_as_float(w.y);
-                GP_BINARY_AB(GP_ADD + sel, tos, cv, tos);
-            } else {
-                float lv[K];
-                GP_LEAF(false, w.y, lv);
-                GP_BINARY_AB(GP_ADD + sel, tos, lv, tos);
-            }
-        } else if (!(f & kFUn)) {
-            // the old top moves into the stack (slot MAXD-1 never holds a
-            // live element, so a push onto an empty stack writes there),
-            // the leaf becomes the top
-#pragma unroll
-            for (int j = 0; j < K; ++j) GP_CHUNK_PUT(slot, j, tos[j]);
-            GP_LEAF(f & kFConst, w.y, tos);
-        } else {
+        if (f & kFUn) {
             if (f & kFPush) {
                 // f(leaf): the old top is saved first
 #pragma unroll
@@ -1257,27 +1237,26 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
         {
             switch (uop) {
             case GP_SIN:
-            case GP_COS: {
-                // fast path when every case of the wavefront has |x| <= 2^17;
-                // otherwise per case, the library function (with its
-                // large-argument reduction) beyond the fast range
+                // the fast kernel when every case of the wavefront has
+                // |x| <= 2^17; otherwise per case, the library function
+                // (with its large-argument reduction) beyond the fast range
                 if (__builtin_expect(wave_any_above<K>(tos, kTrigFastLimit), 0)) {
-                    if (uop == GP_SIN) {
 #pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = sin_value(tos[j]);
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < K; ++j) tos[j] = cos_value(tos[j]);
-                    }
-                } else if (uop == GP_SIN) {
+                    for (int j = 0; j < K; ++j) tos[j] = sin_value(tos[j]);
+                } else {
 #pragma unroll
                     for (int j = 0; j < K; ++j) tos[j] = sin_fast(tos[j]);
+                }
+                break;
+            case GP_COS:
+                if (__builtin_expect(wave_any_above<K>(tos, kTrigFastLimit), 0)) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) tos[j] = cos_value(tos[j]);
                 } else {
 #pragma unroll
                     for (int j = 0; j < K; ++j) tos[j] = cos_fast(tos[j]);
                 }
                 break;
-            }
             case GP_EXP:
                 // same split as sin/cos, at |x| <= 87 (per case values equal
                 // exp_value's either way)
@@ -1297,10 +1276,10 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                 // the hardware root directly unless some case of the
                 // wavefront is below the scaling threshold (or NaN);
                 // sqrt_abs gives the same value for the others
-                uint64_t tiny = 0;
+                float mn = fabsf(tos[0]);
 #pragma unroll
-                for (int j = 0; j < K; ++j) tiny |= __ballot(!(fabsf(tos[j]) >= kSqrtTiny));
-                if (__builtin_expect(tiny != 0ull, 0)) {
+                for (int j = 1; j < K; ++j) mn = __builtin_fminf(mn, fabsf(tos[j]));
+                if (__builtin_expect(__ballot(!(mn >= kSqrtTiny)) != 0ull, 0)) {
 #pragma unroll
                     for (int j = 0; j < K; ++j) tos[j] = sqrt_value(tos[j]);
                 } else {
@@ -1315,8 +1294,35 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                 break;
             }
             }
+        } else if (f & kFSBin) {
+            // a = second from top (stack slot `slot`), b = top
+            float sv[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) sv[j] = GP_CHUNK_GET(slot, j);
+            GP_BINARY(GP_ADD + sel, sv, tos);
+        } else if (f & kFLBin) {
+            // top OP leaf; a constant leaf gets its own copy of the op
+            // switch so the constant stays a scalar operand instead of
+            // being broadcast into registers first
+            if (f & kFConst) {
+                float cv[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) cv[j] = __uint_as_float(w.y);
+                GP_BINARY_AB(GP_ADD + sel, tos, cv, tos);
+            } else {
+                float lv[K];
+                GP_LEAF(false, w.y, lv);
+                GP_BINARY_AB(GP_ADD + sel, tos, lv, tos);
+            }
+        } else {
+            // the old top moves into the stack (slot MAXD-1 never holds a
+            // live element, so a push onto an empty stack writes there),
+            // the leaf becomes the top
+#pragma unroll
+            for (int j = 0; j < K; ++j) GP_CHUNK_PUT(slot, j, tos[j]);
+            GP_LEAF(f & kFConst, w.y, tos);
         }
-    } while (!(f & kFLast));
+    } while ((int32_t)f >= 0);             // until kFLast (the sign bit)
 }
 
 template <int MAXD, int K>
