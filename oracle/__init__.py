@@ -75,6 +75,9 @@ def lib():
         L.oracle_fitness.argtypes = [vp, vp, i64, vp, i64, vp, i32, i64, vp, i64,
                                      f64, u32, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.oracle_fitness.restype = ctypes.c_int
+        L.oracle_correlation.argtypes = [vp, vp, i64, vp, i64, vp, i32, i64, vp, i64,
+                                         f64, u32, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.oracle_correlation.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -131,6 +134,30 @@ def fitness(nodes, offsets, consts, X, y, tax=0.0, allowed_mask=MASK_BENCH,
     if return_threads:
         return F, mse, status, used
     return F, mse, status
+
+
+def correlation(nodes, offsets, consts, X, y, max_score=1e4, allowed_mask=MASK_BENCH,
+                mode=M64, n_threads=0):
+    """Correlation score per program (the paper's Eq. 1-2): (score, r, status).
+
+    score = M (r^2)^2 (N - (c1 + c2)) - M (c1 - c2), r over the valid pairs
+    (both output and target finite), c1 = pairs with exactly one side
+    invalid, c2 = pairs with both invalid.  Higher is better.  Invalid
+    programs: status != 0 and score = NaN.
+    """
+    nodes, offsets, consts, X, y = _prep(nodes, offsets, consts, X, y)
+    P = offsets.size - 1
+    n_vars, ld = X.shape
+    n_cases = y.size
+    assert ld >= n_cases
+    score = np.empty(P, np.float64)
+    r = np.empty(P, np.float64)
+    status = np.empty(P, np.int32)
+    lib().oracle_correlation(_ptr(nodes), _ptr(offsets), P, _ptr(consts), consts.size,
+                             _ptr(X), n_vars, ld, _ptr(y), n_cases, float(max_score),
+                             allowed_mask, mode, int(n_threads), _ptr(score), _ptr(r),
+                             _ptr(status))
+    return score, r, status
 
 
 def program_outputs(prog, consts, X, n_cases=None, allowed_mask=MASK_BENCH, mode=M64):

@@ -2,6 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY.
 
+Used for both fitness functions: the MSE fitness, and the correlation
+score of Eq. 1-2 (``max_score`` given).
+
 A finite program passes when |F_dev - F_64| <= 1e-4 |F_64| + 1e-12 (the
 relative tolerance of the fitness requirement, plus an absolute floor for
 closed-form zeros).  NaN/inf classification must be identical.  A program
@@ -27,7 +30,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import M32E, M32E_DN, M32E_RAND, M32E_UP, M64, fitness, subset
+from . import M32E, M32E_DN, M32E_RAND, M32E_UP, M64, correlation, fitness, subset
 
 N_RANDOM = 4        # seeded random-perturbation runs per suspicious program
 
@@ -65,12 +68,29 @@ def _close(a, b, rel=REL, abs_=ABS):
 
 
 def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
-          status=None, n_threads=0, max_failures=20):
-    """Gate F_dev (float64[P]) against the oracle.  Returns a GateReport."""
+          status=None, n_threads=0, max_failures=20, max_score=None):
+    """Gate F_dev (float64[P]) against the oracle.  Returns a GateReport.
+
+    With ``max_score`` set, F is the correlation score of Eq. 1-2 with that
+    M (``tax`` unused) and the absolute floor of the tolerance is
+    1e-7 * M * N (a change of 1e-7 in r^4): scores near zero carry the
+    rounding of r^4, not of the score."""
     F_dev = np.asarray(F_dev, np.float64)
+    abs_floor = ABS
+    if max_score is None:
+        def score(nd, of, mode):
+            F, _, st = fitness(nd, of, consts, X, y, tax, allowed_mask, mode, n_threads)
+            return F, st
+    else:
+        abs_floor = 1e-7 * float(max_score) * float(np.asarray(y).size)
+
+        def score(nd, of, mode):
+            F, _, st = correlation(nd, of, consts, X, y, max_score, allowed_mask, mode,
+                                   n_threads)
+            return F, st
+    close = lambda a, b, rel=REL: _close(a, b, rel, abs_floor)
     if F64 is None:
-        F64, _, status = fitness(nodes, offsets, consts, X, y, tax, allowed_mask, M64,
-                                 n_threads)
+        F64, status = score(nodes, offsets, M64)
     rep = GateReport(n=F_dev.size)
     valid = status == 0
     rep.n_invalid_programs = int(np.sum(~valid))
@@ -82,7 +102,7 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
     fin64 = np.isfinite(F64)
     find = np.isfinite(F_dev)
     same_class = fin64 == find
-    good = valid & same_class & (~fin64 | _close(F_dev, F64))
+    good = valid & same_class & (~fin64 | close(F_dev, F64))
     rep.n_pass = int(np.sum(good))
     both = valid & fin64 & find & good
     if both.any():
@@ -94,9 +114,9 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
     sus = np.nonzero(valid & ~good)[0]
     if sus.size:
         sn, so = subset(np.asarray(nodes, np.uint32), np.asarray(offsets, np.int64), sus)
-        F32, _, _ = fitness(sn, so, consts, X, y, tax, allowed_mask, M32E, n_threads)
-        pert = [fitness(sn, so, consts, X, y, tax, allowed_mask, m, n_threads)[0]
-                 for m in [M32E_UP, M32E_DN] + [M32E_RAND + s for s in range(N_RANDOM)]]
+        F32 = score(sn, so, M32E)[0]
+        pert = [score(sn, so, m)[0]
+                for m in [M32E_UP, M32E_DN] + [M32E_RAND + s for s in range(N_RANDOM)]]
         pert = np.stack(pert)
         for i, p in enumerate(sus):
             fd, f64, f32 = F_dev[p], F64[p], F32[i]
@@ -112,12 +132,12 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
                     rep.failures.append((int(p), "class", fd, f64, f32))
                 continue
             # both finite, value mismatch
-            ill = not _close(f32, f64, rel=1e-5, abs_=ABS) if np.isfinite(f32) else True
-            if ill and np.isfinite(f32) and _close(fd, f32):
+            ill = not close(f32, f64, rel=1e-5) if np.isfinite(f32) else True
+            if ill and np.isfinite(f32) and close(fd, f32):
                 rep.n_ill_conditioned += 1
                 continue
             chaotic = (not np.all(np.isfinite(pert[:, i]))
-                       or not np.all(_close(pert[:, i], f32)))
+                       or not np.all(close(pert[:, i], f32)))
             if chaotic:
                 rep.n_chaotic += 1
                 continue

@@ -61,6 +61,22 @@
  *
  * Oracle-only GCL extension (so the paper's printed genomes can run):
  *   DUP, SWAP, DEL, SQUARE (GCL command table).
+ *
+ * Correlation fitness (oracle_correlation; the paper's default fitness,
+ * Sec. "Fitness Functions", Eq. 1 and Eq. 2), written out plainly:
+ *
+ *   a case is a valid pair when f_p(x_i) and y_i are both finite;
+ *   c1 = cases where exactly one of the two is invalid (either side),
+ *   c2 = cases where both are invalid, n = N - c1 - c2 valid pairs;
+ *   r  = sum (y - ybar)(f - fbar) / sqrt(sum (y - ybar)^2 sum (f - fbar)^2)
+ *        over the valid pairs, with the means over the valid pairs (Eq. 1;
+ *        two passes: means first, then the centred sums);
+ *   r  = 0 when n < 2 or either centred sum of squares is 0;
+ *   score = M (r^2)^2 (N - (c1 + c2)) - M (c1 - c2)            (Eq. 2)
+ *
+ * Higher is better.  Readings (listed in the design notes): c1 counts both
+ * mismatch directions; r^4 is the square of the squared r; r = 0 for a
+ * constant output or target; M is a parameter (the paper's maximum score).
  */
 #include <math.h>
 #include <float.h>
@@ -287,6 +303,46 @@ static double program_fitness(const uint32_t* prog, int64_t len,
     return mse + tax * (double)len;
 }
 
+/* Correlation score of one valid program (Eq. 1-2, see the header); f is
+ * scratch for n_cases outputs; *r_out receives r. */
+static double program_correlation(const uint32_t* prog, int64_t len,
+                                  const float* consts, const float* X, int64_t ld_x,
+                                  const float* y, int64_t n_cases, double max_score,
+                                  int mode, double* f, double* r_out)
+{
+    int64_t c1 = 0, c2 = 0, nv = 0;
+    double sum_f = 0.0, sum_y = 0.0;
+    for (int64_t i = 0; i < n_cases; ++i) {
+        f[i] = eval_case(prog, len, consts, X, ld_x, i, mode);
+        const int fv = isfinite(f[i]) != 0, yv = isfinite((double)y[i]) != 0;
+        if (fv && yv) {
+            sum_f += f[i];
+            sum_y += (double)y[i];
+            ++nv;
+        } else if (fv != yv) {
+            ++c1;
+        } else {
+            ++c2;
+        }
+    }
+    double r = 0.0;
+    if (nv >= 2) {
+        const double fbar = sum_f / (double)nv, ybar = sum_y / (double)nv;
+        double sxy = 0.0, sxx = 0.0, syy = 0.0;
+        for (int64_t i = 0; i < n_cases; ++i) {
+            if (!isfinite(f[i]) || !isfinite((double)y[i])) continue;
+            const double dx = f[i] - fbar, dy = (double)y[i] - ybar;
+            sxy += dy * dx;
+            sxx += dx * dx;
+            syy += dy * dy;
+        }
+        if (sxx > 0.0 && syy > 0.0) r = sxy / sqrt(syy * sxx);
+    }
+    *r_out = r;
+    const double r2 = r * r;
+    return max_score * r2 * r2 * (double)(n_cases - (c1 + c2)) - max_score * (double)(c1 - c2);
+}
+
 typedef struct {
     const uint32_t* nodes; const int64_t* offsets;
     const float* consts; int64_t n_consts;
@@ -295,11 +351,21 @@ typedef struct {
     uint32_t allowed_mask; int mode;
     double* out; double* mse; int32_t* status;
     int64_t p0, p1;
+    int correlation;            /* score with Eq. 1-2 instead of the MSE */
+    double max_score;           /* M of Eq. 2 */
 } job_t;
 
 static void* run_job(void* arg)
 {
     job_t* j = (job_t*)arg;
+    double* scratch = NULL;
+    if (j->correlation) {
+        scratch = (double*)malloc(sizeof(double) * (size_t)(j->n_cases > 0 ? j->n_cases : 1));
+        if (!scratch) {
+            for (int64_t p = j->p0; p < j->p1; ++p) j->out[p] = NAN;
+            return NULL;
+        }
+    }
     for (int64_t p = j->p0; p < j->p1; ++p) {
         const uint32_t* prog = j->nodes + j->offsets[p];
         int64_t len = j->offsets[p + 1] - j->offsets[p];
@@ -309,24 +375,30 @@ static void* run_job(void* arg)
         double mse = NAN;
         if (st != ST_VALID) {
             j->out[p] = NAN;    /* not a scorable program */
+        } else if (j->correlation) {
+            j->out[p] = program_correlation(prog, len, j->consts, j->X, j->ld_x, j->y,
+                                            j->n_cases, j->max_score, j->mode, scratch,
+                                            &mse);
         } else {
             j->out[p] = program_fitness(prog, len, j->consts, j->X, j->ld_x,
                                         j->y, j->n_cases, j->tax, j->mode, &mse);
         }
         if (j->mse) j->mse[p] = mse;
     }
+    free(scratch);
     return NULL;
 }
 
 /* Fitness of every program.  Structurally invalid programs get NaN and a
  * nonzero status.  n_threads <= 0 uses every online core.  Returns the
  * number of threads used. */
-int oracle_fitness(const uint32_t* nodes, const int64_t* offsets,
+static int run_all(const uint32_t* nodes, const int64_t* offsets,
                    int64_t n_programs, const float* consts, int64_t n_consts,
                    const float* X, int32_t n_vars, int64_t ld_x,
                    const float* y, int64_t n_cases, double tax,
                    uint32_t allowed_mask, int mode, int n_threads,
-                   double* out_fitness, double* out_mse, int32_t* status)
+                   double* out_fitness, double* out_mse, int32_t* status,
+                   int correlation, double max_score)
 {
     if (n_threads <= 0) n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
     if (n_threads < 1) n_threads = 1;
@@ -345,7 +417,7 @@ int oracle_fitness(const uint32_t* nodes, const int64_t* offsets,
         if (t == n_threads - 1) q = n_programs;
         job_t j = { nodes, offsets, consts, n_consts, X, n_vars, ld_x, y,
                     n_cases, tax, allowed_mask, mode, out_fitness, out_mse,
-                    status, p, q };
+                    status, p, q, correlation, max_score };
         jobs[t] = j;
         p = q;
     }
@@ -354,4 +426,30 @@ int oracle_fitness(const uint32_t* nodes, const int64_t* offsets,
     for (int t = 0; t < n_threads; ++t)
         pthread_join(tids[t], NULL);
     return n_threads;
+}
+
+int oracle_fitness(const uint32_t* nodes, const int64_t* offsets,
+                   int64_t n_programs, const float* consts, int64_t n_consts,
+                   const float* X, int32_t n_vars, int64_t ld_x,
+                   const float* y, int64_t n_cases, double tax,
+                   uint32_t allowed_mask, int mode, int n_threads,
+                   double* out_fitness, double* out_mse, int32_t* status)
+{
+    return run_all(nodes, offsets, n_programs, consts, n_consts, X, n_vars, ld_x, y,
+                   n_cases, tax, allowed_mask, mode, n_threads, out_fitness, out_mse,
+                   status, 0, 0.0);
+}
+
+/* Correlation score (Eq. 1-2) of every program; out_r (optional) receives
+ * r.  Structurally invalid programs get NaN and a nonzero status. */
+int oracle_correlation(const uint32_t* nodes, const int64_t* offsets,
+                       int64_t n_programs, const float* consts, int64_t n_consts,
+                       const float* X, int32_t n_vars, int64_t ld_x,
+                       const float* y, int64_t n_cases, double max_score,
+                       uint32_t allowed_mask, int mode, int n_threads,
+                       double* out_score, double* out_r, int32_t* status)
+{
+    return run_all(nodes, offsets, n_programs, consts, n_consts, X, n_vars, ld_x, y,
+                   n_cases, 0.0, allowed_mask, mode, n_threads, out_score, out_r,
+                   status, 1, max_score);
 }

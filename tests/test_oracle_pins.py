@@ -525,3 +525,113 @@ class TestPrecisionPin:
         F, mse = fit1(prog(("c", 0)), X, y, [0.0])
         exact = Fraction(int(h) ** 2 * (m * m - 1), 12)
         assert mse == float(exact)
+
+
+# ------------------------------------------------- P8: correlation fitness
+def corr1(p, X, y, consts=(), M=1e4, mode=M64):
+    p = np.asarray(p, np.uint32)
+    s, r, st = oracle.correlation(p, [0, p.size], np.array(consts, np.float32),
+                                  np.asarray(X, np.float32), np.asarray(y, np.float32), M,
+                                  allowed_mask=oracle.MASK_GCL, mode=mode)
+    assert st[0] == 0
+    return s[0], r[0]
+
+
+def _eq2(r, N, c1, c2, M):
+    """Eq. 2 with r^4 = (r^2)^2."""
+    return M * (r * r) ** 2 * (N - (c1 + c2)) - M * (c1 - c2)
+
+
+class TestCorrelationPins:
+    """The paper's correlation fitness (Eq. 1-2) pinned to exact rational
+    arithmetic, to numpy's Pearson coefficient, to closed forms and to
+    hand-counted invalid pairs."""
+
+    def test_worked_example_exact(self):
+        # f = x0 = 1, 2, 3, 4 against y = 2, 4, 5, 4: Sxy = 7/2, Sxx = 5,
+        # Syy = 19/4, so r^2 = (49/4) / (95/4) = 49/95
+        xs, ys = [1, 2, 3, 4], [2, 4, 5, 4]
+        fb, yb = Fraction(sum(xs), 4), Fraction(sum(ys), 4)
+        sxy = sum((Fraction(x) - fb) * (Fraction(y) - yb) for x, y in zip(xs, ys))
+        sxx = sum((Fraction(x) - fb) ** 2 for x in xs)
+        syy = sum((Fraction(y) - yb) ** 2 for y in ys)
+        r2 = sxy * sxy / (sxx * syy)
+        assert r2 == Fraction(49, 95)
+        want = float(10000 * r2 * r2 * 4)
+        s, r = corr1(prog(("x", 0)), [xs], ys)
+        assert s == pytest.approx(want, rel=1e-14)
+        assert r == pytest.approx(math.sqrt(49 / 95), rel=1e-14)
+
+    @pytest.mark.parametrize("slope", [3.0, -0.25])
+    def test_perfect_linear_relation_scores_M_N(self, slope):
+        rng = np.random.default_rng(3)
+        x = rng.uniform(-2, 2, 500).astype(np.float32)
+        p = prog(("x", 0), ("c", 0), MUL, ("c", 1), SUB)     # slope * x - 0.5
+        s, r = corr1(p, [x], x, consts=[slope, 0.5])
+        assert abs(r) == pytest.approx(1.0, abs=1e-12)
+        assert s == pytest.approx(1e4 * 500, rel=1e-10)
+
+    def test_constant_output_or_target_scores_zero(self):
+        x = np.linspace(-1, 1, 64, dtype=np.float32)
+        s, r = corr1(prog(("c", 0)), [x], x, consts=[0.75])
+        assert r == 0.0 and s == 0.0
+        s, r = corr1(prog(("x", 0)), [x], np.full(64, 2.0, np.float32))
+        assert r == 0.0 and s == 0.0
+
+    def test_matches_numpy_pearson_on_random_programs(self):
+        from paper_2607_06731_amd import synth
+        w = synth.make_workload("generation", n_programs=60, n_cases=300)
+        s, r, st = oracle.correlation(w.pop.nodes, w.pop.offsets, w.pop.consts,
+                                      w.data.X, w.data.y, 1e4)
+        y = w.data.y.astype(np.float64)
+        checked = 0
+        for p in range(60):
+            f = oracle.program_outputs(w.pop.nodes[w.pop.offsets[p]:w.pop.offsets[p + 1]],
+                                       w.pop.consts, w.data.X)
+            ok = np.isfinite(f) & np.isfinite(y)
+            c1 = int(np.sum(np.isfinite(f) != np.isfinite(y)))
+            c2 = int(np.sum(~np.isfinite(f) & ~np.isfinite(y)))
+            if ok.sum() >= 2 and np.std(f[ok]) > 0:
+                rr = float(np.corrcoef(f[ok], y[ok])[0, 1])
+                checked += 1
+            else:
+                rr = 0.0
+            assert r[p] == pytest.approx(rr, rel=1e-9, abs=1e-12)
+            assert s[p] == pytest.approx(_eq2(rr, 300, c1, c2, 1e4), rel=1e-8, abs=1e-6)
+        assert checked >= 40
+
+    def test_invalid_pairs_counted_on_both_sides(self):
+        # x0 = 200 makes exp(x0) overflow to +inf; y = NaN marks an invalid
+        # target.  Cases: 0-5 valid, 6-7 f invalid, 8-9 y invalid, 10 both.
+        x = np.array([0.1, 0.5, -0.3, 0.9, 0.2, -0.7, 200, 200, 0.4, -0.2, 200], np.float32)
+        y = np.array([1.0, 1.6, 0.8, 2.4, 1.2, 0.5, 3.0, 3.0, np.nan, np.nan, np.inf],
+                     np.float32)
+        s, r = corr1(prog(("x", 0), EXP), [x], y)
+        f = np.exp(x[:6].astype(np.float64))
+        rr = float(np.corrcoef(f, y[:6].astype(np.float64))[0, 1])
+        assert r == pytest.approx(rr, rel=1e-12)
+        # c1 = 4 (cases 6, 7, 8, 9), c2 = 1 (case 10), N = 11
+        assert s == pytest.approx(_eq2(rr, 11, 4, 1, 1e4), rel=1e-12)
+
+    def test_all_outputs_invalid(self):
+        x = np.full(8, 200, np.float32)
+        s, r = corr1(prog(("x", 0), EXP), [x], np.ones(8, np.float32), M=5.0)
+        assert r == 0.0 and s == -5.0 * 8
+
+    def test_affine_invariance(self):
+        from paper_2607_06731_amd import synth
+        w = synth.make_workload("plain", n_programs=40, n_cases=256)
+        base = w.pop
+        c = np.concatenate([base.consts, np.array([2.5, 1.0], np.float32)]).astype(np.float32)
+        ka, kb = base.consts.size, base.consts.size + 1
+        progs = []
+        for p in range(base.n_programs):
+            q = base.nodes[base.offsets[p]:base.offsets[p + 1]]
+            progs.append(np.concatenate([q, [CONST | (ka << 8), MUL, CONST | (kb << 8), ADD]]))
+        nodes2 = np.concatenate(progs).astype(np.uint32)
+        off2 = np.concatenate([[0], np.cumsum([len(q) for q in progs])]).astype(np.int64)
+        s1, r1, _ = oracle.correlation(base.nodes, base.offsets, c, w.data.X, w.data.y, 1e4)
+        s2, r2, _ = oracle.correlation(nodes2, off2, c, w.data.X, w.data.y, 1e4)
+        fin = np.isfinite(s1) & (np.abs(r1) > 1e-3)
+        assert fin.sum() >= 20
+        assert np.allclose(s2[fin], s1[fin], rtol=1e-8)
