@@ -130,6 +130,31 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
             double* out_fitness, int32_t* out_status, hipStream_t stream);
 
 /*
+ * gp_eval_correlation -- score a population with the correlation fitness
+ * (the paper's default, Sec. "Fitness Functions", Eq. 1 and Eq. 2), all
+ * pointers device pointers, arguments as for gp_eval (no length tax).
+ * Per program, over its N = n_cases cases: a valid pair is a case whose
+ * output and target are both finite; c1 counts cases with exactly one of
+ * the two invalid, c2 cases with both invalid; r is Pearson's coefficient
+ * over the valid pairs (0 below two valid pairs or for a constant output or
+ * target); out_score = M (r^2)^2 (N - (c1 + c2)) - M (c1 - c2), M =
+ * max_score (the paper's maximum score; higher is better).  Invalid
+ * programs get NaN and their GP_PROG_* status.  The sums are per-lane
+ * double-double (f, f^2, f*y) and fp64 (y, y^2) over the case tiles, merged
+ * in a fixed order: results are deterministic and independent of the rest
+ * of the population.  Returns GP_E_INVALID_ARG for a non-finite max_score;
+ * other errors as gp_eval.  The workspace's partial buffer takes 72 bytes
+ * per (program, tile) instead of 9 (gp_workspace_size reports the MSE
+ * layout).
+ */
+int gp_eval_correlation(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
+                        int64_t n_nodes, const float* consts, int64_t n_consts,
+                        const float* X, int32_t n_vars, int64_t ld_x,
+                        const float* y, int64_t n_cases, double max_score,
+                        uint32_t allowed_op_mask, double* out_score, int32_t* out_status,
+                        hipStream_t stream);
+
+/*
  * gp_eval_batched -- score the populations of several requests, each
  * against its own resident dataset, in one launch (scoring requests of
  * many concurrent evolutionary runs; the paper spreads populations over

@@ -76,7 +76,7 @@ def lib():
                                      f64, u32, ctypes.c_int, ctypes.c_int, vp, vp, vp]
         L.oracle_fitness.restype = ctypes.c_int
         L.oracle_correlation.argtypes = [vp, vp, i64, vp, i64, vp, i32, i64, vp, i64,
-                                         f64, u32, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+                                         f64, u32, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
         L.oracle_correlation.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -137,8 +137,9 @@ def fitness(nodes, offsets, consts, X, y, tax=0.0, allowed_mask=MASK_BENCH,
 
 
 def correlation(nodes, offsets, consts, X, y, max_score=1e4, allowed_mask=MASK_BENCH,
-                mode=M64, n_threads=0):
-    """Correlation score per program (the paper's Eq. 1-2): (score, r, status).
+                mode=M64, n_threads=0, return_counts=False):
+    """Correlation score per program (the paper's Eq. 1-2): (score, r, status),
+    and with return_counts the int64 counts c1 and c2 as well.
 
     score = M (r^2)^2 (N - (c1 + c2)) - M (c1 - c2), r over the valid pairs
     (both output and target finite), c1 = pairs with exactly one side
@@ -153,10 +154,13 @@ def correlation(nodes, offsets, consts, X, y, max_score=1e4, allowed_mask=MASK_B
     score = np.empty(P, np.float64)
     r = np.empty(P, np.float64)
     status = np.empty(P, np.int32)
+    c12 = np.zeros((P, 2), np.int64)
     lib().oracle_correlation(_ptr(nodes), _ptr(offsets), P, _ptr(consts), consts.size,
                              _ptr(X), n_vars, ld, _ptr(y), n_cases, float(max_score),
                              allowed_mask, mode, int(n_threads), _ptr(score), _ptr(r),
-                             _ptr(status))
+                             _ptr(c12), _ptr(status))
+    if return_counts:
+        return score, r, status, c12[:, 0].copy(), c12[:, 1].copy()
     return score, r, status
 
 

@@ -72,25 +72,35 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
     """Gate F_dev (float64[P]) against the oracle.  Returns a GateReport.
 
     With ``max_score`` set, F is the correlation score of Eq. 1-2 with that
-    M (``tax`` unused) and the absolute floor of the tolerance is
-    1e-7 * M * N (a change of 1e-7 in r^4): scores near zero carry the
-    rounding of r^4, not of the score."""
+    M (``tax`` unused): the relative tolerance (and the reported relative
+    error) is taken on the reference's correlation term M r^4 n, the
+    invalid-pair term must agree exactly, and the absolute floor is
+    1e-9 * M * N (a change of 1e-9 in r^4)."""
     F_dev = np.asarray(F_dev, np.float64)
     abs_floor = ABS
     if max_score is None:
         def score(nd, of, mode):
             F, _, st = fitness(nd, of, consts, X, y, tax, allowed_mask, mode, n_threads)
-            return F, st
+            return F, st, np.abs(F)
     else:
-        abs_floor = 1e-7 * float(max_score) * float(np.asarray(y).size)
+        # the relative tolerance applies to the correlation term M r^4 n of
+        # the reference; the invalid-pair term M (c1 - c2) is a multiple of
+        # M and must agree exactly (a count difference moves the score by M)
+        N = float(np.asarray(y).size)
+        abs_floor = 1e-9 * float(max_score) * N
 
         def score(nd, of, mode):
-            F, _, st = correlation(nd, of, consts, X, y, max_score, allowed_mask, mode,
-                                   n_threads)
-            return F, st
-    close = lambda a, b, rel=REL: _close(a, b, rel, abs_floor)
+            F, r, st, c1, c2 = correlation(nd, of, consts, X, y, max_score, allowed_mask,
+                                           mode, n_threads, return_counts=True)
+            return F, st, float(max_score) * r ** 4 * (N - c1 - c2)
+
+    def close(a, b, scale, rel=REL):
+        return np.abs(a - b) <= rel * scale + abs_floor
+
     if F64 is None:
-        F64, status = score(nodes, offsets, M64)
+        F64, status, T64 = score(nodes, offsets, M64)
+    else:
+        T64 = np.abs(F64)
     rep = GateReport(n=F_dev.size)
     valid = status == 0
     rep.n_invalid_programs = int(np.sum(~valid))
@@ -102,11 +112,13 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
     fin64 = np.isfinite(F64)
     find = np.isfinite(F_dev)
     same_class = fin64 == find
-    good = valid & same_class & (~fin64 | close(F_dev, F64))
+    good = valid & same_class & (~fin64 | close(F_dev, F64, T64))
     rep.n_pass = int(np.sum(good))
-    both = valid & fin64 & find & good
+    # error statistics over programs whose reference is well above the
+    # absolute floor (for the correlation score: r^4 above 1e-6)
+    both = valid & fin64 & find & good & (T64 > 1e3 * abs_floor)
     if both.any():
-        rel = np.abs(F_dev[both] - F64[both]) / np.maximum(np.abs(F64[both]), 1e-300)
+        rel = np.abs(F_dev[both] - F64[both]) / np.maximum(T64[both], 1e-300)
         rep.max_rel_err = float(rel.max())
         rep.median_rel_err = float(np.median(rel))
         rep.p99_rel_err = float(np.quantile(rel, 0.99))
@@ -114,7 +126,7 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
     sus = np.nonzero(valid & ~good)[0]
     if sus.size:
         sn, so = subset(np.asarray(nodes, np.uint32), np.asarray(offsets, np.int64), sus)
-        F32 = score(sn, so, M32E)[0]
+        F32, _, T32 = score(sn, so, M32E)
         pert = [score(sn, so, m)[0]
                 for m in [M32E_UP, M32E_DN] + [M32E_RAND + s for s in range(N_RANDOM)]]
         pert = np.stack(pert)
@@ -132,12 +144,13 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
                     rep.failures.append((int(p), "class", fd, f64, f32))
                 continue
             # both finite, value mismatch
-            ill = not close(f32, f64, rel=1e-5) if np.isfinite(f32) else True
-            if ill and np.isfinite(f32) and close(fd, f32):
+            t64, t32 = T64[p], T32[i]
+            ill = not close(f32, f64, t64, rel=1e-5) if np.isfinite(f32) else True
+            if ill and np.isfinite(f32) and close(fd, f32, t32):
                 rep.n_ill_conditioned += 1
                 continue
             chaotic = (not np.all(np.isfinite(pert[:, i]))
-                       or not np.all(close(pert[:, i], f32)))
+                       or not np.all(close(pert[:, i], f32, t32)))
             if chaotic:
                 rep.n_chaotic += 1
                 continue

@@ -308,7 +308,7 @@ static double program_fitness(const uint32_t* prog, int64_t len,
 static double program_correlation(const uint32_t* prog, int64_t len,
                                   const float* consts, const float* X, int64_t ld_x,
                                   const float* y, int64_t n_cases, double max_score,
-                                  int mode, double* f, double* r_out)
+                                  int mode, double* f, double* r_out, int64_t* c12)
 {
     int64_t c1 = 0, c2 = 0, nv = 0;
     double sum_f = 0.0, sum_y = 0.0;
@@ -339,6 +339,7 @@ static double program_correlation(const uint32_t* prog, int64_t len,
         if (sxx > 0.0 && syy > 0.0) r = sxy / sqrt(syy * sxx);
     }
     *r_out = r;
+    if (c12) { c12[0] = c1; c12[1] = c2; }
     const double r2 = r * r;
     return max_score * r2 * r2 * (double)(n_cases - (c1 + c2)) - max_score * (double)(c1 - c2);
 }
@@ -353,6 +354,7 @@ typedef struct {
     int64_t p0, p1;
     int correlation;            /* score with Eq. 1-2 instead of the MSE */
     double max_score;           /* M of Eq. 2 */
+    int64_t* c12;               /* optional (c1, c2) per program */
 } job_t;
 
 static void* run_job(void* arg)
@@ -378,7 +380,7 @@ static void* run_job(void* arg)
         } else if (j->correlation) {
             j->out[p] = program_correlation(prog, len, j->consts, j->X, j->ld_x, j->y,
                                             j->n_cases, j->max_score, j->mode, scratch,
-                                            &mse);
+                                            &mse, j->c12 ? j->c12 + 2 * p : NULL);
         } else {
             j->out[p] = program_fitness(prog, len, j->consts, j->X, j->ld_x,
                                         j->y, j->n_cases, j->tax, j->mode, &mse);
@@ -398,7 +400,7 @@ static int run_all(const uint32_t* nodes, const int64_t* offsets,
                    const float* y, int64_t n_cases, double tax,
                    uint32_t allowed_mask, int mode, int n_threads,
                    double* out_fitness, double* out_mse, int32_t* status,
-                   int correlation, double max_score)
+                   int correlation, double max_score, int64_t* c12)
 {
     if (n_threads <= 0) n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
     if (n_threads < 1) n_threads = 1;
@@ -417,7 +419,7 @@ static int run_all(const uint32_t* nodes, const int64_t* offsets,
         if (t == n_threads - 1) q = n_programs;
         job_t j = { nodes, offsets, consts, n_consts, X, n_vars, ld_x, y,
                     n_cases, tax, allowed_mask, mode, out_fitness, out_mse,
-                    status, p, q, correlation, max_score };
+                    status, p, q, correlation, max_score, c12 };
         jobs[t] = j;
         p = q;
     }
@@ -437,19 +439,20 @@ int oracle_fitness(const uint32_t* nodes, const int64_t* offsets,
 {
     return run_all(nodes, offsets, n_programs, consts, n_consts, X, n_vars, ld_x, y,
                    n_cases, tax, allowed_mask, mode, n_threads, out_fitness, out_mse,
-                   status, 0, 0.0);
+                   status, 0, 0.0, NULL);
 }
 
 /* Correlation score (Eq. 1-2) of every program; out_r (optional) receives
- * r.  Structurally invalid programs get NaN and a nonzero status. */
+ * r, out_c12 (optional, 2 per program) the counts c1 and c2.  Structurally
+ * invalid programs get NaN and a nonzero status. */
 int oracle_correlation(const uint32_t* nodes, const int64_t* offsets,
                        int64_t n_programs, const float* consts, int64_t n_consts,
                        const float* X, int32_t n_vars, int64_t ld_x,
                        const float* y, int64_t n_cases, double max_score,
                        uint32_t allowed_mask, int mode, int n_threads,
-                       double* out_score, double* out_r, int32_t* status)
+                       double* out_score, double* out_r, int64_t* out_c12, int32_t* status)
 {
     return run_all(nodes, offsets, n_programs, consts, n_consts, X, n_vars, ld_x, y,
                    n_cases, 0.0, allowed_mask, mode, n_threads, out_score, out_r,
-                   status, 1, max_score);
+                   status, 1, max_score, out_c12);
 }

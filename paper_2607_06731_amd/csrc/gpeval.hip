@@ -1325,14 +1325,109 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
     } while ((int32_t)f >= 0);             // until kFLast (the sign bit)
 }
 
-template <int MAXD, int K>
+// ------------------------------------------------- correlation fitness
+// Per (program, tile) sums of the correlation fitness (Eq. 1-2) over the
+// valid pairs (output and target both finite): the sums of f, f^2 and f*y
+// as double-double values (every product of two fp32 values is exact in
+// fp64, so only the additions round), the sums of y and y^2 in fp64, and
+// the counts of pairs with one (c1) or both (c2) sides invalid.  The
+// centred sums are formed once per program from these, in double-double,
+// so the cancellation of a large mean costs nothing visible.
+struct CorrPart {
+    double f_hi, f_lo, ff_hi, ff_lo, fy_hi, fy_lo;
+    double y, yy;
+    int32_t c1, c2;
+};
+static_assert(sizeof(CorrPart) == 72, "CorrPart layout");
+
+enum : int { kFitMse = 0, kFitCorr = 1 };
+constexpr int kCorrMaxG = 32;            // programs per work item in correlation mode (LDS)
+
+// hi + lo += x (Knuth's two-sum on the high part, errors gathered in lo)
+__device__ __forceinline__ void dd_add_d(double& hi, double& lo, double x)
+{
+    const double s = hi + x;
+    const double bp = s - hi;
+    lo += (hi - (s - bp)) + (x - bp);
+    hi = s;
+}
+
+__device__ __forceinline__ void corr_zero(CorrPart& c)
+{
+    c.f_hi = c.f_lo = c.ff_hi = c.ff_lo = c.fy_hi = c.fy_lo = 0.0;
+    c.y = c.yy = 0.0;
+    c.c1 = c.c2 = 0;
+}
+
+// one case: f the program's output, y the target
+__device__ __forceinline__ void corr_case(CorrPart& c, float f, float y)
+{
+    const bool fv = __builtin_isfinite(f), yv = __builtin_isfinite(y);
+    if (fv && yv) {
+        const double fd = (double)f, yd = (double)y;
+        dd_add_d(c.f_hi, c.f_lo, fd);
+        dd_add_d(c.ff_hi, c.ff_lo, fd * fd);
+        dd_add_d(c.fy_hi, c.fy_lo, fd * yd);
+        c.y += yd;
+        c.yy += yd * yd;
+    } else if (fv != yv) {
+        ++c.c1;
+    } else {
+        ++c.c2;
+    }
+}
+
+// a += b (fixed order: the result depends only on the two operands)
+__device__ __forceinline__ void corr_merge(CorrPart& a, const CorrPart& b)
+{
+    dd_add_d(a.f_hi, a.f_lo, b.f_hi);
+    a.f_lo += b.f_lo;
+    dd_add_d(a.ff_hi, a.ff_lo, b.ff_hi);
+    a.ff_lo += b.ff_lo;
+    dd_add_d(a.fy_hi, a.fy_lo, b.fy_hi);
+    a.fy_lo += b.fy_lo;
+    a.y += b.y;
+    a.yy += b.yy;
+    a.c1 += b.c1;
+    a.c2 += b.c2;
+}
+
+// wavefront tree: every lane ends with the same sums
+__device__ __forceinline__ void corr_wave_reduce(CorrPart& c)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        CorrPart o;
+        o.f_hi = __shfl_xor(c.f_hi, off);
+        o.f_lo = __shfl_xor(c.f_lo, off);
+        o.ff_hi = __shfl_xor(c.ff_hi, off);
+        o.ff_lo = __shfl_xor(c.ff_lo, off);
+        o.fy_hi = __shfl_xor(c.fy_hi, off);
+        o.fy_lo = __shfl_xor(c.fy_lo, off);
+        o.y = __shfl_xor(c.y, off);
+        o.yy = __shfl_xor(c.yy, off);
+        o.c1 = __shfl_xor(c.c1, off);
+        o.c2 = __shfl_xor(c.c2, off);
+        // the lower lane's sums first, so both lanes of a pair compute the
+        // same bits
+        if ((__lane_id() & off) == 0) {
+            corr_merge(c, o);
+        } else {
+            corr_merge(o, c);
+            c = o;
+        }
+    }
+}
+
+template <int MAXD, int K, int FIT>
 __global__ __launch_bounds__(kWG) void k_eval(
     const uint2* __restrict__ code, const ProgMeta* __restrict__ meta,
     const int32_t* __restrict__ order, const int32_t* __restrict__ class_info,
     uint32_t* __restrict__ work_counter, const DevDataset* __restrict__ ds,
     const int32_t* __restrict__ seg_ds, const int32_t* __restrict__ seg_cnt,
     const int32_t* __restrict__ seg_pos, const uint32_t* __restrict__ item_pre,
-    const int32_t* __restrict__ class_g, float2* __restrict__ part, uint8_t* __restrict__ part_bad, EvalConst a)
+    const int32_t* __restrict__ class_g, float2* __restrict__ part, uint8_t* __restrict__ part_bad,
+    CorrPart* __restrict__ part_corr, EvalConst a)
 {
     static_assert(K == 2 || K == 4 || K == 8, "cases per lane");
     static_assert(MAXD == 8 || MAXD == 16 || MAXD == 32, "stack class");
@@ -1343,6 +1438,9 @@ __global__ __launch_bounds__(kWG) void k_eval(
     float* xt = lds;                              // window: [W][n_vars + 1][SUB]
     float2* acc = reinterpret_cast<float2*>(lds + a.tile_floats);            // [G]
     uint32_t* accbad = reinterpret_cast<uint32_t*>(acc + a.G);               // [G]
+    // correlation mode: one CorrPart per program instead (the tile floats are
+    // a multiple of 2, so the array is 8-byte aligned)
+    CorrPart* cacc = reinterpret_cast<CorrPart*>(lds + a.tile_floats);       // [G]
     __shared__ uint32_t s_item, s_next;
 
     const int tid = threadIdx.x;
@@ -1360,8 +1458,12 @@ __global__ __launch_bounds__(kWG) void k_eval(
     for (;;) {
         if (tid == 0) s_item = atomicAdd(work_counter, 1u);
         if (tid < G) {
-            acc[tid] = make_float2(0.f, 0.f);
-            accbad[tid] = 0u;
+            if constexpr (FIT == kFitCorr) {
+                corr_zero(cacc[tid]);
+            } else {
+                acc[tid] = make_float2(0.f, 0.f);
+                accbad[tid] = 0u;
+            }
         }
         __syncthreads();
         const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
@@ -1426,8 +1528,11 @@ __global__ __launch_bounds__(kWG) void k_eval(
                 const int pid = order[obase + g];
                 const ProgMeta m = meta[pid];
                 // fused residual, validity and scaled compensated square sum
+                // (MSE), or the sums of the correlation fitness
                 float hi = 0.f, lo_ = 0.f;
                 bool bad = false;
+                CorrPart cl;
+                if constexpr (FIT == kFitCorr) corr_zero(cl);
                 for (int b = 0; b < nw; ++b) {
                     const float* blk = xt + b * rows * SUB;
                     float tos[K];
@@ -1438,15 +1543,24 @@ __global__ __launch_bounds__(kWG) void k_eval(
                     for (int j = 0; j < K; ++j) {
                         if (base + lane + j * 64 < n_cases) {
                             const float f = tos[j];
-                            bad |= !__builtin_isfinite(f);
-                            const float r = (f - yt[lane + j * 64]) * scale;
-                            float s, e;
-                            two_sum(hi, r * r, s, e);
-                            hi = s;
-                            lo_ += e;
+                            if constexpr (FIT == kFitCorr) {
+                                corr_case(cl, f, yt[lane + j * 64]);
+                            } else {
+                                bad |= !__builtin_isfinite(f);
+                                const float r = (f - yt[lane + j * 64]) * scale;
+                                float s, e;
+                                two_sum(hi, r * r, s, e);
+                                hi = s;
+                                lo_ += e;
+                            }
                         }
                     }
                 }
+                if constexpr (FIT == kFitCorr) {
+                    corr_wave_reduce(cl);
+                    // the windows add up in order, whichever wavefront ran them
+                    if (lane == 0) corr_merge(cacc[g], cl);
+                } else {
                 // wavefront tree: every lane ends with the same pair
 #pragma unroll
                 for (int off = 32; off >= 1; off >>= 1) {
@@ -1463,14 +1577,19 @@ __global__ __launch_bounds__(kWG) void k_eval(
                     acc[g] = make_float2(h, l);
                     if (wave_bad) accbad[g] = 1u;
                 }
+                }
             }
             __syncthreads();
         }
         if (tid < gn) {
             const int pid = order[obase + tid];
             const int64_t slot = (int64_t)pid * a.part_stride + tile;
-            part[slot] = acc[tid];
-            part_bad[slot] = (uint8_t)(accbad[tid] != 0u);
+            if constexpr (FIT == kFitCorr) {
+                part_corr[slot] = cacc[tid];
+            } else {
+                part[slot] = acc[tid];
+                part_bad[slot] = (uint8_t)(accbad[tid] != 0u);
+            }
         }
         __syncthreads();
     }
@@ -1555,8 +1674,10 @@ struct ReduceArgs {
     const DevDataset* ds;
     const float2* part;
     const uint8_t* part_bad;
+    const CorrPart* part_corr;
     int64_t n_programs;
     int32_t part_stride;
+    double max_score;
 };
 
 __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
@@ -1583,6 +1704,82 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
     R.out[q] = (bad || !(mse <= (double)FLT_MAX)) ? __builtin_inf() : mse + D.tax * (double)m.len;
 }
 
+// Double-double helpers for the final centred sums (Dekker's product via
+// fma, Knuth's two-sum).
+struct DDv { double hi, lo; };
+__device__ __forceinline__ DDv dd_norm(double hi, double lo)
+{
+    const double s = hi + lo;
+    return DDv{s, lo - (s - hi)};
+}
+__device__ __forceinline__ DDv dd_add(DDv a, DDv b)
+{
+    const double s = a.hi + b.hi;
+    const double bp = s - a.hi;
+    const double e = (a.hi - (s - bp)) + (b.hi - bp);
+    return dd_norm(s, e + a.lo + b.lo);
+}
+__device__ __forceinline__ DDv dd_neg(DDv a) { return DDv{-a.hi, -a.lo}; }
+__device__ __forceinline__ DDv dd_mul(DDv a, DDv b)
+{
+    const double p = a.hi * b.hi;
+    const double e = fma(a.hi, b.hi, -p);
+    return dd_norm(p, e + (a.hi * b.lo + a.lo * b.hi));
+}
+__device__ __forceinline__ DDv dd_div_d(DDv a, double d)
+{
+    const double q1 = a.hi / d;
+    const DDv r = dd_add(a, dd_neg(dd_mul(DDv{q1, 0.0}, DDv{d, 0.0})));
+    return dd_norm(q1, (r.hi + r.lo) / d);
+}
+
+// Correlation score per program (Eq. 2 with r of Eq. 1 over the valid
+// pairs): the tiles' sums in order, then the centred sums
+// Sxx = S(f^2) - S(f)^2/n, Sxy = S(fy) - S(f)S(y)/n, Syy = S(y^2) - S(y)^2/n
+// in double-double.  r = 0 below two valid pairs, or when a centred sum
+// of squares is zero (below 2^-80 of its raw sum: a constant output or
+// target, whose double-double difference is a rounding residue).
+__global__ __launch_bounds__(256) void k_reduce_corr(ReduceArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n_programs) return;
+    const int r = a.pds[p];
+    const DevRequest& R = a.reqs[r];
+    const int64_t q = p - a.seg_start[r];
+    if (!R.out || q >= R.n_programs) return;     // only for inconsistent tables
+    const int c = a.cls[p];
+    if (c >= kKeys) { R.out[q] = __builtin_nan(""); return; }
+    const DevDataset& D = a.ds[R.dataset];
+    const int nt = D.n_tiles[c / kLenBuckets];
+    DDv sf{0.0, 0.0}, sff{0.0, 0.0}, sfy{0.0, 0.0};
+    double sy = 0.0, syy = 0.0;
+    int64_t c1 = 0, c2 = 0;
+    for (int t = 0; t < nt; ++t) {
+        const CorrPart v = a.part_corr[p * a.part_stride + t];
+        sf = dd_add(sf, DDv{v.f_hi, v.f_lo});
+        sff = dd_add(sff, DDv{v.ff_hi, v.ff_lo});
+        sfy = dd_add(sfy, DDv{v.fy_hi, v.fy_lo});
+        sy += v.y;
+        syy += v.yy;
+        c1 += v.c1;
+        c2 += v.c2;
+    }
+    const int64_t N = D.n_cases;
+    const int64_t n = N - c1 - c2;
+    double rr = 0.0;
+    if (n >= 2) {
+        const double dn = (double)n;
+        const DDv Y{sy, 0.0};
+        const DDv sxx = dd_add(sff, dd_neg(dd_div_d(dd_mul(sf, sf), dn)));
+        const DDv sxy = dd_add(sfy, dd_neg(dd_div_d(dd_mul(sf, Y), dn)));
+        const DDv syy2 = dd_add(DDv{syy, 0.0}, dd_neg(dd_div_d(dd_mul(Y, Y), dn)));
+        const double vx = sxx.hi + sxx.lo, vy = syy2.hi + syy2.lo;
+        if (vx > 0x1p-80 * sff.hi && vy > 0x1p-80 * syy) rr = (sxy.hi + sxy.lo) / sqrt(vx * vy);
+    }
+    const double r2 = rr * rr;
+    R.out[q] = a.max_score * r2 * r2 * (double)n - a.max_score * (double)(c1 - c2);
+}
+
 // ----------------------------------------------------------- workspaces
 struct Layout {
     size_t code, meta, cls, order, blk_counts, blk_base, blk_slen, blk_code, class_info, class_g;
@@ -1594,7 +1791,7 @@ struct Layout {
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride, int32_t n_ds,
-                   int32_t n_seg)
+                   int32_t n_seg, int fit = kFitMse)
 {
     Layout L;
     const int64_t n_blk = (n_programs + kBucketBlock - 1) / kBucketBlock;
@@ -1611,8 +1808,11 @@ Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride, int
     L.class_info = off; off = align_up(off + 2 * kClasses * 4);
     L.class_g = off;    off = align_up(off + kClasses * 4);
     L.counters = off;   off = align_up(off + kClasses * 4);
-    L.part = off;       off = align_up(off + (size_t)n_programs * part_stride * sizeof(float2));
-    L.part_bad = off;   off = align_up(off + (size_t)n_programs * part_stride);
+    // per (program, tile) partials: a compensated pair and a bad flag
+    // (MSE), or the correlation sums
+    const size_t part_elem = fit == kFitCorr ? sizeof(CorrPart) : sizeof(float2);
+    L.part = off;       off = align_up(off + (size_t)n_programs * part_stride * part_elem);
+    L.part_bad = off;   off = align_up(off + (fit == kFitCorr ? 0 : (size_t)n_programs * part_stride));
     L.ds = off;         off = align_up(off + (size_t)n_ds * sizeof(DevDataset));
     L.req = off;        off = align_up(off + (size_t)n_seg * sizeof(DevRequest));
     L.seg_ds = off;     off = align_up(off + (size_t)n_seg * 4);
@@ -1642,6 +1842,7 @@ struct Staged {
     uint32_t* counters;
     float2* part;
     uint8_t* part_bad;
+    CorrPart* part_corr;            // the same memory as part, correlation mode
     DevDataset* ds;
     DevRequest* req;
     int32_t* seg_ds;
@@ -1670,6 +1871,7 @@ Staged carve(void* base, const Layout& L)
     st.class_g = reinterpret_cast<int32_t*>(ws + L.class_g);
     st.counters = reinterpret_cast<uint32_t*>(ws + L.counters);
     st.part = reinterpret_cast<float2*>(ws + L.part);
+    st.part_corr = reinterpret_cast<CorrPart*>(ws + L.part);
     st.part_bad = reinterpret_cast<uint8_t*>(ws + L.part_bad);
     st.ds = reinterpret_cast<DevDataset*>(ws + L.ds);
     st.req = reinterpret_cast<DevRequest*>(ws + L.req);
@@ -1813,6 +2015,8 @@ struct Problem {
     int64_t max_cases;
     uint32_t allowed;
     int32_t need_out;               // fitness outputs required (not for gp_predict)
+    int32_t fit;                    // kFitMse, or kFitCorr (gp_eval_correlation)
+    double max_score;               // M of the correlation score
 };
 
 int check_common(int64_t n_programs, int64_t n_nodes, int64_t n_consts, int32_t n_vars,
@@ -1896,24 +2100,25 @@ size_t eval_tile_floats(int n_vars)
     return one > budget ? one : budget;
 }
 
-template <int MAXD, int K>
+template <int MAXD, int K, int FIT>
 size_t eval_lds_bytes(int n_vars, int G)
 {
-    return eval_tile_floats<MAXD, K>(n_vars) * sizeof(float) + (size_t)G * sizeof(float2) +
-           (size_t)G * sizeof(uint32_t);
+    const size_t acc = FIT == kFitCorr ? (size_t)G * sizeof(CorrPart)
+                                       : (size_t)G * (sizeof(float2) + sizeof(uint32_t));
+    return eval_tile_floats<MAXD, K>(n_vars) * sizeof(float) + acc;
 }
 
 // Grid size of one class kernel (LDS attribute set outside any capture).
-template <int MAXD, int K>
+template <int MAXD, int K, int FIT>
 int eval_grid(int n_vars, int G, int wg_per_cu, int cus, int* grid, size_t* lds_out)
 {
-    const size_t lds = eval_lds_bytes<MAXD, K>(n_vars, G);
+    const size_t lds = eval_lds_bytes<MAXD, K, FIT>(n_vars, G);
     if (lds > 64 * 1024) {
-        GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval<MAXD, K>),
+        GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval<MAXD, K, FIT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
     int per_cu = 0;
-    GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval<MAXD, K>, kWG, lds));
+    GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval<MAXD, K, FIT>, kWG, lds));
     if (per_cu < 1) return set_error(GP_E_TOO_LARGE, "n_vars=%d needs %zu bytes of LDS per workgroup", n_vars, lds);
     if (wg_per_cu > 0 && wg_per_cu < per_cu) per_cu = wg_per_cu;
     *grid = cus * per_cu;
@@ -1929,6 +2134,13 @@ struct EvalLaunch {
     Layout layout;
 };
 
+// Programs per work item at most (the LDS accumulators' capacity): the
+// tuning's value, capped in correlation mode (larger per-program sums).
+int group_capacity(const Problem& pb, const Tuning& tu)
+{
+    return pb.fit == kFitCorr && tu.G > kCorrMaxG ? kCorrMaxG : tu.G;
+}
+
 int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
 {
     int cus = 0;
@@ -1942,10 +2154,17 @@ int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
         if (t > el->stride) el->stride = t;
     }
     el->target_items = 4 * 6 * cus;     // ~4 items per workgroup slot
-    if ((rc = eval_grid<8, 4>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
-    if ((rc = eval_grid<16, kK1>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
-    if ((rc = eval_grid<32, 2>(pb.max_vars, tu.G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2])) != GP_OK) return rc;
-    el->layout = make_layout(pb.n_programs, pb.n_nodes, el->stride, pb.n_ds, pb.n_req);
+    const int G = group_capacity(pb, tu);
+    if (pb.fit == kFitCorr) {
+        if ((rc = eval_grid<8, 4, kFitCorr>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
+        if ((rc = eval_grid<16, kK1, kFitCorr>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
+        if ((rc = eval_grid<32, 2, kFitCorr>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2])) != GP_OK) return rc;
+    } else {
+        if ((rc = eval_grid<8, 4, kFitMse>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
+        if ((rc = eval_grid<16, kK1, kFitMse>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
+        if ((rc = eval_grid<32, 2, kFitMse>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2])) != GP_OK) return rc;
+    }
+    el->layout = make_layout(pb.n_programs, pb.n_nodes, el->stride, pb.n_ds, pb.n_req, pb.fit);
     return GP_OK;
 }
 
@@ -1987,11 +2206,12 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
                        st.seg_cnt);
     GP_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(64), 0, stream, st.seg_cnt, st.seg_ds, st.ds,
-                       pb.n_req, tu.G, el.target_items, st.seg_pos, st.item_pre, st.class_g);
+                       pb.n_req, group_capacity(pb, tu), el.target_items, st.seg_pos, st.item_pre,
+                       st.class_g);
     GP_HIP_TRY(hipGetLastError());
 
     EvalConst ea{};
-    ea.G = tu.G;
+    ea.G = group_capacity(pb, tu);
     ea.part_stride = el.stride;
     ea.max_vars = pb.max_vars;
     ea.n_seg = pb.n_req;
@@ -2005,9 +2225,18 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
         ea.cls = c;
         const dim3 g(el.grid[c]), b(kWG);
 #define GP_LAUNCH_EVAL(MD, KK)                                                                 \
-        hipLaunchKernelGGL((k_eval<MD, KK>), g, b, el.lds[c], sc, st.code, st.meta, st.order,  \
-                           st.class_info, st.counters + c, st.ds, st.seg_ds, st.seg_cnt,       \
-                           st.seg_pos, st.item_pre, st.class_g, st.part, st.part_bad, ea)
+        do {                                                                                   \
+            if (pb.fit == kFitCorr)                                                            \
+                hipLaunchKernelGGL((k_eval<MD, KK, kFitCorr>), g, b, el.lds[c], sc, st.code,   \
+                                   st.meta, st.order, st.class_info, st.counters + c, st.ds,   \
+                                   st.seg_ds, st.seg_cnt, st.seg_pos, st.item_pre, st.class_g, \
+                                   st.part, st.part_bad, st.part_corr, ea);                   \
+            else                                                                               \
+                hipLaunchKernelGGL((k_eval<MD, KK, kFitMse>), g, b, el.lds[c], sc, st.code,    \
+                                   st.meta, st.order, st.class_info, st.counters + c, st.ds,   \
+                                   st.seg_ds, st.seg_cnt, st.seg_pos, st.item_pre, st.class_g, \
+                                   st.part, st.part_bad, st.part_corr, ea);                   \
+        } while (0)
         if (c == 0) {
             ea.tile_floats = (int32_t)eval_tile_floats<8, 4>(pb.max_vars);
             GP_LAUNCH_EVAL(8, 4);
@@ -2030,11 +2259,16 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
     ReduceArgs ra{};
     ra.meta = st.meta; ra.cls = st.cls; ra.pds = st.pds; ra.reqs = st.req;
     ra.seg_start = st.seg_start; ra.ds = st.ds;
-    ra.part = st.part; ra.part_bad = st.part_bad;
+    ra.part = st.part; ra.part_bad = st.part_bad; ra.part_corr = st.part_corr;
     ra.n_programs = pb.n_programs; ra.part_stride = el.stride;
+    ra.max_score = pb.max_score;
     if ((rc = ce.mark(4, stream)) != GP_OK) return rc;
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((pb.n_programs + 255) / 256)), dim3(256), 0,
-                       stream, ra);
+    if (pb.fit == kFitCorr)
+        hipLaunchKernelGGL(k_reduce_corr, dim3((unsigned)((pb.n_programs + 255) / 256)), dim3(256),
+                           0, stream, ra);
+    else
+        hipLaunchKernelGGL(k_reduce, dim3((unsigned)((pb.n_programs + 255) / 256)), dim3(256), 0,
+                           stream, ra);
     GP_HIP_TRY(hipGetLastError());
     if ((rc = ce.mark(5, stream)) != GP_OK) return rc;
     return GP_OK;
@@ -2329,6 +2563,22 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
     const gp_problem d{nodes, offsets, n_programs, n_nodes, consts, n_consts, X, n_vars, ld_x,
                        y, n_cases, tax_on_length, allowed_op_mask, out_fitness, out_status};
     return eval_problem(make_problem(&d), stream);
+}
+
+int gp_eval_correlation(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
+                        int64_t n_nodes, const float* consts, int64_t n_consts,
+                        const float* X, int32_t n_vars, int64_t ld_x,
+                        const float* y, int64_t n_cases, double max_score,
+                        uint32_t allowed_op_mask, double* out_score, int32_t* out_status,
+                        hipStream_t stream)
+{
+    if (!std::isfinite(max_score)) return set_error(GP_E_INVALID_ARG, "max_score is not finite");
+    const gp_problem d{nodes, offsets, n_programs, n_nodes, consts, n_consts, X, n_vars, ld_x,
+                       y, n_cases, 0.0, allowed_op_mask, out_score, out_status};
+    Problem pb = make_problem(&d);
+    pb.fit = kFitCorr;
+    pb.max_score = max_score;
+    return eval_problem(pb, stream);
 }
 
 int gp_eval_batched(const gp_request* requests_dev, int32_t n_requests,

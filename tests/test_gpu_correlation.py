@@ -1,0 +1,157 @@
+"""GPU parity of the correlation fitness (the paper's Eq. 1-2) through the
+C ABI (gp_eval_correlation) against the fp64 oracle's two-pass definition.
+
+Floating point: the gate of oracle.gate in correlation mode (1e-4 relative
+plus an absolute floor of 1e-9 M N, fp32-certified exceptions counted).
+Closed forms (a perfect linear relation scores M N, a constant output 0,
+all-invalid outputs -M N) and population independence are checked exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import ADD, CONST, EXP, LOAD, MUL, SUB, gate
+
+pytestmark = pytest.mark.gpu
+M = 1e4
+
+
+def _gp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_06731_amd as gp
+    gp.lib()
+    return gp
+
+
+def _say(msg):
+    print("[gpu] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def _gate(S, nodes, offsets, consts, X, y, mask, label):
+    rep = gate.check(S, nodes, offsets, consts, X, y, 0.0, mask, max_score=M)
+    _say(label + ": " + rep.summary())
+    assert rep.ok(), rep.failures[:10]
+    return rep
+
+
+@pytest.mark.parametrize("name,P,n", [("plain", None, None), ("generation", 4000, None),
+                                      ("uneven", 3000, 4000), ("precision", 48, 1 << 20),
+                                      ("generation", 2000, 1025), ("generation", 2000, 7)])
+def test_correlation_parity(name, P, n):
+    gp = _gp()
+    from paper_2607_06731_amd import synth
+    w = synth.make_workload(name, n_programs=P, n_cases=n)
+    label = "correlation %s P=%d n=%d" % (name, w.pop.n_programs, w.data.n_cases)
+    _say(label)
+    S = gp.evaluate_correlation(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y,
+                                M, w.allowed_mask)
+    _gate(S, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.allowed_mask,
+          label)
+
+
+def test_correlation_invalid_targets():
+    """Targets with NaN and inf: pairs with one or both sides invalid are
+    counted (c1, c2) and leave r to the valid pairs."""
+    gp = _gp()
+    from paper_2607_06731_amd import synth
+    w = synth.make_workload("generation", n_programs=3000, n_cases=3000)
+    y = w.data.y.copy()
+    rng = np.random.default_rng(12)
+    y[rng.choice(y.size, 60, replace=False)] = np.nan
+    y[rng.choice(y.size, 30, replace=False)] = np.inf
+    _say("correlation with invalid targets")
+    S = gp.evaluate_correlation(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, y, M,
+                                w.allowed_mask)
+    _gate(S, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, y, w.allowed_mask,
+          "correlation invalid targets")
+
+
+def test_correlation_closed_forms():
+    gp = _gp()
+    rng = np.random.default_rng(2)
+    n = 5000
+    X = rng.uniform(-2, 2, (1, n)).astype(np.float32)
+    X[0, :7] = 300.0                      # exp overflows on these cases
+    y = X[0].copy()
+    y[:7] = 1.0
+    consts = np.array([3.0, 0.5, 0.75], np.float32)
+    progs = [
+        [LOAD, CONST | (0 << 8), MUL, CONST | (1 << 8), SUB],    # 3x - 0.5 on y = x
+        [CONST | (2 << 8)],                                        # constant
+        [LOAD, EXP, EXP],                                          # +inf everywhere it overflows
+    ]
+    nodes = np.array([t for p in progs for t in p], np.uint32)
+    off = np.concatenate([[0], np.cumsum([len(p) for p in progs])]).astype(np.int64)
+    _say("correlation closed forms")
+    S = gp.evaluate_correlation(nodes, off, consts, X, y, M)
+    _gate(S, nodes, off, consts, X, y, oracle.MASK_BENCH, "correlation closed forms")
+    assert S[1] == 0.0                    # constant output: r = 0
+    # a perfect linear relation scores exactly M n
+    Xp = rng.uniform(-2, 2, (1, n)).astype(np.float32)
+    S2 = gp.evaluate_correlation(nodes[:5], off[:2], consts, Xp, Xp[0].copy(), M)
+    assert S2[0] == pytest.approx(M * n, rel=1e-12)
+    # every output invalid: -M n
+    Xi = np.full((1, 64), 300.0, np.float32)
+    S3 = gp.evaluate_correlation(np.array([LOAD, EXP, EXP], np.uint32), np.array([0, 3]),
+                                 consts, Xi, np.ones(64, np.float32), M)
+    assert S3[0] == -M * 64
+
+
+def test_correlation_population_independent():
+    """A program's score does not depend on the rest of the population."""
+    gp = _gp()
+    from paper_2607_06731_amd import synth
+    w = synth.make_workload("generation", n_programs=5000, n_cases=4096)
+    S = gp.evaluate_correlation(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y,
+                                M, w.allowed_mask)
+    idx = np.random.default_rng(3).choice(5000, 300, replace=False)
+    sub = w.pop.take(idx)
+    S_sub = gp.evaluate_correlation(sub.nodes, sub.offsets, sub.consts, w.data.X, w.data.y,
+                                    M, w.allowed_mask)
+    _say("correlation population independence")
+    assert np.array_equal(S[idx], S_sub)
+    S_again = gp.evaluate_correlation(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X,
+                                      w.data.y, M, w.allowed_mask)
+    assert np.array_equal(S, S_again)
+
+
+def test_correlation_large_offsets():
+    """Outputs with a large constant offset over a small variation (the
+    case that breaks naive raw-moment formulas) still match the oracle."""
+    gp = _gp()
+    rng = np.random.default_rng(8)
+    n = 4096
+    X = rng.uniform(-1, 1, (1, n)).astype(np.float32)
+    y = (X[0] + rng.normal(0, 0.1, n)).astype(np.float32)
+    consts = np.array([1e3, 1e5, 3e6, 2.0], np.float32)
+    progs = [[LOAD, CONST | (j << 8), ADD] for j in range(3)]
+    progs += [[LOAD, CONST | (3 << 8), MUL, CONST | (j << 8), ADD] for j in range(3)]
+    nodes = np.array([t for p in progs for t in p], np.uint32)
+    off = np.concatenate([[0], np.cumsum([len(p) for p in progs])]).astype(np.int64)
+    _say("correlation large offsets")
+    S = gp.evaluate_correlation(nodes, off, consts, X, y, M)
+    _gate(S, nodes, off, consts, X, y, oracle.MASK_BENCH, "correlation large offsets")
+
+
+def test_correlation_full_size_sampled():
+    """Full generation launch (100,000 programs x 4,096 cases) in
+    correlation mode, gated on a seeded length-stratified sample."""
+    gp = _gp()
+    from paper_2607_06731_amd import synth
+    w = synth.make_workload("generation")
+    _say("correlation generation full size")
+    S = gp.evaluate_correlation(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y,
+                                M, w.allowed_mask)
+    rng = np.random.default_rng(46)
+    L = w.pop.lengths
+    idx = np.concatenate([rng.choice(np.nonzero(L == l)[0], 6, replace=False)
+                          for l in range(3, 65)])
+    sub = w.pop.take(idx)
+    _gate(S[idx], sub.nodes, sub.offsets, sub.consts, w.data.X, w.data.y, w.allowed_mask,
+          "correlation generation full (sampled %d)" % idx.size)
+    assert np.isfinite(S).all()

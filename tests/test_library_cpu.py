@@ -89,6 +89,18 @@ def test_eval_rejects_bad_arguments_before_device_work(L):
     assert L.gp_eval(None, c, 0, 0, None, 0, None, 0, 1, c, 1, 0.0, 0, None, None, None) == gp.GP_OK
 
 
+def test_correlation_rejects_bad_arguments_before_device_work(L):
+    c = ctypes.c_void_p(1)
+    for M in (float("nan"), float("inf")):
+        assert L.gp_eval_correlation(c, c, 1, 1, c, 0, c, 1, 1, c, 1, M, 0, c, None,
+                                     None) == gp.GP_E_INVALID_ARG
+        assert b"max_score" in L.gp_last_error()
+    assert L.gp_eval_correlation(c, c, -1, 0, c, 0, c, 1, 1, c, 1, 1e4, 0, c, None,
+                                 None) == gp.GP_E_INVALID_ARG
+    assert L.gp_eval_correlation(None, c, 0, 0, None, 0, None, 0, 1, c, 1, 1e4, 0, None,
+                                 None, None) == gp.GP_OK
+
+
 def test_binding_refuses_host_tensors():
     import torch
     with pytest.raises(TypeError):

@@ -612,6 +612,11 @@ class TestCorrelationPins:
         assert r == pytest.approx(rr, rel=1e-12)
         # c1 = 4 (cases 6, 7, 8, 9), c2 = 1 (case 10), N = 11
         assert s == pytest.approx(_eq2(rr, 11, 4, 1, 1e4), rel=1e-12)
+        p = prog(("x", 0), EXP)
+        _, _, _, c1, c2 = oracle.correlation(p, [0, p.size], np.zeros(0, np.float32),
+                                             x.reshape(1, -1), y, 1e4,
+                                             allowed_mask=oracle.MASK_GCL, return_counts=True)
+        assert (c1[0], c2[0]) == (4, 1)
 
     def test_all_outputs_invalid(self):
         x = np.full(8, 200, np.float32)
