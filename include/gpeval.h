@@ -155,6 +155,34 @@ int gp_eval_correlation(const uint32_t* nodes, const int64_t* offsets, int64_t n
                         hipStream_t stream);
 
 /*
+ * gp_mc_rank -- the paper's Monte-Carlo ranking (Sec. "Monte-Carlo
+ * Ranking", Table 2) on the device, without sorting the population.  All
+ * pointers are device pointers; asynchronous on `stream`.
+ *   fitness         n doubles (e.g. the output of gp_eval: lower is better,
+ *                   higher_is_better = 0; or of gp_eval_correlation: 1).
+ *                   NaN is the worst value and ties with -inf (after the
+ *                   direction is applied).
+ *   seed            the sample: draw k (0 <= k < sample_size) is individual
+ *                   floor(h_k * n / 2^64), h_k the k-th SplitMix64 output
+ *                   of the sequence started at seed (with replacement).
+ *   sample_size     1..1024 (the paper samples 100).
+ *   out_band        n int32: 10 * floor(p / 10), capped at 90, where the
+ *                   percentile p = floor(100 * (sampled values strictly
+ *                   worse than the individual) / sample_size).
+ *   out_children    optional n floats: the band's expected number of
+ *                   children (Table 2: 4, 2.5, 1.5, 1, 0.5, 0.25, 0.15,
+ *                   0.06, 0.03, 0.01 from the top band down).
+ *   out_sample_keys optional sample_size doubles: the sampled values,
+ *                   larger-is-better keys (v or -v, NaN as -inf), ascending.
+ * Integer work: results are exact and depend only on (fitness, seed,
+ * sample_size, direction).  Errors: GP_E_INVALID_ARG for n < 0, a sample
+ * size out of range, or NULL fitness/out_band with n > 0.
+ */
+int gp_mc_rank(const double* fitness, int64_t n, int32_t higher_is_better, uint64_t seed,
+               int32_t sample_size, int32_t* out_band, float* out_children,
+               double* out_sample_keys, hipStream_t stream);
+
+/*
  * gp_eval_batched -- score the populations of several requests, each
  * against its own resident dataset, in one launch (scoring requests of
  * many concurrent evolutionary runs; the paper spreads populations over

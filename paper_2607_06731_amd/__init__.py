@@ -109,6 +109,8 @@ def lib():
         L.gp_eval_correlation.argtypes = [vp, vp, i64, i64, vp, i64, vp, i32, i64, vp, i64,
                                           ctypes.c_double, u32, vp, vp, vp]
         L.gp_eval_correlation.restype = ctypes.c_int
+        L.gp_mc_rank.argtypes = [vp, i64, i32, ctypes.c_uint64, i32, vp, vp, vp, vp]
+        L.gp_mc_rank.restype = ctypes.c_int
         L.gp_eval_batched.argtypes = [vp, i32, vp, i32, i64, i64, i32, i64, u32, vp]
         L.gp_eval_batched.restype = ctypes.c_int
         L.gp_predict.argtypes = [vp, vp, i64, i64, vp, i64, vp, i32, i64, i64, u32, vp, i64,
@@ -276,6 +278,26 @@ def gp_eval_correlation(nodes, offsets, consts, X, y, max_score, out_score,
         _dev_ptr(out_status, torch.int32, "out_status"), _stream_handle(stream))
     _check(rc)
     return out_score
+
+
+def gp_mc_rank(fitness, higher_is_better, seed, out_band, out_children=None,
+               out_sample_keys=None, sample_size=100, stream=None):
+    """Monte-Carlo ranking of a device float64 fitness tensor (asynchronous):
+    percentile bands into out_band (int32), Table 2's expected children
+    into out_children (float32, optional), the sorted sample keys into
+    out_sample_keys (float64[sample_size], optional)."""
+    import torch
+    n = fitness.numel()
+    if out_band.numel() != n:
+        raise ValueError("out_band must have one entry per individual")
+    rc = lib().gp_mc_rank(_dev_ptr(fitness, torch.float64, "fitness"), n,
+                          1 if higher_is_better else 0, int(seed) & ((1 << 64) - 1),
+                          int(sample_size), _dev_ptr(out_band, torch.int32, "out_band"),
+                          _dev_ptr(out_children, torch.float32, "out_children"),
+                          _dev_ptr(out_sample_keys, torch.float64, "out_sample_keys"),
+                          _stream_handle(stream))
+    _check(rc)
+    return out_band
 
 
 def table_tensor(entries, device="cuda"):

@@ -2505,6 +2505,85 @@ int eval_problem(const Problem& pb, hipStream_t stream)
     return GP_OK;
 }
 
+// ------------------------------------------------- Monte-Carlo ranking
+// The paper's ranking without a sort (Sec. "Monte-Carlo Ranking", Table 2):
+// a random sample of the population's fitness values estimates the
+// percentiles, then one pass places every individual in its percentile
+// band and gives the band's expected number of children.
+//
+// key(v): larger is better; NaN (a program that could not be scored) is
+// the worst value and ties with -inf (an invalid MSE of +inf).
+__device__ __forceinline__ double rank_key(double v, int higher_is_better)
+{
+    if (v != v) return -__builtin_inf();
+    return higher_is_better ? v : -v;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): the k-th output of the sequence
+// started at `seed`, computed directly from the counter.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+constexpr int kMaxRankSample = 1024;
+
+// One workgroup: draw the sample (index k = high 64 bits of h_k * n), read
+// the keys, sort them ascending by counting (ties by sample position, so
+// the order is a function of the keys only), store them.
+__global__ __launch_bounds__(1024) void k_rank_sample(const double* __restrict__ fitness,
+                                                      int64_t n, int32_t higher, uint64_t seed,
+                                                      int32_t S, double* __restrict__ sorted)
+{
+    __shared__ double keys[kMaxRankSample];
+    const int t = threadIdx.x;
+    if (t < S) {
+        const uint64_t h = splitmix64_at(seed, (uint64_t)t);
+        const int64_t idx = (int64_t)__umul64hi(h, (uint64_t)n);
+        keys[t] = rank_key(fitness[idx], higher);
+    }
+    __syncthreads();
+    if (t < S) {
+        const double v = keys[t];
+        int pos = 0;
+        for (int j = 0; j < S; ++j) {
+            const double u = keys[j];
+            pos += (u < v) || (u == v && j < t);
+        }
+        sorted[pos] = v;
+    }
+}
+
+// Expected children per percentile band (Table 2), band b = 10 b ... 10 b + 9.
+__constant__ float kChildrenByBand[10] = {0.01f, 0.03f, 0.06f, 0.15f, 0.25f,
+                                          0.5f, 1.0f, 1.5f, 2.5f, 4.0f};
+
+// One thread per individual: the percentile is 100 x (sampled keys strictly
+// below its key) / S, rounded down; the band is that percentile's tens digit
+// (90 and above is the top band).
+__global__ __launch_bounds__(256) void k_rank_assign(const double* __restrict__ fitness, int64_t n,
+                                                     int32_t higher, int32_t S,
+                                                     const double* __restrict__ sorted,
+                                                     int32_t* __restrict__ out_band,
+                                                     float* __restrict__ out_children)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = rank_key(fitness[i], higher);
+    int lo = 0, hi = S;                         // first sorted key not below v
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sorted[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    const int pct = (int)((100LL * lo) / S);
+    const int band = pct >= 90 ? 9 : pct / 10;
+    out_band[i] = band * 10;
+    if (out_children) out_children[i] = kChildrenByBand[band];
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -2579,6 +2658,32 @@ int gp_eval_correlation(const uint32_t* nodes, const int64_t* offsets, int64_t n
     pb.fit = kFitCorr;
     pb.max_score = max_score;
     return eval_problem(pb, stream);
+}
+
+int gp_mc_rank(const double* fitness, int64_t n, int32_t higher_is_better, uint64_t seed,
+               int32_t sample_size, int32_t* out_band, float* out_children,
+               double* out_sample_keys, hipStream_t stream)
+{
+    if (n < 0) return set_error(GP_E_INVALID_ARG, "n < 0");
+    if (sample_size < 1 || sample_size > kMaxRankSample)
+        return set_error(GP_E_INVALID_ARG, "sample_size must be 1..%d", kMaxRankSample);
+    if (n == 0) return GP_OK;
+    if (!fitness || !out_band) return set_error(GP_E_INVALID_ARG, "NULL fitness or out_band");
+    double* sorted = out_sample_keys;
+    if (!sorted) {
+        Workspace* w = nullptr;
+        const int rc = get_workspace(stream, (size_t)sample_size * sizeof(double), &w);
+        if (rc != GP_OK) return rc;
+        sorted = static_cast<double*>(w->ptr);
+    }
+    const int32_t hb = higher_is_better ? 1 : 0;
+    hipLaunchKernelGGL(k_rank_sample, dim3(1), dim3(kMaxRankSample), 0, stream, fitness, n, hb,
+                       seed, sample_size, sorted);
+    GP_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_rank_assign, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       fitness, n, hb, sample_size, sorted, out_band, out_children);
+    GP_HIP_TRY(hipGetLastError());
+    return GP_OK;
 }
 
 int gp_eval_batched(const gp_request* requests_dev, int32_t n_requests,
