@@ -78,6 +78,11 @@ def lib():
         L.oracle_correlation.argtypes = [vp, vp, i64, vp, i64, vp, i32, i64, vp, i64,
                                          f64, u32, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
         L.oracle_correlation.restype = ctypes.c_int
+        L.oracle_case_rewards.argtypes = [vp, vp, i64, f64, i32, vp]
+        L.oracle_case_rewards.restype = None
+        L.oracle_reward.argtypes = [vp, vp, i64, vp, i64, vp, i32, i64, vp, i64, f64,
+                                    ctypes.c_int, u32, ctypes.c_int, ctypes.c_int, vp, vp]
+        L.oracle_reward.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -162,6 +167,40 @@ def correlation(nodes, offsets, consts, X, y, max_score=1e4, allowed_mask=MASK_B
     if return_counts:
         return score, r, status, c12[:, 0].copy(), c12[:, 1].copy()
     return score, r, status
+
+
+def reward(nodes, offsets, consts, X, y, max_score=1e4, power=1, allowed_mask=MASK_BENCH,
+           mode=M64, n_threads=0):
+    """Integer point-to-point reward per program (the paper's Eq. 5, StdFitFunc,
+    and its Square/Cube/Hyper variants for power 2, 3, 8), summed over the
+    cases: (total, status).  Higher is better; invalid programs get NaN."""
+    if power not in (1, 2, 3, 8):
+        raise ValueError("power must be 1, 2, 3 or 8")
+    if not (float(max_score) == int(max_score) and abs(max_score) <= 2 ** 24):
+        raise ValueError("max_score must be an integer of magnitude <= 2^24")
+    nodes, offsets, consts, X, y = _prep(nodes, offsets, consts, X, y)
+    P = offsets.size - 1
+    n_vars, ld = X.shape
+    n_cases = y.size
+    assert ld >= n_cases
+    total = np.empty(P, np.float64)
+    status = np.empty(P, np.int32)
+    lib().oracle_reward(_ptr(nodes), _ptr(offsets), P, _ptr(consts), consts.size, _ptr(X),
+                        n_vars, ld, _ptr(y), n_cases, float(max_score), int(power),
+                        allowed_mask, mode, int(n_threads), _ptr(total), _ptr(status))
+    return total, status
+
+
+def case_rewards(o, y, max_score=1e4, power=1):
+    """Per-case integer rewards (int64) of outputs ``o`` against targets
+    ``y`` (same shape): the rule summed by :func:`reward`."""
+    if power not in (1, 2, 3, 8):
+        raise ValueError("power must be 1, 2, 3 or 8")
+    o = np.ascontiguousarray(o, np.float64)
+    y = np.ascontiguousarray(np.broadcast_to(np.asarray(y, np.float32), o.shape))
+    out = np.empty(o.shape, np.int64)
+    lib().oracle_case_rewards(_ptr(o), _ptr(y), o.size, float(max_score), int(power), _ptr(out))
+    return out
 
 
 def program_outputs(prog, consts, X, n_cases=None, allowed_mask=MASK_BENCH, mode=M64):

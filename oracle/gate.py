@@ -2,8 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY.
 
-Used for both fitness functions: the MSE fitness, and the correlation
-score of Eq. 1-2 (``max_score`` given).
+Used for the three fitness functions: the MSE fitness, the correlation
+score of Eq. 1-2 (``max_score`` given) and the integer reward of Eq. 5
+(``max_score`` and ``reward_power`` given).
 
 A finite program passes when |F_dev - F_64| <= 1e-4 |F_64| + 1e-12 (the
 relative tolerance of the fitness requirement, plus an absolute floor for
@@ -22,6 +23,19 @@ modes; it is excused only when the arithmetic itself explains it:
     M32E's (an fp32 overflow-range or threshold flip), or equals that of a
     perturbed run (chaotic).
 
+The integer reward sums per-case decisions that amplify an output error
+by M before rounding, so a suspicious reward is judged on the outputs
+instead:
+
+  * output window: per case, the hull of the oracle's outputs in M64, M32E,
+    M32E_UP, M32E_DN and the M32E_RAND runs, widened on each side by its
+    own width and by 4 fp32 ulps; the reward is piecewise monotone in the
+    output (breakpoints at 0 and +-|y|), so its least and greatest value
+    over the window are found among the window's ends and those
+    breakpoints (the invalid-pair value joins when a candidate is not
+    finite).  The device total must lie between the sums of the per-case
+    least and greatest values.
+
 Everything else is a failure.  Counts of each category are reported.
 """
 from __future__ import annotations
@@ -30,7 +44,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import M32E, M32E_DN, M32E_RAND, M32E_UP, M64, correlation, fitness, subset
+from . import (M32E, M32E_DN, M32E_RAND, M32E_UP, M64, case_rewards, correlation, fitness,
+               program_outputs, reward, subset)
 
 N_RANDOM = 4        # seeded random-perturbation runs per suspicious program
 
@@ -46,6 +61,7 @@ class GateReport:
     n_ill_conditioned: int = 0
     n_chaotic: int = 0
     n_class_flip_certified: int = 0
+    n_output_window: int = 0          # reward: within the output-window bounds
     n_fail: int = 0
     max_rel_err: float = 0.0          # over passing finite programs
     median_rel_err: float = 0.0
@@ -56,11 +72,64 @@ class GateReport:
         return self.n_fail == 0
 
     def summary(self):
-        return ("n=%d pass=%d ill=%d chaotic=%d flip=%d fail=%d invalid=%d "
-                "rel_err median=%.2g p99=%.2g max=%.3g"
-                % (self.n, self.n_pass, self.n_ill_conditioned, self.n_chaotic,
-                   self.n_class_flip_certified, self.n_fail, self.n_invalid_programs,
-                   self.median_rel_err, self.p99_rel_err, self.max_rel_err))
+        s = ("n=%d pass=%d ill=%d chaotic=%d flip=%d fail=%d invalid=%d "
+             "rel_err median=%.2g p99=%.2g max=%.3g"
+             % (self.n, self.n_pass, self.n_ill_conditioned, self.n_chaotic,
+                self.n_class_flip_certified, self.n_fail, self.n_invalid_programs,
+                self.median_rel_err, self.p99_rel_err, self.max_rel_err))
+        if self.n_output_window:
+            s += " window=%d" % self.n_output_window
+        return s
+
+
+def window_bounds(O, y, max_score, power):
+    """Per-case reward bounds over output windows.  O: [k, n] candidate
+    outputs (fp64; non-finite allowed), y: [n] fp32 targets.  Returns
+    (rmin, rmax, a, b): the least and greatest reward per case over the
+    fp32 values in [a, b], the hull of the finite candidates widened by its
+    width and 4 fp32 ulps on each side, joined with the invalid-pair value
+    where a candidate is not finite."""
+    y = np.ascontiguousarray(y, np.float32)
+    n = y.size
+    with np.errstate(over="ignore", invalid="ignore"):
+        fin = np.isfinite(O) & np.isfinite(O.astype(np.float32))
+    any_bad = (~fin).any(axis=0)
+    all_bad = (~fin).all(axis=0)
+    lo = np.where(fin, O, np.inf).min(axis=0)
+    hi = np.where(fin, O, -np.inf).max(axis=0)
+    lo = np.where(all_bad, 0.0, lo)
+    hi = np.where(all_bad, 0.0, hi)
+    width = hi - lo
+
+    def ulp(v):
+        v32 = np.minimum(np.abs(v), np.finfo(np.float32).max).astype(np.float32)
+        return np.spacing(v32).astype(np.float64)
+
+    a = lo - width - 4.0 * ulp(lo)
+    b = hi + width + 4.0 * ulp(hi)
+    ay = np.abs(y.astype(np.float64))
+    ay = np.where(np.isnan(ay), 0.0, ay)          # a NaN target has no breakpoint
+    tiny = float(np.finfo(np.float32).smallest_subnormal)
+    zero = np.zeros(n)
+    # window ends and the breakpoints of the piecewise-monotone reward
+    cands = np.stack([np.clip(c, a, b) for c in (a, b, zero, ay, -ay, zero + tiny,
+                                                 zero - tiny)])
+    R = case_rewards(cands, np.broadcast_to(y, cands.shape), max_score, power)
+    rmin, rmax = R.min(axis=0), R.max(axis=0)
+    inv = case_rewards(np.full(n, np.nan), y, max_score, power)
+    rmin = np.where(all_bad, inv, np.where(any_bad, np.minimum(rmin, inv), rmin))
+    rmax = np.where(all_bad, inv, np.where(any_bad, np.maximum(rmax, inv), rmax))
+    return rmin, rmax, a, b
+
+
+def reward_window(prog, consts, X, y, max_score, power, allowed_mask):
+    """Least and greatest integer reward of one program over the per-case
+    output windows described in the module docstring: (lo, hi)."""
+    y = np.ascontiguousarray(y, np.float32)
+    modes = [M64, M32E, M32E_UP, M32E_DN] + [M32E_RAND + s for s in range(N_RANDOM)]
+    O = np.stack([program_outputs(prog, consts, X, y.size, allowed_mask, m) for m in modes])
+    rmin, rmax, _, _ = window_bounds(O, y, max_score, power)
+    return int(rmin.sum()), int(rmax.sum())
 
 
 def _close(a, b, rel=REL, abs_=ABS):
@@ -68,20 +137,32 @@ def _close(a, b, rel=REL, abs_=ABS):
 
 
 def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
-          status=None, n_threads=0, max_failures=20, max_score=None):
+          status=None, n_threads=0, max_failures=20, max_score=None, reward_power=None):
     """Gate F_dev (float64[P]) against the oracle.  Returns a GateReport.
 
     With ``max_score`` set, F is the correlation score of Eq. 1-2 with that
     M (``tax`` unused): the relative tolerance (and the reported relative
     error) is taken on the reference's correlation term M r^4 n, the
     invalid-pair term must agree exactly, and the absolute floor is
-    1e-9 * M * N (a change of 1e-9 in r^4)."""
+    1e-9 * M * N (a change of 1e-9 in r^4).
+
+    With ``reward_power`` also set, F is the integer reward of Eq. 5 (power
+    1, 2, 3 or 8) summed over the cases; the relative tolerance is taken on
+    |F| + 0.01 M N (rounding flips of single cases are expected between an
+    fp32 and an fp64 evaluation)."""
     F_dev = np.asarray(F_dev, np.float64)
     abs_floor = ABS
     if max_score is None:
         def score(nd, of, mode):
             F, _, st = fitness(nd, of, consts, X, y, tax, allowed_mask, mode, n_threads)
             return F, st, np.abs(F)
+    elif reward_power is not None:
+        spread = 1e-2 * float(max_score) * float(np.asarray(y).size)
+
+        def score(nd, of, mode):
+            F, st = reward(nd, of, consts, X, y, max_score, reward_power, allowed_mask, mode,
+                           n_threads)
+            return F, st, np.abs(F) + spread
     else:
         # the relative tolerance applies to the correlation term M r^4 n of
         # the reference; the invalid-pair term M (c1 - c2) is a multiple of
@@ -124,6 +205,19 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
         rep.p99_rel_err = float(np.quantile(rel, 0.99))
 
     sus = np.nonzero(valid & ~good)[0]
+    if sus.size and reward_power is not None:
+        nodes_a = np.asarray(nodes, np.uint32)
+        offs_a = np.asarray(offsets, np.int64)
+        for p in sus:
+            lo, hi = reward_window(nodes_a[offs_a[p]:offs_a[p + 1]], consts, X, y, max_score,
+                                   reward_power, allowed_mask)
+            if lo <= F_dev[p] <= hi:
+                rep.n_output_window += 1
+                continue
+            rep.n_fail += 1
+            if len(rep.failures) < max_failures:
+                rep.failures.append((int(p), "outside output window", F_dev[p], F64[p], lo, hi))
+        return rep
     if sus.size:
         sn, so = subset(np.asarray(nodes, np.uint32), np.asarray(offsets, np.int64), sus)
         F32, _, T32 = score(sn, so, M32E)

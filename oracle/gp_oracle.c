@@ -77,6 +77,20 @@
  * Higher is better.  Readings (listed in the design notes): c1 counts both
  * mismatch directions; r^4 is the square of the squared r; r = 0 for a
  * constant output or target; M is a parameter (the paper's maximum score).
+ *
+ * Point-to-point integer reward (oracle_reward; StdFitFunc of the section
+ * on fitness functions, Eq. 5, and its Square/Cube/Hyper variants), per
+ * case, then summed over the cases in int64 (higher is better):
+ *
+ *   valid pair (output and target finite), in fp32 (the reward function
+ *   takes fp32 values; the output is rounded to fp32 first):
+ *     M                                   if max(|o|, |y|) = 0
+ *     rint(M * ratio^p - M/11)            if o and y have opposite signs
+ *     rint(M * ratio^p)                   otherwise
+ *     ratio = min(|o|,|y|) / max(|o|,|y|), ratio^p by repeated products
+ *     (p = 1, 2 = r*r, 3 = r^2*r, 8 = ((r^2)^2)^2), rint = round half to
+ *     even, M/11 the fp32 quotient;
+ *   invalid pair: +M when both are invalid, -M when one is.
  */
 #include <math.h>
 #include <float.h>
@@ -344,6 +358,43 @@ static double program_correlation(const uint32_t* prog, int64_t len,
     return max_score * r2 * r2 * (double)(n_cases - (c1 + c2)) - max_score * (double)(c1 - c2);
 }
 
+/* fp32 reward of one valid pair (see the header). */
+static int64_t pair_reward(float o, float y, float M, int power)
+{
+    const float ao = fabsf(o), ay = fabsf(y);
+    const float mx = ao > ay ? ao : ay, mn = ao > ay ? ay : ao;
+    if (mx == 0.0f) return (int64_t)M;
+    const float r = mn / mx;
+    float rp = r;
+    if (power == 2) rp = r * r;
+    else if (power == 3) rp = (r * r) * r;
+    else if (power == 8) { const float r2 = r * r, r4 = r2 * r2; rp = r4 * r4; }
+    float v = M * rp;
+    if ((o < 0.0f && y > 0.0f) || (o > 0.0f && y < 0.0f)) v = v - M / 11.0f;
+    return (int64_t)rintf(v);
+}
+
+/* Reward of one case from the program's output f (rounded to fp32 here). */
+static int64_t case_reward(double f, float y, float M, int power)
+{
+    const float o = (float)f;
+    const int ov = isfinite(f) && isfinite(o), yv = isfinite(y) != 0;
+    if (ov && yv) return pair_reward(o, y, M, power);
+    return (ov || yv) ? -(int64_t)M : (int64_t)M;
+}
+
+/* Integer reward of one valid program (summed over the cases). */
+static double program_reward(const uint32_t* prog, int64_t len, const float* consts,
+                             const float* X, int64_t ld_x, const float* y, int64_t n_cases,
+                             double max_score, int power, int mode)
+{
+    const float M = (float)max_score;
+    int64_t total = 0;
+    for (int64_t i = 0; i < n_cases; ++i)
+        total += case_reward(eval_case(prog, len, consts, X, ld_x, i, mode), y[i], M, power);
+    return (double)total;
+}
+
 typedef struct {
     const uint32_t* nodes; const int64_t* offsets;
     const float* consts; int64_t n_consts;
@@ -352,16 +403,17 @@ typedef struct {
     uint32_t allowed_mask; int mode;
     double* out; double* mse; int32_t* status;
     int64_t p0, p1;
-    int correlation;            /* score with Eq. 1-2 instead of the MSE */
-    double max_score;           /* M of Eq. 2 */
+    int correlation;            /* 1: Eq. 1-2; 2: the integer reward (Eq. 5) */
+    double max_score;           /* M of Eq. 2 or Eq. 5 */
     int64_t* c12;               /* optional (c1, c2) per program */
+    int power;                  /* reward power (1, 2, 3 or 8) */
 } job_t;
 
 static void* run_job(void* arg)
 {
     job_t* j = (job_t*)arg;
     double* scratch = NULL;
-    if (j->correlation) {
+    if (j->correlation == 1) {
         scratch = (double*)malloc(sizeof(double) * (size_t)(j->n_cases > 0 ? j->n_cases : 1));
         if (!scratch) {
             for (int64_t p = j->p0; p < j->p1; ++p) j->out[p] = NAN;
@@ -377,6 +429,9 @@ static void* run_job(void* arg)
         double mse = NAN;
         if (st != ST_VALID) {
             j->out[p] = NAN;    /* not a scorable program */
+        } else if (j->correlation == 2) {
+            j->out[p] = program_reward(prog, len, j->consts, j->X, j->ld_x, j->y,
+                                       j->n_cases, j->max_score, j->power, j->mode);
         } else if (j->correlation) {
             j->out[p] = program_correlation(prog, len, j->consts, j->X, j->ld_x, j->y,
                                             j->n_cases, j->max_score, j->mode, scratch,
@@ -400,7 +455,7 @@ static int run_all(const uint32_t* nodes, const int64_t* offsets,
                    const float* y, int64_t n_cases, double tax,
                    uint32_t allowed_mask, int mode, int n_threads,
                    double* out_fitness, double* out_mse, int32_t* status,
-                   int correlation, double max_score, int64_t* c12)
+                   int correlation, double max_score, int64_t* c12, int power)
 {
     if (n_threads <= 0) n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
     if (n_threads < 1) n_threads = 1;
@@ -419,7 +474,7 @@ static int run_all(const uint32_t* nodes, const int64_t* offsets,
         if (t == n_threads - 1) q = n_programs;
         job_t j = { nodes, offsets, consts, n_consts, X, n_vars, ld_x, y,
                     n_cases, tax, allowed_mask, mode, out_fitness, out_mse,
-                    status, p, q, correlation, max_score, c12 };
+                    status, p, q, correlation, max_score, c12, power };
         jobs[t] = j;
         p = q;
     }
@@ -439,7 +494,7 @@ int oracle_fitness(const uint32_t* nodes, const int64_t* offsets,
 {
     return run_all(nodes, offsets, n_programs, consts, n_consts, X, n_vars, ld_x, y,
                    n_cases, tax, allowed_mask, mode, n_threads, out_fitness, out_mse,
-                   status, 0, 0.0, NULL);
+                   status, 0, 0.0, NULL, 1);
 }
 
 /* Correlation score (Eq. 1-2) of every program; out_r (optional) receives
@@ -454,5 +509,29 @@ int oracle_correlation(const uint32_t* nodes, const int64_t* offsets,
 {
     return run_all(nodes, offsets, n_programs, consts, n_consts, X, n_vars, ld_x, y,
                    n_cases, 0.0, allowed_mask, mode, n_threads, out_score, out_r,
-                   status, 1, max_score, out_c12);
+                   status, 1, max_score, out_c12, 1);
+}
+
+/* Integer reward (Eq. 5 and its powers; see the header) of every program,
+ * summed over the cases.  power is 1, 2, 3 or 8.  Structurally invalid
+ * programs get NaN and a nonzero status. */
+/* Per-case rewards of given outputs: out[i] = the reward of output o[i]
+ * against target y[i] (the per-case rule above, o rounded to fp32). */
+void oracle_case_rewards(const double* o, const float* y, int64_t n, double max_score,
+                         int power, int64_t* out)
+{
+    const float M = (float)max_score;
+    for (int64_t i = 0; i < n; ++i) out[i] = case_reward(o[i], y[i], M, power);
+}
+
+int oracle_reward(const uint32_t* nodes, const int64_t* offsets,
+                  int64_t n_programs, const float* consts, int64_t n_consts,
+                  const float* X, int32_t n_vars, int64_t ld_x,
+                  const float* y, int64_t n_cases, double max_score, int power,
+                  uint32_t allowed_mask, int mode, int n_threads,
+                  double* out_reward, int32_t* status)
+{
+    return run_all(nodes, offsets, n_programs, consts, n_consts, X, n_vars, ld_x, y,
+                   n_cases, 0.0, allowed_mask, mode, n_threads, out_reward, NULL,
+                   status, 2, max_score, NULL, power);
 }

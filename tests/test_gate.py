@@ -48,3 +48,97 @@ def test_correlation_gate_passes_oracle_and_fails_planted_error():
     assert big.size == 5
     bad[big] *= 1.001
     assert gate.check(bad, *args, max_score=1e4).n_fail >= 4
+
+
+def test_reward_gate_passes_oracle_and_fails_planted_error():
+    w = _workload()
+    args = (w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, 0.0,
+            w.allowed_mask)
+    for power in (1, 8):
+        R64, st = oracle.reward(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y,
+                                1e4, power, w.allowed_mask)
+        rep = gate.check(R64, *args, max_score=1e4, reward_power=power)
+        assert rep.ok() and rep.n_pass == rep.n
+        R32, _ = oracle.reward(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y,
+                               1e4, power, w.allowed_mask, oracle.M32E)
+        rep = gate.check(R32, *args, max_score=1e4, reward_power=power)
+        assert rep.ok(), rep.failures
+        # a planted error of 0.2 M per case on a few programs
+        bad = R64.copy()
+        idx = np.nonzero(st == 0)[0][:6]
+        bad[idx] += 0.2e4 * w.data.n_cases
+        rep = gate.check(bad, *args, max_score=1e4, reward_power=power)
+        assert rep.n_fail >= 5, rep.summary()
+
+
+def test_reward_window_brackets_oracle_modes():
+    """The output window of every sampled program holds the oracle's own
+    fp64 and fp32 totals, and is tight for most programs."""
+    w = _workload()
+    for power in (1, 3):
+        R64, st = oracle.reward(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y,
+                                1e4, power, w.allowed_mask)
+        R32, _ = oracle.reward(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y,
+                               1e4, power, w.allowed_mask, oracle.M32E_UP)
+        widths = []
+        for p in np.nonzero(st == 0)[0][:80]:
+            prog = w.pop.nodes[w.pop.offsets[p]:w.pop.offsets[p + 1]]
+            lo, hi = gate.reward_window(prog, w.pop.consts, w.data.X, w.data.y, 1e4, power,
+                                        w.allowed_mask)
+            assert lo <= R64[p] <= hi and lo <= R32[p] <= hi
+            widths.append(hi - lo)
+        assert np.median(widths) <= 1e-3 * 1e4 * w.data.n_cases
+
+
+def _all_f32_between(a, b):
+    """Every fp32 value in [a, b] (a <= b, finite, a small range)."""
+    a32 = np.float32(a)
+    if a32 < a:
+        a32 = np.nextafter(a32, np.float32(np.inf))
+    out = []
+    x = a32
+    while x <= b:
+        out.append(x)
+        x = np.nextafter(x, np.float32(np.inf))
+    return np.array(out, np.float32)
+
+
+def test_reward_window_bounds_against_brute_force():
+    """window_bounds' least and greatest per-case reward equal those found
+    by enumerating every fp32 value of the window (small windows around
+    zero, around +-|y|, and away from both)."""
+    rng = np.random.default_rng(31)
+    tiny = float(np.finfo(np.float32).smallest_subnormal)
+    cases = []
+    for _ in range(40):
+        y = np.float32(rng.choice([-1.0, 1.0]) * 10.0 ** rng.uniform(-3, 3))
+        kind = rng.integers(0, 4)
+        if kind == 0:
+            c = float(y)                                   # around o = y
+        elif kind == 1:
+            c = -float(y)                                  # around o = -y
+        elif kind == 2:
+            c = 0.0                                        # around zero (subnormals)
+        else:
+            c = float(y) * rng.uniform(-3, 3)
+        span = rng.integers(1, 300)
+        step = tiny if kind == 2 else float(np.spacing(np.float32(abs(c) + 1e-30)))
+        O = np.array([[c - span * step], [c + span * step * rng.uniform(0.2, 1.0)]])
+        cases.append((O, y))
+    cases.append((np.array([[np.nan], [1.0]]), np.float32(1.5)))     # a candidate invalid
+    cases.append((np.array([[np.inf], [np.nan]]), np.float32(2.0)))  # all invalid
+    cases.append((np.array([[0.5], [0.5]]), np.float32(np.nan)))     # invalid target
+    for M in (1e4, 8.0, -3.0):
+        for power in (1, 2, 3, 8):
+            for O, y in cases:
+                rmin, rmax, a, b = gate.window_bounds(O, np.array([y]), M, power)
+                fin = np.isfinite(O[:, 0])
+                vals = []
+                if fin.any():
+                    xs = _all_f32_between(a[0], b[0]).astype(np.float64)
+                    vals.append(oracle.case_rewards(xs, np.full(xs.size, y), M, power))
+                if not fin.all():
+                    vals.append(oracle.case_rewards(np.array([np.nan]), np.array([y]), M,
+                                                    power))
+                v = np.concatenate(vals)
+                assert rmin[0] == v.min() and rmax[0] == v.max(), (O, y, M, power)

@@ -640,3 +640,58 @@ class TestCorrelationPins:
         fin = np.isfinite(s1) & (np.abs(r1) > 1e-3)
         assert fin.sum() >= 20
         assert np.allclose(s2[fin], s1[fin], rtol=1e-8)
+
+
+# ---------------------------------------- P9: integer point-to-point reward
+def _reward_of_pairs(o, y, power=1, M=1e4):
+    """Reward of the identity program (output = x0 exactly) on pairs."""
+    X = np.asarray(o, np.float32).reshape(1, -1)
+    t, st = oracle.reward(np.array([LOAD], np.uint32), [0, 1], np.zeros(0, np.float32), X,
+                          np.asarray(y, np.float32), M, power)
+    assert st[0] == 0
+    return t[0]
+
+
+class TestRewardPins:
+    """Eq. 5 (StdFitFunc) and its powers, pinned to hand-computed values."""
+
+    def test_hand_computed_cases(self):
+        M = 1e4
+        # ratio 1/2 -> 5000; opposite signs -> 5000 - 10000/11 = 4090.9 -> 4091;
+        # both zero -> M; equal -> M; zero against nonzero -> ratio 0 -> 0
+        assert _reward_of_pairs([2], [4]) == 5000
+        assert _reward_of_pairs([-2], [4]) == 4091
+        assert _reward_of_pairs([0], [0]) == M
+        assert _reward_of_pairs([3], [3]) == M
+        assert _reward_of_pairs([0], [5]) == 0
+        assert _reward_of_pairs([-0.0], [5]) == 0          # -0 has no sign penalty
+        # invalid pairs: one side -> -M, both -> +M
+        assert _reward_of_pairs([np.nan], [1]) == -M
+        assert _reward_of_pairs([1], [np.inf]) == -M
+        assert _reward_of_pairs([np.inf], [np.nan]) == M
+        # the sum over cases
+        assert _reward_of_pairs([2, -2, 0, 3, 0, np.nan, np.inf, 0.5],
+                                [4, 4, 0, 3, 5, 1, np.nan, 1]) == 34091
+
+    def test_powers(self):
+        # ratio 1/2: ^2 -> 2500, ^3 -> 1250, ^8 -> 39.0625 -> 39;
+        # with the sign penalty 39.0625 - 909.09 = -870.03 -> -870
+        assert _reward_of_pairs([2], [4], 2) == 2500
+        assert _reward_of_pairs([2], [4], 3) == 1250
+        assert _reward_of_pairs([2], [4], 8) == 39
+        assert _reward_of_pairs([-2], [4], 8) == -870
+
+    def test_round_half_to_even(self):
+        # M = 3, ratio 1/2 -> 1.5 -> 2; M = 5 -> 2.5 -> 2; M = 1 -> 0.5 -> 0
+        assert _reward_of_pairs([1], [2], M=3.0) == 2
+        assert _reward_of_pairs([1], [2], M=5.0) == 2
+        assert _reward_of_pairs([1], [2], M=1.0) == 0
+
+    def test_symmetry_and_scale_invariance(self):
+        rng = np.random.default_rng(4)
+        o = rng.standard_normal(200).astype(np.float32)
+        y = rng.standard_normal(200).astype(np.float32)
+        for p in (1, 2, 3, 8):
+            a = _reward_of_pairs(o, y, p)
+            assert _reward_of_pairs(y, o, p) == a            # min/max and sign symmetric
+            assert _reward_of_pairs(o * 8, y * 8, p) == a    # powers of two keep the ratio
