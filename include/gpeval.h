@@ -55,6 +55,7 @@ extern "C" {
 #define GP_MAX_STACK 32           /* stack limit (StackSize in the GCL section) */
 #define GP_MAX_CONSTS (1 << 24)   /* a node's arg field has 24 bits */
 #define GP_MAX_VARS (1 << 24)
+#define GP_MAX_REWARD_SCORE 16777216.0   /* |M| of gp_eval_reward: 2^24 */
 
 enum gp_status {
     GP_OK = 0,
@@ -153,6 +154,35 @@ int gp_eval_correlation(const uint32_t* nodes, const int64_t* offsets, int64_t n
                         const float* y, int64_t n_cases, double max_score,
                         uint32_t allowed_op_mask, double* out_score, int32_t* out_status,
                         hipStream_t stream);
+
+/*
+ * gp_eval_reward -- score a population with the point-to-point integer
+ * reward (Sec. "Fitness Functions", Eq. 5 for power 1, StdFitFunc, and its
+ * Square, Cube and Hyper variants for power 2, 3 and 8), all pointers
+ * device pointers, arguments as for gp_eval (no length tax).  M = max_score
+ * is the paper's maximum score, an integer (exact in fp32).  Per case, in
+ * fp32, with o the program's output and y the target:
+ *   o and y both finite:  M if max(|o|,|y|) = 0; otherwise
+ *                         rint(M * q^power - [sign(o) = -sign(y) != 0] * M/11)
+ *                         with q = min(|o|,|y|) / max(|o|,|y|), q^power
+ *                         formed by repeated fp32 products (q*q, (q*q)*q,
+ *                         ((q*q)^2)^2) and rint rounding half to even;
+ *   exactly one invalid:  -M;   both invalid: +M.
+ * out_reward is the sum
+ * over the cases in int64, converted to double (exact while |sum| < 2^53);
+ * higher is better.  Invalid programs get NaN and their GP_PROG_* status.
+ * The integer sum makes the result independent of summation order: the
+ * output is deterministic.  Returns GP_E_INVALID_ARG for a max_score that
+ * is not an integer or exceeds GP_MAX_REWARD_SCORE in magnitude, or a power
+ * other than 1, 2, 3, 8; other errors as gp_eval.  The workspace's partial
+ * buffer takes 8 bytes per (program, tile).
+ */
+int gp_eval_reward(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
+                   int64_t n_nodes, const float* consts, int64_t n_consts,
+                   const float* X, int32_t n_vars, int64_t ld_x,
+                   const float* y, int64_t n_cases, double max_score, int32_t power,
+                   uint32_t allowed_op_mask, double* out_reward, int32_t* out_status,
+                   hipStream_t stream);
 
 /*
  * gp_mc_rank -- the paper's Monte-Carlo ranking (Sec. "Monte-Carlo

@@ -109,6 +109,9 @@ def lib():
         L.gp_eval_correlation.argtypes = [vp, vp, i64, i64, vp, i64, vp, i32, i64, vp, i64,
                                           ctypes.c_double, u32, vp, vp, vp]
         L.gp_eval_correlation.restype = ctypes.c_int
+        L.gp_eval_reward.argtypes = [vp, vp, i64, i64, vp, i64, vp, i32, i64, vp, i64,
+                                     ctypes.c_double, i32, u32, vp, vp, vp]
+        L.gp_eval_reward.restype = ctypes.c_int
         L.gp_mc_rank.argtypes = [vp, i64, i32, ctypes.c_uint64, i32, vp, vp, vp, vp]
         L.gp_mc_rank.restype = ctypes.c_int
         L.gp_eval_batched.argtypes = [vp, i32, vp, i32, i64, i64, i32, i64, u32, vp]
@@ -278,6 +281,31 @@ def gp_eval_correlation(nodes, offsets, consts, X, y, max_score, out_score,
         _dev_ptr(out_status, torch.int32, "out_status"), _stream_handle(stream))
     _check(rc)
     return out_score
+
+
+def gp_eval_reward(nodes, offsets, consts, X, y, max_score, power, out_reward,
+                   out_status=None, allowed_op_mask=0, ld_x=None, n_cases=None, stream=None):
+    """Integer point-to-point reward (Eq. 5; power 1, 2, 3 or 8) of the
+    population held in device tensors (asynchronous on stream); arguments
+    as gp_eval, max_score = M."""
+    import torch
+    P = offsets.numel() - 1
+    if out_reward.numel() != P:
+        raise ValueError("out_reward must have n_programs entries")
+    if X.dim() != 2:
+        raise ValueError("X must be 2-D [n_vars, ld_x]")
+    n_vars = X.shape[0]
+    ld = X.shape[1] if ld_x is None else int(ld_x)
+    n = y.numel() if n_cases is None else int(n_cases)
+    rc = lib().gp_eval_reward(
+        _dev_ptr(nodes, torch.uint32, "nodes"), _dev_ptr(offsets, torch.int64, "offsets"),
+        P, nodes.numel(), _dev_ptr(consts, torch.float32, "consts"), consts.numel(),
+        _dev_ptr(X, torch.float32, "X"), n_vars, ld, _dev_ptr(y, torch.float32, "y"), n,
+        float(max_score), int(power), int(allowed_op_mask),
+        _dev_ptr(out_reward, torch.float64, "out_reward"),
+        _dev_ptr(out_status, torch.int32, "out_status"), _stream_handle(stream))
+    _check(rc)
+    return out_reward
 
 
 def gp_mc_rank(fitness, higher_is_better, seed, out_band, out_children=None,
@@ -492,6 +520,22 @@ def evaluate_correlation(nodes, offsets, consts, X, y, max_score=1e4, allowed_op
     st = torch.empty(pop.n_programs, dtype=torch.int32, device=device) if return_status else None
     gp_eval_correlation(pop.nodes, pop.offsets, pop.consts, data.X, data.y, max_score, out, st,
                         allowed_op_mask)
+    torch.cuda.synchronize()
+    if return_status:
+        return out.cpu().numpy(), st.cpu().numpy()
+    return out.cpu().numpy()
+
+
+def evaluate_reward(nodes, offsets, consts, X, y, max_score=1e4, power=1, allowed_op_mask=0,
+                    return_status=False, device="cuda"):
+    """numpy in, numpy out: upload, integer reward, download (synchronizes)."""
+    import torch
+    pop = DevicePopulation(nodes, offsets, consts, device)
+    data = DeviceDataset(X, y, device)
+    out = torch.empty(pop.n_programs, dtype=torch.float64, device=device)
+    st = torch.empty(pop.n_programs, dtype=torch.int32, device=device) if return_status else None
+    gp_eval_reward(pop.nodes, pop.offsets, pop.consts, data.X, data.y, max_score, power, out,
+                   st, allowed_op_mask)
     torch.cuda.synchronize()
     if return_status:
         return out.cpu().numpy(), st.cpu().numpy()

@@ -1106,6 +1106,9 @@ struct EvalConst {
     int64_t ld_x;
     int64_t n_cases;
     int32_t n_vars;
+    // integer reward mode
+    int32_t reward_power;
+    float reward_M;
 };
 
 // Error-free sum: s + e == a + b exactly (Knuth's TwoSum).
@@ -1340,7 +1343,7 @@ struct CorrPart {
 };
 static_assert(sizeof(CorrPart) == 72, "CorrPart layout");
 
-enum : int { kFitMse = 0, kFitCorr = 1 };
+enum : int { kFitMse = 0, kFitCorr = 1, kFitReward = 2 };
 constexpr int kCorrMaxG = 32;            // programs per work item in correlation mode (LDS)
 
 // hi + lo += x (Knuth's two-sum on the high part, errors gathered in lo)
@@ -1375,6 +1378,28 @@ __device__ __forceinline__ void corr_case(CorrPart& c, float f, float y)
     } else {
         ++c.c2;
     }
+}
+
+// Integer point-to-point reward of one case (StdFitFunc, Eq. 5, and its
+// Square/Cube/Hyper variants: the ratio raised to `power`), in fp32 as the
+// paper's reward function takes fp32 values: M when both are zero, else
+// rint(M ratio^p), less M/11 for opposite signs; an invalid pair gives -M
+// (one side invalid) or +M (both).  rint rounds half to even.
+__device__ __forceinline__ long long pair_reward(float o, float y, float M, int power)
+{
+    const bool ov = __builtin_isfinite(o), yv = __builtin_isfinite(y);
+    if (!(ov && yv)) return (ov || yv) ? -(long long)M : (long long)M;
+    const float ao = fabsf(o), ay = fabsf(y);
+    const float mx = ao > ay ? ao : ay, mn = ao > ay ? ay : ao;
+    if (mx == 0.0f) return (long long)M;
+    const float r = mn / mx;
+    float rp = r;
+    if (power == 2) rp = r * r;
+    else if (power == 3) rp = (r * r) * r;
+    else if (power == 8) { const float r2 = r * r, r4 = r2 * r2; rp = r4 * r4; }
+    float v = M * rp;
+    if ((o < 0.0f && y > 0.0f) || (o > 0.0f && y < 0.0f)) v = v - M / 11.0f;
+    return (long long)rintf(v);
 }
 
 // a += b (fixed order: the result depends only on the two operands)
@@ -1441,6 +1466,8 @@ __global__ __launch_bounds__(kWG) void k_eval(
     // correlation mode: one CorrPart per program instead (the tile floats are
     // a multiple of 2, so the array is 8-byte aligned)
     CorrPart* cacc = reinterpret_cast<CorrPart*>(lds + a.tile_floats);       // [G]
+    // integer reward mode: one int64 total per program
+    long long* racc = reinterpret_cast<long long*>(lds + a.tile_floats);     // [G]
     __shared__ uint32_t s_item, s_next;
 
     const int tid = threadIdx.x;
@@ -1460,6 +1487,8 @@ __global__ __launch_bounds__(kWG) void k_eval(
         if (tid < G) {
             if constexpr (FIT == kFitCorr) {
                 corr_zero(cacc[tid]);
+            } else if constexpr (FIT == kFitReward) {
+                racc[tid] = 0;
             } else {
                 acc[tid] = make_float2(0.f, 0.f);
                 accbad[tid] = 0u;
@@ -1533,6 +1562,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
                 bool bad = false;
                 CorrPart cl;
                 if constexpr (FIT == kFitCorr) corr_zero(cl);
+                long long rl = 0;
                 for (int b = 0; b < nw; ++b) {
                     const float* blk = xt + b * rows * SUB;
                     float tos[K];
@@ -1545,6 +1575,9 @@ __global__ __launch_bounds__(kWG) void k_eval(
                             const float f = tos[j];
                             if constexpr (FIT == kFitCorr) {
                                 corr_case(cl, f, yt[lane + j * 64]);
+                            } else if constexpr (FIT == kFitReward) {
+                                rl += pair_reward(f, yt[lane + j * 64], a.reward_M,
+                                                  a.reward_power);
                             } else {
                                 bad |= !__builtin_isfinite(f);
                                 const float r = (f - yt[lane + j * 64]) * scale;
@@ -1560,6 +1593,11 @@ __global__ __launch_bounds__(kWG) void k_eval(
                     corr_wave_reduce(cl);
                     // the windows add up in order, whichever wavefront ran them
                     if (lane == 0) corr_merge(cacc[g], cl);
+                } else if constexpr (FIT == kFitReward) {
+                    // integers: exact in any order
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) rl += __shfl_xor(rl, off);
+                    if (lane == 0) racc[g] += rl;
                 } else {
                 // wavefront tree: every lane ends with the same pair
 #pragma unroll
@@ -1586,6 +1624,8 @@ __global__ __launch_bounds__(kWG) void k_eval(
             const int64_t slot = (int64_t)pid * a.part_stride + tile;
             if constexpr (FIT == kFitCorr) {
                 part_corr[slot] = cacc[tid];
+            } else if constexpr (FIT == kFitReward) {
+                reinterpret_cast<long long*>(part)[slot] = racc[tid];
             } else {
                 part[slot] = acc[tid];
                 part_bad[slot] = (uint8_t)(accbad[tid] != 0u);
@@ -1780,6 +1820,26 @@ __global__ __launch_bounds__(256) void k_reduce_corr(ReduceArgs a)
     R.out[q] = a.max_score * r2 * r2 * (double)n - a.max_score * (double)(c1 - c2);
 }
 
+// Integer reward per program (Eq. 5 and its power variants): the tiles'
+// int64 totals added exactly, returned as a double (exact below 2^53).
+__global__ __launch_bounds__(256) void k_reduce_reward(ReduceArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n_programs) return;
+    const int r = a.pds[p];
+    const DevRequest& R = a.reqs[r];
+    const int64_t q = p - a.seg_start[r];
+    if (!R.out || q >= R.n_programs) return;     // only for inconsistent tables
+    const int c = a.cls[p];
+    if (c >= kKeys) { R.out[q] = __builtin_nan(""); return; }
+    const DevDataset& D = a.ds[R.dataset];
+    const int nt = D.n_tiles[c / kLenBuckets];
+    const long long* part = reinterpret_cast<const long long*>(a.part);
+    long long s = 0;
+    for (int t = 0; t < nt; ++t) s += part[p * a.part_stride + t];
+    R.out[q] = (double)s;
+}
+
 // ----------------------------------------------------------- workspaces
 struct Layout {
     size_t code, meta, cls, order, blk_counts, blk_base, blk_slen, blk_code, class_info, class_g;
@@ -1809,10 +1869,10 @@ Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride, int
     L.class_g = off;    off = align_up(off + kClasses * 4);
     L.counters = off;   off = align_up(off + kClasses * 4);
     // per (program, tile) partials: a compensated pair and a bad flag
-    // (MSE), or the correlation sums
+    // (MSE), the correlation sums, or an int64 reward total
     const size_t part_elem = fit == kFitCorr ? sizeof(CorrPart) : sizeof(float2);
     L.part = off;       off = align_up(off + (size_t)n_programs * part_stride * part_elem);
-    L.part_bad = off;   off = align_up(off + (fit == kFitCorr ? 0 : (size_t)n_programs * part_stride));
+    L.part_bad = off;   off = align_up(off + (fit != kFitMse ? 0 : (size_t)n_programs * part_stride));
     L.ds = off;         off = align_up(off + (size_t)n_ds * sizeof(DevDataset));
     L.req = off;        off = align_up(off + (size_t)n_seg * sizeof(DevRequest));
     L.seg_ds = off;     off = align_up(off + (size_t)n_seg * 4);
@@ -2015,8 +2075,9 @@ struct Problem {
     int64_t max_cases;
     uint32_t allowed;
     int32_t need_out;               // fitness outputs required (not for gp_predict)
-    int32_t fit;                    // kFitMse, or kFitCorr (gp_eval_correlation)
-    double max_score;               // M of the correlation score
+    int32_t fit;                    // kFitMse, kFitCorr or kFitReward
+    double max_score;               // M of the correlation score or the reward
+    int32_t reward_power;           // 1, 2, 3 or 8 (reward mode)
 };
 
 int check_common(int64_t n_programs, int64_t n_nodes, int64_t n_consts, int32_t n_vars,
@@ -2103,8 +2164,9 @@ size_t eval_tile_floats(int n_vars)
 template <int MAXD, int K, int FIT>
 size_t eval_lds_bytes(int n_vars, int G)
 {
-    const size_t acc = FIT == kFitCorr ? (size_t)G * sizeof(CorrPart)
-                                       : (size_t)G * (sizeof(float2) + sizeof(uint32_t));
+    const size_t acc = FIT == kFitCorr     ? (size_t)G * sizeof(CorrPart)
+                       : FIT == kFitReward ? (size_t)G * sizeof(long long)
+                                           : (size_t)G * (sizeof(float2) + sizeof(uint32_t));
     return eval_tile_floats<MAXD, K>(n_vars) * sizeof(float) + acc;
 }
 
@@ -2159,6 +2221,10 @@ int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
         if ((rc = eval_grid<8, 4, kFitCorr>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
         if ((rc = eval_grid<16, kK1, kFitCorr>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
         if ((rc = eval_grid<32, 2, kFitCorr>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2])) != GP_OK) return rc;
+    } else if (pb.fit == kFitReward) {
+        if ((rc = eval_grid<8, 4, kFitReward>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
+        if ((rc = eval_grid<16, kK1, kFitReward>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
+        if ((rc = eval_grid<32, 2, kFitReward>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2])) != GP_OK) return rc;
     } else {
         if ((rc = eval_grid<8, 4, kFitMse>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
         if ((rc = eval_grid<16, kK1, kFitMse>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
@@ -2215,6 +2281,8 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
     ea.part_stride = el.stride;
     ea.max_vars = pb.max_vars;
     ea.n_seg = pb.n_req;
+    ea.reward_power = pb.reward_power;
+    ea.reward_M = (float)pb.max_score;
     if (tu.concurrent) {
         GP_HIP_TRY(hipEventRecord(side.fork, stream));
         for (auto& x : side.s) GP_HIP_TRY(hipStreamWaitEvent(x, side.fork, 0));
@@ -2228,6 +2296,11 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
         do {                                                                                   \
             if (pb.fit == kFitCorr)                                                            \
                 hipLaunchKernelGGL((k_eval<MD, KK, kFitCorr>), g, b, el.lds[c], sc, st.code,   \
+                                   st.meta, st.order, st.class_info, st.counters + c, st.ds,   \
+                                   st.seg_ds, st.seg_cnt, st.seg_pos, st.item_pre, st.class_g, \
+                                   st.part, st.part_bad, st.part_corr, ea);                   \
+            else if (pb.fit == kFitReward)                                                     \
+                hipLaunchKernelGGL((k_eval<MD, KK, kFitReward>), g, b, el.lds[c], sc, st.code, \
                                    st.meta, st.order, st.class_info, st.counters + c, st.ds,   \
                                    st.seg_ds, st.seg_cnt, st.seg_pos, st.item_pre, st.class_g, \
                                    st.part, st.part_bad, st.part_corr, ea);                   \
@@ -2266,6 +2339,9 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
     if (pb.fit == kFitCorr)
         hipLaunchKernelGGL(k_reduce_corr, dim3((unsigned)((pb.n_programs + 255) / 256)), dim3(256),
                            0, stream, ra);
+    else if (pb.fit == kFitReward)
+        hipLaunchKernelGGL(k_reduce_reward, dim3((unsigned)((pb.n_programs + 255) / 256)),
+                           dim3(256), 0, stream, ra);
     else
         hipLaunchKernelGGL(k_reduce, dim3((unsigned)((pb.n_programs + 255) / 256)), dim3(256), 0,
                            stream, ra);
@@ -2657,6 +2733,26 @@ int gp_eval_correlation(const uint32_t* nodes, const int64_t* offsets, int64_t n
     Problem pb = make_problem(&d);
     pb.fit = kFitCorr;
     pb.max_score = max_score;
+    return eval_problem(pb, stream);
+}
+
+int gp_eval_reward(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
+                   int64_t n_nodes, const float* consts, int64_t n_consts,
+                   const float* X, int32_t n_vars, int64_t ld_x,
+                   const float* y, int64_t n_cases, double max_score, int32_t power,
+                   uint32_t allowed_op_mask, double* out_reward, int32_t* out_status,
+                   hipStream_t stream)
+{
+    if (!(std::fabs(max_score) <= GP_MAX_REWARD_SCORE) || max_score != std::trunc(max_score))
+        return set_error(GP_E_INVALID_ARG, "max_score is not an integer of magnitude <= 2^24");
+    if (power != 1 && power != 2 && power != 3 && power != 8)
+        return set_error(GP_E_INVALID_ARG, "power %d is not 1, 2, 3 or 8", (int)power);
+    const gp_problem d{nodes, offsets, n_programs, n_nodes, consts, n_consts, X, n_vars, ld_x,
+                       y, n_cases, 0.0, allowed_op_mask, out_reward, out_status};
+    Problem pb = make_problem(&d);
+    pb.fit = kFitReward;
+    pb.max_score = max_score;
+    pb.reward_power = power;
     return eval_problem(pb, stream);
 }
 

@@ -17,7 +17,7 @@ def _bench(*args):
 def test_help_lists_workloads():
     r = _bench("--help")
     assert r.returncode == 0, r.stderr
-    for name in ("plain", "generation", "uneven", "precision", "serving"):
+    for name in ("plain", "generation", "uneven", "precision", "serving", "reward"):
         assert name in r.stdout
 
 

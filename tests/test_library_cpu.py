@@ -101,6 +101,23 @@ def test_correlation_rejects_bad_arguments_before_device_work(L):
                                  None, None) == gp.GP_OK
 
 
+def test_reward_rejects_bad_arguments_before_device_work(L):
+    c = ctypes.c_void_p(1)
+    for M in (float("nan"), float("inf"), -float("inf"), 2.0 ** 24 + 2.0, 7.75, -0.5):
+        assert L.gp_eval_reward(c, c, 1, 1, c, 0, c, 1, 1, c, 1, M, 1, 0, c, None,
+                                None) == gp.GP_E_INVALID_ARG
+        assert b"max_score" in L.gp_last_error()
+    for power in (0, 4, 5, -1, 16):
+        assert L.gp_eval_reward(c, c, 1, 1, c, 0, c, 1, 1, c, 1, 1e4, power, 0, c, None,
+                                None) == gp.GP_E_INVALID_ARG
+        assert b"power" in L.gp_last_error()
+    assert L.gp_eval_reward(c, c, -1, 0, c, 0, c, 1, 1, c, 1, 1e4, 2, 0, c, None,
+                            None) == gp.GP_E_INVALID_ARG
+    for power in (1, 2, 3, 8):
+        assert L.gp_eval_reward(None, c, 0, 0, None, 0, None, 0, 1, c, 1, 1e4, power, 0, None,
+                                None, None) == gp.GP_OK
+
+
 def test_binding_refuses_host_tensors():
     import torch
     with pytest.raises(TypeError):
