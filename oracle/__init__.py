@@ -11,7 +11,10 @@ expression tree, pure Python) used to cross-check it on brute-force sets;
 
 Op numbering of the interchange format (node = op | arg << 8):
 LOAD 0, CONST 1, ADD 2, SUB 3, MUL 4, DIV 5, SIN 6, COS 7, EXP 8, LOG 9,
-SQRT 10, ABS 11; oracle-only GCL extension DUP 12, SWAP 13, DEL 14, SQUARE 15.
+SQRT 10, ABS 11; the rest of the GCL command table: DUP 12, SWAP 13, DEL 14,
+SQUARE 15, SIGN 16, CUBE 17, CBRT 18, TAN 19, ARCSIN 20, ARCCOS 21, ARCTAN 22,
+TANH 23, SQRT_RAW 24 (the paper's unprotected SQRT), POW 25, COPY 26, PASTE 27
+(COPY/PASTE carry the variable name k < 16 in the arg field).
 """
 from __future__ import annotations
 
@@ -27,17 +30,20 @@ _LIB_PATH = os.path.join(_HERE, "libgp_oracle.so")
 
 LOAD, CONST, ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, ABS = range(12)
 DUP, SWAP, DEL, SQUARE = 12, 13, 14, 15
+SIGN, CUBE, CBRT, TAN, ASIN, ACOS, ATAN, TANH, SQRT_RAW, POW, COPY, PASTE = range(16, 28)
+N_OPS = 28
 
 M64, M32E, M32E_UP, M32E_DN = 0, 1, 2, 3
 M32E_RAND = 16      # M32E_RAND + seed: random +-2 ulp elementary functions
 
 ST_VALID, ST_EMPTY, ST_BAD_OP, ST_BAD_VAR, ST_BAD_CONST = 0, 1, 2, 3, 4
 ST_UNDERFLOW, ST_TOO_DEEP, ST_FINAL_DEPTH = 5, 6, 7
+ST_BAD_PAIR = 10
 
 #: every op of the benchmark set (LOAD..ABS)
 MASK_BENCH = (1 << 12) - 1
-#: benchmark set plus the GCL stack ops and SQUARE
-MASK_GCL = (1 << 16) - 1
+#: the whole GCL command table (plus ABS)
+MASK_GCL = (1 << N_OPS) - 1
 
 THETA = float(np.float32(0.001))
 

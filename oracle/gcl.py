@@ -2,19 +2,23 @@
 
 TEST INFRASTRUCTURE ONLY.  Token forms follow the GCL command table: CONST
 carries a literal, LOAD carries ``label:index`` with a zero-based index.
-Produces the oracle's interchange arrays (nodes, consts); DUP, SWAP, DEL and
-SQUARE map to the oracle-only extension opcodes.
+COPY and PASTE carry a variable name ``@k``.  Produces the oracle's
+interchange arrays (nodes, consts).  SQRT maps to the protected square root
+(sqrt |a|) of the benchmark set.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import (ABS, ADD, CONST, COS, DEL, DIV, DUP, EXP, LOAD, LOG, MUL, SIN,
-               SQRT, SQUARE, SUB, SWAP)
+from . import (ABS, ACOS, ADD, ASIN, ATAN, CBRT, CONST, COPY, COS, CUBE, DEL, DIV, DUP,
+               EXP, LOAD, LOG, MUL, PASTE, POW, SIGN, SIN, SQRT, SQUARE, SUB, SWAP, TAN,
+               TANH)
 
 _NAMES = {"ADD": ADD, "SUB": SUB, "MUL": MUL, "DIV": DIV, "SIN": SIN,
           "COS": COS, "EXP": EXP, "LN": LOG, "SQRT": SQRT, "ABS": ABS,
-          "DUP": DUP, "SWAP": SWAP, "DEL": DEL, "SQUARE": SQUARE}
+          "DUP": DUP, "SWAP": SWAP, "DEL": DEL, "SQUARE": SQUARE, "POW": POW,
+          "SIGN": SIGN, "CUBE": CUBE, "CBRT": CBRT, "TAN": TAN, "ARCSIN": ASIN,
+          "ARCCOS": ACOS, "ARCTAN": ATAN, "TANH": TANH}
 
 
 def parse(text):
@@ -32,6 +36,9 @@ def parse(text):
         elif name == "LOAD":
             idx = int(parts[1].split(":")[1])
             nodes.append(LOAD | (idx << 8))
+        elif name in ("COPY", "PASTE"):
+            k = int(parts[1].lstrip("@"))
+            nodes.append((COPY if name == "COPY" else PASTE) | (k << 8))
         elif name in _NAMES:
             nodes.append(_NAMES[name])
         else:

@@ -59,8 +59,22 @@
  *                case): an fp32 evaluator whose elementary functions are
  *                within 2 ulps.  Also certification only.
  *
- * Oracle-only GCL extension (so the paper's printed genomes can run):
- *   DUP, SWAP, DEL, SQUARE (GCL command table).
+ * The rest of the GCL command table (the paper's Table of GCL commands):
+ *   DUP, SWAP, DEL          stack moves;
+ *   SQUARE a*a, SIGN -a, CUBE a*a*a, CBRT, TAN, ARCSIN, ARCCOS, ARCTAN,
+ *   TANH                    C99 functions, unprotected (NaN outside the
+ *                           domain, as the paper's fitness expects);
+ *   SQRT_RAW                the paper's SQRT, C99 sqrt (NaN below zero);
+ *                           SQRT above stays the protected sqrt(|a|);
+ *   POW                     pow(second, top), C99 special cases;
+ *   COPY @k, PASTE @k       variables: COPY stores the top without
+ *                           touching the stack, PASTE pushes the stored
+ *                           value and frees the variable.
+ * Readings for the variables (listed in the design notes): k < 16; a valid
+ * program copies a variable only while it is free and pastes it only while
+ * it holds a value, and ends with every variable free; a live variable
+ * occupies one of the 32 stack cells, so stack depth plus live variables
+ * never exceeds 32.  The reported maximum depth is the maximum of that sum.
  *
  * Correlation fitness (oracle_correlation; the paper's default fitness,
  * Sec. "Fitness Functions", Eq. 1 and Eq. 2), written out plainly:
@@ -106,9 +120,11 @@ enum {
     OP_CONST = 1,  /* arg = index into the constant pool                 */
     OP_ADD = 2, OP_SUB = 3, OP_MUL = 4, OP_DIV = 5,
     OP_SIN = 6, OP_COS = 7, OP_EXP = 8, OP_LOG = 9, OP_SQRT = 10, OP_ABS = 11,
-    /* oracle-only GCL extension */
-    OP_DUP = 12, OP_SWAP = 13, OP_DEL = 14, OP_SQUARE = 15,
-    OP_COUNT = 16
+    /* the rest of the GCL command table */
+    OP_DUP = 12, OP_SWAP = 13, OP_DEL = 14, OP_SQUARE = 15, OP_SIGN = 16, OP_CUBE = 17,
+    OP_CBRT = 18, OP_TAN = 19, OP_ASIN = 20, OP_ACOS = 21, OP_ATAN = 22, OP_TANH = 23,
+    OP_SQRT_RAW = 24, OP_POW = 25, OP_COPY = 26, OP_PASTE = 27,
+    OP_COUNT = 28
 };
 
 enum {
@@ -119,10 +135,11 @@ enum {
 /* per-program validation status */
 enum {
     ST_VALID = 0, ST_EMPTY = 1, ST_BAD_OP = 2, ST_BAD_VAR = 3, ST_BAD_CONST = 4,
-    ST_UNDERFLOW = 5, ST_TOO_DEEP = 6, ST_FINAL_DEPTH = 7
+    ST_UNDERFLOW = 5, ST_TOO_DEEP = 6, ST_FINAL_DEPTH = 7, ST_BAD_PAIR = 10
 };
 
 #define STACK_LIMIT 32
+#define GCL_VARS 16             /* variable names @0 .. @15 */
 
 /* theta = the fp32 number nearest to 0.001 (protected DIV and LOG). */
 static double theta(void) { return (double)0.001f; }
@@ -133,14 +150,18 @@ static int op_shape(uint32_t op, int* needs, int* delta)
 {
     switch (op) {
     case OP_LOAD: case OP_CONST: *needs = 0; *delta = +1; return 1;
-    case OP_ADD: case OP_SUB: case OP_MUL: case OP_DIV:
+    case OP_ADD: case OP_SUB: case OP_MUL: case OP_DIV: case OP_POW:
         *needs = 2; *delta = -1; return 1;
     case OP_SIN: case OP_COS: case OP_EXP: case OP_LOG: case OP_SQRT:
-    case OP_ABS: case OP_SQUARE:
+    case OP_ABS: case OP_SQUARE: case OP_SIGN: case OP_CUBE: case OP_CBRT:
+    case OP_TAN: case OP_ASIN: case OP_ACOS: case OP_ATAN: case OP_TANH:
+    case OP_SQRT_RAW:
         *needs = 1; *delta = 0; return 1;
     case OP_DUP: *needs = 1; *delta = +1; return 1;
     case OP_SWAP: *needs = 2; *delta = 0; return 1;
     case OP_DEL: *needs = 1; *delta = -1; return 1;
+    case OP_COPY: *needs = 1; *delta = 0; return 1;
+    case OP_PASTE: *needs = 0; *delta = +1; return 1;
     default: return 0;
     }
 }
@@ -150,7 +171,8 @@ int oracle_check_program(const uint32_t* prog, int64_t len, int64_t n_consts,
                          int32_t n_vars, uint32_t allowed_mask,
                          int32_t* max_depth_out)
 {
-    int depth = 0, max_depth = 0;
+    int depth = 0, max_depth = 0, live = 0;
+    int holds[GCL_VARS] = {0};  /* variable k holds a value */
     if (max_depth_out) *max_depth_out = 0;
     if (len <= 0) return ST_EMPTY;
     for (int64_t i = 0; i < len; ++i) {
@@ -162,12 +184,22 @@ int oracle_check_program(const uint32_t* prog, int64_t len, int64_t n_consts,
         if (op == OP_LOAD && (int64_t)arg >= (int64_t)n_vars) return ST_BAD_VAR;
         if (op == OP_CONST && (int64_t)arg >= n_consts) return ST_BAD_CONST;
         if (depth < needs) return ST_UNDERFLOW;
+        if (op == OP_COPY) {
+            if (arg >= GCL_VARS || holds[arg]) return ST_BAD_PAIR;
+            holds[arg] = 1;
+            ++live;
+        } else if (op == OP_PASTE) {
+            if (arg >= GCL_VARS || !holds[arg]) return ST_BAD_PAIR;
+            holds[arg] = 0;
+            --live;
+        }
         depth += delta;
-        if (depth > STACK_LIMIT) return ST_TOO_DEEP;
-        if (depth > max_depth) max_depth = depth;
+        if (depth + live > STACK_LIMIT) return ST_TOO_DEEP;
+        if (depth + live > max_depth) max_depth = depth + live;
     }
     if (max_depth_out) *max_depth_out = max_depth;
     if (depth != 1) return ST_FINAL_DEPTH;
+    if (live != 0) return ST_BAD_PAIR;
     return ST_VALID;
 }
 
@@ -236,6 +268,7 @@ static double eval_case(const uint32_t* prog, int64_t len, const float* consts,
                         const float* X, int64_t ld_x, int64_t i, int mode)
 {
     double st[STACK_LIMIT];
+    double var[GCL_VARS];       /* COPY/PASTE variables */
     int sp = 0;                 /* number of values on the stack */
     const double th = theta();
     for (int64_t k = 0; k < len; ++k) {
@@ -254,6 +287,31 @@ static double eval_case(const uint32_t* prog, int64_t len, const float* consts,
             else v = (fabs(b) <= th) ? 1.0 : a / b;
             st[sp++] = round_mode(v, mode);
             break;
+        case OP_POW:            /* second raised to the top */
+            b = st[--sp];
+            a = st[--sp];
+            v = round_mode(pow(a, b), mode);
+            if (mode >= ORACLE_M32E_UP) v = nudge(v, mode, k, i);
+            st[sp++] = v;
+            break;
+        case OP_CBRT: case OP_TAN: case OP_ASIN: case OP_ACOS: case OP_ATAN:
+        case OP_TANH: case OP_SQRT_RAW:
+            a = st[--sp];
+            if (op == OP_CBRT) v = cbrt(a);
+            else if (op == OP_TAN) v = tan(a);
+            else if (op == OP_ASIN) v = asin(a);
+            else if (op == OP_ACOS) v = acos(a);
+            else if (op == OP_ATAN) v = atan(a);
+            else if (op == OP_TANH) v = tanh(a);
+            else v = sqrt(a);
+            v = round_mode(v, mode);
+            if (mode >= ORACLE_M32E_UP) v = nudge(v, mode, k, i);
+            st[sp++] = v;
+            break;
+        case OP_SIGN: a = st[--sp]; st[sp++] = -a; break;
+        case OP_CUBE: a = st[--sp]; st[sp++] = round_mode(a * a * a, mode); break;
+        case OP_COPY: var[arg] = st[sp - 1]; break;
+        case OP_PASTE: st[sp++] = var[arg]; break;
         case OP_SIN: case OP_COS: case OP_EXP: case OP_LOG:
             a = st[--sp];
             if (op == OP_SIN) v = sin(a);

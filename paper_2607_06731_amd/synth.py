@@ -12,7 +12,10 @@ Program arrays (the library's interchange format):
     y       float32[n_cases]
 
 Op numbering: LOAD 0, CONST 1, ADD 2, SUB 3, MUL 4, DIV 5, SIN 6, COS 7,
-EXP 8, LOG 9, SQRT 10, ABS 11.
+EXP 8, LOG 9, SQRT 10, ABS 11; the rest of the GCL command table: DUP 12,
+SWAP 13, DEL 14, SQUARE 15, SIGN 16, CUBE 17, CBRT 18, TAN 19, ARCSIN 20,
+ARCCOS 21, ARCTAN 22, TANH 23, SQRT_RAW 24, POW 25, COPY 26, PASTE 27 (COPY
+and PASTE carry a variable name k < 16 in the arg field).
 
 Workload recipes (fixed for this project; the paper benchmarks on data it
 does not ship, so these stand in for it):
@@ -29,6 +32,10 @@ does not ship, so these stand in for it):
   precision         50,000 programs, len U{3..64}, set 2, 3 vars,
                     1,048,576 cases, X ~ U(-10,10), y = degree-3 polynomial
                     (20 monomials) scaled to max|y| = 1e4, no noise
+  gcl               20,000 programs, len U{3..48}, the whole GCL command
+                    table (sample_gcl_programs), 4 vars, 2,048 cases,
+                    X ~ U(-1,1), y = x0^2 + sin(x1) x2 - x3/2 + N(0, 0.01),
+                    tax 1e-3
   serving           64 runs, each n_vars U{1..20}, cases log-U[256, 65536],
                     X ~ N(0,1), y = <=32 random degree<=3 monomials + N(0,
                     0.05); requests of log-U[1k, 200k] programs, len
@@ -52,10 +59,16 @@ from dataclasses import dataclass, field
 import numpy as np
 
 LOAD, CONST, ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG, SQRT, ABS = range(12)
+(DUP, SWAP, DEL, SQUARE, SIGN, CUBE, CBRT, TAN, ASIN, ACOS, ATAN, TANH, SQRT_RAW, POW,
+ COPY, PASTE) = range(12, 28)
+N_OPS = 28
 BINARY = (ADD, SUB, MUL, DIV)
 UNARY_1 = (SIN, COS, EXP, LOG)
 UNARY_2 = (SIN, COS, EXP, LOG, SQRT, ABS)
+UNARY_GCL = UNARY_2 + (SQUARE, SIGN, CUBE, CBRT, TAN, ASIN, ACOS, ATAN, TANH, SQRT_RAW)
+BINARY_GCL = BINARY + (POW,)
 STACK_LIMIT = 32
+GCL_VARS = 16
 
 
 def op_mask(ops):
@@ -67,6 +80,7 @@ def op_mask(ops):
 
 MASK_1 = op_mask(BINARY + UNARY_1)
 MASK_2 = op_mask(BINARY + UNARY_2)
+MASK_GCL = (1 << N_OPS) - 1
 
 
 @dataclass
@@ -133,8 +147,9 @@ class Workload:
 
 
 # Each workload draws from its own seed stream (default entropy 1000 + id).
-WORKLOAD_IDS = {"plain": 1, "generation": 2, "uneven": 3, "precision": 4, "serving": 5}
-WORKLOADS = ("plain", "generation", "uneven", "precision")
+WORKLOAD_IDS = {"plain": 1, "generation": 2, "uneven": 3, "precision": 4, "serving": 5,
+                "gcl": 6}
+WORKLOADS = ("plain", "generation", "uneven", "precision", "gcl")
 
 
 def _rngs(name, seed=None):
@@ -205,6 +220,88 @@ def sample_programs(rng, lengths, n_vars, unary, binary=BINARY,
     return Population(nodes, offsets, consts)
 
 
+# token classes of the GCL sampler and their weights
+_GCL_CLASSES = ("leaf", "unary", "binary", "dup", "swap", "del", "copy", "paste")
+_GCL_WEIGHTS = np.array([3.0, 2.0, 3.0, 0.6, 0.6, 0.4, 0.5, 1.5])
+
+
+def sample_gcl_programs(rng, lengths, n_vars, const_lo=-5.0, const_hi=5.0, p_var=0.5,
+                        p_pow=0.04):
+    """Programs over the whole GCL command table, one token at a time.
+
+    State: depth d, live variables l, r tokens still to come after this one.
+    A class is feasible when its result keeps d + l <= 32 and can still end
+    at depth 1 with every variable pasted (each live variable needs a PASTE
+    and a binary op: d' - 1 + 2 l' <= r):
+      leaf d+1; unary d >= 1; binary d >= 2; DUP d >= 1, d+1; SWAP d >= 2;
+      DEL d >= 2, d-1; COPY d >= 1, l < 16, l+1; PASTE l >= 1, d+1, l-1.
+    A feasible class is drawn with the weights above, then an op uniformly
+    inside it (POW with probability p_pow among the binary ops); COPY takes
+    the lowest free variable name, PASTE a live one uniformly.  Leaves are
+    as in sample_programs.  Never dead-ends (PASTE, a binary op, a unary op
+    or a leaf stays feasible), ends at depth 1 with no live variable."""
+    lengths = np.asarray(lengths, dtype=np.int64)
+    P = lengths.size
+    offsets = np.zeros(P + 1, np.int64)
+    np.cumsum(lengths, out=offsets[1:])
+    nodes = np.zeros(int(offsets[-1]), np.uint32)
+    consts = []
+    unary = np.array(UNARY_GCL, np.uint32)
+    for p in range(P):
+        Lp = int(lengths[p])
+        d, live = 0, []
+        pos = int(offsets[p])
+        u = rng.random((Lp, 5))
+        for t in range(Lp):
+            r = Lp - t - 1
+            l = len(live)
+            feas = np.array([
+                d + 1 + l <= STACK_LIMIT and d + 2 * l <= r,             # leaf
+                d >= 1 and d - 1 + 2 * l <= r,                            # unary
+                d >= 2 and d - 2 + 2 * l <= r,                            # binary
+                d >= 1 and d + 1 + l <= STACK_LIMIT and d + 2 * l <= r,   # dup
+                d >= 2 and d - 1 + 2 * l <= r,                            # swap
+                d >= 2 and d - 2 + 2 * l <= r,                            # del
+                d >= 1 and l < GCL_VARS and d + l + 1 <= STACK_LIMIT
+                and d + 1 + 2 * l <= r,                                   # copy
+                l >= 1 and d + 2 * (l - 1) <= r,                          # paste
+            ])
+            w = _GCL_WEIGHTS * feas
+            cls = _GCL_CLASSES[min(int(np.searchsorted(np.cumsum(w), u[t, 0] * w.sum(),
+                                                       side="right")), 7)]
+            if cls == "leaf":
+                if u[t, 1] < p_var:
+                    tok = LOAD | (min(int(u[t, 2] * n_vars), n_vars - 1) << 8)
+                else:
+                    consts.append(np.float32(const_lo + (const_hi - const_lo) * u[t, 2]))
+                    tok = CONST | ((len(consts) - 1) << 8)
+                d += 1
+            elif cls == "unary":
+                tok = int(unary[min(int(u[t, 1] * unary.size), unary.size - 1)])
+            elif cls == "binary":
+                tok = POW if u[t, 1] < p_pow else BINARY[min(int(u[t, 2] * 4), 3)]
+                d -= 1
+            elif cls == "dup":
+                tok = DUP
+                d += 1
+            elif cls == "swap":
+                tok = SWAP
+            elif cls == "del":
+                tok = DEL
+                d -= 1
+            elif cls == "copy":
+                k = min(set(range(GCL_VARS)) - set(live))
+                live.append(k)
+                tok = COPY | (k << 8)
+            else:
+                k = live.pop(min(int(u[t, 1] * l), l - 1))
+                tok = PASTE | (k << 8)
+                d += 1
+            nodes[pos + t] = tok
+        assert d == 1 and not live
+    return Population(nodes, offsets, np.array(consts, np.float32))
+
+
 def monomials(n_vars, degree=3):
     """All exponent tuples of total degree <= degree (constant term first)."""
     out = []
@@ -233,12 +330,15 @@ def length_law(name, rng, n):
         return np.clip(rng.geometric(1.0 / 24.0, n), 3, 128)
     if name == "serving":
         return rng.integers(3, 129, n)
+    if name == "gcl":
+        return rng.integers(3, 49, n)
     raise ValueError(name)
 
 
 # programs, cases, variables at full size
 SIZES = {"plain": (1_000, 1_024, 3), "generation": (100_000, 4_096, 5),
-         "uneven": (1_000_000, 16_384, 10), "precision": (50_000, 1_048_576, 3)}
+         "uneven": (1_000_000, 16_384, 10), "precision": (50_000, 1_048_576, 3),
+         "gcl": (20_000, 2_048, 4)}
 
 
 def make_dataset(name, n_cases=None, seed=None):
@@ -264,6 +364,10 @@ def make_dataset(name, n_cases=None, seed=None):
         terms = monomials(n_vars)
         y = poly_eval(X.astype(np.float64), terms, rpoly.uniform(-1, 1, len(terms)))
         y *= 1e4 / np.max(np.abs(y))
+    elif name == "gcl":
+        X = rx.uniform(-1, 1, (n_vars, n)).astype(np.float32)
+        X64 = X.astype(np.float64)
+        y = X64[0] ** 2 + np.sin(X64[1]) * X64[2] - 0.5 * X64[3] + rnoise.normal(0, 0.01, n)
     else:
         raise ValueError(name)
     return Dataset(np.ascontiguousarray(X), y.astype(np.float32))
@@ -276,11 +380,14 @@ def make_workload(name, n_programs=None, n_cases=None, seed=None):
     P_default, _, n_vars = SIZES[name]
     P = P_default if n_programs is None else int(n_programs)
     plain = name == "plain"
-    unary = UNARY_1 if plain else UNARY_2
-    pop = sample_programs(rp, length_law(name, rp, P), n_vars, unary)
+    if name == "gcl":
+        pop = sample_gcl_programs(rp, length_law(name, rp, P), n_vars)
+    else:
+        pop = sample_programs(rp, length_law(name, rp, P), n_vars,
+                              UNARY_1 if plain else UNARY_2)
     data = make_dataset(name, n_cases, seed)
     tax = 0.0 if plain else 1e-3
-    mask = MASK_1 if plain else MASK_2
+    mask = MASK_1 if plain else (MASK_GCL if name == "gcl" else MASK_2)
     return Workload(name, pop, data, tax, mask)
 
 

@@ -50,3 +50,18 @@ def test_workload_shapes():
     runs = synth.make_serving_runs(8)
     for r in runs:
         assert 1 <= r.data.n_vars <= 20 and 256 <= r.data.n_cases <= 65536
+
+
+def test_gcl_sampler_valid_and_covers_the_command_table():
+    w = synth.make_workload("gcl", n_programs=3000, n_cases=64)
+    st, md = oracle.validate(w.pop.nodes, w.pop.offsets, w.pop.consts.size,
+                             w.data.n_vars, w.allowed_mask)
+    assert np.all(st == 0)
+    assert md.max() <= 32
+    L = w.pop.lengths
+    assert L.min() >= 3 and L.max() <= 48
+    ops = np.bincount(w.pop.nodes & 0xFF, minlength=synth.N_OPS)
+    assert ops.size == synth.N_OPS and np.all(ops > 0)       # every command occurs
+    # COPY/PASTE names stay below 16
+    vp = (w.pop.nodes & 0xFF) >= synth.COPY
+    assert np.all((w.pop.nodes[vp] >> 8) < synth.GCL_VARS)
