@@ -425,7 +425,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="generation", choices=sorted(synth.WORKLOADS) + ["serving"])
+    # the GCL workload uses the whole command table, which scoring does not take
+    ap.add_argument("--workload", default="generation",
+                    choices=sorted(w for w in synth.WORKLOADS if w != "gcl") + ["serving"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fitness", default="mse", choices=["mse", "correlation", "reward"],
                     help="correlation: the paper's Eq. 1-2 score through gp_eval_correlation; "

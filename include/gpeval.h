@@ -66,7 +66,8 @@ enum gp_status {
     GP_E_HIP = -5            /* a HIP runtime call failed */
 };
 
-/* Opcodes (GCL command table; ABS is not a GCL command). */
+/* Opcodes (GCL command table; ABS is not a GCL command).  0-11 are the
+ * benchmark set; 12-27 complete the paper's command table. */
 enum gp_op {
     GP_LOAD = 0,    /* push X[arg][i]; arg = zero-based input index   */
     GP_CONST = 1,   /* push consts[arg]                               */
@@ -80,16 +81,47 @@ enum gp_op {
     GP_LOG = 9,     /* a -> |a| <= fp32(0.001) ? 0 : ln |a|           */
     GP_SQRT = 10,   /* a -> sqrt |a|                                  */
     GP_ABS = 11,    /* a -> |a|                                       */
-    GP_N_OPS = 12
+    GP_DUP = 12,    /* a -> a a                                       */
+    GP_SWAP = 13,   /* a b -> b a                                     */
+    GP_DEL = 14,    /* a -> (nothing)                                 */
+    GP_SQUARE = 15, /* a -> a * a                                     */
+    GP_SIGN = 16,   /* a -> -a                                        */
+    GP_CUBE = 17,   /* a -> a * a * a (rounded once)                  */
+    GP_CBRT = 18,   /* a -> cube root of a (real, any sign)           */
+    GP_TAN = 19,    /* a -> tan a                                     */
+    GP_ASIN = 20,   /* a -> arcsin a (NaN outside [-1, 1])            */
+    GP_ACOS = 21,   /* a -> arccos a (NaN outside [-1, 1])            */
+    GP_ATAN = 22,   /* a -> arctan a                                  */
+    GP_TANH = 23,   /* a -> tanh a                                    */
+    GP_SQRT_RAW = 24, /* a -> sqrt a (NaN below zero; the paper's SQRT) */
+    GP_POW = 25,    /* a b -> a^b (C99 pow special cases)             */
+    GP_COPY = 26,   /* variable @arg := top; the stack is unchanged  */
+    GP_PASTE = 27,  /* push variable @arg; the variable is freed      */
+    GP_N_OPS = 28
 };
 #define GP_ALL_OPS ((1u << GP_N_OPS) - 1u)
+/* The benchmark set LOAD..ABS.  The scoring entry points (gp_eval,
+ * gp_eval_correlation, gp_eval_reward, gp_eval_batched, plans, the server)
+ * take op masks within it: 0 means GP_BASE_OPS for them, and a mask with any
+ * other bit gives GP_E_INVALID_ARG before device work.  gp_validate and
+ * gp_predict take the whole command table (0 means GP_ALL_OPS); gp_predict
+ * runs an interpreter built for it when its mask reaches beyond
+ * GP_BASE_OPS. */
+#define GP_BASE_OPS ((1u << 12) - 1u)
+/* COPY/PASTE variable names: @0 .. @15.  A valid program copies into a free
+ * variable only, pastes a held one only, and ends with every variable
+ * free; a held variable takes one of the GP_MAX_STACK cells, so the stack
+ * depth plus the held variables never exceeds GP_MAX_STACK (else
+ * GP_PROG_TOO_DEEP). */
+#define GP_GCL_VARS 16
 
 /* Per-program validation codes. */
 enum gp_prog_status {
     GP_PROG_OK = 0, GP_PROG_EMPTY = 1, GP_PROG_BAD_OP = 2, GP_PROG_BAD_VAR = 3,
     GP_PROG_BAD_CONST = 4, GP_PROG_UNDERFLOW = 5, GP_PROG_TOO_DEEP = 6,
     GP_PROG_FINAL_DEPTH = 7, GP_PROG_BAD_OFFSETS = 8,
-    GP_PROG_BAD_TABLE = 9     /* gp_eval_batched: invalid dataset/request table */
+    GP_PROG_BAD_TABLE = 9,    /* gp_eval_batched: invalid dataset/request table */
+    GP_PROG_BAD_PAIR = 10     /* COPY/PASTE not paired (see GP_GCL_VARS) */
 };
 
 /* Thread-local text for the last non-OK status returned on this thread. */
@@ -102,7 +134,8 @@ int gp_version(void);
  * gp_validate -- host-side check of a population (host pointers).
  * allowed_op_mask: bit op set = op allowed (GetAllowedOperations in the
  * optional MLSetup overrides); 0 means GP_ALL_OPS.  status/max_depth:
- * optional host arrays of n_programs entries.  *first_bad (optional) gets
+ * optional host arrays of n_programs entries; max_depth is the largest
+ * stack depth plus held variables over the program.  *first_bad (optional) gets
  * the first invalid program index or -1.  Returns GP_OK when every program
  * is valid, GP_E_BAD_PROGRAM otherwise.  Pure and thread-safe.
  */

@@ -25,7 +25,10 @@ LIB_PATH = os.environ.get("GPEVAL_LIB") or os.path.join(_PKG, "libgpeval.so")
 
 GP_OK, GP_E_INVALID_ARG, GP_E_BAD_PROGRAM, GP_E_TOO_LARGE, GP_E_NO_MEMORY, GP_E_HIP = \
     0, -1, -2, -3, -4, -5
-GP_ALL_OPS = (1 << 12) - 1
+GP_N_OPS = 28
+GP_ALL_OPS = (1 << GP_N_OPS) - 1
+GP_BASE_OPS = (1 << 12) - 1       # LOAD..ABS, the benchmark set
+GP_PROG_BAD_PAIR = 10
 
 _lib = None
 

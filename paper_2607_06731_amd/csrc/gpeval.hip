@@ -124,6 +124,13 @@ constexpr uint32_t kFSBin = 4u;
 constexpr uint32_t kFLBin = 8u;
 constexpr uint32_t kFLast = 0x80000000u;  // the program's last instruction (sign bit)
 constexpr uint32_t kFConst = 32u;       // the leaf is a constant
+// Cell moves (DUP, SWAP, DEL, COPY, PASTE; full command table only):
+// slot field = cell read, payload = cell written | (compaction source << 8)
+// | (compaction target << 16), all pre-scaled; the selector says which
+// parts run, in this order: tmp = read cell; write cell = top; top = tmp;
+// compaction target = compaction source.
+constexpr uint32_t kFMove = 16u;
+constexpr uint32_t kMvRead = 1u, kMvWrite = 2u, kMvTop = 4u, kMvCompact = 8u;
 
 __host__ __device__ inline uint2 staged_word(uint32_t flags, uint32_t sel, uint32_t slot,
                                              uint32_t payload)
@@ -135,6 +142,89 @@ __host__ __device__ inline int depth_class(int maxd)
 {
     return maxd <= 8 ? 0 : (maxd <= 16 ? 1 : 2);
 }
+
+// Op kinds of the command table.  Unary selectors: the benchmark set's six
+// (SIN..ABS) first, then SQUARE..SQRT_RAW; binary selectors ADD..DIV, POW.
+__host__ __device__ constexpr bool op_is_binary(uint32_t op)
+{
+    return (op >= GP_ADD && op <= GP_DIV) || op == GP_POW;
+}
+__host__ __device__ constexpr bool op_is_unary(uint32_t op)
+{
+    return (op >= GP_SIN && op <= GP_ABS) || (op >= GP_SQUARE && op <= GP_SQRT_RAW);
+}
+__host__ __device__ constexpr uint32_t bop_sel(uint32_t op) { return op == GP_POW ? 4u : op - GP_ADD; }
+__host__ __device__ constexpr uint32_t uop_sel(uint32_t op)
+{
+    return op <= GP_ABS ? op - GP_SIN : op - GP_SQUARE + 6u;
+}
+constexpr uint32_t kUnSquare = 6u;      // first selector beyond the benchmark set
+constexpr uint32_t kBinPow = 4u;
+
+// The GCL stack and variable discipline, one node at a time; the host
+// validator and the device staging passes share it, so both accept the
+// same programs.  Held variables fill the storage cells from the top:
+// variable k sits `pos` cells below the top cell; a PASTE frees its cell
+// and the variable in the lowest held cell moves into it, so the held
+// variables always occupy the top `live` cells.
+struct GclCheck {
+    int depth = 0, live = 0, maxd = 0;
+    uint32_t held = 0u;                 // bit k: variable k holds a value
+    uint64_t pos = 0ull;                // 4 bits per variable
+
+    __host__ __device__ int var_pos(uint32_t k) const { return (int)((pos >> (4u * k)) & 15ull); }
+    __host__ __device__ void set_pos(uint32_t k, int p)
+    {
+        pos = (pos & ~(15ull << (4u * k))) | ((uint64_t)p << (4u * k));
+    }
+    // COPY @k of a free variable: its cell position.
+    __host__ __device__ int copy(uint32_t k)
+    {
+        held |= 1u << k;
+        set_pos(k, live);
+        return live++;
+    }
+    // PASTE @k of a held variable: the position of the variable that moves
+    // into k's freed cell, or -1.
+    __host__ __device__ int paste(uint32_t k)
+    {
+        const int p = var_pos(k);
+        held &= ~(1u << k);
+        --live;
+        if (p == live) return -1;
+        for (uint32_t m = 0; m < GP_GCL_VARS; ++m)
+            if (((held >> m) & 1u) && var_pos(m) == live) set_pos(m, p);
+        return live;
+    }
+    // Applies one node; returns its GP_PROG_* status (checks in the order
+    // op, operand range, underflow, pairing, depth).
+    __host__ __device__ int step(uint32_t op, uint32_t arg, uint32_t allowed, int32_t n_vars,
+                                 int64_t n_consts)
+    {
+        if (op >= GP_N_OPS || !((allowed >> op) & 1u)) return GP_PROG_BAD_OP;
+        if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) return GP_PROG_BAD_VAR;
+        if (op == GP_CONST && (int64_t)arg >= n_consts) return GP_PROG_BAD_CONST;
+        const int need = op_is_binary(op) || op == GP_SWAP ? 2
+                         : (op == GP_LOAD || op == GP_CONST || op == GP_PASTE ? 0 : 1);
+        if (depth < need) return GP_PROG_UNDERFLOW;
+        if (op == GP_COPY) {
+            if (arg >= GP_GCL_VARS || ((held >> arg) & 1u)) return GP_PROG_BAD_PAIR;
+            copy(arg);
+        } else if (op == GP_PASTE) {
+            if (arg >= GP_GCL_VARS || !((held >> arg) & 1u)) return GP_PROG_BAD_PAIR;
+            paste(arg);
+        }
+        if (op == GP_LOAD || op == GP_CONST || op == GP_PASTE || op == GP_DUP) ++depth;
+        else if (op_is_binary(op) || op == GP_DEL) --depth;
+        if (depth + live > GP_MAX_STACK) return GP_PROG_TOO_DEEP;
+        if (depth + live > maxd) maxd = depth + live;
+        return GP_PROG_OK;
+    }
+    __host__ __device__ int finish() const
+    {
+        return depth != 1 ? GP_PROG_FINAL_DEPTH : (live != 0 ? GP_PROG_BAD_PAIR : GP_PROG_OK);
+    }
+};
 
 // Cases per lane for a depth class: deeper stacks hold fewer cases per
 // lane so that the register stack (MAXD * K VGPRs) stays bounded.  (8 cases
@@ -483,26 +573,59 @@ __attribute__((noinline)) __device__ float cos_value(float x) { return cos_value
 __attribute__((noinline)) __device__ float exp_value(float x) { return exp_value_inl(x); }
 __attribute__((noinline)) __device__ float sqrt_value(float x) { return sqrt_abs(x); }
 
+// The rest of the command table: ROCm's fp32 library functions, out of
+// line (the full-table interpreter calls them per case; constant folding
+// calls the same functions, so both give the same bits).  CUBE is formed
+// in fp64 (a*a is exact there) and rounded once; SQRT_RAW is the
+// benchmark set's root with NaN below zero.
+__attribute__((noinline)) __device__ float cbrt_value(float x) { return cbrtf(x); }
+__attribute__((noinline)) __device__ float tan_value(float x) { return tanf(x); }
+__attribute__((noinline)) __device__ float asin_value(float x) { return asinf(x); }
+__attribute__((noinline)) __device__ float acos_value(float x) { return acosf(x); }
+__attribute__((noinline)) __device__ float atan_value(float x) { return atanf(x); }
+__attribute__((noinline)) __device__ float tanh_value(float x) { return tanhf(x); }
+__attribute__((noinline)) __device__ float pow_value(float a, float b) { return powf(a, b); }
+__device__ __forceinline__ float cube_value(float x)
+{
+    const double d = (double)x;
+    return (float)(d * d * d);
+}
+__device__ __forceinline__ float sqrt_raw(float x)
+{
+    return x < 0.f ? __builtin_nanf("") : sqrt_abs(x);
+}
+
 // One operator on one value, exactly as the interpreter computes it for a
 // case (used to fold constant subtrees while staging).
-__device__ __forceinline__ float binary_value(uint32_t bop, float a, float b)
+__device__ __forceinline__ float binary_value(uint32_t op, float a, float b)
 {
-    switch (bop) {
+    switch (op) {
     case GP_ADD: return a + b;
     case GP_SUB: return a - b;
     case GP_MUL: return a * b;
+    case GP_POW: return pow_value(a, b);
     default: return div_protected(a, b);
     }
 }
 
-__device__ __forceinline__ float unary_value(uint32_t uop, float x)
+__device__ __forceinline__ float unary_value(uint32_t op, float x)
 {
-    switch (uop) {
+    switch (op) {
     case GP_SIN: return sin_value_inl(x);
     case GP_COS: return cos_value_inl(x);
     case GP_EXP: return exp_value_inl(x);
     case GP_LOG: return log_protected(x);
     case GP_SQRT: return sqrt_abs(x);
+    case GP_SQUARE: return x * x;
+    case GP_SIGN: return -x;
+    case GP_CUBE: return cube_value(x);
+    case GP_CBRT: return cbrt_value(x);
+    case GP_TAN: return tan_value(x);
+    case GP_ASIN: return asin_value(x);
+    case GP_ACOS: return acos_value(x);
+    case GP_ATAN: return atan_value(x);
+    case GP_TANH: return tanh_value(x);
+    case GP_SQRT_RAW: return sqrt_raw(x);
     default: return fabsf(x);
     }
 }
@@ -602,16 +725,19 @@ __device__ bool cache_block_nodes(bool mine, int r, int64_t s, int64_t e,
 }
 
 // Emits the staged instructions of one valid program (k_validate counts
-// them with the same rules as it validates).  Constants are held back on a shadow stack and folded: an operator
-// whose operands are all held-back constants is computed here, once, with
-// the interpreter's own scalar arithmetic (the same bits every case would
-// get), and only its value travels on.  Held-back constants always sit on
-// top of the runtime stack; they are pushed ("flushed") before a variable is
-// pushed above them, combined with the runtime top as "top = top OP c", or
-// pushed at the end when the whole program is constant.  A variable directly
-// followed by an operator folds into it (top OP x, or save + f(x)).  What is
-// folded depends only on the node kinds, never on values, so counting and
-// emitting agree.
+// them with the same rules as it validates).  Constants are held back on a
+// shadow stack and folded: an operator whose operands are all held-back
+// constants is computed here, once, with the interpreter's own scalar
+// arithmetic (the same bits every case would get), and only its value
+// travels on.  Held-back constants always sit on top of the runtime stack;
+// they are pushed ("flushed") before a variable or a moved cell is pushed
+// above them, combined with the runtime top as "top = top OP c", or pushed
+// at the end when the whole program is constant.  A variable directly
+// followed by an operator folds into it (top OP x, or save + f(x)).  DUP,
+// SWAP, DEL, COPY and PASTE become one cell move each (no more instructions
+// than nodes); held variables take the cells from the top down (GclCheck).
+// What is folded depends only on the node kinds, never on values, so
+// counting and emitting agree.
 template <class Nodes, class Consts>
 __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, uint32_t J,
                               uint32_t row_bytes, uint2* __restrict__ out, int64_t cap,
@@ -624,7 +750,13 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
     auto put = [&](int64_t i, uint2 v) {
         if (i < cap) out[i] = v;
     };
-    const uint32_t dummy = 32u - J;              // slot MAXD-1: never live
+    // A push onto an empty stack saves the meaningless old top in cell 0:
+    // no element sits there below depth 2, and after a push depth + held
+    // variables <= MAXD keeps every held variable above it.
+    const uint32_t dummy = 0u;
+    // cell (pre-scaled) of the held variable at position q from the top
+    auto vcell = [&](int q) { return 32u - J * (uint32_t)(q + 1); };
+    GclCheck gc;
     int rt = 0;                                  // runtime stack depth
     int np = 0;                                  // held-back constants
     int64_t n = 0;                               // emitted instructions
@@ -652,12 +784,12 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
             const uint32_t payload = arg * row_bytes;
             const uint32_t nx = k + 1 < e ? (nodes(k + 1) & 0xFFu) : 0xFFu;
             const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
-            if (nx >= GP_ADD && nx <= GP_DIV) {
+            if (op_is_binary(nx)) {
                 // top = top OP x (the binary op has a runtime element below)
-                put(n, staged_word(kFLBin, nx - GP_ADD, 0u, payload));
+                put(n, staged_word(kFLBin, bop_sel(nx), 0u, payload));
                 ++k;
-            } else if (nx >= GP_SIN && nx < GP_N_OPS) {
-                put(n, staged_word(kFPush | kFUn, nx - GP_SIN, wr, payload));
+            } else if (op_is_unary(nx)) {
+                put(n, staged_word(kFPush | kFUn, uop_sel(nx), wr, payload));
                 ++rt;
                 ++k;
             } else {
@@ -667,8 +799,8 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
             ++n;
             continue;
         }
-        if (op <= GP_DIV) {
-            const uint32_t bop = op - GP_ADD;
+        if (op_is_binary(op)) {
+            const uint32_t bop = bop_sel(op);
             if (np >= 2) {
                 --np;
                 pv(np - 1) = binary_value(op, pv(np - 1), pv(np));
@@ -685,11 +817,46 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
             }
             continue;
         }
-        if (np >= 1) {
-            pv(np - 1) = unary_value(op, pv(np - 1));
+        if (op_is_unary(op)) {
+            if (np >= 1) {
+                pv(np - 1) = unary_value(op, pv(np - 1));
+            } else {
+                put(n, staged_word(kFUn, uop_sel(op), 0u, 0u));
+                ++n;
+            }
+            continue;
+        }
+        // cell moves
+        flush();
+        const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
+        if (op == GP_DUP) {
+            put(n++, staged_word(kFMove, kMvWrite, 0u, wr));
+            ++rt;
+        } else if (op == GP_SWAP) {
+            const uint32_t c2 = (uint32_t)(rt - 2) * J;
+            put(n++, staged_word(kFMove, kMvRead | kMvWrite | kMvTop, c2, c2));
+        } else if (op == GP_DEL) {
+            // the element below becomes the top; deleting the only element
+            // moves nothing
+            if (rt >= 2) put(n++, staged_word(kFMove, kMvRead | kMvTop, (uint32_t)(rt - 2) * J, 0u));
+            --rt;
+        } else if (op == GP_COPY) {
+            const int q = gc.copy(arg);
+            put(n++, staged_word(kFMove, kMvWrite, 0u, vcell(q)));
         } else {
-            put(n, staged_word(kFUn, op - GP_SIN, 0u, 0u));
-            ++n;
+            // PASTE: the variable becomes the top (the old top saved unless
+            // the stack was empty); the lowest held variable moves into the
+            // freed cell
+            const int q = gc.var_pos(arg);
+            const int from = gc.paste(arg);
+            uint32_t sel = kMvRead | kMvTop | (rt >= 1 ? kMvWrite : 0u);
+            uint32_t pay = wr;
+            if (from >= 0) {
+                sel |= kMvCompact;
+                pay |= (vcell(from) << 8) | (vcell(q) << 16);
+            }
+            put(n++, staged_word(kFMove, sel, vcell(q), pay));
+            ++rt;
         }
     }
     // a constant program: its value is pushed
@@ -704,48 +871,50 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
 #undef pv
 }
 
-// Validation of one program (GCL stack discipline, operand ranges,
-// allowed ops) and the count of staged instructions, by the same rules
-// stage_walk emits them: held-back constants (np), a variable folding into
-// the operator after it.
+// Validation of one program (GclCheck: stack and variable discipline,
+// operand ranges, allowed ops) and the count of staged instructions, by
+// the same rules stage_walk emits them: held-back constants (np), a
+// variable folding into the operator after it, one instruction per cell
+// move (none for DEL of the only element).
 template <class Nodes>
 __device__ void check_program(Nodes nodes, int64_t s, int64_t e, uint32_t allowed,
                               int32_t n_vars, int64_t n_consts, int& status, int& maxd,
                               int64_t& n_staged)
 {
-    int depth = 0;
+    GclCheck gc;
     int64_t n_st = 0;
     int np = 0;
     bool taken = false;
     for (int64_t k = s; k < e; ++k) {
         const uint32_t w = nodes(k);
         const uint32_t op = w & 0xFFu, arg = w >> 8;
-        if (op >= GP_N_OPS || !((allowed >> op) & 1u)) { status = GP_PROG_BAD_OP; break; }
-        if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) { status = GP_PROG_BAD_VAR; break; }
-        if (op == GP_CONST && (int64_t)arg >= n_consts) { status = GP_PROG_BAD_CONST; break; }
-        const int need = op <= GP_CONST ? 0 : (op <= GP_DIV ? 2 : 1);
-        if (depth < need) { status = GP_PROG_UNDERFLOW; break; }
-        depth += op <= GP_CONST ? 1 : (op <= GP_DIV ? -1 : 0);
-        if (depth > GP_MAX_STACK) { status = GP_PROG_TOO_DEEP; break; }
-        if (depth > maxd) maxd = depth;
+        const int depth0 = gc.depth;
+        status = gc.step(op, arg, allowed, n_vars, n_consts);
+        if (status != GP_PROG_OK) break;
         if (op == GP_CONST) {
             if (np == kHeldConsts) { n_st += np; np = 0; }   // pushed, as in staging
             ++np;
         } else if (op == GP_LOAD) {
             n_st += np + 1;                   // flush, then the variable
             np = 0;
-            taken = k + 1 < e && (nodes(k + 1) & 0xFFu) > GP_CONST;
+            const uint32_t nx = k + 1 < e ? (nodes(k + 1) & 0xFFu) : 0xFFu;
+            taken = op_is_binary(nx) || op_is_unary(nx);
         } else if (taken) {
             taken = false;                    // folded into the variable
-        } else if (op <= GP_DIV) {
+        } else if (op_is_binary(op)) {
             if (np >= 2) --np;
             else if (np == 1) { np = 0; ++n_st; }
             else ++n_st;
-        } else if (np == 0) {
-            ++n_st;
+        } else if (op_is_unary(op)) {
+            if (np == 0) ++n_st;
+        } else {
+            n_st += np;                       // flush, then the cell move
+            np = 0;
+            if (op != GP_DEL || depth0 >= 2) ++n_st;
         }
     }
-    if (status == GP_PROG_OK && depth != 1) status = GP_PROG_FINAL_DEPTH;
+    maxd = gc.maxd;
+    if (status == GP_PROG_OK) status = gc.finish();
     n_staged = n_st + np;
 }
 
@@ -1202,7 +1371,60 @@ __device__ __forceinline__ bool wave_any_above(const float (&v)[K], float limit)
     return __ballot(m > limit) != 0ull;
 }
 
-template <int MAXD, int K>
+// The commands beyond the benchmark set on the top values (unary
+// selectors kUnSquare..15), per case, with the functions constant folding
+// uses.
+template <int K>
+__device__ __forceinline__ void ext_unary(uint32_t sel, float (&t)[K])
+{
+    switch (sel) {
+    case kUnSquare:
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = t[j] * t[j];
+        break;
+    case kUnSquare + 1:
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = -t[j];
+        break;
+    case kUnSquare + 2:
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = cube_value(t[j]);
+        break;
+    case kUnSquare + 3:
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = cbrt_value(t[j]);
+        break;
+    case kUnSquare + 4:
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = tan_value(t[j]);
+        break;
+    case kUnSquare + 5:
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = asin_value(t[j]);
+        break;
+    case kUnSquare + 6:
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = acos_value(t[j]);
+        break;
+    case kUnSquare + 7:
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = atan_value(t[j]);
+        break;
+    case kUnSquare + 8:
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = tanh_value(t[j]);
+        break;
+    default:
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = sqrt_raw(t[j]);
+        break;
+    }
+}
+
+// EXT: the interpreter for the whole command table (POW, the unary
+// commands beyond the benchmark set, cell moves); without it the code is
+// the benchmark set's alone.
+template <int MAXD, int K, bool EXT>
 __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                                             const float* __restrict__ xl, float (&tos)[K])
 {
@@ -1237,7 +1459,9 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
             }
         // unary: replaces the top
         const uint32_t uop = GP_SIN + sel;
-        {
+        if (EXT && sel >= kUnSquare) {
+            ext_unary<K>(sel, tos);
+        } else {
             switch (uop) {
             case GP_SIN:
                 // the fast kernel when every case of the wavefront has
@@ -1302,12 +1526,22 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
             float sv[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) sv[j] = GP_CHUNK_GET(slot, j);
-            GP_BINARY(GP_ADD + sel, sv, tos);
+            if (EXT && sel == kBinPow) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) tos[j] = pow_value(sv[j], tos[j]);
+            } else {
+                GP_BINARY(GP_ADD + sel, sv, tos);
+            }
         } else if (f & kFLBin) {
             // top OP leaf; a constant leaf gets its own copy of the op
             // switch so the constant stays a scalar operand instead of
             // being broadcast into registers first
-            if (f & kFConst) {
+            if (EXT && sel == kBinPow) {
+                float lv[K];
+                GP_LEAF(f & kFConst, w.y, lv);
+#pragma unroll
+                for (int j = 0; j < K; ++j) tos[j] = pow_value(tos[j], lv[j]);
+            } else if (f & kFConst) {
                 float cv[K];
 #pragma unroll
                 for (int j = 0; j < K; ++j) cv[j] = __uint_as_float(w.y);
@@ -1316,6 +1550,35 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                 float lv[K];
                 GP_LEAF(false, w.y, lv);
                 GP_BINARY_AB(GP_ADD + sel, tos, lv, tos);
+            }
+        } else if (EXT && (f & kFMove)) {
+            // cell move; every cell index is masked to a multiple of J
+            // inside the chunk
+            constexpr uint32_t kCellMask = 32u - J;
+            const uint32_t rs = slot & kCellMask;
+            const uint32_t ws = w.y & kCellMask;
+            float tv[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) tv[j] = tos[j];
+            if (sel & kMvRead) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) tv[j] = GP_CHUNK_GET(rs, j);
+            }
+            if (sel & kMvWrite) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) GP_CHUNK_PUT(ws, j, tos[j]);
+            }
+            if (sel & kMvTop) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) tos[j] = tv[j];
+            }
+            if (sel & kMvCompact) {
+                const uint32_t cs = (w.y >> 8) & kCellMask, cd = (w.y >> 16) & kCellMask;
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const float v = GP_CHUNK_GET(cs, j);
+                    GP_CHUNK_PUT(cd, j, v);
+                }
             }
         } else {
             // the old top moves into the stack (slot MAXD-1 never holds a
@@ -1566,7 +1829,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
                 for (int b = 0; b < nw; ++b) {
                     const float* blk = xt + b * rows * SUB;
                     float tos[K];
-                    run_program<MAXD, K>(code + m.start, blk + lane, tos);
+                    run_program<MAXD, K, false>(code + m.start, blk + lane, tos);
                     const int64_t base = (first + b) * SUB;
                     const float* yt = blk + n_vars * SUB;
 #pragma unroll
@@ -1639,7 +1902,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
 // Per-case outputs f_p(x_i) of the programs of one depth class: persistent
 // workgroups pull (group of four programs, sub-tile) items; each wavefront
 // runs one program of the group and each lane writes its K values.
-template <int MAXD, int K>
+template <int MAXD, int K, bool EXT>
 __global__ __launch_bounds__(kWG) void k_predict(
     const uint2* __restrict__ code, const ProgMeta* __restrict__ meta,
     const int32_t* __restrict__ order, const int32_t* __restrict__ class_info,
@@ -1683,7 +1946,7 @@ __global__ __launch_bounds__(kWG) void k_predict(
             const int pid = order[start + g];
             const ProgMeta m = meta[pid];
             float tos[K];
-            run_program<MAXD, K>(code + m.start, xt + lane, tos);
+            run_program<MAXD, K, EXT>(code + m.start, xt + lane, tos);
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int64_t gi = base + lane + j * 64;
@@ -2112,6 +2375,11 @@ int check_problem(const Problem& pb)
     int rc = check_common(pb.n_programs, pb.n_nodes, batched ? 0 : pb.one_req.n_consts,
                           pb.max_vars, batched ? pb.max_cases : pb.one.ld_x, pb.max_cases);
     if (rc != GP_OK) return rc;
+    // scoring runs the benchmark set's interpreter (the whole command table
+    // is evaluated by gp_predict)
+    if (pb.need_out && (pb.allowed & ~GP_BASE_OPS))
+        return set_error(GP_E_INVALID_ARG, "allowed_op_mask reaches beyond GP_BASE_OPS: scoring "
+                                           "takes the benchmark set, gp_predict the whole table");
     if (batched) {
         if (!pb.ds_dev) return set_error(GP_E_INVALID_ARG, "datasets_dev is NULL");
         if (pb.n_ds < 1) return set_error(GP_E_INVALID_ARG, "n_datasets < 1");
@@ -2170,6 +2438,10 @@ size_t eval_lds_bytes(int n_vars, int G)
     return eval_tile_floats<MAXD, K>(n_vars) * sizeof(float) + acc;
 }
 
+// Whether a gp_predict call runs the interpreter built for the whole
+// command table (its op mask reaches beyond the benchmark set).
+inline bool pb_ext(uint32_t allowed) { return (allowed & ~GP_BASE_OPS) != 0u; }
+
 // Grid size of one class kernel (LDS attribute set outside any capture).
 template <int MAXD, int K, int FIT>
 int eval_grid(int n_vars, int G, int wg_per_cu, int cus, int* grid, size_t* lds_out)
@@ -2203,6 +2475,15 @@ int group_capacity(const Problem& pb, const Tuning& tu)
     return pb.fit == kFitCorr && tu.G > kCorrMaxG ? kCorrMaxG : tu.G;
 }
 
+template <int FIT>
+int eval_grids(const Problem& pb, const Tuning& tu, int G, int cus, EvalLaunch* el)
+{
+    int rc;
+    if ((rc = eval_grid<8, 4, FIT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
+    if ((rc = eval_grid<16, kK1, FIT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
+    return eval_grid<32, 2, FIT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2]);
+}
+
 int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
 {
     int cus = 0;
@@ -2217,19 +2498,10 @@ int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
     }
     el->target_items = 4 * 6 * cus;     // ~4 items per workgroup slot
     const int G = group_capacity(pb, tu);
-    if (pb.fit == kFitCorr) {
-        if ((rc = eval_grid<8, 4, kFitCorr>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
-        if ((rc = eval_grid<16, kK1, kFitCorr>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
-        if ((rc = eval_grid<32, 2, kFitCorr>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2])) != GP_OK) return rc;
-    } else if (pb.fit == kFitReward) {
-        if ((rc = eval_grid<8, 4, kFitReward>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
-        if ((rc = eval_grid<16, kK1, kFitReward>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
-        if ((rc = eval_grid<32, 2, kFitReward>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2])) != GP_OK) return rc;
-    } else {
-        if ((rc = eval_grid<8, 4, kFitMse>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
-        if ((rc = eval_grid<16, kK1, kFitMse>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
-        if ((rc = eval_grid<32, 2, kFitMse>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2])) != GP_OK) return rc;
-    }
+    if (pb.fit == kFitCorr) rc = eval_grids<kFitCorr>(pb, tu, G, cus, el);
+    else if (pb.fit == kFitReward) rc = eval_grids<kFitReward>(pb, tu, G, cus, el);
+    else rc = eval_grids<kFitMse>(pb, tu, G, cus, el);
+    if (rc != GP_OK) return rc;
     el->layout = make_layout(pb.n_programs, pb.n_nodes, el->stride, pb.n_ds, pb.n_req, pb.fit);
     return GP_OK;
 }
@@ -2257,6 +2529,16 @@ int enqueue_stage(const Problem& pb, const Staged& st, hipStream_t stream)
                        st.cls, st.meta, st.code, st.order);
     GP_HIP_TRY(hipGetLastError());
     return GP_OK;
+}
+
+// One class kernel of the evaluation.
+template <int MD, int KK, int FIT>
+void launch_eval(dim3 g, size_t lds, hipStream_t sc, const Staged& st, int c,
+                 const EvalConst& ea)
+{
+    hipLaunchKernelGGL((k_eval<MD, KK, FIT>), g, dim3(kWG), lds, sc, st.code, st.meta, st.order,
+                       st.class_info, st.counters + c, st.ds, st.seg_ds, st.seg_cnt, st.seg_pos,
+                       st.item_pre, st.class_g, st.part, st.part_bad, st.part_corr, ea);
 }
 
 // The whole evaluation as stream work (no allocation, no synchronization:
@@ -2291,24 +2573,15 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
         if ((rc = ce.mark(1 + c, stream)) != GP_OK) return rc;
         const hipStream_t sc = (tu.concurrent && c > 0) ? side.s[c - 1] : stream;
         ea.cls = c;
-        const dim3 g(el.grid[c]), b(kWG);
+        const dim3 g(el.grid[c]);
 #define GP_LAUNCH_EVAL(MD, KK)                                                                 \
         do {                                                                                   \
             if (pb.fit == kFitCorr)                                                            \
-                hipLaunchKernelGGL((k_eval<MD, KK, kFitCorr>), g, b, el.lds[c], sc, st.code,   \
-                                   st.meta, st.order, st.class_info, st.counters + c, st.ds,   \
-                                   st.seg_ds, st.seg_cnt, st.seg_pos, st.item_pre, st.class_g, \
-                                   st.part, st.part_bad, st.part_corr, ea);                   \
+                launch_eval<MD, KK, kFitCorr>(g, el.lds[c], sc, st, c, ea);                    \
             else if (pb.fit == kFitReward)                                                     \
-                hipLaunchKernelGGL((k_eval<MD, KK, kFitReward>), g, b, el.lds[c], sc, st.code, \
-                                   st.meta, st.order, st.class_info, st.counters + c, st.ds,   \
-                                   st.seg_ds, st.seg_cnt, st.seg_pos, st.item_pre, st.class_g, \
-                                   st.part, st.part_bad, st.part_corr, ea);                   \
+                launch_eval<MD, KK, kFitReward>(g, el.lds[c], sc, st, c, ea);                  \
             else                                                                               \
-                hipLaunchKernelGGL((k_eval<MD, KK, kFitMse>), g, b, el.lds[c], sc, st.code,    \
-                                   st.meta, st.order, st.class_info, st.counters + c, st.ds,   \
-                                   st.seg_ds, st.seg_cnt, st.seg_pos, st.item_pre, st.class_g, \
-                                   st.part, st.part_bad, st.part_corr, ea);                   \
+                launch_eval<MD, KK, kFitMse>(g, el.lds[c], sc, st, c, ea);                     \
         } while (0)
         if (c == 0) {
             ea.tile_floats = (int32_t)eval_tile_floats<8, 4>(pb.max_vars);
@@ -2350,19 +2623,19 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
     return GP_OK;
 }
 
-template <int MAXD, int K>
+template <int MAXD, int K, bool EXT>
 int launch_predict(const EvalPtrs& p, float* out, int64_t ld_out, const EvalConst& args,
                    hipStream_t stream, int cus)
 {
     const size_t lds = (size_t)args.n_vars * 64 * K * sizeof(float);
     if (lds > 64 * 1024) {
-        GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_predict<MAXD, K>),
+        GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_predict<MAXD, K, EXT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
     int per_cu = 0;
-    GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_predict<MAXD, K>, kWG, lds));
+    GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_predict<MAXD, K, EXT>, kWG, lds));
     if (per_cu < 1) return set_error(GP_E_TOO_LARGE, "n_vars=%d needs %zu bytes of LDS per workgroup", args.n_vars, lds);
-    hipLaunchKernelGGL((k_predict<MAXD, K>), dim3(cus * per_cu), dim3(kWG), lds, stream, p.code,
+    hipLaunchKernelGGL((k_predict<MAXD, K, EXT>), dim3(cus * per_cu), dim3(kWG), lds, stream, p.code,
                        p.meta, p.order, p.class_info, p.work_counter, p.X, out, ld_out, args);
     GP_HIP_TRY(hipGetLastError());
     return GP_OK;
@@ -2559,7 +2832,7 @@ Problem make_problem(const gp_problem* d)
     pb.ds_dev = nullptr; pb.n_ds = 1;
     pb.n_programs = d->n_programs; pb.n_nodes = d->n_nodes;
     pb.max_vars = d->n_vars; pb.max_cases = d->n_cases;
-    pb.allowed = d->allowed_op_mask ? d->allowed_op_mask : GP_ALL_OPS;
+    pb.allowed = d->allowed_op_mask ? d->allowed_op_mask : GP_BASE_OPS;
     pb.need_out = 1;
     return pb;
 }
@@ -2680,24 +2953,16 @@ int gp_validate(const uint32_t* nodes, const int64_t* offsets, int64_t n_program
     int64_t bad_at = -1;
     for (int64_t p = 0; p < n_programs; ++p) {
         const int64_t s = offsets[p], e = offsets[p + 1];
-        int st = GP_PROG_OK, depth = 0, md = 0;
+        int st = GP_PROG_OK, md = 0;
         if (s < 0 || e < s) st = GP_PROG_BAD_OFFSETS;
         else if (e == s) st = GP_PROG_EMPTY;
         else if (!nodes) st = GP_PROG_BAD_OFFSETS;
         else {
-            for (int64_t k = s; k < e; ++k) {
-                const uint32_t op = nodes[k] & 0xFFu, arg = nodes[k] >> 8;
-                if (op >= GP_N_OPS || !((allowed >> op) & 1u)) { st = GP_PROG_BAD_OP; break; }
-                if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) { st = GP_PROG_BAD_VAR; break; }
-                if (op == GP_CONST && (int64_t)arg >= n_consts) { st = GP_PROG_BAD_CONST; break; }
-                const int need = op <= GP_CONST ? 0 : (op <= GP_DIV ? 2 : 1);
-                const int delta = op <= GP_CONST ? 1 : (op <= GP_DIV ? -1 : 0);
-                if (depth < need) { st = GP_PROG_UNDERFLOW; break; }
-                depth += delta;
-                if (depth > GP_MAX_STACK) { st = GP_PROG_TOO_DEEP; break; }
-                if (depth > md) md = depth;
-            }
-            if (st == GP_PROG_OK && depth != 1) st = GP_PROG_FINAL_DEPTH;
+            GclCheck gc;
+            for (int64_t k = s; k < e && st == GP_PROG_OK; ++k)
+                st = gc.step(nodes[k] & 0xFFu, nodes[k] >> 8, allowed, n_vars, n_consts);
+            if (st == GP_PROG_OK) st = gc.finish();
+            md = gc.maxd;
         }
         if (status) status[p] = st;
         if (max_depth) max_depth[p] = md;
@@ -2794,7 +3059,7 @@ int gp_eval_batched(const gp_request* requests_dev, int32_t n_requests,
     pb.ds_dev = datasets_dev; pb.n_ds = n_datasets;
     pb.n_programs = total_programs; pb.n_nodes = total_nodes;
     pb.max_vars = max_n_vars; pb.max_cases = max_n_cases;
-    pb.allowed = allowed_op_mask ? allowed_op_mask : GP_ALL_OPS;
+    pb.allowed = allowed_op_mask ? allowed_op_mask : GP_BASE_OPS;
     pb.need_out = 1;
     return eval_problem(pb, stream);
 }
@@ -2840,9 +3105,13 @@ int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs
     for (int c = 0; c < kClasses; ++c) {
         ea.cls = c;
         ep.work_counter = st.counters + c;
-        if (c == 0) rc = launch_predict<8, 4>(ep, out, ld_out, ea, stream, cus);
-        else if (c == 1) rc = launch_predict<16, kK1>(ep, out, ld_out, ea, stream, cus);
-        else rc = launch_predict<32, 2>(ep, out, ld_out, ea, stream, cus);
+        const bool ext = pb_ext(pb.allowed);
+        if (c == 0) rc = ext ? launch_predict<8, 4, true>(ep, out, ld_out, ea, stream, cus)
+                             : launch_predict<8, 4, false>(ep, out, ld_out, ea, stream, cus);
+        else if (c == 1) rc = ext ? launch_predict<16, kK1, true>(ep, out, ld_out, ea, stream, cus)
+                                  : launch_predict<16, kK1, false>(ep, out, ld_out, ea, stream, cus);
+        else rc = ext ? launch_predict<32, 2, true>(ep, out, ld_out, ea, stream, cus)
+                      : launch_predict<32, 2, false>(ep, out, ld_out, ea, stream, cus);
         if (rc != GP_OK) return rc;
     }
     hipLaunchKernelGGL(k_fill_invalid, dim3((unsigned)n_programs), dim3(256), 0, stream, st.cls,

@@ -603,7 +603,9 @@ int gp_server_create(gp_server** server, const gp_server_config* config)
     if (!c.n_streams) c.n_streams = 2;
     if (!c.max_batch_chunks) c.max_batch_chunks = 1024;
     if (c.one_launch_per_request) c.n_streams = 1;
-    if (!c.allowed_op_mask) c.allowed_op_mask = GP_ALL_OPS;
+    if (!c.allowed_op_mask) c.allowed_op_mask = GP_BASE_OPS;
+    if (c.allowed_op_mask & ~GP_BASE_OPS)
+        return fail(GP_E_INVALID_ARG, "allowed_op_mask reaches beyond GP_BASE_OPS (scoring takes the benchmark set)");
     if (c.device_budget_bytes < (int64_t(16) << 20))
         return fail(GP_E_INVALID_ARG, "device budget below 16 MiB");
 

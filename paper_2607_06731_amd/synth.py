@@ -226,7 +226,7 @@ _GCL_WEIGHTS = np.array([3.0, 2.0, 3.0, 0.6, 0.6, 0.4, 0.5, 1.5])
 
 
 def sample_gcl_programs(rng, lengths, n_vars, const_lo=-5.0, const_hi=5.0, p_var=0.5,
-                        p_pow=0.04):
+                        p_pow=0.04, unary=UNARY_GCL, binary=BINARY):
     """Programs over the whole GCL command table, one token at a time.
 
     State: depth d, live variables l, r tokens still to come after this one.
@@ -236,7 +236,8 @@ def sample_gcl_programs(rng, lengths, n_vars, const_lo=-5.0, const_hi=5.0, p_var
       leaf d+1; unary d >= 1; binary d >= 2; DUP d >= 1, d+1; SWAP d >= 2;
       DEL d >= 2, d-1; COPY d >= 1, l < 16, l+1; PASTE l >= 1, d+1, l-1.
     A feasible class is drawn with the weights above, then an op uniformly
-    inside it (POW with probability p_pow among the binary ops); COPY takes
+    inside it (unary from ``unary``; POW with probability p_pow, else one of
+    ``binary``); COPY takes
     the lowest free variable name, PASTE a live one uniformly.  Leaves are
     as in sample_programs.  Never dead-ends (PASTE, a binary op, a unary op
     or a leaf stays feasible), ends at depth 1 with no live variable."""
@@ -246,7 +247,8 @@ def sample_gcl_programs(rng, lengths, n_vars, const_lo=-5.0, const_hi=5.0, p_var
     np.cumsum(lengths, out=offsets[1:])
     nodes = np.zeros(int(offsets[-1]), np.uint32)
     consts = []
-    unary = np.array(UNARY_GCL, np.uint32)
+    unary = np.array(unary, np.uint32)
+    nb = len(binary)
     for p in range(P):
         Lp = int(lengths[p])
         d, live = 0, []
@@ -279,7 +281,7 @@ def sample_gcl_programs(rng, lengths, n_vars, const_lo=-5.0, const_hi=5.0, p_var
             elif cls == "unary":
                 tok = int(unary[min(int(u[t, 1] * unary.size), unary.size - 1)])
             elif cls == "binary":
-                tok = POW if u[t, 1] < p_pow else BINARY[min(int(u[t, 2] * 4), 3)]
+                tok = POW if u[t, 1] < p_pow else binary[min(int(u[t, 2] * nb), nb - 1)]
                 d -= 1
             elif cls == "dup":
                 tok = DUP

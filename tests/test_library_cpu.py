@@ -118,6 +118,18 @@ def test_reward_rejects_bad_arguments_before_device_work(L):
                                 None, None) == gp.GP_OK
 
 
+def test_scoring_rejects_masks_beyond_the_benchmark_set(L):
+    c = ctypes.c_void_p(1)
+    for mask in (gp.GP_ALL_OPS, 1 << 12, gp.GP_BASE_OPS | (1 << 27)):
+        assert L.gp_eval(c, c, 1, 1, c, 0, c, 1, 1, c, 1, 0.0, mask, c, None,
+                         None) == gp.GP_E_INVALID_ARG
+        assert b"GP_BASE_OPS" in L.gp_last_error()
+        assert L.gp_eval_correlation(c, c, 1, 1, c, 0, c, 1, 1, c, 1, 1e4, mask, c, None,
+                                     None) == gp.GP_E_INVALID_ARG
+        assert L.gp_eval_reward(c, c, 1, 1, c, 0, c, 1, 1, c, 1, 1e4, 1, mask, c, None,
+                                None) == gp.GP_E_INVALID_ARG
+
+
 def test_binding_refuses_host_tensors():
     import torch
     with pytest.raises(TypeError):
@@ -164,3 +176,41 @@ def test_batched_and_server_reject_bad_arguments(L):
     t = ctypes.c_int64()
     assert L.gp_server_submit(None, 0, None, 0, c, 0, None, 0, None, None,
                               ctypes.byref(t)) == gp.GP_E_INVALID_ARG
+
+
+def test_host_validate_matches_oracle_on_the_full_command_table():
+    """Status codes and maximum depth (stack plus held variables) of the
+    host validator equal the oracle's over every program of up to five
+    tokens of an alphabet with the stack moves, variables and POW, and over
+    mutated programs of the GCL workload."""
+    import itertools
+    from oracle import COPY, DEL, DUP, PASTE, POW, SWAP
+    L0, C0 = oracle.LOAD, oracle.CONST
+    alphabet = [L0, C0, oracle.SIN, oracle.ADD, POW, DUP, SWAP, DEL, COPY, PASTE,
+                COPY | (1 << 8), PASTE | (1 << 8), COPY | (16 << 8), 28]
+    progs = [t for n in range(1, 5) for t in itertools.product(alphabet, repeat=n)]
+    lens = np.array([len(p) for p in progs], np.int64)
+    off = np.zeros(lens.size + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    nodes = np.array([w for p in progs for w in p], np.uint32)
+    st_o, md_o = oracle.validate(nodes, off, 1, 1, oracle.MASK_GCL)
+    st_g, md_g, _ = gp.gp_validate(nodes, off, 1, 1, gp.GP_ALL_OPS)
+    assert np.array_equal(st_o, st_g)
+    ok = st_o == 0
+    assert ok.sum() > 100 and np.array_equal(md_o[ok], md_g[ok])
+    # a mask without the moves rejects them
+    st_b, _, _ = gp.gp_validate(nodes, off, 1, 1, gp.GP_BASE_OPS)
+    st_ob, _ = oracle.validate(nodes, off, 1, 1, oracle.MASK_BENCH)
+    assert np.array_equal(st_b, st_ob)
+    w = synth.make_workload("gcl", n_programs=2000, n_cases=64)
+    rng = np.random.default_rng(3)
+    nodes = w.pop.nodes.copy()
+    idx = rng.choice(nodes.size, 400, replace=False)
+    nodes[idx[:200]] = rng.integers(0, 30, 200).astype(np.uint32)
+    nodes[idx[200:]] = (nodes[idx[200:]] & 0xFF) | (rng.integers(0, 18, 200).astype(np.uint32) << 8)
+    st_o, md_o = oracle.validate(nodes, w.pop.offsets, w.pop.consts.size, 4, w.allowed_mask)
+    st_g, md_g, _ = gp.gp_validate(nodes, w.pop.offsets, w.pop.consts.size, 4, w.allowed_mask)
+    assert np.array_equal(st_o, st_g)
+    ok = st_o == 0
+    assert np.array_equal(md_o[ok], md_g[ok])
+    assert (st_o == oracle.ST_BAD_PAIR).sum() > 10
