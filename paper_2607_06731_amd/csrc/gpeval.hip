@@ -145,13 +145,16 @@ __host__ __device__ inline int depth_class(int maxd)
 
 // Op kinds of the command table.  Unary selectors: the benchmark set's six
 // (SIN..ABS) first, then SQUARE..SQRT_RAW; binary selectors ADD..DIV, POW.
+// (bit tables over the 28 opcodes: one shift per test)
+constexpr uint32_t kBinaryOps = 0x3Cu | (1u << GP_POW);                    // ADD..DIV, POW
+constexpr uint32_t kUnaryOps = 0xFC0u | (((1u << 10) - 1u) << GP_SQUARE);  // SIN..ABS, SQUARE..SQRT_RAW
 __host__ __device__ constexpr bool op_is_binary(uint32_t op)
 {
-    return (op >= GP_ADD && op <= GP_DIV) || op == GP_POW;
+    return op < 32u && ((kBinaryOps >> op) & 1u);
 }
 __host__ __device__ constexpr bool op_is_unary(uint32_t op)
 {
-    return (op >= GP_SIN && op <= GP_ABS) || (op >= GP_SQUARE && op <= GP_SQRT_RAW);
+    return op < 32u && ((kUnaryOps >> op) & 1u);
 }
 __host__ __device__ constexpr uint32_t bop_sel(uint32_t op) { return op == GP_POW ? 4u : op - GP_ADD; }
 __host__ __device__ constexpr uint32_t uop_sel(uint32_t op)
@@ -201,21 +204,28 @@ struct GclCheck {
     __host__ __device__ int step(uint32_t op, uint32_t arg, uint32_t allowed, int32_t n_vars,
                                  int64_t n_consts)
     {
-        if (op >= GP_N_OPS || !((allowed >> op) & 1u)) return GP_PROG_BAD_OP;
-        if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) return GP_PROG_BAD_VAR;
-        if (op == GP_CONST && (int64_t)arg >= n_consts) return GP_PROG_BAD_CONST;
-        const int need = op_is_binary(op) || op == GP_SWAP ? 2
-                         : (op == GP_LOAD || op == GP_CONST || op == GP_PASTE ? 0 : 1);
-        if (depth < need) return GP_PROG_UNDERFLOW;
-        if (op == GP_COPY) {
-            if (arg >= GP_GCL_VARS || ((held >> arg) & 1u)) return GP_PROG_BAD_PAIR;
-            copy(arg);
-        } else if (op == GP_PASTE) {
-            if (arg >= GP_GCL_VARS || !((held >> arg) & 1u)) return GP_PROG_BAD_PAIR;
-            paste(arg);
+        if (op < GP_DUP) {
+            // the benchmark set: leaves push, binary ops pop one, unary ops
+            // keep the depth
+            if (!((allowed >> op) & 1u)) return GP_PROG_BAD_OP;
+            if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) return GP_PROG_BAD_VAR;
+            if (op == GP_CONST && (int64_t)arg >= n_consts) return GP_PROG_BAD_CONST;
+            if (depth < (op <= GP_CONST ? 0 : (op <= GP_DIV ? 2 : 1))) return GP_PROG_UNDERFLOW;
+            depth += op <= GP_CONST ? 1 : (op <= GP_DIV ? -1 : 0);
+        } else {
+            if (op >= GP_N_OPS || !((allowed >> op) & 1u)) return GP_PROG_BAD_OP;
+            const int need = op == GP_SWAP || op == GP_POW ? 2 : (op == GP_PASTE ? 0 : 1);
+            if (depth < need) return GP_PROG_UNDERFLOW;
+            if (op == GP_COPY) {
+                if (arg >= GP_GCL_VARS || ((held >> arg) & 1u)) return GP_PROG_BAD_PAIR;
+                copy(arg);
+            } else if (op == GP_PASTE) {
+                if (arg >= GP_GCL_VARS || !((held >> arg) & 1u)) return GP_PROG_BAD_PAIR;
+                paste(arg);
+            }
+            if (op == GP_PASTE || op == GP_DUP) ++depth;
+            else if (op == GP_POW || op == GP_DEL) --depth;
         }
-        if (op == GP_LOAD || op == GP_CONST || op == GP_PASTE || op == GP_DUP) ++depth;
-        else if (op_is_binary(op) || op == GP_DEL) --depth;
         if (depth + live > GP_MAX_STACK) return GP_PROG_TOO_DEEP;
         if (depth + live > maxd) maxd = depth + live;
         return GP_PROG_OK;
@@ -595,15 +605,16 @@ __device__ __forceinline__ float sqrt_raw(float x)
     return x < 0.f ? __builtin_nanf("") : sqrt_abs(x);
 }
 
-// One operator on one value, exactly as the interpreter computes it for a
-// case (used to fold constant subtrees while staging).
+// One operator of the benchmark set on one value, exactly as the
+// interpreter computes it for a case (used to fold constant subtrees while
+// staging; the commands beyond the set are not folded, so staging makes no
+// calls).
 __device__ __forceinline__ float binary_value(uint32_t op, float a, float b)
 {
     switch (op) {
     case GP_ADD: return a + b;
     case GP_SUB: return a - b;
     case GP_MUL: return a * b;
-    case GP_POW: return pow_value(a, b);
     default: return div_protected(a, b);
     }
 }
@@ -616,16 +627,6 @@ __device__ __forceinline__ float unary_value(uint32_t op, float x)
     case GP_EXP: return exp_value_inl(x);
     case GP_LOG: return log_protected(x);
     case GP_SQRT: return sqrt_abs(x);
-    case GP_SQUARE: return x * x;
-    case GP_SIGN: return -x;
-    case GP_CUBE: return cube_value(x);
-    case GP_CBRT: return cbrt_value(x);
-    case GP_TAN: return tan_value(x);
-    case GP_ASIN: return asin_value(x);
-    case GP_ACOS: return acos_value(x);
-    case GP_ATAN: return atan_value(x);
-    case GP_TANH: return tanh_value(x);
-    case GP_SQRT_RAW: return sqrt_raw(x);
     default: return fabsf(x);
     }
 }
@@ -773,14 +774,18 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
             }
             np = 0;
         };
+        // one flush site: before a variable, a move or a command that is
+        // not folded (the commands beyond the set; POW over two held
+        // constants), and when the held run is full
+        if ((op == GP_CONST && np == kHeldConsts) || op == GP_LOAD ||
+            (op >= GP_DUP && (op != GP_POW || np >= 2)))
+            flush();
         if (op == GP_CONST) {
-            if (np == kHeldConsts) flush();
             pv(np & (kHeldConsts - 1)) = consts(arg);
             ++np;
             continue;
         }
         if (op == GP_LOAD) {
-            flush();
             const uint32_t payload = arg * row_bytes;
             const uint32_t nx = k + 1 < e ? (nodes(k + 1) & 0xFFu) : 0xFFu;
             const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
@@ -827,7 +832,6 @@ __device__ int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, 
             continue;
         }
         // cell moves
-        flush();
         const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
         if (op == GP_DUP) {
             put(n++, staged_word(kFMove, kMvWrite, 0u, wr));
@@ -902,10 +906,12 @@ __device__ void check_program(Nodes nodes, int64_t s, int64_t e, uint32_t allowe
         } else if (taken) {
             taken = false;                    // folded into the variable
         } else if (op_is_binary(op)) {
+            if (np >= 2 && op == GP_POW) { n_st += np; np = 0; }   // pushed, not folded
             if (np >= 2) --np;
             else if (np == 1) { np = 0; ++n_st; }
             else ++n_st;
         } else if (op_is_unary(op)) {
+            if (op > GP_ABS) { n_st += np; np = 0; }               // pushed, not folded
             if (np == 0) ++n_st;
         } else {
             n_st += np;                       // flush, then the cell move
