@@ -146,8 +146,10 @@ def test_empty_stack_moves():
 
 
 def test_constant_folding_through_moves():
-    """Constants held back for folding are pushed before a move; folded
-    subtrees with the new commands give the per-case bits."""
+    """Constants held back for folding are pushed before a move and before
+    a command beyond the benchmark set (not folded); either way the values
+    equal those of the same programs reading the constants from input
+    rows, bit for bit."""
     gp = _gp()
     L = lambda i: LOAD | (i << 8)
     C = lambda i: CONST | (i << 8)
