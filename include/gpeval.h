@@ -153,6 +153,8 @@ int gp_validate(const uint32_t* nodes, const int64_t* offsets, int64_t n_program
  * synchronized.  Inputs must stay alive until then.  The library keeps a
  * per-(device, stream) workspace that grows on demand; concurrent calls on
  * one stream from several host threads are not supported.
+ * allowed_op_mask: within GP_BASE_OPS (0 means GP_BASE_OPS; any other bit
+ * is GP_E_INVALID_ARG).
  * Determinism: a program's result depends only on the program, the data and
  * n_cases, never on the rest of the population.
  */
@@ -296,6 +298,8 @@ int gp_eval_batched(const gp_request* requests_dev, int32_t n_requests,
  * out: float32, out[p * ld_out + i] for i < n_cases, ld_out >= n_cases,
  * caller-owned device memory of n_programs * ld_out floats.  Values are the
  * fp32 results of the same interpreter gp_eval runs (NaN and +-inf kept).
+ * allowed_op_mask may reach beyond GP_BASE_OPS (0 means GP_ALL_OPS): then
+ * the interpreter built for the whole command table runs.
  * Programs that fail validation get a NaN row and a nonzero out_status.
  * Asynchronous on `stream`; shares gp_eval's per-stream workspace.
  */
@@ -392,7 +396,7 @@ typedef struct {
     int32_t max_batch_chunks;       /* chunks per launch, 1..4096 (0: 1024) */
     int32_t one_launch_per_request; /* 1: FIFO, one gp_eval per request on one
                                        stream, no chunking (comparison mode) */
-    uint32_t allowed_op_mask;       /* 0: GP_ALL_OPS */
+    uint32_t allowed_op_mask;       /* within GP_BASE_OPS (0: GP_BASE_OPS) */
 } gp_server_config;
 
 typedef struct {

@@ -1,32 +1,39 @@
 // gpeval.hip -- gfx950 kernels and C ABI of the batched fitness evaluator.
 //
-// Path of one gp_eval call (all on the caller's stream):
+// Path of one scoring call (all on the caller's stream):
 //   k_tables         one workgroup: check the dataset and request tables, lay
 //                    the requests out back to back, derive tile shapes.
-//   k_validate       one thread per program: validate (GCL stack discipline,
-//                    32-element limit, opcode/operand ranges, allowed ops),
-//                    count staged instructions, depth class and partition
-//                    key; per-block key counts and staged sizes.
+//   k_validate       one thread per program: validate (GCL stack and
+//                    variable discipline, 32-cell limit, opcode/operand
+//                    ranges, allowed ops), count staged instructions, depth
+//                    class and partition key; per-block key counts and
+//                    staged sizes.
 //   k_class_scan     one workgroup: scans of both; class ranges.
-//   k_stage          one thread per program: stage each instruction as 16
-//                    bytes {flags | op, payload, read slot or leaf kind,
-//                    write slot} at a range of its own, folding a leaf into
-//                    the operator after it; stable scatter of program ids by
+//   k_stage          one thread per program: stage each instruction as one
+//                    8-byte word {flags | selector | slot, payload} at a
+//                    range of its own, folding constant subtrees and a leaf
+//                    into the operator after it (stack moves and variables
+//                    become cell moves); stable scatter of program ids by
 //                    (depth class, length band): each depth class (max
 //                    depth <= 8, <= 16, <= 32) runs a kernel whose register
 //                    stack is only as deep as needed, longest programs first.
 //   k_seg_count /    per (class, request): program counts, positions and
 //   k_seg_scan       work-item prefixes.
-//   k_eval<MAXD,K>   persistent workgroups pull (program group, case tile)
+//   k_eval<MAXD,K,FIT> persistent workgroups pull (program group, case tile)
 //                    items from an atomic counter; the tile's inputs and
 //                    targets are staged in LDS; each wavefront takes the
 //                    group's programs one at a time and runs one over the
 //                    64*K cases of the sub-tile (K per lane) with the value
-//                    stack in VGPRs; residual, scaled square and compensated
-//                    (TwoSum) accumulation are fused; a wave shuffle tree
-//                    gives one {hi, lo, bad} partial per (program, tile).
-//   k_reduce         one thread per program: fp64 sum of its tile partials
-//                    in fixed order, unscaling, tax, classification.
+//                    stack in VGPRs; the fitness epilogue is fused (MSE:
+//                    scaled square with TwoSum accumulation; correlation:
+//                    double-double sums over valid pairs; integer reward:
+//                    int64 per case) and a wave shuffle tree gives one
+//                    partial per (program, tile).
+//   k_reduce[_corr|_reward]  one thread per program: its tile partials in
+//                    fixed order, then the score.
+// gp_predict runs the same staging and k_predict<MAXD,K,EXT> (per-case
+// outputs; EXT: the interpreter for the whole command table); gp_mc_rank
+// runs k_rank_sample and k_rank_assign.
 //
 // Semantics follow the paper's GCL section (RPN stack machine, 32-element
 // stack, command table operand order) and the protected-operator readings
