@@ -175,13 +175,14 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
  * over the valid pairs (0 below two valid pairs or for a constant output or
  * target); out_score = M (r^2)^2 (N - (c1 + c2)) - M (c1 - c2), M =
  * max_score (the paper's maximum score; higher is better).  Invalid
- * programs get NaN and their GP_PROG_* status.  The sums are per-lane
- * double-double (f, f^2, f*y) and fp64 (y, y^2) over the case tiles, merged
- * in a fixed order: results are deterministic and independent of the rest
- * of the population.  Returns GP_E_INVALID_ARG for a non-finite max_score;
- * other errors as gp_eval.  The workspace's partial buffer takes 72 bytes
- * per (program, tile) instead of 9 (gp_workspace_size reports the MSE
- * layout).
+ * programs get NaN and their GP_PROG_* status.  The sums are fp64 sums of
+ * shifted values (f - s, (f - s)^2, y - t, (y - t)^2, (f - s)(y - t), the
+ * shift (s, t) one valid pair of the data) over the case tiles, merged in a
+ * fixed order with exact shift changes: results are deterministic and
+ * independent of the rest of the population.  Returns GP_E_INVALID_ARG for
+ * a non-finite max_score; other errors as gp_eval.  The workspace's partial
+ * buffer takes 80 bytes per (program, tile) instead of 9
+ * (gp_workspace_size reports the MSE layout).
  */
 int gp_eval_correlation(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
                         int64_t n_nodes, const float* consts, int64_t n_consts,

@@ -1606,49 +1606,51 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
 
 // ------------------------------------------------- correlation fitness
 // Per (program, tile) sums of the correlation fitness (Eq. 1-2) over the
-// valid pairs (output and target both finite): the sums of f, f^2 and f*y
-// as double-double values (every product of two fp32 values is exact in
-// fp64, so only the additions round), the sums of y and y^2 in fp64, and
-// the counts of pairs with one (c1) or both (c2) sides invalid.  The
-// centred sums are formed once per program from these, in double-double,
-// so the cancellation of a large mean costs nothing visible.
+// valid pairs (output and target both finite), kept about a shift (s, t)
+// that is itself one valid pair of the data, so a large mean cancels before
+// anything is squared: n valid pairs, Sd = sum (f - s), Sdd = sum (f - s)^2,
+// Se = sum (y - t), See = sum (y - t)^2, Sde = sum (f - s)(y - t) in fp64,
+// and the pairs with one (c1) or both (c2) sides invalid.  A wavefront
+// shares one shift per (program, window), so its lanes add plainly; windows
+// and tiles merge by the exact shift-change identities, in a fixed order.
 struct CorrPart {
-    double f_hi, f_lo, ff_hi, ff_lo, fy_hi, fy_lo;
-    double y, yy;
-    int32_t c1, c2;
+    double s, t, sd, sdd, se, see, sde;
+    int64_t n, c1, c2;
 };
-static_assert(sizeof(CorrPart) == 72, "CorrPart layout");
+static_assert(sizeof(CorrPart) == 80, "CorrPart layout");
+
+// one lane's sums over its cases of a window (the shift is the wavefront's)
+struct CorrLane {
+    double sd, sdd, se, see, sde;
+    int32_t n, c1, c2;
+};
 
 enum : int { kFitMse = 0, kFitCorr = 1, kFitReward = 2 };
 constexpr int kCorrMaxG = 32;            // programs per work item in correlation mode (LDS)
 
-// hi + lo += x (Knuth's two-sum on the high part, errors gathered in lo)
-__device__ __forceinline__ void dd_add_d(double& hi, double& lo, double x)
-{
-    const double s = hi + x;
-    const double bp = s - hi;
-    lo += (hi - (s - bp)) + (x - bp);
-    hi = s;
-}
-
 __device__ __forceinline__ void corr_zero(CorrPart& c)
 {
-    c.f_hi = c.f_lo = c.ff_hi = c.ff_lo = c.fy_hi = c.fy_lo = 0.0;
-    c.y = c.yy = 0.0;
-    c.c1 = c.c2 = 0;
+    c.s = c.t = c.sd = c.sdd = c.se = c.see = c.sde = 0.0;
+    c.n = c.c1 = c.c2 = 0;
+}
+__device__ __forceinline__ void corr_zero(CorrLane& c)
+{
+    c.sd = c.sdd = c.se = c.see = c.sde = 0.0;
+    c.n = c.c1 = c.c2 = 0;
 }
 
-// one case: f the program's output, y the target
-__device__ __forceinline__ void corr_case(CorrPart& c, float f, float y)
+// one case: f the program's output, y the target, (s, t) the shift
+__device__ __forceinline__ void corr_case(CorrLane& c, float f, float y, double s, double t)
 {
     const bool fv = __builtin_isfinite(f), yv = __builtin_isfinite(y);
     if (fv && yv) {
-        const double fd = (double)f, yd = (double)y;
-        dd_add_d(c.f_hi, c.f_lo, fd);
-        dd_add_d(c.ff_hi, c.ff_lo, fd * fd);
-        dd_add_d(c.fy_hi, c.fy_lo, fd * yd);
-        c.y += yd;
-        c.yy += yd * yd;
+        const double d = (double)f - s, e = (double)y - t;
+        c.sd += d;
+        c.sdd = fma(d, d, c.sdd);
+        c.se += e;
+        c.see = fma(e, e, c.see);
+        c.sde = fma(d, e, c.sde);
+        ++c.n;
     } else if (fv != yv) {
         ++c.c1;
     } else {
@@ -1678,45 +1680,44 @@ __device__ __forceinline__ long long pair_reward(float o, float y, float M, int 
     return (long long)rintf(v);
 }
 
-// a += b (fixed order: the result depends only on the two operands)
+// a += b (fixed order: the result depends only on the two operands).  b's
+// sums move to a's shift: with dl = b.s - a.s and el = b.t - a.t,
+// sum (f - a.s) = Sd + n dl, sum (f - a.s)^2 = Sdd + dl (2 Sd + n dl),
+// sum (f - a.s)(y - a.t) = Sde + dl Se + el (Sd + n dl), and likewise in y.
 __device__ __forceinline__ void corr_merge(CorrPart& a, const CorrPart& b)
 {
-    dd_add_d(a.f_hi, a.f_lo, b.f_hi);
-    a.f_lo += b.f_lo;
-    dd_add_d(a.ff_hi, a.ff_lo, b.ff_hi);
-    a.ff_lo += b.ff_lo;
-    dd_add_d(a.fy_hi, a.fy_lo, b.fy_hi);
-    a.fy_lo += b.fy_lo;
-    a.y += b.y;
-    a.yy += b.yy;
     a.c1 += b.c1;
     a.c2 += b.c2;
+    if (b.n == 0) return;
+    if (a.n == 0) {
+        a.s = b.s; a.t = b.t;
+        a.sd = b.sd; a.sdd = b.sdd; a.se = b.se; a.see = b.see; a.sde = b.sde;
+        a.n = b.n;
+        return;
+    }
+    const double dl = b.s - a.s, el = b.t - a.t, nb = (double)b.n;
+    a.sdd += b.sdd + dl * (2.0 * b.sd + nb * dl);
+    a.see += b.see + el * (2.0 * b.se + nb * el);
+    a.sde += b.sde + dl * b.se + el * (b.sd + nb * dl);
+    a.sd += b.sd + nb * dl;
+    a.se += b.se + nb * el;
+    a.n += b.n;
 }
 
-// wavefront tree: every lane ends with the same sums
-__device__ __forceinline__ void corr_wave_reduce(CorrPart& c)
+// wavefront tree: every lane ends with the same sums (one shared shift,
+// and fp64 addition is commutative, so both lanes of a pair agree)
+__device__ __forceinline__ void corr_wave_reduce(CorrLane& c)
 {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
-        CorrPart o;
-        o.f_hi = __shfl_xor(c.f_hi, off);
-        o.f_lo = __shfl_xor(c.f_lo, off);
-        o.ff_hi = __shfl_xor(c.ff_hi, off);
-        o.ff_lo = __shfl_xor(c.ff_lo, off);
-        o.fy_hi = __shfl_xor(c.fy_hi, off);
-        o.fy_lo = __shfl_xor(c.fy_lo, off);
-        o.y = __shfl_xor(c.y, off);
-        o.yy = __shfl_xor(c.yy, off);
-        o.c1 = __shfl_xor(c.c1, off);
-        o.c2 = __shfl_xor(c.c2, off);
-        // the lower lane's sums first, so both lanes of a pair compute the
-        // same bits
-        if ((__lane_id() & off) == 0) {
-            corr_merge(c, o);
-        } else {
-            corr_merge(o, c);
-            c = o;
-        }
+        c.sd += __shfl_xor(c.sd, off);
+        c.sdd += __shfl_xor(c.sdd, off);
+        c.se += __shfl_xor(c.se, off);
+        c.see += __shfl_xor(c.see, off);
+        c.sde += __shfl_xor(c.sde, off);
+        c.n += __shfl_xor(c.n, off);
+        c.c1 += __shfl_xor(c.c1, off);
+        c.c2 += __shfl_xor(c.c2, off);
     }
 }
 
@@ -1836,8 +1837,10 @@ __global__ __launch_bounds__(kWG) void k_eval(
                 // (MSE), or the sums of the correlation fitness
                 float hi = 0.f, lo_ = 0.f;
                 bool bad = false;
-                CorrPart cl;
+                CorrLane cl;
                 if constexpr (FIT == kFitCorr) corr_zero(cl);
+                double cs = 0.0, ct = 0.0;                // the wavefront's shift
+                bool have_shift = false;
                 long long rl = 0;
                 for (int b = 0; b < nw; ++b) {
                     const float* blk = xt + b * rows * SUB;
@@ -1845,12 +1848,33 @@ __global__ __launch_bounds__(kWG) void k_eval(
                     run_program<MAXD, K, false>(code + m.start, blk + lane, tos);
                     const int64_t base = (first + b) * SUB;
                     const float* yt = blk + n_vars * SUB;
+                    if constexpr (FIT == kFitCorr) {
+                        // the shift: the window's first valid pair, in the
+                        // order (sub-tile, j, lane)
+#pragma unroll
+                        for (int j = 0; j < K; ++j) {
+                            if (!have_shift) {
+                                const float yj = yt[lane + j * 64];
+                                const bool v = base + lane + j * 64 < n_cases &&
+                                               __builtin_isfinite(tos[j]) && __builtin_isfinite(yj);
+                                const unsigned long long mk = __ballot(v);
+                                if (mk != 0ull) {
+                                    const int src = __builtin_ctzll(mk);
+                                    cs = (double)__int_as_float(__builtin_amdgcn_readlane(
+                                        __float_as_int(tos[j]), src));
+                                    ct = (double)__int_as_float(__builtin_amdgcn_readlane(
+                                        __float_as_int(yj), src));
+                                    have_shift = true;
+                                }
+                            }
+                        }
+                    }
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
                         if (base + lane + j * 64 < n_cases) {
                             const float f = tos[j];
                             if constexpr (FIT == kFitCorr) {
-                                corr_case(cl, f, yt[lane + j * 64]);
+                                corr_case(cl, f, yt[lane + j * 64], cs, ct);
                             } else if constexpr (FIT == kFitReward) {
                                 rl += pair_reward(f, yt[lane + j * 64], a.reward_M,
                                                   a.reward_power);
@@ -1868,7 +1892,14 @@ __global__ __launch_bounds__(kWG) void k_eval(
                 if constexpr (FIT == kFitCorr) {
                     corr_wave_reduce(cl);
                     // the windows add up in order, whichever wavefront ran them
-                    if (lane == 0) corr_merge(cacc[g], cl);
+                    if (lane == 0) {
+                        CorrPart w;
+                        w.s = cs; w.t = ct;
+                        w.sd = cl.sd; w.sdd = cl.sdd; w.se = cl.se; w.see = cl.see;
+                        w.sde = cl.sde;
+                        w.n = cl.n; w.c1 = cl.c1; w.c2 = cl.c2;
+                        corr_merge(cacc[g], w);
+                    }
                 } else if constexpr (FIT == kFitReward) {
                     // integers: exact in any order
 #pragma unroll
@@ -2020,41 +2051,11 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
     R.out[q] = (bad || !(mse <= (double)FLT_MAX)) ? __builtin_inf() : mse + D.tax * (double)m.len;
 }
 
-// Double-double helpers for the final centred sums (Dekker's product via
-// fma, Knuth's two-sum).
-struct DDv { double hi, lo; };
-__device__ __forceinline__ DDv dd_norm(double hi, double lo)
-{
-    const double s = hi + lo;
-    return DDv{s, lo - (s - hi)};
-}
-__device__ __forceinline__ DDv dd_add(DDv a, DDv b)
-{
-    const double s = a.hi + b.hi;
-    const double bp = s - a.hi;
-    const double e = (a.hi - (s - bp)) + (b.hi - bp);
-    return dd_norm(s, e + a.lo + b.lo);
-}
-__device__ __forceinline__ DDv dd_neg(DDv a) { return DDv{-a.hi, -a.lo}; }
-__device__ __forceinline__ DDv dd_mul(DDv a, DDv b)
-{
-    const double p = a.hi * b.hi;
-    const double e = fma(a.hi, b.hi, -p);
-    return dd_norm(p, e + (a.hi * b.lo + a.lo * b.hi));
-}
-__device__ __forceinline__ DDv dd_div_d(DDv a, double d)
-{
-    const double q1 = a.hi / d;
-    const DDv r = dd_add(a, dd_neg(dd_mul(DDv{q1, 0.0}, DDv{d, 0.0})));
-    return dd_norm(q1, (r.hi + r.lo) / d);
-}
-
 // Correlation score per program (Eq. 2 with r of Eq. 1 over the valid
-// pairs): the tiles' sums in order, then the centred sums
-// Sxx = S(f^2) - S(f)^2/n, Sxy = S(fy) - S(f)S(y)/n, Syy = S(y^2) - S(y)^2/n
-// in double-double.  r = 0 below two valid pairs, or when a centred sum
-// of squares is zero (below 2^-80 of its raw sum: a constant output or
-// target, whose double-double difference is a rounding residue).
+// pairs): the tiles' shifted sums merged in order, then the centred sums
+// Sxx = Sdd - Sd^2/n, Sxy = Sde - Sd Se/n, Syy = See - Se^2/n.  r = 0 below
+// two valid pairs, or when a centred sum of squares is not positive (a
+// constant output or target gives exactly zero: every shifted value is 0).
 __global__ __launch_bounds__(256) void k_reduce_corr(ReduceArgs a)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2067,30 +2068,19 @@ __global__ __launch_bounds__(256) void k_reduce_corr(ReduceArgs a)
     if (c >= kKeys) { R.out[q] = __builtin_nan(""); return; }
     const DevDataset& D = a.ds[R.dataset];
     const int nt = D.n_tiles[c / kLenBuckets];
-    DDv sf{0.0, 0.0}, sff{0.0, 0.0}, sfy{0.0, 0.0};
-    double sy = 0.0, syy = 0.0;
-    int64_t c1 = 0, c2 = 0;
-    for (int t = 0; t < nt; ++t) {
-        const CorrPart v = a.part_corr[p * a.part_stride + t];
-        sf = dd_add(sf, DDv{v.f_hi, v.f_lo});
-        sff = dd_add(sff, DDv{v.ff_hi, v.ff_lo});
-        sfy = dd_add(sfy, DDv{v.fy_hi, v.fy_lo});
-        sy += v.y;
-        syy += v.yy;
-        c1 += v.c1;
-        c2 += v.c2;
-    }
-    const int64_t N = D.n_cases;
-    const int64_t n = N - c1 - c2;
+    CorrPart acc;
+    corr_zero(acc);
+    for (int t = 0; t < nt; ++t) corr_merge(acc, a.part_corr[p * a.part_stride + t]);
+    const int64_t n = acc.n, c1 = acc.c1, c2 = acc.c2;
     double rr = 0.0;
     if (n >= 2) {
+        // centred sums from the shifted ones (the shift is a data value, so
+        // these subtract quantities of the size of the spread)
         const double dn = (double)n;
-        const DDv Y{sy, 0.0};
-        const DDv sxx = dd_add(sff, dd_neg(dd_div_d(dd_mul(sf, sf), dn)));
-        const DDv sxy = dd_add(sfy, dd_neg(dd_div_d(dd_mul(sf, Y), dn)));
-        const DDv syy2 = dd_add(DDv{syy, 0.0}, dd_neg(dd_div_d(dd_mul(Y, Y), dn)));
-        const double vx = sxx.hi + sxx.lo, vy = syy2.hi + syy2.lo;
-        if (vx > 0x1p-80 * sff.hi && vy > 0x1p-80 * syy) rr = (sxy.hi + sxy.lo) / sqrt(vx * vy);
+        const double vx = acc.sdd - acc.sd * (acc.sd / dn);
+        const double vy = acc.see - acc.se * (acc.se / dn);
+        const double vxy = acc.sde - acc.sd * (acc.se / dn);
+        if (vx > 0.0 && vy > 0.0) rr = vxy / sqrt(vx * vy);
     }
     const double r2 = rr * rr;
     R.out[q] = a.max_score * r2 * r2 * (double)n - a.max_score * (double)(c1 - c2);
