@@ -26,7 +26,7 @@
 //                    64*K cases of the sub-tile (K per lane) with the value
 //                    stack in VGPRs; the fitness epilogue is fused (MSE:
 //                    scaled square with TwoSum accumulation; correlation:
-//                    double-double sums over valid pairs; integer reward:
+//                    shifted fp64 sums over valid pairs; integer reward:
 //                    int64 per case) and a wave shuffle tree gives one
 //                    partial per (program, tile).
 //   k_reduce[_corr|_reward]  one thread per program: its tile partials in
