@@ -108,6 +108,16 @@ def oracle_threads(n_programs):
     return max(1, min(os.cpu_count() or 1, 256, n_programs))
 
 
+def kernel_source_digest():
+    """SHA-256 over the kernel sources (gpeval.hip, then staging.h)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("gpeval.hip", "staging.h"):
+        with open(os.path.join(ROOT, "paper_2607_06731_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_counters(workload):
     """Counter figures of the dominant kernel (HBM bytes per launch, VALU busy
     fraction, VALU lane-slots per node evaluation, scalar instructions per
@@ -119,10 +129,9 @@ def measured_counters(workload):
     if workload != "generation":
         return {}
     summary = os.path.join(ROOT, "profiles", "k_eval_generation_counters.md")
-    src = os.path.join(ROOT, "paper_2607_06731_amd", "csrc", "gpeval.hip")
     try:
         text = open(summary).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        digest = kernel_source_digest()
     except OSError:
         return {}
     m = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)

@@ -1,0 +1,199 @@
+// Host harness for the library's staging walk (paper_2607_06731_amd/csrc/
+// staging.h), built by tests/test_staging_host.py with the host compiler.
+//
+// TEST INFRASTRUCTURE.  For every program of an input population it runs
+// the library's check_program (status, maximum depth, staged-instruction
+// count) and stage_walk (the staged words, depth class picked from the
+// maximum depth as the device does), then evaluates the staged words on
+// each case with a plain evaluator of the staged format written here: one
+// value per case, the stack cells in an array indexed by the staged cell
+// numbers.  The folding functions are the host's fp32 operations (exact for
+// + - * / and |a|, library functions otherwise).
+//
+// Input (binary, little endian): int64 P, n_nodes, n_consts, n_vars, n_cases;
+// uint32 nodes[n_nodes]; int64 offsets[P + 1]; float consts[n_consts];
+// float X[n_vars][n_cases].
+// Output: per program int64 {status, max_depth, counted, emitted,
+// end_flag_ok, within_nodes}; then float out[P][n_cases] (NaN for invalid
+// programs).
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#define __host__
+#define __device__
+#include "gpeval.h"
+
+// uint2 and make_uint2 come with the HIP headers gpeval.h includes
+static inline uint32_t __float_as_uint(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+typedef float lds_f32;
+constexpr int kHeldConsts = 16;
+constexpr int kBucketBlock = 1;        // one program per "block": held constant i at pvs[i]
+
+static inline float div_protected(float a, float b) { return fabsf(b) <= 0.001f ? 1.f : a / b; }
+static inline float binary_value(uint32_t op, float a, float b)
+{
+    switch (op) {
+    case GP_ADD: return a + b;
+    case GP_SUB: return a - b;
+    case GP_MUL: return a * b;
+    default: return div_protected(a, b);
+    }
+}
+static inline float unary_value(uint32_t op, float x)
+{
+    switch (op) {
+    case GP_SIN: return sinf(x);
+    case GP_COS: return cosf(x);
+    case GP_EXP: return expf(x);
+    case GP_LOG: return fabsf(x) <= 0.001f ? 0.f : logf(fabsf(x));
+    case GP_SQRT: return sqrtf(fabsf(x));
+    default: return fabsf(x);
+    }
+}
+
+#define GP_STAGING_FN
+#include "staging.h"
+
+struct Nodes {
+    const uint32_t* p;
+    uint32_t operator()(int64_t k) const { return p[k]; }
+};
+struct Consts {
+    const float* p;
+    float operator()(uint32_t j) const { return p[j]; }
+};
+
+static float unary_sel(uint32_t sel, float x)
+{
+    switch (sel) {
+    case 0: return sinf(x);
+    case 1: return cosf(x);
+    case 2: return expf(x);
+    case 3: return fabsf(x) <= 0.001f ? 0.f : logf(fabsf(x));
+    case 4: return sqrtf(fabsf(x));
+    case 5: return fabsf(x);
+    case 6: return x * x;
+    case 7: return -x;
+    case 8: return (float)((double)x * (double)x * (double)x);
+    case 9: return cbrtf(x);
+    case 10: return tanf(x);
+    case 11: return asinf(x);
+    case 12: return acosf(x);
+    case 13: return atanf(x);
+    case 14: return tanhf(x);
+    default: return x < 0.f ? NAN : sqrtf(x);
+    }
+}
+static float binary_sel(uint32_t sel, float a, float b)
+{
+    switch (sel) {
+    case 0: return a + b;
+    case 1: return a - b;
+    case 2: return a * b;
+    case 3: return div_protected(a, b);
+    default: return powf(a, b);
+    }
+}
+
+template <class T> static bool rd(FILE* f, T* p, size_t n) { return fread(p, sizeof(T), n, f) == n; }
+
+int main(int argc, char** argv)
+{
+    if (argc != 3) return 2;
+    FILE* in = fopen(argv[1], "rb");
+    if (!in) return 2;
+    int64_t hd[5];
+    if (!rd(in, hd, 5)) return 2;
+    const int64_t P = hd[0], NN = hd[1], NCo = hd[2], NV = hd[3], NC = hd[4];
+    std::vector<uint32_t> nodes(NN + 1);
+    std::vector<int64_t> off(P + 1);
+    std::vector<float> consts(NCo + 1), X(NV * NC + 1);
+    if (!rd(in, nodes.data(), NN) || !rd(in, off.data(), P + 1) || !rd(in, consts.data(), NCo) ||
+        !rd(in, X.data(), NV * NC))
+        return 2;
+    fclose(in);
+    std::vector<int64_t> info(P * 6, 0);
+    std::vector<float> out(P * NC, NAN);
+    const uint32_t row_bytes = 4;              // a variable leaf's payload is 4 * index here
+    for (int64_t p = 0; p < P; ++p) {
+        int status = GP_PROG_OK, maxd = 0;
+        int64_t counted = 0;
+        check_program(Nodes{nodes.data()}, off[p], off[p + 1], GP_ALL_OPS, (int32_t)NV, NCo,
+                      status, maxd, counted);
+        int64_t* I = &info[p * 6];
+        I[0] = status;
+        I[1] = maxd;
+        I[2] = counted;
+        if (status != GP_PROG_OK) continue;
+        const uint32_t J = 32u / (uint32_t)(maxd <= 8 ? 8 : (maxd <= 16 ? 16 : 32));
+        std::vector<uint2> code(counted + 1, make_uint2(0u, 0u));
+        float pvs[kHeldConsts];
+        const int64_t n = stage_walk(Nodes{nodes.data()}, off[p], off[p + 1],
+                                     Consts{consts.data()}, J, row_bytes, code.data(), counted,
+                                     pvs);
+        I[3] = n;
+        bool flag_ok = n > 0 && n <= counted;
+        for (int64_t k = 0; k < n && k < counted; ++k)
+            flag_ok = flag_ok && (((code[k].x & kFLast) != 0) == (k == n - 1));
+        I[4] = flag_ok;
+        I[5] = n <= off[p + 1] - off[p];
+        if (!flag_ok) continue;
+        const uint32_t mask = 32u - J;
+        for (int64_t c = 0; c < NC; ++c) {
+            float cells[32];
+            for (float& v : cells) v = NAN;
+            float top = NAN;
+            auto leaf = [&](bool is_const, uint32_t pay) {
+                if (is_const) {
+                    float v;
+                    memcpy(&v, &pay, 4);
+                    return v;
+                }
+                return X[(int64_t)(pay / row_bytes) * NC + c];
+            };
+            int64_t k = 0;
+            uint32_t f;
+            do {
+                const uint2 w = code[k++];
+                f = w.x;
+                const uint32_t sel = (f >> 8) & 0xFu, cell = (f >> 16) & 31u;
+                if (f & kFUn) {
+                    if (f & kFPush) {
+                        cells[cell] = top;
+                        top = leaf(f & kFConst, w.y);
+                    }
+                    top = unary_sel(sel, top);
+                } else if (f & kFSBin) {
+                    top = binary_sel(sel, cells[cell], top);
+                } else if (f & kFLBin) {
+                    top = binary_sel(sel, top, leaf(f & kFConst, w.y));
+                } else if (f & kFMove) {
+                    const uint32_t rs = cell & mask, ws = w.y & mask;
+                    float t = top;
+                    if (sel & kMvRead) t = cells[rs];
+                    if (sel & kMvWrite) cells[ws] = top;
+                    if (sel & kMvTop) top = t;
+                    if (sel & kMvCompact) cells[(w.y >> 16) & mask] = cells[(w.y >> 8) & mask];
+                } else {
+                    cells[cell] = top;
+                    top = leaf(f & kFConst, w.y);
+                }
+            } while (!(f & kFLast));
+            out[p * NC + c] = top;
+        }
+    }
+    FILE* o = fopen(argv[2], "wb");
+    if (!o) return 2;
+    fwrite(info.data(), sizeof(int64_t), info.size(), o);
+    fwrite(out.data(), sizeof(float), out.size(), o);
+    fclose(o);
+    return 0;
+}
