@@ -962,7 +962,7 @@ __global__ __launch_bounds__(64) void k_seg_scan(const int32_t* __restrict__ seg
 struct EvalConst {
     int32_t cls;
     int32_t G;              // programs per work item
-    int32_t part_stride;
+    int32_t part_stride;    // partial of (program p, tile t) at t * part_stride + p
     int32_t max_vars;       // largest n_vars of the call
     int32_t n_seg;
     int32_t tile_floats;    // LDS floats for input windows
@@ -1610,7 +1610,8 @@ __global__ __launch_bounds__(kWG) void k_eval(
         }
         if (tid < gn) {
             const int pid = order[obase + tid];
-            const int64_t slot = (int64_t)pid * a.part_stride + tile;
+            // tile-major partials: the reduction reads neighbours' together
+            const int64_t slot = (int64_t)tile * a.part_stride + pid;
             if constexpr (FIT == kFitCorr) {
                 part_corr[slot] = cacc[tid];
             } else if constexpr (FIT == kFitReward) {
@@ -1705,7 +1706,7 @@ struct ReduceArgs {
     const uint8_t* part_bad;
     const CorrPart* part_corr;
     int64_t n_programs;
-    int32_t part_stride;
+    int32_t part_stride;    // tile stride of the partials (the program count)
     double max_score;
 };
 
@@ -1725,9 +1726,9 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
     double s = 0.0;
     bool bad = false;
     for (int t = 0; t < nt; ++t) {
-        const float2 v = a.part[p * a.part_stride + t];
+        const float2 v = a.part[(int64_t)t * a.part_stride + p];
         s += (double)v.x + (double)v.y;
-        bad |= a.part_bad[p * a.part_stride + t] != 0;
+        bad |= a.part_bad[(int64_t)t * a.part_stride + p] != 0;
     }
     const double mse = s * D.unscale;
     R.out[q] = (bad || !(mse <= (double)FLT_MAX)) ? __builtin_inf() : mse + D.tax * (double)m.len;
@@ -1752,7 +1753,7 @@ __global__ __launch_bounds__(256) void k_reduce_corr(ReduceArgs a)
     const int nt = D.n_tiles[c / kLenBuckets];
     CorrPart acc;
     corr_zero(acc);
-    for (int t = 0; t < nt; ++t) corr_merge(acc, a.part_corr[p * a.part_stride + t]);
+    for (int t = 0; t < nt; ++t) corr_merge(acc, a.part_corr[(int64_t)t * a.part_stride + p]);
     const int64_t n = acc.n, c1 = acc.c1, c2 = acc.c2;
     double rr = 0.0;
     if (n >= 2) {
@@ -1784,7 +1785,7 @@ __global__ __launch_bounds__(256) void k_reduce_reward(ReduceArgs a)
     const int nt = D.n_tiles[c / kLenBuckets];
     const long long* part = reinterpret_cast<const long long*>(a.part);
     long long s = 0;
-    for (int t = 0; t < nt; ++t) s += part[p * a.part_stride + t];
+    for (int t = 0; t < nt; ++t) s += part[(int64_t)t * a.part_stride + p];
     R.out[q] = (double)s;
 }
 
@@ -2245,7 +2246,7 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
 
     EvalConst ea{};
     ea.G = group_capacity(pb, tu);
-    ea.part_stride = el.stride;
+    ea.part_stride = (int32_t)pb.n_programs;      // tile stride of the partials
     ea.max_vars = pb.max_vars;
     ea.n_seg = pb.n_req;
     ea.reward_power = pb.reward_power;
@@ -2291,7 +2292,7 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
     ra.meta = st.meta; ra.cls = st.cls; ra.pds = st.pds; ra.reqs = st.req;
     ra.seg_start = st.seg_start; ra.ds = st.ds;
     ra.part = st.part; ra.part_bad = st.part_bad; ra.part_corr = st.part_corr;
-    ra.n_programs = pb.n_programs; ra.part_stride = el.stride;
+    ra.n_programs = pb.n_programs; ra.part_stride = (int32_t)pb.n_programs;
     ra.max_score = pb.max_score;
     if ((rc = ce.mark(4, stream)) != GP_OK) return rc;
     if (pb.fit == kFitCorr)
