@@ -13,9 +13,13 @@
  *
  *   F(p)       = +inf                     if invalid(p)
  *              = MSE(p) + tau * len(p)    otherwise
- *   MSE(p)     = (1/n) * sum_i (f_p(x_i) - y_i)^2         (fp64, plain loop)
- *   invalid(p) = some f_p(x_i) is NaN or +-inf, or MSE(p) > FLT_MAX
+ *   MSE(p)     = (1/n) * sum over valid pairs i of (f_p(x_i) - y_i)^2
+ *                                                        (fp64, plain loop)
+ *   invalid(p) = for some case exactly one of f_p(x_i), y_i is NaN or
+ *                +-inf, or MSE(p) > FLT_MAX
  *   f_p(x_i)   = postfix (RPN) evaluation of p on case i
+ *   a valid pair is a case whose output and target are both finite; a case
+ *   where both are NaN/inf is a matched invalid pair and adds nothing
  *
  * Sources in the paper:
  *   - RPN stack machine: unary ops replace the top element, binary ops replace
@@ -23,9 +27,13 @@
  *   - Stack limit of 32 elements (same section, StackSize).
  *   - Op semantics and operand order: SUB is second-top minus top, DIV is
  *     second-top divided by top (GCL command table, Table 3).
- *   - Invalid values (NaN, Inf) are kept and handled per case, not removed
- *     (Sec. "Fitness Functions", the text around Eq. 1-2); here any invalid
- *     case output gives the program the worst fitness, +inf.
+ *   - Invalid values (NaN, Inf) in the model output or in the dataset are
+ *     kept and handled per case, not removed (Sec. "Fitness Functions", the
+ *     text around Eq. 1-2, whose Eq. 2 rewards matched invalid pairs and
+ *     penalises mismatched ones); here a mismatched case (one side invalid)
+ *     gives the program the worst fitness, +inf, and a matched one is an
+ *     exact prediction.  With finite targets this is: any invalid case
+ *     output gives +inf.
  *   - Length tax = "Tax on Length" / parsimony pressure (Table 1 and the
  *     ScriptLengthTaxRateInternal paragraph), charged per node.
  *   - Inputs and targets are fp32 (MLSetup data interface, float[] / float).
@@ -354,7 +362,12 @@ int oracle_program_outputs(const uint32_t* prog, int64_t len,
     return ST_VALID;
 }
 
-/* Fitness of one program; also returns the fp64 MSE (NaN if invalid). */
+/* Fitness of one program; also returns the fp64 MSE (NaN if invalid).
+ * A case is a valid pair when the output and the target are both finite
+ * (the invalid pairs of Eq. 2, Sec. "Fitness Functions"): a valid pair adds
+ * its squared residual; a case where both are invalid is a matched pair
+ * and adds nothing; a case where exactly one of them is invalid makes the
+ * fitness the worst value, +inf.  The mean divides by all n cases. */
 static double program_fitness(const uint32_t* prog, int64_t len,
                               const float* consts, const float* X, int64_t ld_x,
                               const float* y, int64_t n_cases, double tax,
@@ -364,9 +377,12 @@ static double program_fitness(const uint32_t* prog, int64_t len,
     int bad = 0;
     for (int64_t i = 0; i < n_cases; ++i) {
         double f = eval_case(prog, len, consts, X, ld_x, i, mode);
-        if (!isfinite(f)) bad = 1;
-        double r = f - (double)y[i];
-        sum += r * r;
+        int fv = isfinite(f) != 0, yv = isfinite(y[i]) != 0;
+        if (fv != yv) bad = 1;
+        if (fv && yv) {
+            double r = f - (double)y[i];
+            sum += r * r;
+        }
     }
     if (bad) { *mse_out = NAN; return INFINITY; }
     double mse = sum / (double)n_cases;

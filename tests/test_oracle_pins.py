@@ -318,6 +318,67 @@ class TestClosedForms:
         assert abs(mse - float(ex)) <= 1e-13 * float(ex)
 
 
+class TestInvalidTargets:
+    """P3b: targets that are NaN or +-inf (Sec. "Fitness Functions": invalid
+    values in the model output or the dataset are handled, not removed; as
+    in Eq. 2, a case where output and target are both invalid is a matched
+    pair, a case where exactly one is invalid is a mismatch).  Reading: a
+    matched pair adds no error, a mismatch makes F = +inf, and the mean
+    divides by all n cases.  Every value here is computed by hand."""
+
+    INF, NAN = float("inf"), float("nan")
+
+    def _fit(self, p, xs, y, consts=(), tax=0.0):
+        X = np.array(xs, np.float32).reshape(1, -1)
+        return fit1(p, X, np.array(y, np.float32), consts, tax)
+
+    def test_matched_pairs_add_nothing(self):
+        # outputs [inf, 1, 2], targets [nan, 1, 5]: case 0 matched (both
+        # invalid), case 1 error 0, case 2 error (2 - 5)^2 = 9: MSE = 9/3
+        F, mse = self._fit(prog(("x", 0)), [self.INF, 1.0, 2.0], [self.NAN, 1.0, 5.0],
+                           tax=0.5)
+        assert mse == 3.0 and F == 3.5
+
+    @pytest.mark.parametrize("yv", [float("nan"), float("inf"), -float("inf")])
+    def test_finite_output_against_invalid_target_is_worst(self, yv):
+        F, _ = self._fit(prog(("x", 0)), [0.0, 1.0, 2.0], [yv, 1.0, 2.0])
+        assert F == math.inf
+
+    def test_invalid_output_against_finite_target_is_worst(self):
+        # exp(89) overflows fp32: +inf against a finite target
+        F, _ = self._fit(prog(("x", 0), EXP), [89.0, 0.0], [1.0, 1.0])
+        assert F == math.inf
+
+    def test_any_pairing_of_nan_and_inf_is_matched(self):
+        # exp(89) = +inf against -inf, sin(inf) = NaN against +inf, and
+        # 0 * inf = NaN against NaN are all matched; the last case adds
+        # (1 - 3)^2 = 4 out of 4 cases
+        p_exp = prog(("x", 0), EXP)
+        F, mse = self._fit(p_exp, [89.0, 89.0, 0.0, 0.0],
+                           [-self.INF, self.NAN, 1.0, 3.0])
+        assert mse == 1.0 and F == 1.0
+        F, mse = self._fit(prog(("x", 0), SIN), [self.INF, 0.5], [self.INF, f32(math.sin(0.5))])
+        assert mse == (f32(math.sin(0.5)) - math.sin(f32(0.5))) ** 2 / 2
+
+    def test_all_cases_matched_gives_tax_only(self):
+        F, mse = self._fit(prog(("x", 0), ("x", 0), MUL), [self.INF, self.NAN],
+                           [self.NAN, -self.INF], tax=0.25)
+        assert mse == 0.0 and F == 0.75
+
+    def test_valid_program_never_nan(self):
+        # every mixture of finite and invalid targets gives a number or +inf
+        rng = np.random.default_rng(3)
+        X = rng.uniform(-2, 2, (2, 64)).astype(np.float32)
+        X[0, ::7] = np.inf
+        y = rng.uniform(-2, 2, 64).astype(np.float32)
+        y[::5] = np.nan
+        y[1::9] = -np.inf
+        for toks in [(("x", 0),), (("x", 1),), (("x", 0), ("x", 1), ADD),
+                     (("x", 0), EXP), (("x", 1), LOG)]:
+            F, _ = fit1(prog(*toks), X, y)
+            assert not math.isnan(F)
+
+
 # ---------------------------------------------------------------- P4
 def _int_tree_value(tree, xs):
     """Exact integer evaluation of a {+,-,*} tree: (value, largest |value| of
