@@ -8,9 +8,12 @@ score of Eq. 1-2 (``max_score`` given) and the integer reward of Eq. 5
 
 A finite program passes when |F_dev - F_64| <= 1e-4 |F_64| + 1e-12 (the
 relative tolerance of the fitness requirement, plus an absolute floor for
-closed-form zeros).  NaN/inf classification must be identical.  A program
-that fails either test is examined further with the oracle's fp32-emulating
-modes; it is excused only when the arithmetic itself explains it:
+closed-form zeros).  Classification must be identical, and it has three
+values: NaN only for a structurally invalid program (status != 0; a valid
+program that comes out NaN on either side is a failure), +inf for the worst
+fitness of a valid program, and finite.  A program that fails the value or
+class test is examined further with the oracle's fp32-emulating modes; it
+is excused only when the arithmetic itself explains it:
 
   * fp32 ill-conditioned: the correctly rounded fp32 evaluation (M32E)
     differs from M64 by more than 1e-5 relative, and the device result
@@ -18,10 +21,15 @@ modes; it is excused only when the arithmetic itself explains it:
   * chaotic: moving every sin/cos/exp/log/sqrt result one fp32 ulp
     (M32E_UP / M32E_DN), or by seeded pseudo-random amounts within +-2 ulps
     (M32E_RAND; the accuracy class of fp32 elementary-function code),
-    changes F by more than the tolerance, or changes its class;
+    changes F by more than the tolerance, or changes its class -- and the
+    device value lies in the envelope of those runs: the hull of the M64,
+    M32E, M32E_UP/DN and M32E_RAND results, widened on each side by its own
+    width and by 4 fp32 ulps of its largest end (the rule the reward's
+    output window applies per case);
   * certified class flip: the device class differs from M64's but equals
-    M32E's (an fp32 overflow-range or threshold flip), or equals that of a
-    perturbed run (chaotic).
+    M32E's (an fp32 overflow-range or threshold flip) or that of a
+    perturbed run; a finite device value must then also lie in the
+    envelope of the finite results.
 
 The integer reward sums per-case decisions that amplify an output error
 by M before rounding, so a suspicious reward is judged on the outputs
@@ -132,26 +140,24 @@ def reward_window(prog, consts, X, y, max_score, power, allowed_mask):
     return int(rmin.sum()), int(rmax.sum())
 
 
-def _close(a, b, rel=REL, abs_=ABS):
-    return np.abs(a - b) <= rel * np.abs(b) + abs_
-
-
 def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
           status=None, n_threads=0, max_failures=20, max_score=None, reward_power=None):
     """Gate F_dev (float64[P]) against the oracle.  Returns a GateReport.
 
     With ``max_score`` set, F is the correlation score of Eq. 1-2 with that
     M (``tax`` unused): the relative tolerance (and the reported relative
-    error) is taken on the reference's correlation term M r^4 n, the
-    invalid-pair term must agree exactly, and the absolute floor is
-    1e-9 * M * N (a change of 1e-9 in r^4).
+    error) is taken on the reference's correlation term M r^4 n, and the
+    invalid-pair term must agree exactly.  An absolute floor of 1e-9 M N (a
+    change of 1e-9 in r^4) applies only where r^4 is about zero: where the
+    correlation term itself is below the floor; everywhere else a mismatch
+    beyond the relative tolerance must be certified.
 
     With ``reward_power`` also set, F is the integer reward of Eq. 5 (power
     1, 2, 3 or 8) summed over the cases; the relative tolerance is taken on
     |F| + 0.01 M N (rounding flips of single cases are expected between an
     fp32 and an fp64 evaluation)."""
     F_dev = np.asarray(F_dev, np.float64)
-    abs_floor = ABS
+    corr = max_score is not None and reward_power is None
     if max_score is None:
         def score(nd, of, mode):
             F, _, st = fitness(nd, of, consts, X, y, tax, allowed_mask, mode, n_threads)
@@ -168,15 +174,25 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
         # the reference; the invalid-pair term M (c1 - c2) is a multiple of
         # M and must agree exactly (a count difference moves the score by M)
         N = float(np.asarray(y).size)
-        abs_floor = 1e-9 * float(max_score) * N
 
         def score(nd, of, mode):
             F, r, st, c1, c2 = correlation(nd, of, consts, X, y, max_score, allowed_mask,
                                            mode, n_threads, return_counts=True)
             return F, st, float(max_score) * r ** 4 * (N - c1 - c2)
 
+    if corr:
+        MN = abs(float(max_score)) * float(np.asarray(y).size)
+
+        def floor(T):
+            # the absolute floor only where r^4 is about zero
+            return np.where(np.abs(T) < 1e-9 * MN, 1e-9 * MN, ABS)
+    else:
+        def floor(T):
+            return ABS
+
     def close(a, b, scale, rel=REL):
-        return np.abs(a - b) <= rel * scale + abs_floor
+        with np.errstate(invalid="ignore"):          # inf - inf: not close
+            return np.abs(a - b) <= rel * scale + floor(scale)
 
     if F64 is None:
         F64, status, T64 = score(nodes, offsets, M64)
@@ -189,22 +205,31 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
     for p in bad_invalid[:max_failures]:
         rep.failures.append((int(p), "invalid program not NaN", F_dev[p], F64[p]))
     rep.n_fail += bad_invalid.size
+    # NaN marks a structurally invalid program only: a valid program is
+    # finite or +inf on both sides
+    if np.any(valid & np.isnan(F64)):
+        raise AssertionError("oracle returned NaN for a valid program")
+    nan_valid = np.nonzero(valid & np.isnan(F_dev))[0]
+    for p in nan_valid[:max(0, max_failures - len(rep.failures))]:
+        rep.failures.append((int(p), "valid program NaN", F_dev[p], F64[p]))
+    rep.n_fail += nan_valid.size
 
     fin64 = np.isfinite(F64)
     find = np.isfinite(F_dev)
-    same_class = fin64 == find
-    good = valid & same_class & (~fin64 | close(F_dev, F64, T64))
+    same_class = (fin64 == find) & (fin64 | (F_dev == F64))
+    good = valid & ~np.isnan(F_dev) & same_class & (~fin64 | close(F_dev, F64, T64))
     rep.n_pass = int(np.sum(good))
-    # error statistics over programs whose reference is well above the
-    # absolute floor (for the correlation score: r^4 above 1e-6)
-    both = valid & fin64 & find & good & (T64 > 1e3 * abs_floor)
+    # error statistics over programs well above the absolute floor (for the
+    # correlation score: r^4 of at least 1e-6)
+    both = valid & fin64 & find & good
+    both &= (T64 >= 1e-6 * MN) if corr else (T64 > 1e3 * ABS)
     if both.any():
         rel = np.abs(F_dev[both] - F64[both]) / np.maximum(T64[both], 1e-300)
         rep.max_rel_err = float(rel.max())
         rep.median_rel_err = float(np.median(rel))
         rep.p99_rel_err = float(np.quantile(rel, 0.99))
 
-    sus = np.nonzero(valid & ~good)[0]
+    sus = np.nonzero(valid & ~good & ~np.isnan(F_dev))[0]
     if sus.size and reward_power is not None:
         nodes_a = np.asarray(nodes, np.uint32)
         offs_a = np.asarray(offsets, np.int64)
@@ -226,16 +251,24 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
         pert = np.stack(pert)
         for i, p in enumerate(sus):
             fd, f64, f32 = F_dev[p], F64[p], F32[i]
-            if np.isfinite(fd) != np.isfinite(f64):
-                if np.isfinite(f32) == np.isfinite(fd):
+            runs = np.concatenate([[f64, f32], pert[:, i]])
+            if np.isfinite(fd) != np.isfinite(f64) or (not np.isfinite(fd) and fd != f64):
+                flip = "class"
+                if np.isfinite(f32) == np.isfinite(fd) and (np.isfinite(fd) or fd == f32):
+                    flip = "flip"
+                elif np.any((np.isfinite(pert[:, i]) == np.isfinite(fd))
+                            & (np.isfinite(fd) | (pert[:, i] == fd))):
+                    flip = "chaotic"
+                if flip != "class" and np.isfinite(fd) and not in_envelope(fd, runs):
+                    flip = "class (outside envelope)"
+                if flip == "flip":
                     rep.n_class_flip_certified += 1
-                    continue
-                if np.any(np.isfinite(pert[:, i]) == np.isfinite(fd)):
+                elif flip == "chaotic":
                     rep.n_chaotic += 1
-                    continue
-                rep.n_fail += 1
-                if len(rep.failures) < max_failures:
-                    rep.failures.append((int(p), "class", fd, f64, f32))
+                else:
+                    rep.n_fail += 1
+                    if len(rep.failures) < max_failures:
+                        rep.failures.append((int(p), flip, fd, f64, f32))
                 continue
             # both finite, value mismatch
             t64, t32 = T64[p], T32[i]
@@ -245,10 +278,30 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
                 continue
             chaotic = (not np.all(np.isfinite(pert[:, i]))
                        or not np.all(close(pert[:, i], f32, t32)))
-            if chaotic:
+            if chaotic and in_envelope(fd, runs):
                 rep.n_chaotic += 1
                 continue
             rep.n_fail += 1
             if len(rep.failures) < max_failures:
-                rep.failures.append((int(p), "value", fd, f64, f32))
+                rep.failures.append((int(p), "value (chaotic, outside envelope)" if chaotic
+                                     else "value", fd, f64, f32))
     return rep
+
+
+def envelope(runs):
+    """The interval of values certified by a set of oracle runs: the hull of
+    the finite results, widened on each side by its own width and by 4 fp32
+    ulps of its largest end (None when no run is finite)."""
+    runs = np.asarray(runs, np.float64)
+    fin = runs[np.isfinite(runs)]
+    if fin.size == 0:
+        return None
+    lo, hi = float(fin.min()), float(fin.max())
+    w = hi - lo
+    ulp = float(np.spacing(np.float32(min(max(abs(lo), abs(hi)), np.finfo(np.float32).max))))
+    return lo - w - 4.0 * ulp, hi + w + 4.0 * ulp
+
+
+def in_envelope(v, runs):
+    env = envelope(runs)
+    return env is not None and env[0] <= v <= env[1]

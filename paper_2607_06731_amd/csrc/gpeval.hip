@@ -25,7 +25,7 @@
 //                    group's programs one at a time and runs one over the
 //                    64*K cases of the sub-tile (K per lane) with the value
 //                    stack in VGPRs; the fitness epilogue is fused (MSE:
-//                    scaled square with TwoSum accumulation; correlation:
+//                    scaled square with Kahan accumulation; correlation:
 //                    shifted fp64 sums over valid pairs; integer reward:
 //                    int64 per case) and a wave shuffle tree gives one
 //                    partial per (program, tile).
@@ -992,6 +992,36 @@ __device__ __forceinline__ void acc_pair(float& hi, float& lo, float h2, float l
     lo = (lo + l2) + e;
 }
 
+// One case of the MSE fitness into a lane's Kahan pair (the represented sum
+// is hi + lo).  ys is the target pre-scaled by the dataset's power of two s,
+// so fma(f, s, -ys) is the scaled residual (f - y) s rounded once: the same
+// value as rounding f - y and scaling it.  CHECK: the targets may hold NaN
+// or +-inf (Sec. "Fitness Functions": invalid values in the dataset are
+// handled as in Eq. 2): a case whose output and target are both invalid is
+// a matched pair and adds nothing, a case where exactly one of them is
+// invalid marks the program (worst fitness).  Without CHECK (every target
+// finite) an invalid output needs no mark: its residual is NaN or +-inf and
+// so is the lane's sum from then on, which the reduction turns into the
+// worst fitness, as it does a sum that overflows.
+template <bool CHECK>
+__device__ __forceinline__ void mse_case(float f, float ys, float s, float& hi, float& lo,
+                                         bool& bad)
+{
+    const float d = fmaf(f, s, -ys);
+    float t = d * d;
+    if constexpr (CHECK) {
+        const bool fv = __builtin_isfinite(f), yv = __builtin_isfinite(ys);
+        bad |= fv != yv;
+        t = fv && yv ? t : 0.f;
+    }
+    // Kahan's compensated step (every term is >= 0, so the running sum
+    // dominates the term after the first few cases)
+    const float yk = t + lo;
+    const float u = hi + yk;
+    lo = yk - (u - hi);
+    hi = u;
+}
+
 // The value stack below the top lives in VGPR arrays of 32 floats ("chunks"):
 // chunk c holds cases [c*J, (c+1)*J) of every slot, element index
 // slot*J + (case mod J), J = 32 / MAXD.  A uniform dynamic index into a
@@ -1440,6 +1470,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
     const uint32_t n_items = pre_c[a.n_seg];
     int staged_d = -1;                            // dataset and first sub-tile in LDS
     int64_t staged = -1;
+    int ynf = 0;                                  // the staged window holds a NaN/inf target
 
     for (;;) {
         if (tid == 0) s_item = atomicAdd(work_counter, 1u);
@@ -1491,16 +1522,27 @@ __global__ __launch_bounds__(kWG) void k_eval(
             const int nw = (int)min((int64_t)min(window, passes - w0), n_sub - first);
             if (first != staged || d != staged_d) {
                 // lane t's case j of a sub-tile is element j*64 + t of a
-                // row: conflict-free, lane-contiguous reads
+                // row: conflict-free, lane-contiguous reads.  MSE mode
+                // stores the targets pre-scaled (an exact power of two).
+                int nf = 0;
                 for (int i = tid; i < nw * rows * SUB; i += kWG) {
                     const int blk = i / (rows * SUB);
                     const int r = i - blk * rows * SUB;
                     const int v = r / SUB, cc = r - v * SUB;
                     const int64_t gi = (first + blk) * SUB + cc;
                     float val = 0.f;
-                    if (gi < n_cases) val = v < n_vars ? Xd[(int64_t)v * ld_x + gi] : yd[gi];
+                    if (gi < n_cases) {
+                        if (v < n_vars) {
+                            val = Xd[(int64_t)v * ld_x + gi];
+                        } else {
+                            val = FIT == kFitMse ? yd[gi] * scale : yd[gi];
+                            nf |= !__builtin_isfinite(val);
+                        }
+                    }
                     xt[i] = val;
                 }
+                // (block-uniform branch: every thread reaches the barrier)
+                ynf = __syncthreads_or(nf);
                 staged = first;
                 staged_d = d;
             }
@@ -1551,24 +1593,33 @@ __global__ __launch_bounds__(kWG) void k_eval(
                             }
                         }
                     }
+                    if constexpr (FIT == kFitMse) {
+                        // a whole sub-tile in range with finite targets: no
+                        // per-case tests (wave-uniform branches)
+                        if (base + SUB <= n_cases && !ynf) {
+#pragma unroll
+                            for (int j = 0; j < K; ++j)
+                                mse_case<false>(tos[j], yt[lane + j * 64], scale, hi, lo_, bad);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < K; ++j)
+                                if (base + lane + j * 64 < n_cases)
+                                    mse_case<true>(tos[j], yt[lane + j * 64], scale, hi, lo_,
+                                                   bad);
+                        }
+                    } else {
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
                         if (base + lane + j * 64 < n_cases) {
                             const float f = tos[j];
                             if constexpr (FIT == kFitCorr) {
                                 corr_case(cl, f, yt[lane + j * 64], cs, ct);
-                            } else if constexpr (FIT == kFitReward) {
+                            } else {
                                 rl += pair_reward(f, yt[lane + j * 64], a.reward_M,
                                                   a.reward_power);
-                            } else {
-                                bad |= !__builtin_isfinite(f);
-                                const float r = (f - yt[lane + j * 64]) * scale;
-                                float s, e;
-                                two_sum(hi, r * r, s, e);
-                                hi = s;
-                                lo_ += e;
                             }
                         }
+                    }
                     }
                 }
                 if constexpr (FIT == kFitCorr) {

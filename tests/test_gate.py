@@ -1,7 +1,12 @@
 """The parity gate on the CPU: it passes the oracle's own values, catches a
 planted error, and certifies fp32 effects only when the oracle's
-fp32-emulating modes explain them (both fitness functions)."""
+fp32-emulating modes explain them (all three fitness functions); a
+certified program's device value must still lie in the envelope of the
+oracle's runs, and NaN is reserved for structurally invalid programs."""
+import math
+
 import numpy as np
+import pytest
 
 import oracle
 from oracle import gate
@@ -142,3 +147,116 @@ def test_reward_window_bounds_against_brute_force():
                                                     power))
                 v = np.concatenate(vals)
                 assert rmin[0] == v.min() and rmax[0] == v.max(), (O, y, M, power)
+
+
+def _one(toks, consts=()):
+    out = []
+    for t in toks:
+        if isinstance(t, tuple):
+            out.append((oracle.LOAD if t[0] == "x" else oracle.CONST) | (t[1] << 8))
+        else:
+            out.append(t)
+    nodes = np.array(out, np.uint32)
+    return nodes, np.array([0, nodes.size], np.int64), np.array(consts, np.float32)
+
+
+def _chaotic_case():
+    """sin(exp(6 x0)) on x0 in (-3, 3): exp reaches ~6.6e7, where one fp32
+    ulp of its result moves the sine anywhere in [-1, 1]."""
+    rng = np.random.default_rng(5)
+    X = rng.uniform(-3, 3, (1, 512)).astype(np.float32)
+    y = rng.uniform(-1, 1, 512).astype(np.float32)
+    nodes, offs, consts = _one([("x", 0), ("c", 0), oracle.MUL, oracle.EXP, oracle.SIN], [6.0])
+    return nodes, offs, consts, X, y
+
+
+def test_chaotic_excuse_is_bounded_by_the_envelope():
+    nodes, offs, consts, X, y = _chaotic_case()
+    args = (nodes, offs, consts, X, y, 0.0, oracle.MASK_BENCH)
+    runs = [oracle.fitness(nodes, offs, consts, X, y, 0.0, oracle.MASK_BENCH, m)[0][0]
+            for m in [oracle.M64, oracle.M32E, oracle.M32E_UP, oracle.M32E_DN] +
+            [oracle.M32E_RAND + s for s in range(gate.N_RANDOM)]]
+    lo, hi = min(runs), max(runs)
+    assert hi - lo > 1e-3 * hi                       # the program is chaotic
+    # a value among the runs is certified as chaotic ...
+    rep = gate.check(np.array([runs[2]]), *args)
+    assert rep.ok() and (rep.n_chaotic == 1 or rep.n_pass == 1), rep.summary()
+    # ... one far outside their envelope is not, however chaotic the program
+    for planted in (hi + 5 * (hi - lo) + 1.0, max(lo - 5 * (hi - lo) - 1.0, -1.0)):
+        rep = gate.check(np.array([planted]), *args)
+        assert rep.n_fail == 1, (planted, rep.summary())
+
+
+def test_certified_class_flip_bounds_a_finite_device_value():
+    """x0 * 1e19 squared: in fp32 the MSE is near FLT_MAX; a device class
+    flip to a finite value is certified only inside the runs' envelope."""
+    X = np.array([[1.0, 1.0, 1.0, 1.0]], np.float32)
+    y = np.zeros(4, np.float32)
+    c = float(np.float32(1.8446742e19))            # c^2 ~ FLT_MAX: at the class edge
+    nodes, offs, consts = _one([("x", 0), ("c", 0), oracle.MUL], [c])
+    args = (nodes, offs, consts, X, y, 0.0, oracle.MASK_BENCH)
+    F64 = oracle.fitness(nodes, offs, consts, X, y, 0.0, oracle.MASK_BENCH)[0][0]
+    assert math.isfinite(F64)
+    # the oracle's own value passes, a planted infinite class fails
+    assert gate.check(np.array([F64]), *args).n_pass == 1
+    assert gate.check(np.array([math.inf]), *args).n_fail == 1
+    assert gate.check(np.array([F64 * 0.5]), *args).n_fail == 1
+
+
+def test_nan_is_reserved_for_invalid_programs():
+    w = _workload()
+    F64, _, st = oracle.fitness(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X,
+                                w.data.y, w.tax, w.allowed_mask)
+    fin = np.nonzero(np.isfinite(F64) & (st == 0))[0][:3]
+    inf = np.nonzero(np.isinf(F64) & (st == 0))[0][:3]
+    assert fin.size == 3 and inf.size == 3
+    bad = F64.copy()
+    bad[fin] = np.nan
+    bad[inf] = np.nan
+    rep = gate.check(bad, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y,
+                     w.tax, w.allowed_mask)
+    assert rep.n_fail == 6
+    assert sum(1 for f in rep.failures if f[1] == "valid program NaN") == 6
+
+
+def test_mse_gate_with_invalid_targets():
+    """3% NaN/+-inf targets: the oracle's own values pass (finite and +inf
+    classes both occur), the fp32 evaluation is certified, a swapped class
+    fails."""
+    w = _workload()
+    y = w.data.y.copy()
+    rng = np.random.default_rng(9)
+    idx = rng.choice(y.size, y.size * 3 // 100, replace=False)
+    y[idx] = rng.choice(np.array([np.nan, np.inf, -np.inf], np.float32), idx.size)
+    args = (w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, y, w.tax, w.allowed_mask)
+    F64, _, st = oracle.fitness(*args)
+    assert not np.any(np.isnan(F64[st == 0]))
+    rep = gate.check(F64, *args)
+    assert rep.ok() and rep.n_pass == rep.n
+    F32, _, _ = oracle.fitness(*args, mode=oracle.M32E)
+    assert gate.check(F32, *args).ok()
+
+
+def test_correlation_floor_only_near_zero():
+    """A planted error of 1e-3 relative on a well-conditioned program with a
+    small but clearly nonzero r^4 fails: the absolute floor (1e-9 M N) no
+    longer hides it."""
+    rng = np.random.default_rng(2)
+    n = 4096
+    X = rng.uniform(-1, 1, (2, n)).astype(np.float32)
+    M = 1e4
+    hit = None
+    for a in np.linspace(0.005, 0.05, 40):
+        y = (X[1] + np.float32(a) * X[0]).astype(np.float32)
+        nodes, offs, consts = _one([("x", 0), ("c", 0), oracle.MUL], [1.5])
+        S, r, st = oracle.correlation(nodes, offs, consts, X, y, M, oracle.MASK_BENCH)
+        if 2e-7 < r[0] ** 4 < 2e-6:
+            hit = (y, nodes, offs, consts, S[0], r[0])
+            break
+    assert hit is not None
+    y, nodes, offs, consts, S, r = hit
+    args = (nodes, offs, consts, X, y, 0.0, oracle.MASK_BENCH)
+    assert gate.check(np.array([S]), *args, max_score=M).n_pass == 1
+    planted = S * (1 + 1e-3)
+    assert abs(planted - S) < 1e-9 * M * n       # inside the old floor
+    assert gate.check(np.array([planted]), *args, max_score=M).n_fail == 1

@@ -58,6 +58,62 @@ def test_workload_parity(name, P, n):
           w.allowed_mask, label)
 
 
+@pytest.mark.parametrize("n", [4096, 1025])
+def test_invalid_targets_parity(n):
+    """3% of the targets NaN, +inf or -inf (Sec. "Fitness Functions": invalid
+    values in the dataset are handled, not removed): matched invalid pairs
+    add nothing, a mismatched case gives +inf; the gate separates NaN
+    (structurally invalid) from +inf, and no valid program comes out NaN."""
+    gp = _need_gpu()
+    from paper_2607_06731_amd import synth
+    w = synth.make_workload("generation", n_programs=3000, n_cases=n)
+    y = w.data.y.copy()
+    rng = np.random.default_rng(17)
+    idx = rng.choice(y.size, max(1, y.size * 3 // 100), replace=False)
+    y[idx] = rng.choice(np.array([np.nan, np.inf, -np.inf], np.float32), idx.size)
+    label = "generation P=3000 n=%d, 3%% invalid targets" % n
+    _say(label)
+    F = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, y, w.tax,
+             w.allowed_mask)
+    rep = _gate(F, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, y, w.tax,
+                w.allowed_mask, label)
+    assert not np.isnan(F).any()
+    assert np.isfinite(F).sum() > 0 and np.isinf(F).sum() > 0
+
+
+def test_matched_invalid_pairs_exact():
+    """Hand-computed: outputs inf, NaN, -inf against NaN, inf, -inf targets
+    are matched (no error); the finite cases give an exact MSE."""
+    gp = _need_gpu()
+    from oracle import EXP, LOAD, SIN
+    inf, nan = np.inf, np.nan
+    n = 300                       # a ragged sub-tile as well
+    x = np.tile(np.array([inf, 0.5, -inf, 2.0, 89.0, 1.0], np.float32), n // 6)
+    y = np.tile(np.array([nan, 1.5, -inf, 2.0, inf, 3.0], np.float32), n // 6)
+    X = x.reshape(1, -1)
+    progs = [[LOAD], [LOAD, EXP], [LOAD, SIN]]
+    lens = np.array([len(q) for q in progs], np.int64)
+    off = np.zeros(len(progs) + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    nodes = np.array([t for q in progs for t in q], np.uint32)
+    _say("matched invalid pairs")
+    F = _run(gp, nodes, off, np.zeros(0, np.float32), X, y, 0.0, oracle.MASK_BENCH)
+    # x0: cases inf/nan, -inf/-inf matched; 0.5 vs 1.5 -> 1; 2 vs 2 -> 0;
+    # 89 vs inf: finite vs invalid -> +inf
+    assert F[0] == np.inf
+    F64, _, st = oracle.fitness(nodes, off, np.zeros(0, np.float32), X, y, 0.0)
+    assert (st == 0).all() and not np.isnan(F64).any()
+    assert np.array_equal(np.isinf(F), np.isinf(F64))
+    fin = np.isfinite(F64)
+    assert np.allclose(F[fin], F64[fin], rtol=1e-6, atol=0)
+    # a program whose only mismatch is removed: exact value by hand
+    x2 = np.tile(np.array([inf, 0.5, -inf, 2.0, 1.0], np.float32), 60)
+    y2 = np.tile(np.array([nan, 1.5, inf, 2.0, 3.0], np.float32), 60)
+    F2 = _run(gp, np.array([LOAD], np.uint32), [0, 1], np.zeros(0, np.float32),
+              x2.reshape(1, -1), y2, 0.0, oracle.MASK_BENCH)
+    assert F2[0] == (1.0 + 4.0) / 5.0
+
+
 def test_generation_full_size_sampled():
     """Full generation launch (100,000 programs x 4,096 cases) gated on a
     seeded sample of 400 programs, stratified by length."""
