@@ -7,8 +7,15 @@
  * is run over every fitness case, and one aggregate per program comes back:
  *
  *   F(p) = MSE(p) + tax_on_length * len(p)      for a valid program
- *   F(p) = +INFINITY  if some case output is NaN or +-inf, or MSE(p) > FLT_MAX
- *   MSE(p) = (1/n) * sum_i (f_p(x_i) - y_i)^2
+ *   F(p) = +INFINITY  if for some case exactly one of f_p(x_i) and y_i is
+ *                     NaN or +-inf, or MSE(p) > FLT_MAX
+ *   MSE(p) = (1/n) * sum over valid pairs i of (f_p(x_i) - y_i)^2
+ *
+ * A valid pair is a case whose output and target are both finite; a case
+ * where both are NaN/inf is a matched invalid pair and adds nothing (Sec.
+ * "Fitness Functions": invalid values in the output or the dataset are
+ * handled as in Eq. 2, which rewards matched invalid pairs).  With finite
+ * targets: any NaN/inf case output gives +INFINITY.
  *
  * f_p is the reverse-Polish evaluation of p (Sec. "Genome Computer Language
  * (GCL)": unary ops replace the top of the stack, binary ops replace the top
@@ -20,9 +27,9 @@
  * included ("Tax on Length", Table 1; ScriptLengthTaxRateInternal).
  *
  * Arithmetic: each case is evaluated in fp32; squared residuals are summed
- * in compensated fp32 (power-of-two pre-scaled so no partial sum can exceed
- * the MSE); the per-program cross-block sum, the tax and the classification
- * are fp64.  Program decoding and indexing are exact.
+ * in Kahan-compensated fp32 (power-of-two pre-scaled so no partial sum can
+ * exceed the MSE); the per-program cross-block sum, the tax and the
+ * classification are fp64.  Program decoding and indexing are exact.
  *
  * Program format (device arrays, caller owned):
  *   nodes   uint32[n_nodes]    node = op | (arg << 8)
