@@ -29,7 +29,19 @@ is excused only when the arithmetic itself explains it:
   * certified class flip: the device class differs from M64's but equals
     M32E's (an fp32 overflow-range or threshold flip) or that of a
     perturbed run; a finite device value must then also lie in the
-    envelope of the finite results.
+    envelope of the finite results;
+  * output window (MSE and correlation): per case, the hull of the oracle's
+    outputs in M64, M32E, M32E_UP/DN and the M32E_RAND runs, widened on
+    each side by its own width and by 4 fp32 ulps (the same window as the
+    reward's below), with every run agreeing on which outputs are finite.
+    The device value must lie within what outputs anywhere in those
+    windows can give: for the MSE exactly, |dF| <= (1/n) sum(2|f_i - y_i|
+    w_i + w_i^2) with w_i the window's reach from the M64 output f_i; for
+    the correlation score to first order in r, |dr| <= 2 sum |dr/df_i| w_i
+    (the factor 2 covers the second-order terms), the correlation term
+    staying within [0, M n_valid] and moving by at most
+    M n_valid ((|r| + |dr|)^4 - r^4) (|r| + |dr| capped at 1); the relative
+    tolerance is added on top.
 
 The integer reward sums per-case decisions that amplify an output error
 by M before rounding, so a suspicious reward is judged on the outputs
@@ -244,7 +256,9 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
                 rep.failures.append((int(p), "outside output window", F_dev[p], F64[p], lo, hi))
         return rep
     if sus.size:
-        sn, so = subset(np.asarray(nodes, np.uint32), np.asarray(offsets, np.int64), sus)
+        nodes_a = np.asarray(nodes, np.uint32)
+        offs_a = np.asarray(offsets, np.int64)
+        sn, so = subset(nodes_a, offs_a, sus)
         F32, _, T32 = score(sn, so, M32E)
         pert = [score(sn, so, m)[0]
                 for m in [M32E_UP, M32E_DN] + [M32E_RAND + s for s in range(N_RANDOM)]]
@@ -281,11 +295,78 @@ def check(F_dev, nodes, offsets, consts, X, y, tax, allowed_mask, F64=None,
             if chaotic and in_envelope(fd, runs):
                 rep.n_chaotic += 1
                 continue
+            if window_excuse(fd, f64, t64, nodes_a[offs_a[p]:offs_a[p + 1]], consts, X, y,
+                             allowed_mask, max_score if corr else None):
+                rep.n_output_window += 1
+                continue
             rep.n_fail += 1
             if len(rep.failures) < max_failures:
                 rep.failures.append((int(p), "value (chaotic, outside envelope)" if chaotic
                                      else "value", fd, f64, f32))
     return rep
+
+
+def output_windows(prog, consts, X, y, allowed_mask):
+    """Per-case output windows of one program: (f64, lo, hi, fin) with f64
+    the M64 outputs, [lo, hi] the hull of the M64, M32E, M32E_UP/DN and
+    M32E_RAND outputs widened on each side by its width and 4 fp32 ulps,
+    and fin the cases where every run's output is finite (None when the
+    runs disagree on which outputs are finite)."""
+    n = np.asarray(y).size
+    modes = [M64, M32E, M32E_UP, M32E_DN] + [M32E_RAND + s for s in range(N_RANDOM)]
+    O = np.stack([program_outputs(prog, consts, X, n, allowed_mask, m) for m in modes])
+    with np.errstate(over="ignore", invalid="ignore"):
+        fin_all = np.isfinite(O) & np.isfinite(O.astype(np.float32))
+    fin = fin_all.all(axis=0)
+    if not np.array_equal(fin, fin_all.any(axis=0)):
+        return None
+    Of = np.where(fin, O, 0.0)
+    lo, hi = Of.min(axis=0), Of.max(axis=0)
+    w = hi - lo
+
+    def ulp(v):
+        v32 = np.minimum(np.abs(v), np.finfo(np.float32).max).astype(np.float32)
+        return np.spacing(v32).astype(np.float64)
+
+    return O[0], lo - w - 4.0 * ulp(lo), hi + w + 4.0 * ulp(hi), fin
+
+
+def window_excuse(fd, f64, t64, prog, consts, X, y, allowed_mask, max_score=None):
+    """Whether the finite device value fd of one program lies within what
+    outputs anywhere in its per-case output windows can give (the bounds in
+    the module docstring), the relative tolerance added on top."""
+    ow = output_windows(prog, consts, X, y, allowed_mask)
+    if ow is None:
+        return False
+    f, lo, hi, fin = ow
+    yy = np.asarray(y, np.float32).astype(np.float64)
+    v = fin & np.isfinite(yy)                      # valid pairs
+    reach = np.where(v, np.maximum(hi - f, f - lo), 0.0)
+    if max_score is None:
+        n = yy.size
+        bound = float(np.sum(2.0 * np.abs(np.where(v, f - yy, 0.0)) * reach + reach * reach)) / n
+        return abs(fd - f64) <= REL * abs(t64) + bound + ABS
+    M = abs(float(max_score))
+    nv = int(v.sum())
+    c1 = int(np.sum(fin != np.isfinite(yy)))
+    c2 = int(np.sum(~fin & ~np.isfinite(yy)))
+    T_dev = fd + float(max_score) * (c1 - c2)          # the device's correlation term
+    if not (-1e-6 * M * max(nv, 1) <= T_dev * np.sign(max_score) <= M * nv * (1 + 1e-6)):
+        return False
+    if nv < 2:
+        return abs(fd - f64) <= REL * abs(t64) + ABS
+    fv, yv = f[v], yy[v]
+    df, dy = fv - fv.mean(), yv - yv.mean()
+    sxx, syy = float(np.dot(df, df)), float(np.dot(dy, dy))
+    if sxx == 0.0 or syy == 0.0:
+        r, dr = 0.0, (1.0 if syy > 0.0 and np.any(reach[v] > 0.0) else 0.0)
+    else:
+        r = float(np.dot(df, dy)) / np.sqrt(sxx * syy)
+        grad = dy / np.sqrt(sxx * syy) - r * df / sxx
+        dr = 2.0 * float(np.sum(np.abs(grad) * reach[v]))
+    top = min(1.0, abs(r) + dr)
+    bound = M * nv * (top ** 4 - r ** 4)
+    return abs(fd - f64) <= REL * abs(t64) + bound + ABS
 
 
 def envelope(runs):

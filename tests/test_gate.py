@@ -260,3 +260,79 @@ def test_correlation_floor_only_near_zero():
     planted = S * (1 + 1e-3)
     assert abs(planted - S) < 1e-9 * M * n       # inside the old floor
     assert gate.check(np.array([planted]), *args, max_score=M).n_fail == 1
+
+
+def _window_bound_mse(f, lo, hi, fin, y):
+    yy = y.astype(np.float64)
+    v = fin & np.isfinite(yy)
+    reach = np.where(v, np.maximum(hi - f, f - lo), 0.0)
+    return float(np.sum(2 * np.abs(np.where(v, f - yy, 0.0)) * reach + reach ** 2)) / y.size
+
+
+def test_mse_window_bound_holds_for_outputs_in_the_windows():
+    """The MSE window bound is exact: outputs drawn anywhere in the per-case
+    windows give an MSE within it; a device value beyond it (and outside
+    the runs' envelope) fails, one inside it is excused."""
+    nodes, offs, consts, X, y = _chaotic_case()
+    f, lo, hi, fin = gate.output_windows(nodes, consts, X, y, oracle.MASK_BENCH)
+    assert fin.all()
+    bound = _window_bound_mse(f, lo, hi, fin, y)
+    F64 = float(np.mean((f - y) ** 2))
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        t = rng.uniform(0, 1, y.size)
+        o = lo + t * (hi - lo)
+        assert abs(float(np.mean((o - y) ** 2)) - F64) <= bound
+    args = (nodes, offs, consts, X, y, 0.0, oracle.MASK_BENCH)
+    assert gate.window_excuse(F64 + 0.9 * bound, F64, F64, nodes, consts, X, y,
+                              oracle.MASK_BENCH)
+    assert not gate.window_excuse(F64 + 1.1 * bound + 1e-4 * F64, F64, F64, nodes, consts, X,
+                                  y, oracle.MASK_BENCH)
+    runs = [oracle.fitness(nodes, offs, consts, X, y, 0.0, oracle.MASK_BENCH, m)[0][0]
+            for m in [oracle.M64, oracle.M32E, oracle.M32E_UP, oracle.M32E_DN] +
+            [oracle.M32E_RAND + s for s in range(gate.N_RANDOM)]]
+    env = gate.envelope(runs)
+    planted = max(env[1], F64 + bound) * 1.01 + 1e-3
+    assert gate.check(np.array([planted]), *args).n_fail == 1
+
+
+def test_correlation_window_bound_covers_outputs_in_the_windows():
+    """A weakly correlated program whose outputs carry fp32 error: r over
+    outputs drawn anywhere in the windows stays within the first-order
+    bound (with its factor 2); a device value beyond the bound fails, one
+    inside it is excused, and a correlation term below zero (an r^4 that
+    no outputs can give) fails."""
+    rng = np.random.default_rng(11)
+    n = 2048
+    X = rng.uniform(-3, 3, (2, n)).astype(np.float32)
+    y = (X[1] + np.float32(0.02) * np.sin(X[0] * 40.0)).astype(np.float32)
+    # exp(x0 * 6) / 7 + x1 * 1e-3: large, fp32-rounded outputs, weak r with y
+    nodes, offs, consts = _one([("x", 0), ("c", 0), oracle.MUL, oracle.EXP, ("c", 1), oracle.DIV,
+                                ("x", 1), ("c", 2), oracle.MUL, oracle.ADD], [6.0, 7.0, 1e-3])
+    M = 1e4
+    S, r, st, c1, c2 = oracle.correlation(nodes, offs, consts, X, y, M, oracle.MASK_BENCH,
+                                          return_counts=True)
+    f, lo, hi, fin = gate.output_windows(nodes, consts, X, y, oracle.MASK_BENCH)
+    assert fin.all()
+    yy = y.astype(np.float64)
+    df, dy = f - f.mean(), yy - yy.mean()
+    sxx, syy = df @ df, dy @ dy
+    r0 = (df @ dy) / np.sqrt(sxx * syy)
+    assert abs(r0 - r[0]) < 1e-9
+    reach = np.maximum(hi - f, f - lo)
+    dr = 2 * np.sum(np.abs(dy / np.sqrt(sxx * syy) - r0 * df / sxx) * reach)
+    for _ in range(50):
+        o = lo + rng.uniform(0, 1, n) * (hi - lo)
+        do = o - o.mean()
+        ro = (do @ dy) / np.sqrt((do @ do) * syy)
+        assert abs(ro - r0) <= dr
+    bound = M * n * (min(1.0, abs(r0) + dr) ** 4 - r0 ** 4)
+    T = M * r0 ** 4 * n
+    assert bound < 0.5 * T                       # the bound is informative here
+    F = float(S[0])
+    assert gate.window_excuse(F + 0.9 * bound, F, T, nodes, consts, X, y, oracle.MASK_BENCH, M)
+    assert not gate.window_excuse(F + 1.1 * bound + 1e-4 * T, F, T, nodes, consts, X, y,
+                                  oracle.MASK_BENCH, M)
+    assert not gate.window_excuse(-1.0, F, T, nodes, consts, X, y, oracle.MASK_BENCH, M)
+    args = (nodes, offs, consts, X, y, 0.0, oracle.MASK_BENCH)
+    assert gate.check(np.array([F + 3 * bound + 1e-3 * T]), *args, max_score=M).n_fail == 1

@@ -2,7 +2,8 @@
 C ABI (gp_eval_correlation) against the fp64 oracle's two-pass definition.
 
 Floating point: the gate of oracle.gate in correlation mode (1e-4 relative
-plus an absolute floor of 1e-9 M N, fp32-certified exceptions counted).
+on the correlation term; an absolute floor of 1e-9 M N only where r^4 is
+below 1e-9; fp32-certified exceptions, each bounded, counted).
 Closed forms (a perfect linear relation scores M N, a constant output 0,
 all-invalid outputs -M N) and population independence are checked exactly.
 """
