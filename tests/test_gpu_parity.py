@@ -59,26 +59,39 @@ def test_workload_parity(name, P, n):
 
 
 @pytest.mark.parametrize("n", [4096, 1025])
-def test_invalid_targets_parity(n):
+@pytest.mark.parametrize("matched", [False, True])
+def test_invalid_targets_parity(n, matched):
     """3% of the targets NaN, +inf or -inf (Sec. "Fitness Functions": invalid
     values in the dataset are handled, not removed): matched invalid pairs
     add nothing, a mismatched case gives +inf; the gate separates NaN
-    (structurally invalid) from +inf, and no valid program comes out NaN."""
+    (structurally invalid) from +inf, and no valid program comes out NaN.
+
+    Scattered invalid targets meet finite outputs, so every valid program
+    scores +inf.  With ``matched``, every input of those cases is NaN too:
+    a program that reads a variable outputs NaN there (every op propagates
+    NaN), the pairs match and its score stays finite; a program of
+    constants alone mismatches and scores +inf."""
     gp = _need_gpu()
     from paper_2607_06731_amd import synth
     w = synth.make_workload("generation", n_programs=3000, n_cases=n)
     y = w.data.y.copy()
+    X = w.data.X.copy()
     rng = np.random.default_rng(17)
     idx = rng.choice(y.size, max(1, y.size * 3 // 100), replace=False)
     y[idx] = rng.choice(np.array([np.nan, np.inf, -np.inf], np.float32), idx.size)
-    label = "generation P=3000 n=%d, 3%% invalid targets" % n
+    if matched:
+        X[:, idx] = np.nan
+    label = "generation P=3000 n=%d, 3%% invalid targets%s" % (
+        n, ", NaN inputs there" if matched else "")
     _say(label)
-    F = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, y, w.tax,
-             w.allowed_mask)
-    rep = _gate(F, w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, y, w.tax,
+    F = _run(gp, w.pop.nodes, w.pop.offsets, w.pop.consts, X, y, w.tax, w.allowed_mask)
+    rep = _gate(F, w.pop.nodes, w.pop.offsets, w.pop.consts, X, y, w.tax,
                 w.allowed_mask, label)
     assert not np.isnan(F).any()
-    assert np.isfinite(F).sum() > 0 and np.isinf(F).sum() > 0
+    if matched:
+        assert np.isfinite(F).sum() > 0 and np.isinf(F).sum() > 0
+    else:
+        assert np.all(np.isinf(F))
 
 
 def test_matched_invalid_pairs_exact():
