@@ -173,6 +173,31 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
             double* out_fitness, int32_t* out_status, hipStream_t stream);
 
 /*
+ * gp_eval_noalloc -- gp_eval with no device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Arguments, result and determinism as
+ * gp_eval (the same kernels, so the same bits).  The workspace is a fixed
+ * device array of GP_NOALLOC_WORKSPACE_BYTES (64 MiB) that each GPU the
+ * library runs on holds until the process ends; the first call on a device
+ * takes its address (set-up), later calls make no allocating call of any
+ * kind.  Every depth class runs on `stream` (no side streams) and no
+ * timing events are recorded.  Returns GP_E_TOO_LARGE, before any device
+ * work, when the call needs more workspace than the array holds (about 8
+ * bytes per node plus 27 per program plus 9 per (program, case tile);
+ * gp_workspace_size reports the need, with 25% slack); other errors as
+ * gp_eval.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (several streams or host threads) race, and
+ * the caller must order them (one stream, or events).
+ */
+#define GP_NOALLOC_WORKSPACE_BYTES (64ull << 20)
+int gp_eval_noalloc(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
+                    int64_t n_nodes, const float* consts, int64_t n_consts,
+                    const float* X, int32_t n_vars, int64_t ld_x,
+                    const float* y, int64_t n_cases,
+                    double tax_on_length, uint32_t allowed_op_mask,
+                    double* out_fitness, int32_t* out_status, hipStream_t stream);
+
+/*
  * gp_eval_correlation -- score a population with the correlation fitness
  * (the paper's default, Sec. "Fitness Functions", Eq. 1 and Eq. 2), all
  * pointers device pointers, arguments as for gp_eval (no length tax).

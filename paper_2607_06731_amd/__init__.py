@@ -28,6 +28,7 @@ GP_OK, GP_E_INVALID_ARG, GP_E_BAD_PROGRAM, GP_E_TOO_LARGE, GP_E_NO_MEMORY, GP_E_
 GP_N_OPS = 28
 GP_ALL_OPS = (1 << GP_N_OPS) - 1
 GP_BASE_OPS = (1 << 12) - 1       # LOAD..ABS, the benchmark set
+GP_NOALLOC_WORKSPACE_BYTES = 64 << 20   # the fixed workspace of gp_eval_noalloc
 GP_PROG_BAD_PAIR = 10
 
 _lib = None
@@ -109,6 +110,8 @@ def lib():
         L.gp_eval.argtypes = [vp, vp, i64, i64, vp, i64, vp, i32, i64, vp, i64,
                               ctypes.c_double, u32, vp, vp, vp]
         L.gp_eval.restype = ctypes.c_int
+        L.gp_eval_noalloc.argtypes = L.gp_eval.argtypes
+        L.gp_eval_noalloc.restype = ctypes.c_int
         L.gp_eval_correlation.argtypes = [vp, vp, i64, i64, vp, i64, vp, i32, i64, vp, i64,
                                           ctypes.c_double, u32, vp, vp, vp]
         L.gp_eval_correlation.restype = ctypes.c_int
@@ -243,6 +246,20 @@ def gp_eval(nodes, offsets, consts, X, y, tax_on_length, out_fitness,
     [n_vars, ld_x] (variable major), y float32[>= n_cases], out_fitness
     float64[P], out_status int32[P] or None.
     """
+    return _eval_call(lib().gp_eval, nodes, offsets, consts, X, y, tax_on_length, out_fitness,
+                      out_status, allowed_op_mask, ld_x, n_cases, stream)
+
+
+def gp_eval_noalloc(nodes, offsets, consts, X, y, tax_on_length, out_fitness,
+                    out_status=None, allowed_op_mask=0, ld_x=None, n_cases=None, stream=None):
+    """gp_eval on the library's fixed device workspace (no allocation);
+    arguments and results as gp_eval."""
+    return _eval_call(lib().gp_eval_noalloc, nodes, offsets, consts, X, y, tax_on_length,
+                      out_fitness, out_status, allowed_op_mask, ld_x, n_cases, stream)
+
+
+def _eval_call(fn, nodes, offsets, consts, X, y, tax_on_length, out_fitness, out_status,
+               allowed_op_mask, ld_x, n_cases, stream):
     import torch
     P = offsets.numel() - 1
     if out_fitness.numel() != P:
@@ -252,12 +269,12 @@ def gp_eval(nodes, offsets, consts, X, y, tax_on_length, out_fitness,
     n_vars = X.shape[0]
     ld = X.shape[1] if ld_x is None else int(ld_x)
     n = y.numel() if n_cases is None else int(n_cases)
-    rc = lib().gp_eval(_dev_ptr(nodes, torch.uint32, "nodes"), _dev_ptr(offsets, torch.int64, "offsets"),
-                       P, nodes.numel(), _dev_ptr(consts, torch.float32, "consts"), consts.numel(),
-                       _dev_ptr(X, torch.float32, "X"), n_vars, ld,
-                       _dev_ptr(y, torch.float32, "y"), n, float(tax_on_length),
-                       int(allowed_op_mask), _dev_ptr(out_fitness, torch.float64, "out_fitness"),
-                       _dev_ptr(out_status, torch.int32, "out_status"), _stream_handle(stream))
+    rc = fn(_dev_ptr(nodes, torch.uint32, "nodes"), _dev_ptr(offsets, torch.int64, "offsets"),
+            P, nodes.numel(), _dev_ptr(consts, torch.float32, "consts"), consts.numel(),
+            _dev_ptr(X, torch.float32, "X"), n_vars, ld,
+            _dev_ptr(y, torch.float32, "y"), n, float(tax_on_length),
+            int(allowed_op_mask), _dev_ptr(out_fitness, torch.float64, "out_fitness"),
+            _dev_ptr(out_status, torch.int32, "out_status"), _stream_handle(stream))
     _check(rc)
     return out_fitness
 

@@ -2591,6 +2591,71 @@ int eval_problem(const Problem& pb, hipStream_t stream)
     return GP_OK;
 }
 
+// ------------------------------------------------- no-allocation form
+// gp_eval_noalloc keeps its workspace in one fixed device array per GPU
+// instead of memory the library allocates.  In host code `scratch` names a
+// host-side stand-in, never the device memory: its device address is taken
+// with hipGetSymbolAddress once per device (with that device current, each
+// GPU holding its own copy) and only that address reaches kernels.  Every
+// kernel of the call initializes what it reads (counters, flags, partials),
+// so no clearing is needed between calls; calls that overlap in time on one
+// GPU share the array and race.
+constexpr size_t kScratchBytes = GP_NOALLOC_WORKSPACE_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// This device's scratch address; the first call on a device takes it and
+// also caches the device's CU count (the only set-up that may touch host
+// containers).
+int scratch_for_device(void** out)
+{
+    int dev = 0;
+    GP_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return set_error(GP_E_INVALID_ARG, "device %d: the fixed workspace covers devices 0..%d", dev,
+                         kMaxScratchDevices - 1);
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return set_error(GP_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        }
+        int cus = 0;
+        const int rc = device_cus(&cus);
+        if (rc != GP_OK) return rc;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GP_OK;
+}
+
+// gp_eval's work on the fixed array: every depth class on the caller's
+// stream (no side streams), no timing events, no allocation.
+int eval_problem_noalloc(const Problem& pb, hipStream_t stream)
+{
+    int rc = check_problem(pb);
+    if (rc != GP_OK || pb.n_programs == 0) return rc;
+    void* base = nullptr;
+    if ((rc = scratch_for_device(&base)) != GP_OK) return rc;
+    Tuning tu;
+    tu.concurrent = 0;
+    EvalLaunch el;
+    if ((rc = configure_eval(pb, tu, &el)) != GP_OK) return rc;
+    if (el.layout.total > kScratchBytes)
+        return set_error(GP_E_TOO_LARGE, "the call needs %zu bytes of workspace; the fixed array holds %zu",
+                         el.layout.total, kScratchBytes);
+    const Staged st = carve(base, el.layout);
+    SideStreams unused;
+    CallEvents ce;
+    if ((rc = ce.begin(false)) != GP_OK) return rc;
+    return enqueue_eval(pb, tu, el, st, unused, stream, ce);
+}
+
 // ------------------------------------------------- Monte-Carlo ranking
 // The paper's ranking without a sort (Sec. "Monte-Carlo Ranking", Table 2):
 // a random sample of the population's fitness values estimates the
@@ -2720,6 +2785,18 @@ int gp_eval(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
     const gp_problem d{nodes, offsets, n_programs, n_nodes, consts, n_consts, X, n_vars, ld_x,
                        y, n_cases, tax_on_length, allowed_op_mask, out_fitness, out_status};
     return eval_problem(make_problem(&d), stream);
+}
+
+int gp_eval_noalloc(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,
+                    int64_t n_nodes, const float* consts, int64_t n_consts,
+                    const float* X, int32_t n_vars, int64_t ld_x,
+                    const float* y, int64_t n_cases,
+                    double tax_on_length, uint32_t allowed_op_mask,
+                    double* out_fitness, int32_t* out_status, hipStream_t stream)
+{
+    const gp_problem d{nodes, offsets, n_programs, n_nodes, consts, n_consts, X, n_vars, ld_x,
+                       y, n_cases, tax_on_length, allowed_op_mask, out_fitness, out_status};
+    return eval_problem_noalloc(make_problem(&d), stream);
 }
 
 int gp_eval_correlation(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs,

@@ -89,6 +89,18 @@ def test_eval_rejects_bad_arguments_before_device_work(L):
     assert L.gp_eval(None, c, 0, 0, None, 0, None, 0, 1, c, 1, 0.0, 0, None, None, None) == gp.GP_OK
 
 
+def test_noalloc_rejects_bad_arguments_before_device_work(L):
+    """gp_eval_noalloc checks its arguments as gp_eval does, before it takes
+    the fixed workspace's device address."""
+    c = ctypes.c_void_p(1)
+    f = L.gp_eval_noalloc
+    assert f(c, c, -1, 0, c, 0, c, 1, 1, c, 1, 0.0, 0, c, None, None) == gp.GP_E_INVALID_ARG
+    assert f(c, c, 1, 1, c, 0, c, 1, 10, c, 11, 0.0, 0, c, None, None) == gp.GP_E_INVALID_ARG
+    assert f(c, c, 1, 1, c, 1 << 25, c, 1, 10, c, 10, 0.0, 0, c, None, None) == gp.GP_E_TOO_LARGE
+    assert f(c, c, 1, 1, c, 0, c, 1, 1, c, 1, 0.0, 1 << 20, c, None, None) == gp.GP_E_INVALID_ARG
+    assert f(None, c, 0, 0, None, 0, None, 0, 1, c, 1, 0.0, 0, None, None, None) == gp.GP_OK
+
+
 def test_correlation_rejects_bad_arguments_before_device_work(L):
     c = ctypes.c_void_p(1)
     for M in (float("nan"), float("inf")):
