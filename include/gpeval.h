@@ -70,7 +70,8 @@ enum gp_status {
     GP_E_BAD_PROGRAM = -2,   /* gp_validate found an invalid program */
     GP_E_TOO_LARGE = -3,     /* a size exceeds a documented limit */
     GP_E_NO_MEMORY = -4,     /* device workspace allocation failed */
-    GP_E_HIP = -5            /* a HIP runtime call failed */
+    GP_E_HIP = -5,           /* a HIP runtime call failed */
+    GP_E_CANCELLED = -6      /* a server request was cancelled (gp_server_cancel) */
 };
 
 /* Opcodes (GCL command table; ABS is not a GCL command).  0-11 are the
@@ -107,13 +108,14 @@ enum gp_op {
     GP_N_OPS = 28
 };
 #define GP_ALL_OPS ((1u << GP_N_OPS) - 1u)
-/* The benchmark set LOAD..ABS.  The scoring entry points (gp_eval,
+/* The benchmark set LOAD..ABS.  Every entry point takes op masks within
+ * GP_ALL_OPS (a bit beyond it gives GP_E_INVALID_ARG before device work).
+ * For the scoring entry points (gp_eval, gp_eval_noalloc,
  * gp_eval_correlation, gp_eval_reward, gp_eval_batched, plans, the server)
- * take op masks within it: 0 means GP_BASE_OPS for them, and a mask with any
- * other bit gives GP_E_INVALID_ARG before device work.  gp_validate and
- * gp_predict take the whole command table (0 means GP_ALL_OPS); gp_predict
- * runs an interpreter built for it when its mask reaches beyond
- * GP_BASE_OPS. */
+ * 0 means GP_BASE_OPS; for gp_validate and gp_predict 0 means GP_ALL_OPS.
+ * A mask that reaches beyond GP_BASE_OPS runs an interpreter built for the
+ * whole command table (same values for the benchmark set's commands; more
+ * registers, so fewer wavefronts per SIMD). */
 #define GP_BASE_OPS ((1u << 12) - 1u)
 /* COPY/PASTE variable names: @0 .. @15.  A valid program copies into a free
  * variable only, pastes a held one only, and ends with every variable
@@ -160,8 +162,8 @@ int gp_validate(const uint32_t* nodes, const int64_t* offsets, int64_t n_program
  * synchronized.  Inputs must stay alive until then.  The library keeps a
  * per-(device, stream) workspace that grows on demand; concurrent calls on
  * one stream from several host threads are not supported.
- * allowed_op_mask: within GP_BASE_OPS (0 means GP_BASE_OPS; any other bit
- * is GP_E_INVALID_ARG).
+ * allowed_op_mask: within GP_ALL_OPS (0 means GP_BASE_OPS; a bit beyond
+ * GP_ALL_OPS is GP_E_INVALID_ARG).
  * Determinism: a program's result depends only on the program, the data and
  * n_cases, never on the rest of the population.
  */
@@ -410,7 +412,11 @@ void gp_release_workspaces(void);
  *     (continuous batching);
  *   - results are copied back per request; latency is measured from
  *     gp_server_submit to the moment the results are in the caller's
- *     arrays.
+ *     arrays;
+ *   - a failed launch fails no request by itself: each request it held is
+ *     retried once in launches of its own, and only a request whose retry
+ *     fails too completes with the error (the others are unaffected);
+ *   - a request can be cancelled (gp_server_cancel) until it completes.
  * Each program's result is bit-identical to gp_eval of its population
  * alone.  A scheduler thread owned by the server does all device work; the
  * functions below may be called from any thread.
@@ -429,7 +435,7 @@ typedef struct {
     int32_t max_batch_chunks;       /* chunks per launch, 1..4096 (0: 1024) */
     int32_t one_launch_per_request; /* 1: FIFO, one gp_eval per request on one
                                        stream, no chunking (comparison mode) */
-    uint32_t allowed_op_mask;       /* within GP_BASE_OPS (0: GP_BASE_OPS) */
+    uint32_t allowed_op_mask;       /* within GP_ALL_OPS (0: GP_BASE_OPS) */
 } gp_server_config;
 
 typedef struct {
@@ -441,6 +447,9 @@ typedef struct {
     double wall_ms;                 /* since creation or the last reset */
     int64_t device_bytes_in_use, device_bytes_peak;
     int32_t waiting, in_flight;     /* requests not admitted / admitted, not done */
+    int64_t cancelled;              /* requests completed with GP_E_CANCELLED */
+    int64_t retried;                /* requests sent to a retry of their own
+                                       after a failed launch */
 } gp_server_stats;
 
 /* Creates the server, its streams (default priority), device arena and
@@ -469,6 +478,13 @@ int gp_server_submit(gp_server* server, int32_t dataset_id, const uint32_t* node
                      int64_t n_nodes, const int64_t* offsets, int64_t n_programs,
                      const float* consts, int64_t n_consts, double* out_fitness,
                      int32_t* out_status, int64_t* ticket);
+
+/* Cancels a pending request: one that has not started completes at once
+ * with GP_E_CANCELLED; one with chunks on the device launches no further
+ * chunk and completes with GP_E_CANCELLED once they have finished (its
+ * output arrays are not written).  GP_E_INVALID_ARG for a ticket that is
+ * unknown, completed or already cancelled. */
+int gp_server_cancel(gp_server* server, int64_t ticket);
 
 /* Waits up to timeout_ms (< 0: no limit, 0: just look) for completed
  * requests and returns up to max_n of them (ticket and result code, GP_OK

@@ -25,6 +25,7 @@ LIB_PATH = os.environ.get("GPEVAL_LIB") or os.path.join(_PKG, "libgpeval.so")
 
 GP_OK, GP_E_INVALID_ARG, GP_E_BAD_PROGRAM, GP_E_TOO_LARGE, GP_E_NO_MEMORY, GP_E_HIP = \
     0, -1, -2, -3, -4, -5
+GP_E_CANCELLED = -6
 GP_N_OPS = 28
 GP_ALL_OPS = (1 << GP_N_OPS) - 1
 GP_BASE_OPS = (1 << 12) - 1       # LOAD..ABS, the benchmark set
@@ -84,7 +85,8 @@ class GPServerStats(ctypes.Structure):
                 ("latency_max_ms", ctypes.c_double), ("latency_mean_ms", ctypes.c_double),
                 ("busy_ms", ctypes.c_double), ("wall_ms", ctypes.c_double),
                 ("device_bytes_in_use", ctypes.c_int64), ("device_bytes_peak", ctypes.c_int64),
-                ("waiting", ctypes.c_int32), ("in_flight", ctypes.c_int32)]
+                ("waiting", ctypes.c_int32), ("in_flight", ctypes.c_int32),
+                ("cancelled", ctypes.c_int64), ("retried", ctypes.c_int64)]
 
 
 class GPError(RuntimeError):
@@ -156,6 +158,8 @@ def lib():
         L.gp_server_wait.argtypes = [vp, i64, ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32)]
         L.gp_server_wait.restype = ctypes.c_int
+        L.gp_server_cancel.argtypes = [vp, i64]
+        L.gp_server_cancel.restype = ctypes.c_int
         L.gp_server_get_stats.argtypes = [vp, ctypes.POINTER(GPServerStats)]
         L.gp_server_get_stats.restype = ctypes.c_int
         L.gp_server_reset_stats.argtypes = [vp]
@@ -641,6 +645,10 @@ class Server:
             return None
         _, fit, st = self._pending.pop(int(ticket))
         return res.value, fit, st
+
+    def cancel(self, ticket):
+        """Cancels a pending request (it completes with GP_E_CANCELLED)."""
+        _check(lib().gp_server_cancel(self._h, int(ticket)))
 
     def stats(self):
         s = GPServerStats()

@@ -1433,7 +1433,7 @@ __device__ __forceinline__ void corr_wave_reduce(CorrLane& c)
     }
 }
 
-template <int MAXD, int K, int FIT>
+template <int MAXD, int K, int FIT, bool EXT>
 __global__ __launch_bounds__(kWG) void k_eval(
     const uint2* __restrict__ code, const ProgMeta* __restrict__ meta,
     const int32_t* __restrict__ order, const int32_t* __restrict__ class_info,
@@ -1549,11 +1549,16 @@ __global__ __launch_bounds__(kWG) void k_eval(
             if (tid == 0) s_next = 0u;
             __syncthreads();
             // each wavefront takes the group's programs one at a time and
-            // runs each over the whole window
+            // runs each over the whole window.  The loop has no lane-0-only
+            // region at its head or tail: every lane adds one to the claim
+            // counter (a wavefront's 64 claims are one block of 64, so the
+            // block index is the program), and every lane writes the same
+            // accumulator value after the wavefront tree.  A lane-0-only
+            // claim followed by a lane-0-only update lets the optimizer rotate
+            // the two into one region that lane 0 alone runs between
+            // iterations, so the other lanes would re-read a stale claim.
             for (;;) {
-                uint32_t gq = 0u;
-                if (lane == 0) gq = atomicAdd(&s_next, 1u);
-                const int g = (int)__builtin_amdgcn_readfirstlane(gq);
+                const int g = (int)(__builtin_amdgcn_readfirstlane(atomicAdd(&s_next, 1u)) >> 6);
                 if (g >= gn) break;
                 const int pid = order[obase + g];
                 const ProgMeta m = meta[pid];
@@ -1569,7 +1574,7 @@ __global__ __launch_bounds__(kWG) void k_eval(
                 for (int b = 0; b < nw; ++b) {
                     const float* blk = xt + b * rows * SUB;
                     float tos[K];
-                    run_program<MAXD, K, false>(code + m.start, blk + lane, tos);
+                    run_program<MAXD, K, EXT>(code + m.start, blk + lane, tos);
                     const int64_t base = (first + b) * SUB;
                     const float* yt = blk + n_vars * SUB;
                     if constexpr (FIT == kFitCorr) {
@@ -1624,8 +1629,10 @@ __global__ __launch_bounds__(kWG) void k_eval(
                 }
                 if constexpr (FIT == kFitCorr) {
                     corr_wave_reduce(cl);
-                    // the windows add up in order, whichever wavefront ran them
-                    if (lane == 0) {
+                    // the windows add up in order, whichever wavefront ran
+                    // them (every lane holds the same sums and writes the
+                    // same merged value)
+                    {
                         CorrPart w;
                         w.s = cs; w.t = ct;
                         w.sd = cl.sd; w.sdd = cl.sdd; w.se = cl.se; w.see = cl.see;
@@ -1634,10 +1641,11 @@ __global__ __launch_bounds__(kWG) void k_eval(
                         corr_merge(cacc[g], w);
                     }
                 } else if constexpr (FIT == kFitReward) {
-                    // integers: exact in any order
+                    // integers: exact in any order (every lane holds the
+                    // same total and writes the same sum)
 #pragma unroll
                     for (int off = 32; off >= 1; off >>= 1) rl += __shfl_xor(rl, off);
-                    if (lane == 0) racc[g] += rl;
+                    racc[g] += rl;
                 } else {
                 // wavefront tree: every lane ends with the same pair
 #pragma unroll
@@ -1648,8 +1656,9 @@ __global__ __launch_bounds__(kWG) void k_eval(
                 }
                 const bool wave_bad = __ballot(bad) != 0ull;
                 // one wavefront per program and window: the windows add up
-                // in order, whichever wavefront ran them
-                if (lane == 0) {
+                // in order, whichever wavefront ran them (every lane writes
+                // the same pair)
+                {
                     float h = acc[g].x, l = acc[g].y;
                     acc_pair(h, l, hi, lo_);
                     acc[g] = make_float2(h, l);
@@ -2112,11 +2121,8 @@ int check_problem(const Problem& pb)
     int rc = check_common(pb.n_programs, pb.n_nodes, batched ? 0 : pb.one_req.n_consts,
                           pb.max_vars, batched ? pb.max_cases : pb.one.ld_x, pb.max_cases);
     if (rc != GP_OK) return rc;
-    // scoring runs the benchmark set's interpreter (the whole command table
-    // is evaluated by gp_predict)
-    if (pb.need_out && (pb.allowed & ~GP_BASE_OPS))
-        return set_error(GP_E_INVALID_ARG, "allowed_op_mask reaches beyond GP_BASE_OPS: scoring "
-                                           "takes the benchmark set, gp_predict the whole table");
+    if (pb.allowed & ~GP_ALL_OPS)
+        return set_error(GP_E_INVALID_ARG, "allowed_op_mask has bits beyond GP_ALL_OPS");
     if (batched) {
         if (!pb.ds_dev) return set_error(GP_E_INVALID_ARG, "datasets_dev is NULL");
         if (pb.n_ds < 1) return set_error(GP_E_INVALID_ARG, "n_datasets < 1");
@@ -2175,21 +2181,21 @@ size_t eval_lds_bytes(int n_vars, int G)
     return eval_tile_floats<MAXD, K>(n_vars) * sizeof(float) + acc;
 }
 
-// Whether a gp_predict call runs the interpreter built for the whole
-// command table (its op mask reaches beyond the benchmark set).
+// Whether a call runs the interpreter built for the whole command table
+// (its op mask reaches beyond the benchmark set).
 inline bool pb_ext(uint32_t allowed) { return (allowed & ~GP_BASE_OPS) != 0u; }
 
 // Grid size of one class kernel (LDS attribute set outside any capture).
-template <int MAXD, int K, int FIT>
+template <int MAXD, int K, int FIT, bool EXT>
 int eval_grid(int n_vars, int G, int wg_per_cu, int cus, int* grid, size_t* lds_out)
 {
     const size_t lds = eval_lds_bytes<MAXD, K, FIT>(n_vars, G);
     if (lds > 64 * 1024) {
-        GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval<MAXD, K, FIT>),
+        GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval<MAXD, K, FIT, EXT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     }
     int per_cu = 0;
-    GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval<MAXD, K, FIT>, kWG, lds));
+    GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval<MAXD, K, FIT, EXT>, kWG, lds));
     if (per_cu < 1) return set_error(GP_E_TOO_LARGE, "n_vars=%d needs %zu bytes of LDS per workgroup", n_vars, lds);
     if (wg_per_cu > 0 && wg_per_cu < per_cu) per_cu = wg_per_cu;
     *grid = cus * per_cu;
@@ -2212,13 +2218,20 @@ int group_capacity(const Problem& pb, const Tuning& tu)
     return pb.fit == kFitCorr && tu.G > kCorrMaxG ? kCorrMaxG : tu.G;
 }
 
-template <int FIT>
+template <int FIT, bool EXT>
 int eval_grids(const Problem& pb, const Tuning& tu, int G, int cus, EvalLaunch* el)
 {
     int rc;
-    if ((rc = eval_grid<8, 4, FIT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
-    if ((rc = eval_grid<16, kK1, FIT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
-    return eval_grid<32, 2, FIT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2]);
+    if ((rc = eval_grid<8, 4, FIT, EXT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
+    if ((rc = eval_grid<16, kK1, FIT, EXT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
+    return eval_grid<32, 2, FIT, EXT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2]);
+}
+
+template <int FIT>
+int eval_grids(const Problem& pb, const Tuning& tu, int G, int cus, EvalLaunch* el)
+{
+    return pb_ext(pb.allowed) ? eval_grids<FIT, true>(pb, tu, G, cus, el)
+                              : eval_grids<FIT, false>(pb, tu, G, cus, el);
 }
 
 int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
@@ -2268,14 +2281,22 @@ int enqueue_stage(const Problem& pb, const Staged& st, hipStream_t stream)
     return GP_OK;
 }
 
-// One class kernel of the evaluation.
+// One class kernel of the evaluation (EXT: the interpreter for the whole
+// command table, picked by the op mask).
 template <int MD, int KK, int FIT>
-void launch_eval(dim3 g, size_t lds, hipStream_t sc, const Staged& st, int c,
+void launch_eval(bool ext, dim3 g, size_t lds, hipStream_t sc, const Staged& st, int c,
                  const EvalConst& ea)
 {
-    hipLaunchKernelGGL((k_eval<MD, KK, FIT>), g, dim3(kWG), lds, sc, st.code, st.meta, st.order,
-                       st.class_info, st.counters + c, st.ds, st.seg_ds, st.seg_cnt, st.seg_pos,
-                       st.item_pre, st.class_g, st.part, st.part_bad, st.part_corr, ea);
+    if (ext)
+        hipLaunchKernelGGL((k_eval<MD, KK, FIT, true>), g, dim3(kWG), lds, sc, st.code, st.meta,
+                           st.order, st.class_info, st.counters + c, st.ds, st.seg_ds, st.seg_cnt,
+                           st.seg_pos, st.item_pre, st.class_g, st.part, st.part_bad, st.part_corr,
+                           ea);
+    else
+        hipLaunchKernelGGL((k_eval<MD, KK, FIT, false>), g, dim3(kWG), lds, sc, st.code, st.meta,
+                           st.order, st.class_info, st.counters + c, st.ds, st.seg_ds, st.seg_cnt,
+                           st.seg_pos, st.item_pre, st.class_g, st.part, st.part_bad, st.part_corr,
+                           ea);
 }
 
 // The whole evaluation as stream work (no allocation, no synchronization:
@@ -2306,6 +2327,7 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
         GP_HIP_TRY(hipEventRecord(side.fork, stream));
         for (auto& x : side.s) GP_HIP_TRY(hipStreamWaitEvent(x, side.fork, 0));
     }
+    const bool ext = pb_ext(pb.allowed);
     for (int c = 0; c < kClasses; ++c) {
         if ((rc = ce.mark(1 + c, stream)) != GP_OK) return rc;
         const hipStream_t sc = (tu.concurrent && c > 0) ? side.s[c - 1] : stream;
@@ -2314,11 +2336,11 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
 #define GP_LAUNCH_EVAL(MD, KK)                                                                 \
         do {                                                                                   \
             if (pb.fit == kFitCorr)                                                            \
-                launch_eval<MD, KK, kFitCorr>(g, el.lds[c], sc, st, c, ea);                    \
+                launch_eval<MD, KK, kFitCorr>(ext, g, el.lds[c], sc, st, c, ea);               \
             else if (pb.fit == kFitReward)                                                     \
-                launch_eval<MD, KK, kFitReward>(g, el.lds[c], sc, st, c, ea);                  \
+                launch_eval<MD, KK, kFitReward>(ext, g, el.lds[c], sc, st, c, ea);             \
             else                                                                               \
-                launch_eval<MD, KK, kFitMse>(g, el.lds[c], sc, st, c, ea);                     \
+                launch_eval<MD, KK, kFitMse>(ext, g, el.lds[c], sc, st, c, ea);                \
         } while (0)
         if (c == 0) {
             ea.tile_floats = (int32_t)eval_tile_floats<8, 4>(pb.max_vars);

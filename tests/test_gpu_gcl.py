@@ -1,8 +1,7 @@
 """GPU parity of the whole GCL command table (the paper's Table of GCL
 commands) through the C ABI: the interpreter built for the full table runs
-when a gp_predict call's op mask reaches beyond the benchmark set.  The
-scoring entry points take the benchmark set only; their tests with the
-whole table are kept below, skipped (see the skip reason).
+when a call's op mask reaches beyond the benchmark set, for per-case
+outputs (gp_predict) and for scoring (gp_eval, correlation, reward).
 
 Bit-exact cases: programs of stack moves, variables and the commands whose
 fp32 result is one correctly rounded operation (+, -, *, protected /, |a|,
@@ -251,9 +250,6 @@ def test_paper_genomes_run_on_the_gpu():
         assert np.all(np.abs(out - ref) <= 1e-5 * scale)
 
 
-@pytest.mark.skip(reason="scoring with the whole command table is switched off: its k_eval "
-                  "build stopped responding on the GCL workload and no cause was found by "
-                  "reading; the table is evaluated by gp_predict")
 @pytest.mark.parametrize("P,n", [(4000, None), (3000, 1025), (2000, 7)])
 def test_gcl_workload_parity(P, n):
     gp = _gp()
@@ -272,9 +268,6 @@ def test_gcl_workload_parity(P, n):
     assert np.array_equal(st, st_o)
 
 
-@pytest.mark.skip(reason="scoring with the whole command table is switched off: its k_eval "
-                  "build stopped responding on the GCL workload and no cause was found by "
-                  "reading; the table is evaluated by gp_predict")
 def test_gcl_workload_other_fitness_functions():
     gp = _gp()
     from paper_2607_06731_amd import synth
@@ -293,25 +286,20 @@ def test_gcl_workload_other_fitness_functions():
     assert rep.ok(), rep.failures[:10]
 
 
-@pytest.mark.skip(reason="scoring with the whole command table is switched off: its k_eval "
-                  "build stopped responding on the GCL workload and no cause was found by "
-                  "reading; the table is evaluated by gp_predict")
 def test_base_and_full_table_interpreters_agree():
     """A benchmark-set population scores with the same bits through the
-    full-table interpreter (mask 0 = every op) and the benchmark-set one."""
+    full-table interpreter (mask GP_ALL_OPS) and the benchmark-set one."""
     gp = _gp()
     from paper_2607_06731_amd import synth
     w = synth.make_workload("generation", n_programs=4000, n_cases=2048)
     F_base = gp.evaluate(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
                          w.allowed_mask)
-    F_full = gp.evaluate(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax, 0)
+    F_full = gp.evaluate(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
+                         gp.GP_ALL_OPS)
     _say("base vs full-table interpreter")
     assert np.array_equal(F_base, F_full, equal_nan=True)
 
 
-@pytest.mark.skip(reason="scoring with the whole command table is switched off: its k_eval "
-                  "build stopped responding on the GCL workload and no cause was found by "
-                  "reading; the table is evaluated by gp_predict")
 def test_gcl_full_size_sampled():
     """The GCL workload at full size (20,000 programs x 2,048 cases), gated
     on a seeded length-stratified sample."""

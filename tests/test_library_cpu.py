@@ -97,7 +97,7 @@ def test_noalloc_rejects_bad_arguments_before_device_work(L):
     assert f(c, c, -1, 0, c, 0, c, 1, 1, c, 1, 0.0, 0, c, None, None) == gp.GP_E_INVALID_ARG
     assert f(c, c, 1, 1, c, 0, c, 1, 10, c, 11, 0.0, 0, c, None, None) == gp.GP_E_INVALID_ARG
     assert f(c, c, 1, 1, c, 1 << 25, c, 1, 10, c, 10, 0.0, 0, c, None, None) == gp.GP_E_TOO_LARGE
-    assert f(c, c, 1, 1, c, 0, c, 1, 1, c, 1, 0.0, 1 << 20, c, None, None) == gp.GP_E_INVALID_ARG
+    assert f(c, c, 1, 1, c, 0, c, 1, 1, c, 1, 0.0, 1 << 28, c, None, None) == gp.GP_E_INVALID_ARG
     assert f(None, c, 0, 0, None, 0, None, 0, 1, c, 1, 0.0, 0, None, None, None) == gp.GP_OK
 
 
@@ -130,12 +130,12 @@ def test_reward_rejects_bad_arguments_before_device_work(L):
                                 None, None) == gp.GP_OK
 
 
-def test_scoring_rejects_masks_beyond_the_benchmark_set(L):
+def test_scoring_rejects_masks_beyond_the_command_table(L):
     c = ctypes.c_void_p(1)
-    for mask in (gp.GP_ALL_OPS, 1 << 12, gp.GP_BASE_OPS | (1 << 27)):
+    for mask in (1 << 28, gp.GP_ALL_OPS | (1 << 31), gp.GP_BASE_OPS | (1 << 29)):
         assert L.gp_eval(c, c, 1, 1, c, 0, c, 1, 1, c, 1, 0.0, mask, c, None,
                          None) == gp.GP_E_INVALID_ARG
-        assert b"GP_BASE_OPS" in L.gp_last_error()
+        assert b"GP_ALL_OPS" in L.gp_last_error()
         assert L.gp_eval_correlation(c, c, 1, 1, c, 0, c, 1, 1, c, 1, 1e4, mask, c, None,
                                      None) == gp.GP_E_INVALID_ARG
         assert L.gp_eval_reward(c, c, 1, 1, c, 0, c, 1, 1, c, 1, 1e4, 1, mask, c, None,
