@@ -612,8 +612,9 @@ class Server:
         offsets = np.ascontiguousarray(offsets, np.int64)
         consts = np.ascontiguousarray(consts, np.float32)
         P = offsets.size - 1
-        fit = np.empty(P, np.float64)
-        st = np.empty(P, np.int32)
+        # written by the server only when the request completes with GP_OK
+        fit = np.full(P, -1.0, np.float64)
+        st = np.full(P, -1, np.int32)
         t = ctypes.c_int64()
         _check(lib().gp_server_submit(self._h, int(dataset_id),
                                       nodes.ctypes.data if nodes.size else None, nodes.size,

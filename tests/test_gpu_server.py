@@ -140,3 +140,44 @@ def test_invalid_programs_and_dataset_lifetime():
         t2 = srv.submit(d2, np.zeros(0, np.uint32), np.zeros(1, np.int64), np.zeros(0, np.float32))
         rc2, fit2, _ = srv.wait(t2, timeout_ms=30000.0)
         assert rc2 == 0 and fit2.size == 0
+
+
+def test_cancellation():
+    """Requests cancelled while waiting or in flight complete with
+    GP_E_CANCELLED and their output arrays are never written; the others
+    still equal gp_eval alone; a completed ticket cannot be cancelled."""
+    gp = _gp()
+    import time
+    runs, reqs = _workload(16, seed=17, max_pop=3000, max_cases=8192, n_runs=2)
+    alone = _alone(gp, runs, reqs, 0.0)
+    _say("cancellation")
+    with gp.Server(device_budget_bytes=64 << 20, chunk_node_evals=1 << 22, n_streams=1) as srv:
+        ids = [srv.add_dataset(r.data.X, r.data.y, 0.0) for r in runs]
+        tickets = [srv.submit(ids[i], p.nodes, p.offsets, p.consts) for i, p in reqs]
+        cancel = set()
+        for t in tickets[1::3]:
+            try:
+                srv.cancel(t)
+                cancel.add(t)
+            except gp.GPError as e:          # it had completed already
+                assert e.code == gp.GP_E_INVALID_ARG
+        assert cancel
+        got = {}
+        t0 = time.time()
+        while len(got) < len(tickets):
+            assert time.time() - t0 < 60.0, "requests did not complete"
+            for t, rc, fit, st in srv.poll(timeout_ms=100.0):
+                got[t] = (rc, fit, st)
+        with pytest.raises(gp.GPError) as e:
+            srv.cancel(tickets[0])
+        assert e.value.code == gp.GP_E_INVALID_ARG
+        stats = srv.stats()
+    for k, t in enumerate(tickets):
+        rc, fit, st = got[t]
+        if t in cancel:
+            assert rc == gp.GP_E_CANCELLED
+            assert np.all(fit == -1.0) and np.all(st == -1)
+        else:
+            assert rc == 0
+            assert np.array_equal(fit, alone[k], equal_nan=True)
+    assert stats["cancelled"] == len(cancel) and stats["completed"] == len(tickets) - len(cancel)
