@@ -147,6 +147,57 @@ def measured_counters(workload):
     return out
 
 
+def executed_node_counts(nodes, offsets, chunk=100_000):
+    """Per program, the nodes one case really evaluates once staging has
+    folded every constant subtree into one constant: variable leaves, plus
+    each operator whose value depends on a variable together with its
+    constant operands (a constant operand is one folded value), plus one for
+    a program that is constant as a whole.  Benchmark-set opcodes only
+    (LOAD 0, CONST 1, ADD..DIV 2..5, the unary ops 6..11).  Stacks of
+    constant flags, all programs of a chunk in step by token position."""
+    import numpy as np
+    nodes = np.asarray(nodes, np.uint32)
+    offsets = np.asarray(offsets, np.int64)
+    P = offsets.size - 1
+    lens = np.diff(offsets)
+    out = np.zeros(P, np.int64)
+    for c0 in range(0, P, chunk):
+        c1 = min(P, c0 + chunk)
+        n = c1 - c0
+        L = int(lens[c0:c1].max()) if n else 0
+        pos = offsets[c0:c1, None] + np.arange(L)[None, :]
+        valid = np.arange(L)[None, :] < lens[c0:c1, None]
+        ops = np.where(valid, nodes[np.minimum(pos, nodes.size - 1)] & 0xFF, 255).astype(np.int32)
+        stack = np.zeros((n, 34), bool)
+        depth = np.zeros(n, np.int64)          # index of the top element (0: empty)
+        cnt = np.zeros(n, np.int64)
+        rows = np.arange(n)
+        for t in range(L):
+            op = ops[:, t]
+            leaf = op <= 1
+            un = (op >= 6) & (op <= 11)
+            bi = (op >= 2) & (op <= 5)
+            # leaves: push; a variable is evaluated per case
+            d1 = np.minimum(depth + 1, 33)
+            stack[rows[leaf], d1[leaf]] = op[leaf] == 1
+            cnt += leaf & (op == 0)
+            depth = np.where(leaf, d1, depth)
+            # unary: constant stays constant, otherwise one evaluation
+            top = stack[rows, depth]
+            cnt += un & ~top
+            # binary: a constant operand of a non-constant operator is one value
+            a = stack[rows, np.maximum(depth - 1, 0)]
+            b = top
+            c = a & b
+            cnt += (bi & ~c).astype(np.int64) + (bi & ~c & a) + (bi & ~c & b)
+            nd = np.where(bi, depth - 1, depth)
+            stack[rows[bi], nd[bi]] = c[bi]
+            depth = nd
+        cnt += stack[rows, depth]             # a program that is constant as a whole
+        out[c0:c1] = cnt
+    return out
+
+
 def copy_calibration(n_bytes):
     import torch
     a = torch.empty(n_bytes // 4, dtype=torch.float32, device="cuda")
@@ -252,11 +303,24 @@ def throughput(args):
     ms0 = phases["eval_d8"] / max(n_calls, 1)
     counters = measured_counters(args.workload) if args.fitness == "mse" else {}
     achieved = evals0 / (ms0 * 1e-3) / 1e12
+    # node evaluations the kernel really performs (constant subtrees folded
+    # once per program at staging)
+    ex = executed_node_counts(w.pop.nodes, w.pop.offsets)
+    ex0 = int(ex[cls0].sum()) * w.data.n_cases
+    # algorithmic bytes of the launch: each input read once (the class's
+    # nodes, offsets, the cases and targets) and one value per program out
+    algo0 = (4 * int(lens[cls0].sum()) + 16 * int(cls0.sum())
+             + 4 * (w.data.n_vars + 1) * w.data.n_cases)
+    traffic = counters.get("traffic_bytes_per_launch")
     roofline = {"bound": "alu", "kernel": "k_eval<8,4> (depth<=8 class)",
                 "achieved": round(achieved, 4), "peak": round(PEAK_LANE_OPS / 1e12, 4),
                 "unit": "T node-evals/s vs T fp32 VALU lane-ops/s",
                 "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4),
-                "traffic": counters.get("traffic_bytes_per_launch"),
+                "executed_node_evals_per_launch": ex0,
+                "frac_executed": round(ex0 / (ms0 * 1e-3) / PEAK_LANE_OPS, 4),
+                "algorithmic_bytes_per_launch": algo0,
+                "traffic_over_algorithmic": (round(traffic / algo0, 2) if traffic else None),
+                "traffic": traffic,
                 "valu_busy": counters.get("valu_busy"),
                 "valu_lane_slots_per_node_eval": counters.get("valu_lane_slots_per_node_eval"),
                 "salu_per_dispatch": counters.get("salu_per_dispatch"),
@@ -264,6 +328,7 @@ def throughput(args):
                 "kernel_ms": round(ms0, 4), "node_evals_per_launch": evals0}
     phase_ms = {k: round(v / max(n_calls, 1), 4) for k, v in phases.items()}
 
+    ex_all = int(ex[status == 0].sum()) * w.data.n_cases
     rec = {
         "metric": "program-node evals/sec (GPOPs)",
         "value": round(gpops, 3),
@@ -278,6 +343,7 @@ def throughput(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": describe(args.workload, w), "node_evals_per_step": node_evals,
+                   "executed_node_evals_per_step": ex_all,
                    "fitness": {"mse": "MSE + length tax",
                                "correlation": "correlation (Eq. 1-2, M = %g)" % CORR_MAX_SCORE,
                                "reward": "integer reward (Eq. 5, M = %d, power %d)"

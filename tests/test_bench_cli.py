@@ -25,3 +25,43 @@ def test_more_than_one_gpu_is_refused():
     r = _bench("--gpus", "2")
     assert r.returncode != 0
     assert "one GPU" in r.stderr or "1 GPU" in r.stderr or "single" in r.stderr, r.stderr
+
+
+def _executed_by_tree(prog):
+    """Nodes one case evaluates after constant subtrees fold, by recursion
+    over the expression tree: (count, is_constant) of a subtree."""
+    stack = []
+    for t in prog:
+        op = int(t) & 0xFF
+        if op <= 1:
+            stack.append((1 if op == 0 else 0, op == 1))
+        elif op >= 6:
+            n, c = stack.pop()
+            stack.append((n if c else n + 1, c))
+        else:
+            nb, cb = stack.pop()
+            na, ca = stack.pop()
+            if ca and cb:
+                stack.append((0, True))
+            else:
+                stack.append(((1 if ca else na) + (1 if cb else nb) + 1, False))
+    n, c = stack[0]
+    return 1 if c else n
+
+
+def test_executed_node_counts_match_a_tree_walk():
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2607_06731_amd import synth
+    w = synth.make_workload("generation", n_programs=3000, n_cases=16)
+    got = bench.executed_node_counts(w.pop.nodes, w.pop.offsets, chunk=700)
+    want = np.array([_executed_by_tree(w.pop.nodes[w.pop.offsets[p]:w.pop.offsets[p + 1]])
+                     for p in range(w.pop.n_programs)])
+    assert np.array_equal(got, want)
+    # hand-made cases: x0 c + (3), c c + (1), c sin x0 * (3), x0 c c + * (3), c (1)
+    C = lambda j: 1 | (j << 8)
+    progs = [[0, C(0), 2], [C(0), C(1), 2], [C(0), 6, 0, 4], [0, C(0), C(1), 2, 4], [C(0)]]
+    nodes = np.array([t for q in progs for t in q], np.uint32)
+    off = np.cumsum([0] + [len(q) for q in progs])
+    assert list(bench.executed_node_counts(nodes, off)) == [3, 1, 3, 3, 1]
