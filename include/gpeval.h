@@ -355,13 +355,19 @@ int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs
  * program/data buffers in place between launches (same pointers, same
  * sizes) or calls gp_plan_update for new pointers or sizes (re-capture).
  *
- * gp_tuning holds scheduling knobs only; none of them changes any result
- * (a program's summation order depends on n_cases, n_vars and its own
- * stack depth, never on these).  0 fields mean defaults.  With autotune
- * != 0, gp_plan_create times candidate knobs on the given inputs (this
- * runs the evaluation several times and synchronizes `stream`) and keeps
- * the fastest; results are cached per workload shape in the process and,
- * if the environment variable GPEVAL_TUNE_CACHE names a file, there too.
+ * gp_tuning holds launch knobs; 0 fields mean defaults.  programs_per_item,
+ * wg_per_cu and concurrent_classes change no result.  tile_lds_bytes and
+ * max_tiles shape how a program's cases are grouped into LDS windows and
+ * case tiles, which fixes its summation order together with n_cases, n_vars
+ * and its stack depth: every launch with the same knobs gives the same bits,
+ * and the defaults (24 KiB, 32 tiles) give gp_eval's bits; other values may
+ * differ from gp_eval in the last bits (within the fitness tolerance).
+ * With autotune != 0, gp_plan_create times candidate knobs on the given
+ * inputs (coordinate descent over the five knobs, two sweeps: this runs the
+ * evaluation a few dozen times and synchronizes `stream`) and keeps the
+ * fastest; results are cached per workload shape (device, cases, variables,
+ * programs, mean length, requests) in the process and, if the environment
+ * variable GPEVAL_TUNE_CACHE names a file, there too.
  */
 typedef struct {
     const uint32_t* nodes; const int64_t* offsets; int64_t n_programs; int64_t n_nodes;
@@ -377,6 +383,10 @@ typedef struct {
                                     a depth class with few programs uses fewer */
     int32_t wg_per_cu;           /* persistent workgroups per CU, 0 = occupancy limit */
     int32_t concurrent_classes;  /* 1: depth classes run on forked streams */
+    int32_t tile_lds_bytes;      /* LDS budget of an input window, 4096..65536
+                                    (default 24576) */
+    int32_t max_tiles;           /* case tiles per program, at most, 1..32
+                                    (default 32) */
 } gp_tuning;
 
 typedef struct gp_plan gp_plan;

@@ -65,7 +65,8 @@ class GPRequest(ctypes.Structure):
 class GPTuning(ctypes.Structure):
     """struct gp_tuning of include/gpeval.h"""
     _fields_ = [("programs_per_item", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("concurrent_classes", ctypes.c_int32)]
+                ("concurrent_classes", ctypes.c_int32), ("tile_lds_bytes", ctypes.c_int32),
+                ("max_tiles", ctypes.c_int32)]
 
 
 class GPServerConfig(ctypes.Structure):
@@ -457,7 +458,8 @@ class Plan:
         tu = None
         if tuning is not None:
             tu = GPTuning(int(tuning.get("programs_per_item", 0)), int(tuning.get("wg_per_cu", 0)),
-                          int(tuning.get("concurrent_classes", 0)))
+                          int(tuning.get("concurrent_classes", 0)),
+                          int(tuning.get("tile_lds_bytes", 0)), int(tuning.get("max_tiles", 0)))
         h = ctypes.c_void_p()
         _check(lib().gp_plan_create(ctypes.byref(h), ctypes.byref(pb),
                                     ctypes.byref(tu) if tu is not None else None,
@@ -477,7 +479,8 @@ class Plan:
         t = GPTuning()
         _check(lib().gp_plan_get_tuning(self._h, ctypes.byref(t)))
         return {"programs_per_item": t.programs_per_item, "wg_per_cu": t.wg_per_cu,
-                "concurrent_classes": t.concurrent_classes}
+                "concurrent_classes": t.concurrent_classes, "tile_lds_bytes": t.tile_lds_bytes,
+                "max_tiles": t.max_tiles}
 
     def close(self):
         if getattr(self, "_h", None):

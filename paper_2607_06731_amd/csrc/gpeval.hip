@@ -151,20 +151,21 @@ struct TileShape {
     int32_t window;     // sub-tiles staged in LDS at once
 };
 
-__host__ __device__ inline int32_t tile_window(int k, int n_vars)
+__host__ __device__ inline int32_t tile_window(int k, int n_vars, int32_t lds_bytes)
 {
     const int64_t block = (int64_t)(n_vars + 1) * 64 * k * 4;
-    int64_t w = kTileLds / block;
+    int64_t w = lds_bytes / block;
     return (int32_t)(w < 1 ? 1 : (w > kMaxWindow ? kMaxWindow : w));
 }
 
-__host__ __device__ inline TileShape tile_shape(int64_t n_cases, int k, int n_vars)
+__host__ __device__ inline TileShape tile_shape(int64_t n_cases, int k, int n_vars,
+                                               int32_t lds_bytes, int32_t max_t)
 {
     TileShape t;
     t.sub = 64 * k;
     const int64_t n_sub = (n_cases + t.sub - 1) / t.sub;
-    t.window = tile_window(k, n_vars);
-    int64_t passes = (n_sub + kMaxTiles - 1) / kMaxTiles;
+    t.window = tile_window(k, n_vars, lds_bytes);
+    int64_t passes = (n_sub + max_t - 1) / max_t;
     if (passes < t.window) passes = t.window < n_sub ? t.window : n_sub;
     if (passes < 1) passes = 1;
     t.passes = (int32_t)passes;
@@ -176,10 +177,10 @@ __host__ __device__ inline TileShape tile_shape(int64_t n_cases, int k, int n_va
 // can need: n_tiles never exceeds kMaxTiles or the sub-tile count, and the
 // sub-tile count grows with n_cases, so a smaller dataset can need more
 // tiles than the largest one (33 sub-tiles make 17 tiles, 32 make 32).
-__host__ __device__ inline int32_t max_tiles(int64_t max_cases, int k)
+__host__ __device__ inline int32_t max_tiles(int64_t max_cases, int k, int32_t max_t)
 {
     const int64_t n_sub = (max_cases + 64 * k - 1) / (64 * k);
-    return (int32_t)(n_sub < kMaxTiles ? (n_sub < 1 ? 1 : n_sub) : kMaxTiles);
+    return (int32_t)(n_sub < max_t ? (n_sub < 1 ? 1 : n_sub) : max_t);
 }
 
 
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(256) void k_tables(
     const gp_dataset* __restrict__ ds_in, int32_t n_ds, gp_dataset one,
     const gp_request* __restrict__ req_in, int32_t n_req, gp_request one_req,
     int64_t n_programs, int64_t n_nodes, int32_t max_vars, int64_t max_cases, int32_t need_out,
-    DevDataset* __restrict__ ds_out, DevRequest* __restrict__ req_out,
+    int32_t tile_lds, int32_t tile_max, DevDataset* __restrict__ ds_out, DevRequest* __restrict__ req_out,
     int32_t* __restrict__ seg_ds, int64_t* __restrict__ seg_start, int32_t* __restrict__ bad)
 {
     __shared__ int s_bad;
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(256) void k_tables(
         o.scale = ldexpf(1.0f, -e);
         o.n_vars = ok ? in.n_vars : 0;
         for (int c = 0; c < kClasses; ++c) {
-            const TileShape t = tile_shape(n, class_k(c, o.n_vars), o.n_vars);
+            const TileShape t = tile_shape(n, class_k(c, o.n_vars), o.n_vars, tile_lds, tile_max);
             o.passes[c] = t.passes;
             o.n_tiles[c] = t.n_tiles;
             o.window[c] = t.window;
@@ -2142,12 +2143,18 @@ int check_problem(const Problem& pb)
 }
 
 // --------------------------------------------------- launch configuration
-// Scheduling knobs.  None of them changes a result: a program's summation
-// order is fixed by (n_cases, its depth class, n_vars) alone.
+// Launch knobs.  G, wg_per_cu and concurrent change no result.  The tile
+// knobs (the LDS budget of an input window and the cap on case tiles per
+// program) set how a program's cases are grouped into windows and tiles,
+// so they fix its summation order together with (n_cases, its depth class,
+// n_vars): every call with the same knobs gives the same bits, and the
+// defaults are those of gp_eval, gp_eval_batched and the server.
 struct Tuning {
     int G = 64;             // programs per work item, at most (small classes use fewer)
     int wg_per_cu = 0;      // persistent workgroups per CU (0: occupancy limit)
     int concurrent = 0;     // depth classes on forked streams
+    int tile_lds = kTileLds;    // LDS bytes of an input window
+    int tile_max = kMaxTiles;   // case tiles per program, at most
 };
 
 struct EvalPtrs {
@@ -2163,22 +2170,22 @@ struct EvalPtrs {
 };
 
 template <int MAXD, int K>
-size_t eval_tile_floats(int n_vars)
+size_t eval_tile_floats(int n_vars, int tile_lds)
 {
     // every dataset's window fits the budget; a single sub-tile of a dataset
     // with very many variables may need more
     const size_t one = (size_t)(n_vars + 1) * 64 * K;
-    const size_t budget = kTileLds / sizeof(float);
+    const size_t budget = (size_t)tile_lds / sizeof(float);
     return one > budget ? one : budget;
 }
 
 template <int MAXD, int K, int FIT>
-size_t eval_lds_bytes(int n_vars, int G)
+size_t eval_lds_bytes(int n_vars, int G, int tile_lds)
 {
     const size_t acc = FIT == kFitCorr     ? (size_t)G * sizeof(CorrPart)
                        : FIT == kFitReward ? (size_t)G * sizeof(long long)
                                            : (size_t)G * (sizeof(float2) + sizeof(uint32_t));
-    return eval_tile_floats<MAXD, K>(n_vars) * sizeof(float) + acc;
+    return eval_tile_floats<MAXD, K>(n_vars, tile_lds) * sizeof(float) + acc;
 }
 
 // Whether a call runs the interpreter built for the whole command table
@@ -2187,9 +2194,10 @@ inline bool pb_ext(uint32_t allowed) { return (allowed & ~GP_BASE_OPS) != 0u; }
 
 // Grid size of one class kernel (LDS attribute set outside any capture).
 template <int MAXD, int K, int FIT, bool EXT>
-int eval_grid(int n_vars, int G, int wg_per_cu, int cus, int* grid, size_t* lds_out)
+int eval_grid(int n_vars, int G, const Tuning& tu, int cus, int* grid, size_t* lds_out)
 {
-    const size_t lds = eval_lds_bytes<MAXD, K, FIT>(n_vars, G);
+    const int wg_per_cu = tu.wg_per_cu;
+    const size_t lds = eval_lds_bytes<MAXD, K, FIT>(n_vars, G, tu.tile_lds);
     if (lds > 64 * 1024) {
         GP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval<MAXD, K, FIT, EXT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -2222,9 +2230,9 @@ template <int FIT, bool EXT>
 int eval_grids(const Problem& pb, const Tuning& tu, int G, int cus, EvalLaunch* el)
 {
     int rc;
-    if ((rc = eval_grid<8, 4, FIT, EXT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
-    if ((rc = eval_grid<16, kK1, FIT, EXT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
-    return eval_grid<32, 2, FIT, EXT>(pb.max_vars, G, tu.wg_per_cu, cus, &el->grid[2], &el->lds[2]);
+    if ((rc = eval_grid<8, 4, FIT, EXT>(pb.max_vars, G, tu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
+    if ((rc = eval_grid<16, kK1, FIT, EXT>(pb.max_vars, G, tu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
+    return eval_grid<32, 2, FIT, EXT>(pb.max_vars, G, tu, cus, &el->grid[2], &el->lds[2]);
 }
 
 template <int FIT>
@@ -2243,7 +2251,7 @@ int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
     for (int c = 0; c < kClasses; ++c) {
         // tile counts grow with n_cases, so the largest dataset sizes the
         // partial buffer
-        const int32_t t = max_tiles(pb.max_cases, class_k(c, pb.max_vars));
+        const int32_t t = max_tiles(pb.max_cases, class_k(c, pb.max_vars), tu.tile_max);
         if (t > el->stride) el->stride = t;
     }
     el->target_items = 4 * 6 * cus;     // ~4 items per workgroup slot
@@ -2258,12 +2266,13 @@ int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
 
 // Dataset/segment tables, validation, staging and the stable (depth class,
 // length) partition.
-int enqueue_stage(const Problem& pb, const Staged& st, hipStream_t stream)
+int enqueue_stage(const Problem& pb, const Tuning& tu, const Staged& st, hipStream_t stream)
 {
     const int32_t n_blk = (int32_t)((pb.n_programs + kBucketBlock - 1) / kBucketBlock);
     hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, stream, pb.ds_dev, pb.n_ds, pb.one,
                        pb.req_dev, pb.n_req, pb.one_req, pb.n_programs, pb.n_nodes, pb.max_vars,
-                       pb.max_cases, pb.need_out, st.ds, st.req, st.seg_ds, st.seg_start, st.bad);
+                       pb.max_cases, pb.need_out, tu.tile_lds, tu.tile_max, st.ds, st.req,
+                       st.seg_ds, st.seg_start, st.bad);
     GP_HIP_TRY(hipGetLastError());
     const int32_t lpt = pb.n_req == 1 ? 1 : 0;
     hipLaunchKernelGGL(k_validate, dim3(n_blk), dim3(kBucketBlock), 0, stream, pb.n_programs,
@@ -2306,7 +2315,7 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
 {
     int rc;
     if ((rc = ce.mark(0, stream)) != GP_OK) return rc;
-    if ((rc = enqueue_stage(pb, st, stream)) != GP_OK) return rc;
+    if ((rc = enqueue_stage(pb, tu, st, stream)) != GP_OK) return rc;
     hipLaunchKernelGGL(k_seg_count, dim3((unsigned)((kClasses * pb.n_req + 255) / 256)), dim3(256),
                        0, stream, st.order, st.class_info, st.seg_start, pb.n_req, st.bad,
                        st.seg_cnt);
@@ -2343,13 +2352,13 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
                 launch_eval<MD, KK, kFitMse>(ext, g, el.lds[c], sc, st, c, ea);                \
         } while (0)
         if (c == 0) {
-            ea.tile_floats = (int32_t)eval_tile_floats<8, 4>(pb.max_vars);
+            ea.tile_floats = (int32_t)eval_tile_floats<8, 4>(pb.max_vars, tu.tile_lds);
             GP_LAUNCH_EVAL(8, 4);
         } else if (c == 1) {
-            ea.tile_floats = (int32_t)eval_tile_floats<16, kK1>(pb.max_vars);
+            ea.tile_floats = (int32_t)eval_tile_floats<16, kK1>(pb.max_vars, tu.tile_lds);
             GP_LAUNCH_EVAL(16, kK1);
         } else {
-            ea.tile_floats = (int32_t)eval_tile_floats<32, 2>(pb.max_vars);
+            ea.tile_floats = (int32_t)eval_tile_floats<32, 2>(pb.max_vars, tu.tile_lds);
             GP_LAUNCH_EVAL(32, 2);
         }
 #undef GP_LAUNCH_EVAL
@@ -2437,7 +2446,8 @@ void tune_load_locked()
     if (!f) return;
     char key[200];
     Tuning t;
-    while (fscanf(f, "%199s %d %d %d", key, &t.G, &t.wg_per_cu, &t.concurrent) == 4)
+    while (fscanf(f, "%199s %d %d %d %d %d", key, &t.G, &t.wg_per_cu, &t.concurrent, &t.tile_lds,
+                  &t.tile_max) == 6)
         g_tune[key] = t;
     fclose(f);
 }
@@ -2449,7 +2459,8 @@ void tune_store_locked(const std::string& key, const Tuning& t)
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d\n", key.c_str(), t.G, t.wg_per_cu, t.concurrent);
+    fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), t.G, t.wg_per_cu, t.concurrent, t.tile_lds,
+            t.tile_max);
     fclose(f);
 }
 
@@ -2469,6 +2480,7 @@ struct gp_plan {
     hipGraphExec_t exec = nullptr;
     int device = 0;
     double tuned_ms = 0.0;
+    int tune_trials = 0;
 };
 
 namespace {
@@ -2517,7 +2529,40 @@ int plan_build(gp_plan* p)
     return GP_OK;
 }
 
-// Time candidate scheduling knobs on the real inputs; keep the fastest.
+// Median of three timed runs of one configuration (after one warm-up), or
+// a negative value when it does not fit the plan's workspace.
+int time_config(gp_plan* p, const Tuning& t, hipStream_t stream, hipEvent_t e0, hipEvent_t e1,
+                float* ms_out)
+{
+    *ms_out = -1.f;
+    EvalLaunch el;
+    int rc = configure_eval(p->pb, t, &el);
+    if (rc != GP_OK) return rc;
+    if (el.layout.total > p->ws_bytes) return GP_OK;
+    const Staged st = carve(p->ws, el.layout);
+    CallEvents none;
+    (void)none.begin(false);
+    float ms3[3];
+    if ((rc = enqueue_eval(p->pb, t, el, st, p->side, stream, none)) != GP_OK) return rc;
+    for (int r = 0; r < 3; ++r) {
+        GP_HIP_TRY(hipEventRecord(e0, stream));
+        if ((rc = enqueue_eval(p->pb, t, el, st, p->side, stream, none)) != GP_OK) return rc;
+        GP_HIP_TRY(hipEventRecord(e1, stream));
+        GP_HIP_TRY(hipEventSynchronize(e1));
+        GP_HIP_TRY(hipEventElapsedTime(&ms3[r], e0, e1));
+    }
+    std::sort(ms3, ms3 + 3);
+    *ms_out = ms3[1];
+    return GP_OK;
+}
+
+// Time candidate knobs on the real inputs and keep the fastest: coordinate
+// descent over five axes (programs per work item, workgroups per CU, depth
+// classes on forked streams, the LDS budget of an input window, the cap on
+// case tiles per program), each axis tried in turn with the others at their
+// best so far, two sweeps.  The tile axes set a program's summation order,
+// so the chosen plan is deterministic for its problem shape (the tuning is
+// cached by it) but may differ from gp_eval in the last bits.
 int plan_autotune(gp_plan* p, hipStream_t stream)
 {
     const std::string key = tune_key(p->pb);
@@ -2530,40 +2575,34 @@ int plan_autotune(gp_plan* p, hipStream_t stream)
             return GP_OK;
         }
     }
-    const int Gs[] = {16, 32, 64, 128};
     hipEvent_t e0, e1;
     GP_HIP_TRY(hipEventCreate(&e0));
     GP_HIP_TRY(hipEventCreate(&e1));
+    const int kAxes = 5;
+    const std::vector<int> values[kAxes] = {{32, 64, 128}, {0, 3, 4}, {0, 1},
+                                            {12 * 1024, 24 * 1024, 40 * 1024}, {2, 8, 32}};
+    auto field = [](Tuning& t, int a) -> int& {
+        return a == 0 ? t.G : a == 1 ? t.wg_per_cu : a == 2 ? t.concurrent
+                                                            : a == 3 ? t.tile_lds : t.tile_max;
+    };
     Tuning best = p->tu;
     float best_ms = 1e30f;
-    int rc = GP_OK;
-    for (int conc = 0; conc < 2 && rc == GP_OK; ++conc) {
-        for (int G : Gs) {
-            Tuning t;
-            t.G = G;
-            t.concurrent = conc;
-            EvalLaunch el;
-            if ((rc = configure_eval(p->pb, t, &el)) != GP_OK) break;
-            if (el.layout.total > p->ws_bytes) continue;
-            const Staged st = carve(p->ws, el.layout);
-            CallEvents none;
-            (void)none.begin(false);
-            // one warm-up, then the median of three
-            float ms3[3];
-            if ((rc = enqueue_eval(p->pb, t, el, st, p->side, stream, none)) != GP_OK) break;
-            for (int r = 0; r < 3 && rc == GP_OK; ++r) {
-                if (hipEventRecord(e0, stream) != hipSuccess) { rc = set_error(GP_E_HIP, "event"); break; }
-                rc = enqueue_eval(p->pb, t, el, st, p->side, stream, none);
-                if (rc != GP_OK) break;
-                if (hipEventRecord(e1, stream) != hipSuccess) { rc = set_error(GP_E_HIP, "event"); break; }
-                if (hipEventSynchronize(e1) != hipSuccess) { rc = set_error(GP_E_HIP, "sync"); break; }
-                (void)hipEventElapsedTime(&ms3[r], e0, e1);
-            }
-            if (rc != GP_OK) break;
-            std::sort(ms3, ms3 + 3);
-            if (ms3[1] < best_ms) {
-                best_ms = ms3[1];
-                best = t;
+    int rc = time_config(p, best, stream, e0, e1, &best_ms);
+    if (rc == GP_OK && best_ms < 0.f) best_ms = 1e30f;
+    int tried = 1;
+    for (int sweep = 0; sweep < 2 && rc == GP_OK; ++sweep) {
+        for (int a = 0; a < kAxes && rc == GP_OK; ++a) {
+            for (int v : values[a]) {
+                Tuning t = best;
+                if (field(t, a) == v) continue;
+                field(t, a) = v;
+                float ms = -1.f;
+                if ((rc = time_config(p, t, stream, e0, e1, &ms)) != GP_OK) break;
+                ++tried;
+                if (ms >= 0.f && ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
             }
         }
     }
@@ -2572,6 +2611,7 @@ int plan_autotune(gp_plan* p, hipStream_t stream)
     if (rc != GP_OK) return rc;
     p->tu = best;
     p->tuned_ms = best_ms;
+    p->tune_trials = tried;
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     tune_store_locked(key, best);
     return GP_OK;
@@ -2934,7 +2974,7 @@ int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs
     Workspace* w = nullptr;
     if ((rc = get_workspace(stream, L.total, &w)) != GP_OK) return rc;
     const Staged st = carve(w->ptr, L);
-    if ((rc = enqueue_stage(pb, st, stream)) != GP_OK) return rc;
+    if ((rc = enqueue_stage(pb, Tuning(), st, stream)) != GP_OK) return rc;
     EvalPtrs ep{st.code, st.meta, st.order, st.class_info, nullptr, X, nullptr, nullptr, nullptr};
     EvalConst ea{};
     ea.ld_x = ld_x; ea.n_cases = n_cases; ea.n_vars = n_vars;
@@ -2968,13 +3008,18 @@ int gp_plan_create(gp_plan** plan, const gp_problem* problem, const gp_tuning* t
     gp_plan* p = new gp_plan();
     p->pb = pb;
     if (tuning) {
-        if (tuning->programs_per_item < 0 || tuning->programs_per_item > 128 || tuning->wg_per_cu < 0) {
+        if (tuning->programs_per_item < 0 || tuning->programs_per_item > 128 || tuning->wg_per_cu < 0 ||
+            tuning->tile_lds_bytes < 0 || (tuning->tile_lds_bytes > 0 && (tuning->tile_lds_bytes < 4096 ||
+                                                                         tuning->tile_lds_bytes > 65536)) ||
+            tuning->max_tiles < 0 || tuning->max_tiles > kMaxTiles) {
             delete p;
             return set_error(GP_E_INVALID_ARG, "tuning out of range");
         }
         if (tuning->programs_per_item > 0) p->tu.G = tuning->programs_per_item;
         p->tu.wg_per_cu = tuning->wg_per_cu;
         p->tu.concurrent = tuning->concurrent_classes != 0;
+        if (tuning->tile_lds_bytes > 0) p->tu.tile_lds = tuning->tile_lds_bytes;
+        if (tuning->max_tiles > 0) p->tu.tile_max = tuning->max_tiles;
     }
     if (hipGetDevice(&p->device) != hipSuccess ||
         hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess ||
@@ -2982,10 +3027,12 @@ int gp_plan_create(gp_plan** plan, const gp_problem* problem, const gp_tuning* t
         gp_plan_destroy(p);
         return set_error(GP_E_HIP, "plan stream setup failed");
     }
-    // workspace for the largest candidate configuration
+    // workspace for the largest candidate configuration (the most programs
+    // per item and the most tiles per program)
     EvalLaunch el;
     Tuning big = p->tu;
     big.G = 128;
+    big.tile_max = kMaxTiles;
     if ((rc = configure_eval(pb, big, &el)) != GP_OK ||
         hipMalloc(&p->ws, el.layout.total) != hipSuccess) {
         (void)hipGetLastError();
@@ -3029,6 +3076,8 @@ int gp_plan_get_tuning(const gp_plan* plan, gp_tuning* out)
     out->programs_per_item = plan->tu.G;
     out->wg_per_cu = plan->tu.wg_per_cu;
     out->concurrent_classes = plan->tu.concurrent;
+    out->tile_lds_bytes = plan->tu.tile_lds;
+    out->max_tiles = plan->tu.tile_max;
     return GP_OK;
 }
 
@@ -3094,7 +3143,7 @@ int gp_workspace_size(int64_t n_programs, int64_t n_nodes, int32_t n_requests,
         return set_error(GP_E_INVALID_ARG, "sizes out of range");
     int32_t stride = 1;
     for (int c = 0; c < kClasses; ++c) {
-        const int32_t t = max_tiles(max_n_cases, class_k(c, max_n_vars));
+        const int32_t t = max_tiles(max_n_cases, class_k(c, max_n_vars), kMaxTiles);
         if (t > stride) stride = t;
     }
     const size_t need = make_layout(n_programs, n_nodes, stride, n_datasets, n_requests).total;
