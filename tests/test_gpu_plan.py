@@ -80,8 +80,8 @@ def test_plan_autotune_and_inplace_update():
                         w.allowed_mask)
     _say("tuning %s" % t)
     default_tiles = t["tile_lds_bytes"] == 24576 and t["max_tiles"] == 32
-    same = (lambda a, b: np.array_equal(a, b, equal_nan=True)) if default_tiles else _close
-    assert same(F1, F_ref)
+    agree = (lambda a, b: np.array_equal(a, b, equal_nan=True)) if default_tiles else _close
+    assert agree(F1, F_ref)
     # next generation: same shape, new programs written in place
     w2 = synth.make_workload("generation", n_programs=30000, n_cases=4096, seed=77)
     same = w2.pop.nodes.size == w.pop.nodes.size and w2.pop.consts.size == w.pop.consts.size
@@ -94,7 +94,7 @@ def test_plan_autotune_and_inplace_update():
         F2 = out.cpu().numpy()
         F2_ref = gp.evaluate(w2.pop.nodes, w2.pop.offsets, w2.pop.consts, w.data.X, w.data.y,
                              w.tax, w.allowed_mask)
-        assert same(F2, F2_ref)
+        assert agree(F2, F2_ref)
     # different size: update re-captures
     w3 = synth.make_workload("generation", n_programs=11111, n_cases=4096, seed=78)
     pop3 = gp.DevicePopulation(w3.pop.nodes, w3.pop.offsets, w3.pop.consts)
@@ -104,7 +104,7 @@ def test_plan_autotune_and_inplace_update():
     torch.cuda.synchronize()
     F3_ref = gp.evaluate(w3.pop.nodes, w3.pop.offsets, w3.pop.consts, w.data.X, w.data.y,
                          w.tax, w.allowed_mask)
-    assert same(out3.cpu().numpy(), F3_ref)
+    assert agree(out3.cpu().numpy(), F3_ref)
     plan.close()
 
 
