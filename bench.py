@@ -37,7 +37,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_LANE_OPS = 256 * 64 * 2.4e9      # fp32 VALU lane-slots per second (non-packed)
+# fp32 VALU lane operations per second: 256 CUs x 128 fp32 lanes per clock x
+# 2.4 GHz (the published 157.3 TFLOP/s counts each fused multiply-add lane
+# operation as two flops).  One node evaluation needs at least one such
+# operation.
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
 
 
 def cpu_baseline(w, budget_s=15.0, fitness="mse"):
