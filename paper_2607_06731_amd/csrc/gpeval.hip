@@ -107,6 +107,10 @@ constexpr int kMaxTiles = 32;            // case tiles per program (cap)
 constexpr uint32_t kNoSlot = 0xFFu;      // staged write slot: nothing to save
 constexpr int kBucketBlock = 128;        // programs per staging/partition block
 constexpr int kStageNodes = 6656;        // LDS node cache of a staging block (26 KB, 52 per program)
+// The emitting pass's cache also holds an op byte per node (30 KB for 6144
+// nodes, 48 per program), which with the held constants keeps four of its
+// blocks per CU.
+constexpr int kStageNodesEmit = 6144;
 // Constants held back for folding per program while staging: a longer run
 // of constants is pushed (as runtime values) before the next one is held.
 // 16 keeps the staging block at four per CU (with the node cache).
@@ -538,6 +542,7 @@ __device__ __forceinline__ int request_of(const int64_t* __restrict__ seg_start,
 // LDS-qualified pointers (per-lane LDS addressing without generic loads).
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(3))) float lds_f32;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
 
 // Node readers for the staging passes: straight from the request's array,
 // or from the block's LDS copy of its node range.
@@ -556,14 +561,13 @@ struct GlobalConsts {
     __device__ float operator()(uint32_t j) const { return p[j]; }
 };
 
-// Cooperative, coalesced copy of the node range [min s, max e) of the
-// block's programs into LDS, when they all belong to one request and the
-// range fits.  `mine`: this thread has a program with a valid node range.
-// Every thread of the block must call it.  Returns true when the copy is
-// used (then *lo is the first cached node).
-__device__ bool cache_block_nodes(bool mine, int r, int64_t s, int64_t e,
-                                  const DevRequest* __restrict__ reqs, lds_u32* cache,
-                                  int64_t* lo)
+// The node range [min s, max e) of the block's programs, when they all
+// belong to one request and the range holds at most `cap` nodes.  `mine`:
+// this thread has a program with a valid node range.  Every thread of the
+// block must call it.  Returns true when the range is usable (then *req is
+// the request, *lo the first node and *n the node count).
+__device__ bool block_node_range(bool mine, int r, int64_t s, int64_t e, int cap, int* req,
+                                 int64_t* lo, int* n)
 {
     __shared__ long long s_lo, s_hi;
     __shared__ int s_r, s_mixed, s_any;
@@ -584,13 +588,27 @@ __device__ bool cache_block_nodes(bool mine, int r, int64_t s, int64_t e,
     __syncthreads();
     if (mine && r != s_r) s_mixed = 1;
     __syncthreads();
-    const bool use = s_any && !s_mixed && s_hi - s_lo <= kStageNodes;
+    const bool use = s_any && !s_mixed && s_hi - s_lo <= cap;
+    *req = s_r;
+    *lo = s_lo;
+    *n = use ? (int)(s_hi - s_lo) : 0;
+    return use;
+}
+
+// Cooperative, coalesced copy of the block's node range into LDS (see
+// block_node_range).  Every thread of the block must call it.  Returns true
+// when the copy is used (then *lo is the first cached node).
+__device__ bool cache_block_nodes(bool mine, int r, int64_t s, int64_t e,
+                                  const DevRequest* __restrict__ reqs, lds_u32* cache,
+                                  int64_t* lo)
+{
+    int rq = 0, n = 0;
+    const bool use = block_node_range(mine, r, s, e, kStageNodes, &rq, lo, &n);
     if (use) {
         // 16 independent loads in flight per thread and round: a plain copy
         // loop would wait out the memory latency once per element
         constexpr int kU = 16;
-        const uint32_t* __restrict__ src = reqs[s_r].nodes + s_lo;
-        const int n = (int)(s_hi - s_lo);
+        const uint32_t* __restrict__ src = reqs[rq].nodes + *lo;
         const int step = (int)blockDim.x * kU;
         for (int i0 = 0; i0 < n; i0 += step) {
             uint32_t v[kU];
@@ -605,11 +623,73 @@ __device__ bool cache_block_nodes(bool mine, int r, int64_t s, int64_t e,
                 if (i < n) cache[i] = v[u];
             }
         }
-        *lo = s_lo;
     }
     __syncthreads();
     return use;
 }
+
+// The emitting pass's LDS copy of the block's node range: the op byte of
+// each node, and its payload: the constant's value bits for a constant
+// (whose index is in range), the argument otherwise.  The constants are
+// gathered here, many loads in flight per thread, so the walk that emits
+// the staged words reads only LDS.  Every thread of the block must call it.
+__device__ bool cache_block_stage(bool mine, int r, int64_t s, int64_t e,
+                                  const DevRequest* __restrict__ reqs, lds_u8* ops,
+                                  lds_u32* pay, int64_t* lo)
+{
+    int rq = 0, n = 0;
+    const bool use = block_node_range(mine, r, s, e, kStageNodesEmit, &rq, lo, &n);
+    if (use) {
+        constexpr int kU = 16;
+        const uint32_t* __restrict__ src = reqs[rq].nodes + *lo;
+        const float* __restrict__ cs = reqs[rq].consts;
+        const int64_t nc = reqs[rq].n_consts;
+        const int step = (int)blockDim.x * kU;
+        for (int i0 = 0; i0 < n; i0 += step) {
+            uint32_t v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                v[u] = i < n ? src[i] : 0xFFu;
+            }
+            float c[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint32_t a = v[u] >> 8;
+                c[u] = (v[u] & 0xFFu) == GP_CONST && (int64_t)a < nc ? cs[a] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                if (i < n) {
+                    const uint32_t op = v[u] & 0xFFu;
+                    ops[i] = (uint8_t)op;
+                    pay[i] = op == GP_CONST ? __float_as_uint(c[u]) : v[u] >> 8;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    return use;
+}
+
+// Readers of the benchmark-set emitting walk: op, variable index, constant
+// value, from the block's LDS copy or straight from the request's arrays.
+struct LdsStageReader {
+    const lds_u8* o;
+    const lds_u32* p;
+    int64_t lo;
+    __device__ uint32_t op(int64_t k) const { return o[k - lo]; }
+    __device__ uint32_t arg(int64_t k) const { return p[k - lo]; }
+    __device__ float cval(int64_t k) const { return __uint_as_float(p[k - lo]); }
+};
+struct GlobalStageReader {
+    const uint32_t* __restrict__ n;
+    const float* __restrict__ c;
+    __device__ uint32_t op(int64_t k) const { return n[k] & 0xFFu; }
+    __device__ uint32_t arg(int64_t k) const { return n[k] >> 8; }
+    __device__ float cval(int64_t k) const { return c[n[k] >> 8]; }
+};
 
 #define GP_STAGING_FN __device__
 #include "staging.h"
@@ -663,7 +743,15 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
             status = GP_PROG_EMPTY;
         } else {
             const int32_t n_vars = ds[R.dataset].n_vars;
-            if (cached)
+            // a mask within the benchmark set takes the short walk
+            const bool base = (allowed & ~GP_BASE_OPS) == 0u;
+            if (base && cached)
+                check_program_base(LdsNodes{cache, lo}, s, e, allowed, n_vars, R.n_consts, status,
+                                   maxd, n_staged);
+            else if (base)
+                check_program_base(GlobalNodes{R.nodes}, s, e, allowed, n_vars, R.n_consts,
+                                   status, maxd, n_staged);
+            else if (cached)
                 check_program(LdsNodes{cache, lo}, s, e, allowed, n_vars, R.n_consts, status, maxd,
                               n_staged);
             else
@@ -804,15 +892,22 @@ __global__ __launch_bounds__(kBucketBlock) void k_stage(
     int64_t n_programs, const DevDataset* __restrict__ ds, const DevRequest* __restrict__ reqs,
     const int64_t* __restrict__ seg_start, const int32_t* __restrict__ pds, int32_t n_blk,
     const int64_t* __restrict__ blk_code, const int32_t* __restrict__ blk_base,
-    const int32_t* __restrict__ overflow, uint8_t* __restrict__ cls,
+    const int32_t* __restrict__ overflow, uint32_t allowed, uint8_t* __restrict__ cls,
     ProgMeta* __restrict__ meta, uint2* __restrict__ code, int32_t* __restrict__ order)
 {
     __shared__ long long sc[kBucketBlock];
     constexpr int kW = kBucketBlock / 64;
     __shared__ int wcnt[kW][kKeys];
-    __shared__ uint32_t cache_mem[kStageNodes];
+    // node cache (general walk), or payloads then op bytes (short walk)
+    constexpr int kCacheWords = kStageNodes > kStageNodesEmit + kStageNodesEmit / 4
+                                    ? kStageNodes : kStageNodesEmit + kStageNodesEmit / 4;
+    __shared__ uint32_t cache_mem[kCacheWords];
     __shared__ float pv_mem[kHeldConsts * kBucketBlock];
     lds_u32* cache = (lds_u32*)cache_mem;
+    // a mask within the benchmark set: the short walk over op bytes and
+    // gathered constant values (its cache ends where the op bytes begin)
+    const bool base = (allowed & ~GP_BASE_OPS) == 0u;
+    lds_u8* ops = (lds_u8*)(cache + kStageNodesEmit);
     const int t = threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * kBucketBlock + t;
     int key = p < n_programs ? (int)cls[p] : 0xFF;
@@ -853,13 +948,20 @@ __global__ __launch_bounds__(kBucketBlock) void k_stage(
         e = R.offsets[q + 1];
     }
     int64_t lo = 0;
-    const bool cached = cache_block_nodes(key < kKeys, r, s, e, reqs, cache, &lo);
+    const bool cached = base ? cache_block_stage(key < kKeys, r, s, e, reqs, ops, cache, &lo)
+                             : cache_block_nodes(key < kKeys, r, s, e, reqs, cache, &lo);
     if (key < kKeys) {
         const int c = key / kLenBuckets;
         const uint32_t J = 32u / (uint32_t)class_depth(c);
         const uint32_t row_bytes = (uint32_t)(64 * class_k(c, ds[R.dataset].n_vars)) * 4u;
         lds_f32* pvs = (lds_f32*)pv_mem + t;
-        if (cached)
+        if (base && cached)
+            stage_walk_base(LdsStageReader{ops, cache, lo}, s, e, J, row_bytes, code + start,
+                            m.slen, pvs);
+        else if (base)
+            stage_walk_base(GlobalStageReader{R.nodes, R.consts}, s, e, J, row_bytes,
+                            code + start, m.slen, pvs);
+        else if (cached)
             stage_walk(LdsNodes{cache, lo}, s, e, GlobalConsts{R.consts}, J, row_bytes,
                        code + start, m.slen, pvs);
         else
@@ -2285,7 +2387,7 @@ int enqueue_stage(const Problem& pb, const Tuning& tu, const Staged& st, hipStre
     GP_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_stage, dim3(n_blk), dim3(kBucketBlock), 0, stream, pb.n_programs, st.ds,
                        st.req, st.seg_start, st.pds, n_blk, st.blk_code, st.blk_base, st.overflow,
-                       st.cls, st.meta, st.code, st.order);
+                       pb.allowed, st.cls, st.meta, st.code, st.order);
     GP_HIP_TRY(hipGetLastError());
     return GP_OK;
 }

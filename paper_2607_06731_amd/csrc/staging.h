@@ -332,3 +332,133 @@ GP_STAGING_FN void check_program(Nodes nodes, int64_t s, int64_t e, uint32_t all
     n_staged = n_st + np;
 }
 
+
+// ------------------------------------------------ the benchmark set alone
+// When the op mask stays within GP_BASE_OPS no command beyond the set can
+// pass validation, so the walks need neither the variable discipline nor
+// the cell moves.  These two take the same decisions as check_program and
+// stage_walk for such masks (the host harness compares them word for word)
+// with a loop a fraction of the size: one thread walks each program, and
+// the loop body is what the walk costs per node.
+
+// check_program for a mask within GP_BASE_OPS: the same checks in the same
+// order (op, operand range, underflow, depth), the same count.
+template <class Nodes>
+GP_STAGING_FN void check_program_base(Nodes nodes, int64_t s, int64_t e, uint32_t allowed,
+                                      int32_t n_vars, int64_t n_consts, int& status, int& maxd,
+                                      int64_t& n_staged)
+{
+    int depth = 0, md = 0, np = 0, st = GP_PROG_OK;
+    int64_t n_st = 0;
+    bool taken = false;
+    uint32_t w = s < e ? nodes(s) : 0u;
+    for (int64_t k = s; k < e; ++k) {
+        const uint32_t op = w & 0xFFu, arg = w >> 8;
+        const uint32_t wn = k + 1 < e ? nodes(k + 1) : 0xFFu;   // next word, read early
+        const bool leaf = op <= GP_CONST, bin = op >= GP_ADD && op <= GP_DIV;
+        const int need = leaf ? 0 : (bin ? 2 : 1);
+        const int eff = leaf ? 1 : (bin ? -1 : 0);
+        if (op >= 32u || !((allowed >> op) & 1u)) st = GP_PROG_BAD_OP;
+        else if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) st = GP_PROG_BAD_VAR;
+        else if (op == GP_CONST && (int64_t)arg >= n_consts) st = GP_PROG_BAD_CONST;
+        else if (depth < need) st = GP_PROG_UNDERFLOW;
+        else if (depth + eff > GP_MAX_STACK) st = GP_PROG_TOO_DEEP;
+        if (st != GP_PROG_OK) break;
+        depth += eff;
+        md = depth > md ? depth : md;
+        if (op == GP_CONST) {
+            if (np == kHeldConsts) { n_st += np; np = 0; }
+            ++np;
+        } else if (op == GP_LOAD) {
+            n_st += np + 1;
+            np = 0;
+            const uint32_t nx = wn & 0xFFu;
+            taken = nx >= GP_ADD && nx <= GP_ABS;
+        } else if (taken) {
+            taken = false;
+        } else if (bin) {
+            if (np >= 2) --np;
+            else { np = 0; ++n_st; }
+        } else {
+            n_st += np == 0 ? 1 : 0;
+        }
+        w = wn;
+    }
+    maxd = md;
+    if (st == GP_PROG_OK && depth != 1) st = GP_PROG_FINAL_DEPTH;
+    status = st;
+    n_staged = n_st + np;
+}
+
+// stage_walk for a program that check_program_base accepted.  The reader
+// gives op(k), arg(k) (a variable's index) and cval(k) (a constant node's
+// value), so the device can hand it node words and constant values already
+// gathered into LDS.  Emits the same words as stage_walk.
+template <class Reader>
+GP_STAGING_FN int64_t stage_walk_base(Reader rd, int64_t s, int64_t e, uint32_t J,
+                                      uint32_t row_bytes, uint2* __restrict__ out, int64_t cap,
+                                      lds_f32* pvs)
+{
+#define pv(i) pvs[(i) * kBucketBlock]
+    auto put = [&](int64_t i, uint2 v) {
+        if (i < cap) out[i] = v;
+    };
+    int rt = 0, np = 0;
+    int64_t n = 0;
+    auto flush = [&]() {
+        for (int i = 0; i < np; ++i) {
+            const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : 0u;
+            put(n, staged_word(kFPush | kFConst, 0u, wr, __float_as_uint(pv(i))));
+            ++n;
+            ++rt;
+        }
+        np = 0;
+    };
+    for (int64_t k = s; k < e; ++k) {
+        const uint32_t op = rd.op(k);
+        const uint32_t nx = k + 1 < e ? rd.op(k + 1) : 0xFFu;
+        if (op == GP_CONST) {
+            if (np == kHeldConsts) flush();
+            pv(np) = rd.cval(k);
+            ++np;
+        } else if (op == GP_LOAD) {
+            flush();
+            const uint32_t payload = rd.arg(k) * row_bytes;
+            const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : 0u;
+            if (nx >= GP_ADD && nx <= GP_DIV) {
+                put(n, staged_word(kFLBin, nx - GP_ADD, 0u, payload));
+                ++k;
+            } else if (nx >= GP_SIN && nx <= GP_ABS) {
+                put(n, staged_word(kFPush | kFUn, nx - GP_SIN, wr, payload));
+                ++rt;
+                ++k;
+            } else {
+                put(n, staged_word(kFPush, 0u, wr, payload));
+                ++rt;
+            }
+            ++n;
+        } else if (op <= GP_DIV) {
+            if (np >= 2) {
+                --np;
+                pv(np - 1) = binary_value(op, pv(np - 1), pv(np));
+            } else if (np == 1) {
+                np = 0;
+                put(n, staged_word(kFLBin | kFConst, op - GP_ADD, 0u, __float_as_uint(pv(0))));
+                ++n;
+            } else {
+                put(n, staged_word(kFSBin, op - GP_ADD, (uint32_t)(rt - 2) * J, 0u));
+                ++n;
+                --rt;
+            }
+        } else if (np >= 1) {
+            pv(np - 1) = unary_value(op, pv(np - 1));
+        } else {
+            put(n, staged_word(kFUn, op - GP_SIN, 0u, 0u));
+            ++n;
+        }
+    }
+    flush();
+    if (n > 0 && n <= cap) out[n - 1].x |= kFLast;
+    return n;
+#undef pv
+}

@@ -14,8 +14,10 @@
 // uint32 nodes[n_nodes]; int64 offsets[P + 1]; float consts[n_consts];
 // float X[n_vars][n_cases].
 // Output: per program int64 {status, max_depth, counted, emitted,
-// end_flag_ok, within_nodes}; then float out[P][n_cases] (NaN for invalid
-// programs).
+// end_flag_ok, within_nodes, base_check_agrees, base_words_agree}; then
+// float out[P][n_cases] (NaN for invalid programs).  The last two compare
+// the benchmark-set walks (check_program_base, stage_walk_base) with the
+// general ones under two masks within the benchmark set.
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -70,6 +72,46 @@ struct Consts {
     const float* p;
     float operator()(uint32_t j) const { return p[j]; }
 };
+// reader of the benchmark-set walk: op, variable index, constant value
+struct BaseReader {
+    const uint32_t* p;
+    const float* c;
+    uint32_t op(int64_t k) const { return p[k] & 0xFFu; }
+    uint32_t arg(int64_t k) const { return p[k] >> 8; }
+    float cval(int64_t k) const { return c[p[k] >> 8]; }
+};
+
+// The benchmark-set walks against the general ones for a mask within the
+// set: same status, maximum depth and count, and the same staged words.
+static void compare_base_walks(const std::vector<uint32_t>& nodes, const std::vector<float>& consts,
+                               int64_t s, int64_t e, int32_t NV, int64_t NCo, int64_t* I)
+{
+    const uint32_t masks[2] = {GP_BASE_OPS,
+                               GP_BASE_OPS & ~((1u << GP_SIN) | (1u << GP_DIV) | (1u << GP_LOAD))};
+    bool check_ok = true, words_ok = true;
+    for (uint32_t m : masks) {
+        int st1 = GP_PROG_OK, md1 = 0, st2 = GP_PROG_OK, md2 = 0;
+        int64_t c1 = 0, c2 = 0;
+        if (e > s) {
+            check_program(Nodes{nodes.data()}, s, e, m, NV, NCo, st1, md1, c1);
+            check_program_base(Nodes{nodes.data()}, s, e, m, NV, NCo, st2, md2, c2);
+        }
+        check_ok = check_ok && st1 == st2 && (st1 != GP_PROG_OK || (md1 == md2 && c1 == c2));
+        if (st1 != GP_PROG_OK || st2 != GP_PROG_OK || e == s) continue;
+        const uint32_t J = 32u / (uint32_t)(md1 <= 8 ? 8 : (md1 <= 16 ? 16 : 32));
+        std::vector<uint2> a(c1 + 1, make_uint2(0u, 0u)), b(c1 + 1, make_uint2(0u, 0u));
+        float pa[kHeldConsts], pb[kHeldConsts];
+        const int64_t na = stage_walk(Nodes{nodes.data()}, s, e, Consts{consts.data()}, J, 12, a.data(),
+                                      c1, pa);
+        const int64_t nb = stage_walk_base(BaseReader{nodes.data(), consts.data()}, s, e, J, 12,
+                                           b.data(), c1, pb);
+        words_ok = words_ok && na == nb;
+        for (int64_t k = 0; k < c1 && words_ok; ++k)
+            words_ok = a[k].x == b[k].x && a[k].y == b[k].y;
+    }
+    I[6] = check_ok;
+    I[7] = words_ok;
+}
 
 static float unary_sel(uint32_t sel, float x)
 {
@@ -120,7 +162,7 @@ int main(int argc, char** argv)
         !rd(in, X.data(), NV * NC))
         return 2;
     fclose(in);
-    std::vector<int64_t> info(P * 6, 0);
+    std::vector<int64_t> info(P * 8, 0);
     std::vector<float> out(P * NC, NAN);
     const uint32_t row_bytes = 4;              // a variable leaf's payload is 4 * index here
     for (int64_t p = 0; p < P; ++p) {
@@ -128,7 +170,8 @@ int main(int argc, char** argv)
         int64_t counted = 0;
         check_program(Nodes{nodes.data()}, off[p], off[p + 1], GP_ALL_OPS, (int32_t)NV, NCo,
                       status, maxd, counted);
-        int64_t* I = &info[p * 6];
+        int64_t* I = &info[p * 8];
+        compare_base_walks(nodes, consts, off[p], off[p + 1], (int32_t)NV, NCo, I);
         I[0] = status;
         I[1] = maxd;
         I[2] = counted;
