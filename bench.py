@@ -42,6 +42,15 @@ if ROOT not in sys.path:
 # operation as two flops).  One node evaluation needs at least one such
 # operation.
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
+# fp32 VALU instructions per case of each operator as the interpreter
+# computes it (opcodes LOAD, CONST, ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG,
+# SQRT, ABS): counted in the AMD assembly of the library's own operator
+# functions compiled alone for gfx950 (protected division: IEEE division
+# plus the guard's compare and select; sin, cos and exp: the fast formula
+# plus the range compare; ln: hardware log2 and the split ln 2 product
+# plus the guard; square root: the denormal-safe scaling around the
+# hardware root).  Leaves are LDS reads, no VALU arithmetic.
+OP_VALU = (0, 0, 1, 1, 1, 13, 15, 17, 10, 5, 6, 1)
 
 
 def cpu_baseline(w, budget_s=15.0, fitness="mse"):
@@ -157,14 +166,28 @@ def executed_node_counts(nodes, offsets, chunk=100_000):
     each operator whose value depends on a variable together with its
     constant operands (a constant operand is one folded value), plus one for
     a program that is constant as a whole.  Benchmark-set opcodes only
-    (LOAD 0, CONST 1, ADD..DIV 2..5, the unary ops 6..11).  Stacks of
-    constant flags, all programs of a chunk in step by token position."""
+    (LOAD 0, CONST 1, ADD..DIV 2..5, the unary ops 6..11)."""
+    return _executed(nodes, offsets, None, chunk)[0]
+
+
+def executed_operator_mix(nodes, offsets, select, chunk=100_000):
+    """Over the programs where `select` is true: how many operators of each
+    opcode (index 0..11) one case really evaluates once constant subtrees
+    are folded (the operators whose value depends on a variable)."""
+    return _executed(nodes, offsets, select, chunk)[1]
+
+
+def _executed(nodes, offsets, select, chunk):
+    """Stacks of constant flags, all programs of a chunk in step by token
+    position: per program the executed node count, and over the selected
+    programs the executed operators by opcode."""
     import numpy as np
     nodes = np.asarray(nodes, np.uint32)
     offsets = np.asarray(offsets, np.int64)
     P = offsets.size - 1
     lens = np.diff(offsets)
     out = np.zeros(P, np.int64)
+    by_op = np.zeros(12, np.int64)
     for c0 in range(0, P, chunk):
         c1 = min(P, c0 + chunk)
         n = c1 - c0
@@ -172,6 +195,7 @@ def executed_node_counts(nodes, offsets, chunk=100_000):
         pos = offsets[c0:c1, None] + np.arange(L)[None, :]
         valid = np.arange(L)[None, :] < lens[c0:c1, None]
         ops = np.where(valid, nodes[np.minimum(pos, nodes.size - 1)] & 0xFF, 255).astype(np.int32)
+        sel = np.ones(n, bool) if select is None else np.asarray(select[c0:c1], bool)
         stack = np.zeros((n, 34), bool)
         depth = np.zeros(n, np.int64)          # index of the top element (0: empty)
         cnt = np.zeros(n, np.int64)
@@ -188,18 +212,21 @@ def executed_node_counts(nodes, offsets, chunk=100_000):
             depth = np.where(leaf, d1, depth)
             # unary: constant stays constant, otherwise one evaluation
             top = stack[rows, depth]
-            cnt += un & ~top
+            run_un = un & ~top
+            cnt += run_un
             # binary: a constant operand of a non-constant operator is one value
             a = stack[rows, np.maximum(depth - 1, 0)]
             b = top
             c = a & b
-            cnt += (bi & ~c).astype(np.int64) + (bi & ~c & a) + (bi & ~c & b)
+            run_bi = bi & ~c
+            cnt += run_bi.astype(np.int64) + (run_bi & a) + (run_bi & b)
+            by_op += np.bincount(op[(run_un | run_bi) & sel], minlength=12)[:12]
             nd = np.where(bi, depth - 1, depth)
             stack[rows[bi], nd[bi]] = c[bi]
             depth = nd
         cnt += stack[rows, depth]             # a program that is constant as a whole
         out[c0:c1] = cnt
-    return out
+    return out, by_op
 
 
 def copy_calibration(n_bytes):
@@ -311,6 +338,9 @@ def throughput(args):
     # once per program at staging)
     ex = executed_node_counts(w.pop.nodes, w.pop.offsets)
     ex0 = int(ex[cls0].sum()) * w.data.n_cases
+    # the operators' own arithmetic (OP_VALU lane operations per case)
+    mix0 = executed_operator_mix(w.pop.nodes, w.pop.offsets, cls0)
+    math0 = int(sum(int(mix0[k]) * OP_VALU[k] for k in range(12))) * w.data.n_cases
     # algorithmic bytes of the launch: each input read once (the class's
     # nodes, offsets, the cases and targets) and one value per program out
     algo0 = (4 * int(lens[cls0].sum()) + 16 * int(cls0.sum())
@@ -322,6 +352,8 @@ def throughput(args):
                 "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4),
                 "executed_node_evals_per_launch": ex0,
                 "frac_executed": round(ex0 / (ms0 * 1e-3) / PEAK_LANE_OPS, 4),
+                "operator_lane_ops_per_launch": math0,
+                "frac_operator_math": round(math0 / (ms0 * 1e-3) / PEAK_LANE_OPS, 4),
                 "algorithmic_bytes_per_launch": algo0,
                 "traffic_over_algorithmic": (round(traffic / algo0, 2) if traffic else None),
                 "traffic": traffic,

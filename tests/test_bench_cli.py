@@ -65,3 +65,44 @@ def test_executed_node_counts_match_a_tree_walk():
     nodes = np.array([t for q in progs for t in q], np.uint32)
     off = np.cumsum([0] + [len(q) for q in progs])
     assert list(bench.executed_node_counts(nodes, off)) == [3, 1, 3, 3, 1]
+
+
+def _operators_by_tree(prog, by_op):
+    """Operators that depend on a variable, by recursion over the expression
+    tree (a subtree is a constant flag)."""
+    stack = []
+    for t in prog:
+        op = int(t) & 0xFF
+        if op <= 1:
+            stack.append(op == 1)
+        elif op >= 6:
+            c = stack.pop()
+            if not c:
+                by_op[op] += 1
+            stack.append(c)
+        else:
+            cb, ca = stack.pop(), stack.pop()
+            if not (ca and cb):
+                by_op[op] += 1
+            stack.append(ca and cb)
+
+
+def test_executed_operator_mix_matches_a_tree_walk():
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2607_06731_amd import synth
+    w = synth.make_workload("generation", n_programs=3000, n_cases=16)
+    sel = np.arange(w.pop.n_programs) % 3 != 1
+    got = bench.executed_operator_mix(w.pop.nodes, w.pop.offsets, sel, chunk=700)
+    want = np.zeros(12, np.int64)
+    for p in np.nonzero(sel)[0]:
+        _operators_by_tree(w.pop.nodes[w.pop.offsets[p]:w.pop.offsets[p + 1]], want)
+    assert np.array_equal(got, want)
+    # hand-made: x0 c + (one +), c c + (none), c sin x0 * (one *), x0 sin c sin * (sin, *)
+    C = lambda j: 1 | (j << 8)
+    progs = [[0, C(0), 2], [C(0), C(1), 2], [C(0), 6, 0, 4], [0, 6, C(0), 6, 4]]
+    nodes = np.array([t for q in progs for t in q], np.uint32)
+    off = np.cumsum([0] + [len(q) for q in progs])
+    mix = bench.executed_operator_mix(nodes, off, np.ones(4, bool))
+    assert list(mix) == [0, 0, 1, 0, 2, 0, 1, 0, 0, 0, 0, 0]
