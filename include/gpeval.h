@@ -363,9 +363,10 @@ int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs
  * and the defaults (24 KiB, 32 tiles) give gp_eval's bits; other values may
  * differ from gp_eval in the last bits (within the fitness tolerance).
  * With autotune != 0, gp_plan_create times candidate knobs on the given
- * inputs (coordinate descent over the five knobs, two sweeps: this runs the
- * evaluation a few dozen times and synchronizes `stream`) and keeps the
- * fastest; results are cached per workload shape (device, cases, variables,
+ * inputs (coordinate descent over the five knobs, two sweeps, the median
+ * of five runs per candidate, then a run-off of the three fastest: this
+ * runs the evaluation about 130 times and synchronizes `stream`) and keeps
+ * the fastest; results are cached per workload shape (device, cases, variables,
  * programs, mean length, requests) in the process and, if the environment
  * variable GPEVAL_TUNE_CACHE names a file, there too.
  */

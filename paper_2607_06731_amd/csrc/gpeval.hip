@@ -7,7 +7,8 @@
 //                    variable discipline, 32-cell limit, opcode/operand
 //                    ranges, allowed ops), count staged instructions, depth
 //                    class and partition key; per-block key counts and
-//                    staged sizes.
+//                    staged sizes (a short walk when the op mask stays
+//                    within the benchmark set).
 //   k_class_scan     one workgroup: scans of both; class ranges.
 //   k_stage          one thread per program: stage each instruction as one
 //                    8-byte word {flags | selector | slot, payload} at a
@@ -20,7 +21,9 @@
 //   k_seg_count /    per (class, request): program counts, positions and
 //   k_seg_scan       work-item prefixes.
 //   k_eval<MAXD,K,FIT> persistent workgroups pull (program group, case tile)
-//                    items from an atomic counter; the tile's inputs and
+//                    items from an atomic counter (tile-major, or group-major
+//                    for the depth <= 8 class when the classes run one after
+//                    another); the tile's inputs and
 //                    targets are staged in LDS; each wavefront takes the
 //                    group's programs one at a time and runs one over the
 //                    64*K cases of the sub-tile (K per lane) with the value
@@ -1069,6 +1072,7 @@ struct EvalConst {
     int32_t max_vars;       // largest n_vars of the call
     int32_t n_seg;
     int32_t tile_floats;    // LDS floats for input windows
+    int32_t group_major;    // depth <= 8 class: a group's case tiles are consecutive items
     // single-dataset form (gp_predict)
     int64_t ld_x;
     int64_t n_cases;
@@ -1610,9 +1614,17 @@ __global__ __launch_bounds__(kWG) void k_eval(
         const int window = Dp->window[c];
         const int count = cnt_c[sl];
         const int n_groups = (count + G - 1) / G;
+        // item order inside a segment: tile-major (tile t of every group,
+        // then tile t + 1), or, for the depth <= 8 class when the classes
+        // run one after another, group-major (a group's case tiles are
+        // consecutive items, so workgroups running at the same time read
+        // the group's instruction words while they are in the cache).  The
+        // order changes no result.
         const uint32_t local = item - pre_c[sl];
-        const int tile = (int)(local / (uint32_t)n_groups);
-        const int grp = (int)(local % (uint32_t)n_groups);
+        const uint32_t n_tiles = (uint32_t)Dp->n_tiles[c];
+        const bool gm = MAXD == 8 && a.group_major != 0;
+        const int tile = gm ? (int)(local % n_tiles) : (int)(local / (uint32_t)n_groups);
+        const int grp = gm ? (int)(local / n_tiles) : (int)(local % (uint32_t)n_groups);
         const int g0 = grp * G;
         const int gn = min(G, count - g0);
         const int obase = cstart + pos_c[sl] + g0;
@@ -2434,6 +2446,9 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
     ea.n_seg = pb.n_req;
     ea.reward_power = pb.reward_power;
     ea.reward_M = (float)pb.max_score;
+    // group-major items in the depth <= 8 class pay when that class has the
+    // GPU to itself; overlapped with the other classes, tile-major is faster
+    ea.group_major = tu.concurrent ? 0 : 1;
     if (tu.concurrent) {
         GP_HIP_TRY(hipEventRecord(side.fork, stream));
         for (auto& x : side.s) GP_HIP_TRY(hipStreamWaitEvent(x, side.fork, 0));
@@ -2631,10 +2646,10 @@ int plan_build(gp_plan* p)
     return GP_OK;
 }
 
-// Median of three timed runs of one configuration (after one warm-up), or
-// a negative value when it does not fit the plan's workspace.
+// Median of `runs` timed runs of one configuration (after one warm-up when
+// `warm`), or a negative value when it does not fit the plan's workspace.
 int time_config(gp_plan* p, const Tuning& t, hipStream_t stream, hipEvent_t e0, hipEvent_t e1,
-                float* ms_out)
+                float* ms_out, int runs = 5, bool warm = true)
 {
     *ms_out = -1.f;
     EvalLaunch el;
@@ -2644,17 +2659,18 @@ int time_config(gp_plan* p, const Tuning& t, hipStream_t stream, hipEvent_t e0, 
     const Staged st = carve(p->ws, el.layout);
     CallEvents none;
     (void)none.begin(false);
-    float ms3[3];
-    if ((rc = enqueue_eval(p->pb, t, el, st, p->side, stream, none)) != GP_OK) return rc;
-    for (int r = 0; r < 3; ++r) {
+    float ms[8];
+    runs = std::min(std::max(runs, 1), 8);
+    if (warm && (rc = enqueue_eval(p->pb, t, el, st, p->side, stream, none)) != GP_OK) return rc;
+    for (int r = 0; r < runs; ++r) {
         GP_HIP_TRY(hipEventRecord(e0, stream));
         if ((rc = enqueue_eval(p->pb, t, el, st, p->side, stream, none)) != GP_OK) return rc;
         GP_HIP_TRY(hipEventRecord(e1, stream));
         GP_HIP_TRY(hipEventSynchronize(e1));
-        GP_HIP_TRY(hipEventElapsedTime(&ms3[r], e0, e1));
+        GP_HIP_TRY(hipEventElapsedTime(&ms[r], e0, e1));
     }
-    std::sort(ms3, ms3 + 3);
-    *ms_out = ms3[1];
+    std::sort(ms, ms + runs);
+    *ms_out = ms[runs / 2];
     return GP_OK;
 }
 
@@ -2662,7 +2678,9 @@ int time_config(gp_plan* p, const Tuning& t, hipStream_t stream, hipEvent_t e0, 
 // descent over five axes (programs per work item, workgroups per CU, depth
 // classes on forked streams, the LDS budget of an input window, the cap on
 // case tiles per program), each axis tried in turn with the others at their
-// best so far, two sweeps.  The tile axes set a program's summation order,
+// best so far, two sweeps, each candidate the median of five runs; then the
+// three fastest candidates are timed again in turns (five rounds, one run
+// each per round, so drift hits them alike) and the lowest median wins.  The tile axes set a program's summation order,
 // so the chosen plan is deterministic for its problem shape (the tuning is
 // cached by it) but may differ from gp_eval in the last bits.
 int plan_autotune(gp_plan* p, hipStream_t stream)
@@ -2692,6 +2710,8 @@ int plan_autotune(gp_plan* p, hipStream_t stream)
     int rc = time_config(p, best, stream, e0, e1, &best_ms);
     if (rc == GP_OK && best_ms < 0.f) best_ms = 1e30f;
     int tried = 1;
+    std::vector<std::pair<float, Tuning>> seen;
+    if (best_ms < 1e30f) seen.push_back({best_ms, best});
     for (int sweep = 0; sweep < 2 && rc == GP_OK; ++sweep) {
         for (int a = 0; a < kAxes && rc == GP_OK; ++a) {
             for (int v : values[a]) {
@@ -2701,9 +2721,45 @@ int plan_autotune(gp_plan* p, hipStream_t stream)
                 float ms = -1.f;
                 if ((rc = time_config(p, t, stream, e0, e1, &ms)) != GP_OK) break;
                 ++tried;
+                if (ms >= 0.f) seen.push_back({ms, t});
                 if (ms >= 0.f && ms < best_ms) {
                     best_ms = ms;
                     best = t;
+                }
+            }
+        }
+    }
+    // run-off among the three fastest distinct candidates
+    if (rc == GP_OK && seen.size() > 1) {
+        std::stable_sort(seen.begin(), seen.end(),
+                         [](const std::pair<float, Tuning>& x, const std::pair<float, Tuning>& y) {
+                             return x.first < y.first;
+                         });
+        auto same = [](const Tuning& x, const Tuning& y) {
+            return x.G == y.G && x.wg_per_cu == y.wg_per_cu && x.concurrent == y.concurrent &&
+                   x.tile_lds == y.tile_lds && x.tile_max == y.tile_max;
+        };
+        std::vector<Tuning> top;
+        for (const auto& c : seen) {
+            bool dup = false;
+            for (const auto& u : top) dup = dup || same(u, c.second);
+            if (!dup) top.push_back(c.second);
+            if (top.size() == 3) break;
+        }
+        std::vector<std::vector<float>> smp(top.size());
+        for (int round = 0; round < 5 && rc == GP_OK; ++round)
+            for (size_t i = 0; i < top.size() && rc == GP_OK; ++i) {
+                float ms = -1.f;
+                if ((rc = time_config(p, top[i], stream, e0, e1, &ms, 1, round == 0)) == GP_OK)
+                    smp[i].push_back(ms);
+            }
+        if (rc == GP_OK) {
+            for (size_t i = 0; i < top.size(); ++i) {
+                std::sort(smp[i].begin(), smp[i].end());
+                const float med = smp[i][smp[i].size() / 2];
+                if (i == 0 || med < best_ms) {
+                    best_ms = med;
+                    best = top[i];
                 }
             }
         }

@@ -1,8 +1,10 @@
 // staging.h -- the interpreter's staged program format and the staging
 // walk: validation with the instruction count (check_program) and emission
-// (stage_walk).  Included by gpeval.hip for the device passes (k_validate,
-// k_stage) and by a host test harness, so the count, the emission and the
-// meaning of the staged words can be checked without a GPU.
+// (stage_walk), and their short forms for op masks within the benchmark set
+// (check_program_base, stage_walk_base).  Included by gpeval.hip for the
+// device passes (k_validate, k_stage) and by a host test harness, so the
+// count, the emission and the meaning of the staged words can be checked
+// without a GPU.
 //
 // The includer provides, before this header: gpeval.h, uint2 and
 // make_uint2, __float_as_uint, the LDS float type lds_f32, kHeldConsts and

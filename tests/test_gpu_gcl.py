@@ -300,6 +300,19 @@ def test_base_and_full_table_interpreters_agree():
     assert np.array_equal(F_base, F_full, equal_nan=True)
 
 
+def test_predict_base_and_full_table_masks_agree():
+    """Per-case outputs of benchmark-set programs are the same bits staged
+    by the benchmark-set walks (a mask within GP_BASE_OPS) and by the
+    general walks with the full-table interpreter."""
+    gp = _gp()
+    from paper_2607_06731_amd import synth
+    w = synth.make_workload("generation", n_programs=3000, n_cases=700)
+    base = gp.predict(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.allowed_mask)
+    full = gp.predict(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, gp.GP_ALL_OPS)
+    _say("predict: base vs full-table walks")
+    assert np.array_equal(base.view(np.uint32), full.view(np.uint32))
+
+
 def test_gcl_full_size_sampled():
     """The GCL workload at full size (20,000 programs x 2,048 cases), gated
     on a seeded length-stratified sample."""
