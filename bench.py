@@ -43,14 +43,17 @@ if ROOT not in sys.path:
 # operation.
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # fp32 VALU instructions per case of each operator as the interpreter
-# computes it (opcodes LOAD, CONST, ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG,
-# SQRT, ABS): counted in the AMD assembly of the library's own operator
-# functions compiled alone for gfx950 (protected division: IEEE division
-# plus the guard's compare and select; sin, cos and exp: the fast formula
-# plus the range compare; ln: hardware log2 and the split ln 2 product
-# plus the guard; square root: the denormal-safe scaling around the
-# hardware root).  Leaves are LDS reads, no VALU arithmetic.
-OP_VALU = (0, 0, 1, 1, 1, 13, 15, 17, 10, 5, 6, 1)
+# computes it in its common path (opcodes LOAD, CONST, ADD, SUB, MUL, DIV,
+# SIN, COS, EXP, LOG, SQRT, ABS): the operator's own arithmetic counted in
+# the AMD assembly of the library's operator functions compiled alone for
+# gfx950 (tests/test_op_costs.py recounts them), plus one for the
+# wavefront's range compare where the interpreter makes one (sin, cos and
+# exp: the fast formula; square root: the hardware root of |a|, the
+# denormal-safe scaling only when some case is tiny).  Protected division:
+# IEEE division plus the guard's compare and select; ln: hardware log2,
+# the split ln 2 product and the guard.  Leaves are LDS reads, no VALU
+# arithmetic.
+OP_VALU = (0, 0, 1, 1, 1, 13, 15, 17, 10, 5, 2, 1)
 
 
 def cpu_baseline(w, budget_s=15.0, fitness="mse"):

@@ -350,6 +350,9 @@ GP_STAGING_FN void check_program_base(Nodes nodes, int64_t s, int64_t e, uint32_
                                       int32_t n_vars, int64_t n_consts, int& status, int& maxd,
                                       int64_t& n_staged)
 {
+    // every lane of a wavefront walks a different program, so the step is
+    // written as selects (no branch per node kind): all lanes run the same
+    // instructions whatever their node is
     int depth = 0, md = 0, np = 0, st = GP_PROG_OK;
     int64_t n_st = 0;
     bool taken = false;
@@ -357,33 +360,37 @@ GP_STAGING_FN void check_program_base(Nodes nodes, int64_t s, int64_t e, uint32_
     for (int64_t k = s; k < e; ++k) {
         const uint32_t op = w & 0xFFu, arg = w >> 8;
         const uint32_t wn = k + 1 < e ? nodes(k + 1) : 0xFFu;   // next word, read early
-        const bool leaf = op <= GP_CONST, bin = op >= GP_ADD && op <= GP_DIV;
+        const bool leaf = op <= GP_CONST;
+        const bool bin = op - GP_ADD < 4u;                        // ADD..DIV
+        const bool un = op - GP_SIN < 6u;                         // SIN..ABS
         const int need = leaf ? 0 : (bin ? 2 : 1);
         const int eff = leaf ? 1 : (bin ? -1 : 0);
-        if (op >= 32u || !((allowed >> op) & 1u)) st = GP_PROG_BAD_OP;
-        else if (op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars) st = GP_PROG_BAD_VAR;
-        else if (op == GP_CONST && (int64_t)arg >= n_consts) st = GP_PROG_BAD_CONST;
-        else if (depth < need) st = GP_PROG_UNDERFLOW;
-        else if (depth + eff > GP_MAX_STACK) st = GP_PROG_TOO_DEEP;
-        if (st != GP_PROG_OK) break;
+        const bool ok_op = op < 32u && ((allowed >> (op & 31u)) & 1u);
+        // the checks in check_program's order: the first failing one names it
+        int code = depth + eff > GP_MAX_STACK ? GP_PROG_TOO_DEEP : GP_PROG_OK;
+        code = depth < need ? GP_PROG_UNDERFLOW : code;
+        code = op == GP_CONST && (int64_t)arg >= n_consts ? GP_PROG_BAD_CONST : code;
+        code = op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars ? GP_PROG_BAD_VAR : code;
+        code = ok_op ? code : GP_PROG_BAD_OP;
+        if (code != GP_PROG_OK) {
+            st = code;
+            break;
+        }
         depth += eff;
         md = depth > md ? depth : md;
-        if (op == GP_CONST) {
-            if (np == kHeldConsts) { n_st += np; np = 0; }
-            ++np;
-        } else if (op == GP_LOAD) {
-            n_st += np + 1;
-            np = 0;
-            const uint32_t nx = wn & 0xFFu;
-            taken = nx >= GP_ADD && nx <= GP_ABS;
-        } else if (taken) {
-            taken = false;
-        } else if (bin) {
-            if (np >= 2) --np;
-            else { np = 0; ++n_st; }
-        } else {
-            n_st += np == 0 ? 1 : 0;
-        }
+        // staged words, as stage_walk emits them: a full run of held
+        // constants is pushed before the next is held; a variable pushes
+        // the held ones, then itself; an operator folded into the variable
+        // before it adds nothing; a binary op over fewer than two held
+        // constants is one word, a unary op on the runtime top is one word
+        const bool cst = op == GP_CONST, var = op == GP_LOAD;
+        const bool cap = cst && np == kHeldConsts;
+        const bool run_bin = bin && !taken, run_un = un && !taken;
+        n_st += (cap ? np : 0) + (var ? np + 1 : 0) + (run_bin && np <= 1 ? 1 : 0) +
+                (run_un && np == 0 ? 1 : 0);
+        np = cst ? (cap ? 1 : np + 1) : (var ? 0 : (run_bin ? (np >= 2 ? np - 1 : 0) : np));
+        const uint32_t nx = wn & 0xFFu;
+        taken = var && nx >= GP_ADD && nx <= GP_ABS;
         w = wn;
     }
     maxd = md;
