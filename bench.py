@@ -125,12 +125,19 @@ def oracle_threads(n_programs):
 
 
 def kernel_source_digest():
-    """SHA-256 over the kernel sources (gpeval.hip, then staging.h)."""
+    """SHA-256 over the code of the kernel sources (gpeval.hip, then
+    staging.h) with comments and blank space left out, so an edit of a
+    comment keeps the counters that were taken on the same code, and any
+    change of the code drops them."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("gpeval.hip", "staging.h"):
-        with open(os.path.join(ROOT, "paper_2607_06731_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2607_06731_amd", "csrc", name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -2680,9 +2680,10 @@ int time_config(gp_plan* p, const Tuning& t, hipStream_t stream, hipEvent_t e0, 
 // case tiles per program), each axis tried in turn with the others at their
 // best so far, two sweeps, each candidate the median of five runs; then the
 // three fastest candidates are timed again in turns (five rounds, one run
-// each per round, so drift hits them alike) and the lowest median wins.  The tile axes set a program's summation order,
-// so the chosen plan is deterministic for its problem shape (the tuning is
-// cached by it) but may differ from gp_eval in the last bits.
+// each per round, so drift hits them alike) and the lowest median wins.
+// The tile axes set a program's summation order, so the chosen plan is
+// deterministic for its problem shape (the tuning is cached by it) but may
+// differ from gp_eval in the last bits.
 int plan_autotune(gp_plan* p, hipStream_t stream)
 {
     const std::string key = tune_key(p->pb);
