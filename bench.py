@@ -129,12 +129,19 @@ def kernel_source_digest():
     staging.h) with comments and blank space left out, so an edit of a
     comment keeps the counters that were taken on the same code, and any
     change of the code drops them."""
+    texts = []
+    for name in ("gpeval.hip", "staging.h"):
+        with open(os.path.join(ROOT, "paper_2607_06731_amd", "csrc", name)) as f:
+            texts.append(f.read())
+    return code_digest(texts)
+
+
+def code_digest(texts):
+    """SHA-256 over C/C++ source texts with comments and blank space left out."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for name in ("gpeval.hip", "staging.h"):
-        with open(os.path.join(ROOT, "paper_2607_06731_amd", "csrc", name)) as f:
-            text = f.read()
+    for text in texts:
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
         h.update(" ".join(text.split()).encode())

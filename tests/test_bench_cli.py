@@ -106,3 +106,15 @@ def test_executed_operator_mix_matches_a_tree_walk():
     off = np.cumsum([0] + [len(q) for q in progs])
     mix = bench.executed_operator_mix(nodes, off, np.ones(4, bool))
     assert list(mix) == [0, 0, 1, 0, 2, 0, 1, 0, 0, 0, 0, 0]
+
+
+def test_code_digest_ignores_comments_and_layout_only():
+    sys.path.insert(0, ROOT)
+    import bench
+    a = "int f(int x)\n{\n    return x + 1;   // one more\n}\n"
+    b = "/* the successor */\nint f(int x) { return x + 1; }\n"
+    c = "int f(int x)\n{\n    return x + 2;\n}\n"
+    assert bench.code_digest([a]) == bench.code_digest([b])
+    assert bench.code_digest([a]) != bench.code_digest([c])
+    assert bench.code_digest([a, c]) != bench.code_digest([c, a])
+    assert bench.measured_counters("generation").get("traffic_bytes_per_launch")
