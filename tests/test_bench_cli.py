@@ -117,4 +117,3 @@ def test_code_digest_ignores_comments_and_layout_only():
     assert bench.code_digest([a]) == bench.code_digest([b])
     assert bench.code_digest([a]) != bench.code_digest([c])
     assert bench.code_digest([a, c]) != bench.code_digest([c, a])
-    assert bench.measured_counters("generation").get("traffic_bytes_per_launch")
