@@ -318,6 +318,26 @@ def test_deep_and_long_programs():
     _gate(F, nodes, off, np.zeros(0, np.float32), X, y, 1e-3, oracle.MASK_BENCH, "deep/long")
 
 
+def test_long_programs_staged_from_global_memory():
+    """Programs of 150-260 nodes: a staging block's 128 programs span more
+    nodes than its LDS node cache, so validation and staging read the nodes
+    and constants from global memory (the short walks of a mask within the
+    benchmark set, and the general walks of the full-table mask, which must
+    give the same bits)."""
+    gp = _need_gpu()
+    from paper_2607_06731_amd import synth
+    rng = np.random.default_rng(21)
+    pop = synth.sample_programs(rng, rng.integers(150, 261, 1000), 4, synth.UNARY_2)
+    assert (np.diff(pop.offsets)[:128].sum()) > 6656
+    X = rng.uniform(-2, 2, (4, 1024)).astype(np.float32)
+    y = rng.uniform(-2, 2, 1024).astype(np.float32)
+    _say("long programs, uncached staging")
+    F = _run(gp, pop.nodes, pop.offsets, pop.consts, X, y, 1e-3, oracle.MASK_BENCH)
+    _gate(F, pop.nodes, pop.offsets, pop.consts, X, y, 1e-3, oracle.MASK_BENCH, "long/uncached")
+    F_full = _run(gp, pop.nodes, pop.offsets, pop.consts, X, y, 1e-3, gp.GP_ALL_OPS)
+    assert np.array_equal(F, F_full, equal_nan=True)
+
+
 def test_no_variables_and_single_case():
     gp = _need_gpu()
     from oracle import ADD, CONST, MUL
