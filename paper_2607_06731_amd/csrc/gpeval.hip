@@ -7,19 +7,21 @@
 //                    variable discipline, 32-cell limit, opcode/operand
 //                    ranges, allowed ops), count staged instructions, depth
 //                    class and partition key; per-block key counts and
-//                    staged sizes (a short walk when the op mask stays
-//                    within the benchmark set).
-//   k_class_scan     one workgroup: scans of both; class ranges.
+//                    staged sizes.  With an op mask within the benchmark
+//                    set the same walk stages the program in place (below).
+//   k_class_scan     one workgroup: scans of both; class ranges (and for a
+//                    single request its per-class work-item tables).
 //   k_stage          one thread per program: stage each instruction as one
-//                    8-byte word {flags | selector | slot, payload} at a
-//                    range of its own, folding constant subtrees and a leaf
-//                    into the operator after it (stack moves and variables
-//                    become cell moves); stable scatter of program ids by
-//                    (depth class, length band): each depth class (max
-//                    depth <= 8, <= 16, <= 32) runs a kernel whose register
-//                    stack is only as deep as needed, longest programs first.
-//   k_seg_count /    per (class, request): program counts, positions and
-//   k_seg_scan       work-item prefixes.
+//                    8-byte word {flags | selector | cell, payload} in a
+//                    range of its own (unless k_validate did), folding
+//                    constant subtrees and a leaf into the operator after
+//                    it (stack moves and variables become cell moves);
+//                    stable scatter of program ids by (depth class, length
+//                    band): each depth class (max depth <= 8, <= 16, <= 32)
+//                    runs a kernel whose register stack is only as deep as
+//                    needed, longest programs first.
+//   k_seg_tables     several requests: per (class, request) program counts,
+//                    positions and work-item prefixes.
 //   k_eval<MAXD,K,FIT> persistent workgroups pull (program group, case tile)
 //                    items from an atomic counter (tile-major, or group-major
 //                    for the depth <= 8 class when the classes run one after
@@ -107,13 +109,13 @@ constexpr int kLenBuckets = 8;           // staged length 1, 2-3, ..., 64-127, 1
 constexpr int kKeys = kClasses * kLenBuckets;
 constexpr int kK1 = 4;                  // cases per lane of the depth <= 16 class
 constexpr int kMaxTiles = 32;            // case tiles per program (cap)
-constexpr uint32_t kNoSlot = 0xFFu;      // staged write slot: nothing to save
 constexpr int kBucketBlock = 128;        // programs per staging/partition block
 constexpr int kStageNodes = 6656;        // LDS node cache of a staging block (26 KB, 52 per program)
-// The emitting pass's cache also holds an op byte per node (30 KB for 6144
-// nodes, 48 per program), which with the held constants keeps four of its
-// blocks per CU.
+// The short walk's cache (op masks within the benchmark set) holds an op
+// byte and a payload per node (30 KB for 6144 nodes, 48 per program),
+// which with the held constants keeps four staging blocks per CU.
 constexpr int kStageNodesEmit = 6144;
+constexpr uint32_t kOpByteBadConst = 0xFEu;   // its op byte of a constant out of range
 // Constants held back for folding per program while staging: a longer run
 // of constants is pushed (as runtime values) before the next one is held.
 // 16 keeps the staging block at four per CU (with the node cache).
@@ -238,6 +240,7 @@ struct DevRequest {
 // the single dataset `one` is used; with req_in == NULL the single request
 // `one_req`.  *bad becomes 1 for inconsistent tables; then no program is
 // staged and sizes are clamped so that every later index stays in range.
+// bad[1] (k_validate's restage flag) is cleared.
 __global__ __launch_bounds__(256) void k_tables(
     const gp_dataset* __restrict__ ds_in, int32_t n_ds, gp_dataset one,
     const gp_request* __restrict__ req_in, int32_t n_req, gp_request one_req,
@@ -331,7 +334,10 @@ __global__ __launch_bounds__(256) void k_tables(
     }
     if (threadIdx.x == 0) seg_start[n_req] = n_programs;
     __syncthreads();
-    if (threadIdx.x == 0) *bad = s_bad;
+    if (threadIdx.x == 0) {
+        bad[0] = s_bad;
+        bad[1] = 0;                     // the restage flag, raised by k_validate
+    }
 }
 
 // ------------------------------------------------------------------ sin/cos
@@ -631,11 +637,12 @@ __device__ bool cache_block_nodes(bool mine, int r, int64_t s, int64_t e,
     return use;
 }
 
-// The emitting pass's LDS copy of the block's node range: the op byte of
-// each node, and its payload: the constant's value bits for a constant
-// (whose index is in range), the argument otherwise.  The constants are
-// gathered here, many loads in flight per thread, so the walk that emits
-// the staged words reads only LDS.  Every thread of the block must call it.
+// The short walk's LDS copy of the block's node range: the op byte of
+// each node (kOpByteBadConst for a constant whose index is out of range,
+// 0xFF for any opcode from 32 on) and its payload: the constant's value
+// bits for a constant in range, the argument otherwise.  The constants are
+// gathered here, many loads in flight per thread, so the walk reads only
+// LDS.  Every thread of the block must call it.
 __device__ bool cache_block_stage(bool mine, int r, int64_t s, int64_t e,
                                   const DevRequest* __restrict__ reqs, lds_u8* ops,
                                   lds_u32* pay, int64_t* lo)
@@ -666,8 +673,10 @@ __device__ bool cache_block_stage(bool mine, int r, int64_t s, int64_t e,
                 const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
                 if (i < n) {
                     const uint32_t op = v[u] & 0xFFu;
-                    ops[i] = (uint8_t)op;
-                    pay[i] = op == GP_CONST ? __float_as_uint(c[u]) : v[u] >> 8;
+                    const bool cst = op == GP_CONST;
+                    const bool bad = cst && (int64_t)(v[u] >> 8) >= nc;
+                    ops[i] = (uint8_t)(bad ? kOpByteBadConst : (op < 32u ? op : 0xFFu));
+                    pay[i] = cst ? __float_as_uint(c[u]) : v[u] >> 8;
                 }
             }
         }
@@ -676,42 +685,67 @@ __device__ bool cache_block_stage(bool mine, int r, int64_t s, int64_t e,
     return use;
 }
 
-// Readers of the benchmark-set emitting walk: op, variable index, constant
-// value, from the block's LDS copy or straight from the request's arrays.
+#define GP_STAGING_FN __device__
+#include "staging.h"
+
+// Readers of the benchmark-set walk (stage_check_base): op (kOpBadConst
+// for a constant out of range), variable index, constant value, from the
+// block's LDS copy or straight from the request's arrays.
 struct LdsStageReader {
     const lds_u8* o;
     const lds_u32* p;
     int64_t lo;
-    __device__ uint32_t op(int64_t k) const { return o[k - lo]; }
+    __device__ uint32_t op(int64_t k) const
+    {
+        const uint32_t b = o[k - lo];
+        return b == kOpByteBadConst ? kOpBadConst : b;
+    }
     __device__ uint32_t arg(int64_t k) const { return p[k - lo]; }
     __device__ float cval(int64_t k) const { return __uint_as_float(p[k - lo]); }
 };
 struct GlobalStageReader {
     const uint32_t* __restrict__ n;
     const float* __restrict__ c;
-    __device__ uint32_t op(int64_t k) const { return n[k] & 0xFFu; }
+    int64_t n_consts;
+    __device__ uint32_t op(int64_t k) const
+    {
+        const uint32_t w = n[k], op = w & 0xFFu;
+        return op == GP_CONST && (int64_t)(w >> 8) >= n_consts ? kOpBadConst : op;
+    }
     __device__ uint32_t arg(int64_t k) const { return n[k] >> 8; }
     __device__ float cval(int64_t k) const { return c[n[k] >> 8]; }
 };
 
-#define GP_STAGING_FN __device__
-#include "staging.h"
+// LDS words of a staging block's node copy: the general walk's node
+// words, or the short walk's payloads followed by its op bytes.
+constexpr int kCacheWords = kStageNodes > kStageNodesEmit + kStageNodesEmit / 4
+                                ? kStageNodes : kStageNodesEmit + kStageNodesEmit / 4;
 
 // Pass 1, one thread per program (blocks of kBucketBlock): validate, count
 // staged instructions, derive the depth class and the partition key, and
 // accumulate per-block key counts and staged sizes for the scans that
 // follow.  The block's nodes are read from an LDS copy when they fit.
+// With an op mask within the benchmark set the same walk also stages the
+// program, at its own node offset in the request's part of `code` (staged
+// words never outnumber nodes, so the programs' ranges hold them, disjoint
+// while the offsets never decrease); a program whose offsets do decrease
+// sets *restage, and k_stage then stages every program again, packed.
 __global__ __launch_bounds__(kBucketBlock) void k_validate(
     int64_t n_programs, uint32_t allowed, const DevDataset* __restrict__ ds,
     const DevRequest* __restrict__ reqs, const int64_t* __restrict__ seg_start, int32_t n_seg,
     const int32_t* __restrict__ tables_bad, int32_t lpt, int32_t n_blk,
     ProgMeta* __restrict__ meta, uint8_t* __restrict__ cls, int32_t* __restrict__ pds,
-    int32_t* __restrict__ blk_counts, int64_t* __restrict__ blk_slen)
+    int32_t* __restrict__ blk_counts, int64_t* __restrict__ blk_slen, uint2* __restrict__ code,
+    int32_t* __restrict__ restage)
 {
     __shared__ int cnt[kKeys];
     __shared__ unsigned long long s_slen;
-    __shared__ uint32_t cache_mem[kStageNodes];
+    __shared__ uint32_t cache_mem[kCacheWords];
+    __shared__ float pv_mem[kHeldConsts * kBucketBlock];
     lds_u32* cache = (lds_u32*)cache_mem;
+    // a mask within the benchmark set: the short walk, which also stages
+    const bool base = (allowed & ~GP_BASE_OPS) == 0u;
+    lds_u8* ops = (lds_u8*)(cache + kStageNodesEmit);
     if (threadIdx.x < kKeys) cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_slen = 0ull;
     const int64_t p = (int64_t)blockIdx.x * kBucketBlock + threadIdx.x;
@@ -728,12 +762,14 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
         if (tab_ok) {
             s = R.offsets[q];
             e = R.offsets[q + 1];
+            if (e < s) *restage = 1;
         }
     }
     const bool range_ok = s >= 0 && e >= s && e <= R.n_nodes && e - s <= INT32_MAX - 1;
+    const bool mine = have && tab_ok && range_ok && e > s;
     int64_t lo = 0;
-    const bool cached = cache_block_nodes(have && tab_ok && range_ok && e > s, r, s, e, reqs,
-                                          cache, &lo);
+    const bool cached = base ? cache_block_stage(mine, r, s, e, reqs, ops, cache, &lo)
+                             : cache_block_nodes(mine, r, s, e, reqs, cache, &lo);
     if (have) {
         int status = GP_PROG_OK;
         int maxd = 0;
@@ -746,14 +782,14 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
             status = GP_PROG_EMPTY;
         } else {
             const int32_t n_vars = ds[R.dataset].n_vars;
-            // a mask within the benchmark set takes the short walk
-            const bool base = (allowed & ~GP_BASE_OPS) == 0u;
+            uint2* dst = code + R.node_base + s;
+            lds_f32* pvs = (lds_f32*)pv_mem + threadIdx.x;
             if (base && cached)
-                check_program_base(LdsNodes{cache, lo}, s, e, allowed, n_vars, R.n_consts, status,
-                                   maxd, n_staged);
+                n_staged = stage_check_base(LdsStageReader{ops, cache, lo}, s, e, allowed, n_vars,
+                                            dst, pvs, status, maxd);
             else if (base)
-                check_program_base(GlobalNodes{R.nodes}, s, e, allowed, n_vars, R.n_consts,
-                                   status, maxd, n_staged);
+                n_staged = stage_check_base(GlobalStageReader{R.nodes, R.consts, R.n_consts}, s, e,
+                                            allowed, n_vars, dst, pvs, status, maxd);
             else if (cached)
                 check_program(LdsNodes{cache, lo}, s, e, allowed, n_vars, R.n_consts, status, maxd,
                               n_staged);
@@ -763,7 +799,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
         }
         const int c = status == GP_PROG_OK ? depth_class(maxd) : -1;
         ProgMeta m;
-        m.start = 0;
+        m.start = R.node_base + s;            // where the short walk staged it
         m.len = (int32_t)(status == GP_PROG_BAD_OFFSETS || status == GP_PROG_BAD_TABLE ? 0 : e - s);
         m.slen = c >= 0 ? (int32_t)n_staged : 0;
         meta[p] = m;
@@ -784,264 +820,20 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
     if (threadIdx.x == 0) blk_slen[blockIdx.x] = (int64_t)s_slen;
 }
 
-// One workgroup: exclusive scans of the per-block key counts (key-major
-// order) into blk_base and of the per-block staged sizes into blk_code;
-// class_info[2c] = first position of depth class c, [2c+1] = its size (its
-// keys are contiguous); also clears the per-class work counters.  Staged
-// code never exceeds the call's node count unless programs' node ranges
-// overlap; then *overflow is set, nothing is staged and every class is
-// left empty.
-__global__ __launch_bounds__(1024) void k_class_scan(
-    const int32_t* __restrict__ blk_counts, const int64_t* __restrict__ blk_slen, int32_t n_blk,
-    int64_t code_capacity, int32_t* __restrict__ blk_base, int64_t* __restrict__ blk_code,
-    int32_t* __restrict__ class_info, uint32_t* __restrict__ work_counters,
-    int32_t* __restrict__ overflow)
+// Per depth class c, from its programs per segment (seg_cnt[c * n_seg +
+// s]): the group size (programs per work item) and, per segment, where its
+// programs start inside the class's range of `order` and the prefix of work
+// items (groups times the segment dataset's case tiles).  Groups are as
+// large as g_max allows while the class still has about target_items items
+// (a small class gets smaller groups, so its few programs still spread over
+// the GPU); never below 4, one program per wavefront of a workgroup.
+// Grouping never changes a result.
+__device__ void class_seg_tables(int c, int32_t n_seg, const int32_t* __restrict__ seg_cnt,
+                                 const int32_t* __restrict__ seg_ds,
+                                 const DevDataset* __restrict__ ds, int32_t g_max,
+                                 int32_t target_items, int32_t* __restrict__ seg_pos,
+                                 uint32_t* __restrict__ item_pre, int32_t* __restrict__ class_g)
 {
-    __shared__ int part[1024];
-    __shared__ long long lpart[1024];
-    const int t = threadIdx.x;
-    const int total = kKeys * n_blk;
-    const int chunk = (total + 1023) / 1024;
-    const int lo = t * chunk, hi = min(total, lo + chunk);
-    // loads in batches of 8, so that a thread's loads are in flight together
-    int sum = 0;
-    {
-        int i = lo;
-        for (; i + 8 <= hi; i += 8) {
-            int v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = blk_counts[i + u];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) sum += v[u];
-        }
-        for (; i < hi; ++i) sum += blk_counts[i];
-    }
-    part[t] = sum;
-    const int chunk2 = (n_blk + 1023) / 1024;
-    const int lo2 = t * chunk2, hi2 = min(n_blk, lo2 + chunk2);
-    long long sum2 = 0;
-    for (int i = lo2; i < hi2; ++i) sum2 += blk_slen[i];
-    lpart[t] = sum2;
-    __syncthreads();
-    // inclusive Hillis-Steele scans of the chunk sums
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = t >= off ? part[t - off] : 0;
-        const long long v2 = t >= off ? lpart[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        lpart[t] += v2;
-        __syncthreads();
-    }
-    int run = part[t] - sum;
-    {
-        int i = lo;
-        for (; i + 8 <= hi; i += 8) {
-            int v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = blk_counts[i + u];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                blk_base[i + u] = run;
-                run += v[u];
-            }
-        }
-        for (; i < hi; ++i) {
-            blk_base[i] = run;
-            run += blk_counts[i];
-        }
-    }
-    long long run2 = lpart[t] - sum2;
-    for (int i = lo2; i < hi2; ++i) {
-        blk_code[i] = run2;
-        run2 += blk_slen[i];
-    }
-    if (t < kClasses) {
-        // exclusive prefix of entry i from the scanned chunk sums (LDS)
-        auto prefix = [&](int i) {
-            if (i >= total) return part[1023];
-            const int owner = i / chunk;
-            int b = owner > 0 ? part[owner - 1] : 0;
-            for (int j = owner * chunk; j < i; ++j) b += blk_counts[j];
-            return b;
-        };
-        const bool ovf = lpart[1023] > code_capacity;
-        const int start = prefix(t * kLenBuckets * n_blk);
-        const int end = prefix((t + 1) * kLenBuckets * n_blk);
-        class_info[2 * t] = start;
-        class_info[2 * t + 1] = ovf ? 0 : end - start;
-        work_counters[t] = 0u;
-        if (t == 0) *overflow = ovf ? 1 : 0;
-    }
-}
-
-// Pass 2, same blocks as pass 1: each program's staged range starts at its
-// block's base plus the exclusive scan of staged sizes inside the block, so
-// ranges never overlap whatever the offsets; the program is staged there
-// and its id is scattered (stably) into the partition order.
-//
-// Staged instruction (8 bytes, one scalar load):
-//   x = flags | sel << 8 | slot << 16, y = payload
-//   kFPush  save the top into stack slot `slot`, then the top = leaf
-//   kFUn    the top = unary sel (SIN..ABS as 0..5) of the top
-//   kFSBin  the top = stack slot `slot`  OP_sel  top  (ADD..DIV as 0..3)
-//   kFLBin  the top = top  OP_sel  leaf
-//   kFLast  (with any of the above) the program's last instruction
-// A leaf is the constant with bits y when kFConst is set, else the input
-// row at LDS byte offset y (variable index * sub-tile cases * 4).  Eight
-// bytes (not sixteen) keep the code of the programs that the resident
-// wavefronts run at once small enough to stay in the scalar cache while
-// each program passes over its window.
-__global__ __launch_bounds__(kBucketBlock) void k_stage(
-    int64_t n_programs, const DevDataset* __restrict__ ds, const DevRequest* __restrict__ reqs,
-    const int64_t* __restrict__ seg_start, const int32_t* __restrict__ pds, int32_t n_blk,
-    const int64_t* __restrict__ blk_code, const int32_t* __restrict__ blk_base,
-    const int32_t* __restrict__ overflow, uint32_t allowed, uint8_t* __restrict__ cls,
-    ProgMeta* __restrict__ meta, uint2* __restrict__ code, int32_t* __restrict__ order)
-{
-    __shared__ long long sc[kBucketBlock];
-    constexpr int kW = kBucketBlock / 64;
-    __shared__ int wcnt[kW][kKeys];
-    // node cache (general walk), or payloads then op bytes (short walk)
-    constexpr int kCacheWords = kStageNodes > kStageNodesEmit + kStageNodesEmit / 4
-                                    ? kStageNodes : kStageNodesEmit + kStageNodesEmit / 4;
-    __shared__ uint32_t cache_mem[kCacheWords];
-    __shared__ float pv_mem[kHeldConsts * kBucketBlock];
-    lds_u32* cache = (lds_u32*)cache_mem;
-    // a mask within the benchmark set: the short walk over op bytes and
-    // gathered constant values (its cache ends where the op bytes begin)
-    const bool base = (allowed & ~GP_BASE_OPS) == 0u;
-    lds_u8* ops = (lds_u8*)(cache + kStageNodesEmit);
-    const int t = threadIdx.x;
-    const int64_t p = (int64_t)blockIdx.x * kBucketBlock + t;
-    int key = p < n_programs ? (int)cls[p] : 0xFF;
-    if (*overflow) {
-        // overlapping node ranges: no program of this call is staged
-        if (key < kKeys) {
-            cls[p] = 0xFF;
-            const int r = pds[p];
-            const DevRequest& R = reqs[r];
-            const int64_t q = p - seg_start[r];
-            if (R.out_status && q < R.n_programs) R.out_status[q] = GP_PROG_BAD_OFFSETS;
-        }
-        return;
-    }
-    ProgMeta m;
-    m.start = 0;
-    m.len = 0;
-    m.slen = 0;
-    if (p < n_programs) m = meta[p];
-    // inclusive scan of staged sizes inside the block
-    sc[t] = m.slen;
-    __syncthreads();
-    for (int off = 1; off < kBucketBlock; off <<= 1) {
-        const long long v = t >= off ? sc[t - off] : 0;
-        __syncthreads();
-        sc[t] += v;
-        __syncthreads();
-    }
-    const int64_t start = blk_code[blockIdx.x] + sc[t] - m.slen;
-    int r = 0;
-    int64_t s = 0, e = 0;
-    DevRequest R{};
-    if (key < kKeys) {
-        r = pds[p];
-        R = reqs[r];
-        const int64_t q = p - seg_start[r];
-        s = R.offsets[q];
-        e = R.offsets[q + 1];
-    }
-    int64_t lo = 0;
-    const bool cached = base ? cache_block_stage(key < kKeys, r, s, e, reqs, ops, cache, &lo)
-                             : cache_block_nodes(key < kKeys, r, s, e, reqs, cache, &lo);
-    if (key < kKeys) {
-        const int c = key / kLenBuckets;
-        const uint32_t J = 32u / (uint32_t)class_depth(c);
-        const uint32_t row_bytes = (uint32_t)(64 * class_k(c, ds[R.dataset].n_vars)) * 4u;
-        lds_f32* pvs = (lds_f32*)pv_mem + t;
-        if (base && cached)
-            stage_walk_base(LdsStageReader{ops, cache, lo}, s, e, J, row_bytes, code + start,
-                            m.slen, pvs);
-        else if (base)
-            stage_walk_base(GlobalStageReader{R.nodes, R.consts}, s, e, J, row_bytes,
-                            code + start, m.slen, pvs);
-        else if (cached)
-            stage_walk(LdsNodes{cache, lo}, s, e, GlobalConsts{R.consts}, J, row_bytes,
-                       code + start, m.slen, pvs);
-        else
-            stage_walk(GlobalNodes{R.nodes}, s, e, GlobalConsts{R.consts}, J, row_bytes,
-                       code + start, m.slen, pvs);
-        meta[p].start = start;
-    }
-    // stable scatter into the partition order
-    const int wave = t >> 6, lane = t & 63;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int rank = 0;
-    for (int kk = 0; kk < kKeys; ++kk) {
-        const uint64_t bm = __ballot(key == kk);
-        if (lane == 0) wcnt[wave][kk] = __popcll(bm);
-        if (key == kk) rank = __popcll(bm & below);
-    }
-    __syncthreads();
-    if (key < kKeys) {
-        for (int w2 = 0; w2 < wave; ++w2) rank += wcnt[w2][key];
-        order[blk_base[key * n_blk + blockIdx.x] + rank] = (int32_t)p;
-    }
-}
-
-// Programs of each depth class inside each segment: seg_cnt[c * n_seg + s].
-// One thread per (class, segment).  With several segments the partition
-// keeps each class in program order, so a segment's programs of class c are
-// the class's entries between two lower bounds of the segment's program
-// range; a single segment holds the whole class.
-__global__ __launch_bounds__(256) void k_seg_count(const int32_t* __restrict__ order,
-                                                   const int32_t* __restrict__ class_info,
-                                                   const int64_t* __restrict__ seg_start,
-                                                   int32_t n_seg,
-                                                   const int32_t* __restrict__ tables_bad,
-                                                   int32_t* __restrict__ seg_cnt)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kClasses * n_seg) return;
-    const int c = i / n_seg, sg = i - c * n_seg;
-    const int32_t* __restrict__ ord = order + class_info[2 * c];
-    const int n = class_info[2 * c + 1];
-    int cnt;
-    if (*tables_bad) {
-        cnt = 0;                         // no program was staged
-    } else if (n_seg == 1) {
-        cnt = n;
-    } else {
-        // first position whose program id is >= v
-        auto lower = [&](int64_t v) {
-            int lo = 0, hi = n;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if ((int64_t)ord[mid] < v) lo = mid + 1; else hi = mid;
-            }
-            return lo;
-        };
-        cnt = lower(seg_start[sg + 1]) - lower(seg_start[sg]);
-    }
-    seg_cnt[i] = cnt;
-}
-
-// Per class (one thread each): the group size (programs per work item) and,
-// per segment, where its programs start inside the class's range of
-// `order` and the prefix of work items (groups times the segment dataset's
-// case tiles).  Groups are as large as g_max allows while the class still
-// has about target_items items (a small class gets smaller groups, so its
-// few programs still spread over the GPU); never below 4, one program per
-// wavefront of a workgroup.  Grouping never changes a result.
-__global__ __launch_bounds__(64) void k_seg_scan(const int32_t* __restrict__ seg_cnt,
-                                                 const int32_t* __restrict__ seg_ds,
-                                                 const DevDataset* __restrict__ ds, int32_t n_seg,
-                                                 int32_t g_max, int32_t target_items,
-                                                 int32_t* __restrict__ seg_pos,
-                                                 uint32_t* __restrict__ item_pre,
-                                                 int32_t* __restrict__ class_g)
-{
-    const int c = threadIdx.x;
-    if (c >= kClasses) return;
     double prog_tiles = 0.0;
     for (int s = 0; s < n_seg; ++s)
         prog_tiles += (double)seg_cnt[c * n_seg + s] * (double)ds[seg_ds[s]].n_tiles[c];
@@ -1059,6 +851,275 @@ __global__ __launch_bounds__(64) void k_seg_scan(const int32_t* __restrict__ seg
         items += (uint32_t)((n + G - 1) / G) * (uint32_t)ds[seg_ds[s]].n_tiles[c];
     }
     item_pre[c * (n_seg + 1) + n_seg] = items;
+}
+
+// Where a call of a single request gets its per-class work-item tables
+// (k_class_scan writes them when `single` is set).
+struct SegOut {
+    int32_t single;
+    int32_t g_max, target_items;
+    const int32_t* seg_ds;
+    const DevDataset* ds;
+    int32_t* seg_cnt;
+    int32_t* seg_pos;
+    uint32_t* item_pre;
+    int32_t* class_g;
+};
+
+// One workgroup: exclusive scans of the per-block key counts (key-major
+// order) into blk_base and of the per-block staged sizes into blk_code;
+// class_info[2c] = first position of depth class c, [2c+1] = its size (its
+// keys are contiguous); also clears the per-class work counters.  Staged
+// code never exceeds the call's node count unless programs' node ranges
+// overlap; then *overflow is set, nothing is staged and every class is
+// left empty.  With a single request it also writes the request's
+// per-class tables (class_seg_tables).
+__global__ __launch_bounds__(1024) void k_class_scan(
+    const int32_t* __restrict__ blk_counts, const int64_t* __restrict__ blk_slen, int32_t n_blk,
+    int64_t code_capacity, int32_t* __restrict__ blk_base, int64_t* __restrict__ blk_code,
+    int32_t* __restrict__ class_info, uint32_t* __restrict__ work_counters,
+    int32_t* __restrict__ overflow, SegOut so)
+{
+    __shared__ int part[1024];
+    __shared__ long long lpart[1024];
+    __shared__ int s_bound[kClasses - 1];     // exclusive prefixes where classes 1, 2 begin
+    const int t = threadIdx.x;
+    const int total = kKeys * n_blk;
+    const int chunk = (total + 1023) / 1024;
+    const int lo = t * chunk, hi = min(total, lo + chunk);
+    if (t < kClasses - 1) s_bound[t] = 0;
+    // a thread's counts stay in registers when they fit (all its loads in
+    // flight at once, read once); otherwise loads in batches of 8
+    constexpr int kR = 24;
+    const bool inreg = chunk <= kR;
+    int v[kR];
+    int sum = 0;
+    if (inreg) {
+#pragma unroll
+        for (int u = 0; u < kR; ++u) v[u] = lo + u < hi ? blk_counts[lo + u] : 0;
+#pragma unroll
+        for (int u = 0; u < kR; ++u) sum += v[u];
+    } else {
+        int i = lo;
+        for (; i + 8 <= hi; i += 8) {
+            int w[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) w[u] = blk_counts[i + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) sum += w[u];
+        }
+        for (; i < hi; ++i) sum += blk_counts[i];
+    }
+    part[t] = sum;
+    const int chunk2 = (n_blk + 1023) / 1024;
+    const int lo2 = t * chunk2, hi2 = min(n_blk, lo2 + chunk2);
+    long long sum2 = 0;
+    for (int i = lo2; i < hi2; ++i) sum2 += blk_slen[i];
+    lpart[t] = sum2;
+    __syncthreads();
+    // inclusive Hillis-Steele scans of the chunk sums
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int x = t >= off ? part[t - off] : 0;
+        const long long x2 = t >= off ? lpart[t - off] : 0;
+        __syncthreads();
+        part[t] += x;
+        lpart[t] += x2;
+        __syncthreads();
+    }
+    // exclusive prefixes; the first keys of classes 1 and 2 (keys are
+    // class-major) give the class boundaries
+    const int b1 = kLenBuckets * n_blk, b2 = 2 * kLenBuckets * n_blk;
+    int run = part[t] - sum;
+    auto emit = [&](int i, int cnt) {
+        blk_base[i] = run;
+        if (i == b1) s_bound[0] = run;
+        if (i == b2) s_bound[1] = run;
+        run += cnt;
+    };
+    if (inreg) {
+#pragma unroll
+        for (int u = 0; u < kR; ++u)
+            if (lo + u < hi) emit(lo + u, v[u]);
+    } else {
+        int i = lo;
+        for (; i + 8 <= hi; i += 8) {
+            int w[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) w[u] = blk_counts[i + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) emit(i + u, w[u]);
+        }
+        for (; i < hi; ++i) emit(i, blk_counts[i]);
+    }
+    long long run2 = lpart[t] - sum2;
+    for (int i = lo2; i < hi2; ++i) {
+        blk_code[i] = run2;
+        run2 += blk_slen[i];
+    }
+    __syncthreads();
+    if (t < kClasses) {
+        const bool ovf = lpart[1023] > code_capacity;
+        const int start = t == 0 ? 0 : s_bound[t - 1];
+        const int end = t == kClasses - 1 ? part[1023] : s_bound[t];
+        class_info[2 * t] = start;
+        class_info[2 * t + 1] = ovf ? 0 : end - start;
+        work_counters[t] = 0u;
+        if (t == 0) *overflow = ovf ? 1 : 0;
+        if (so.single) {
+            // one request holds the whole class
+            so.seg_cnt[t] = ovf ? 0 : end - start;
+            class_seg_tables(t, 1, so.seg_cnt, so.seg_ds, so.ds, so.g_max, so.target_items,
+                             so.seg_pos, so.item_pre, so.class_g);
+        }
+    }
+}
+
+// Pass 2, same blocks as pass 1: each program's id is scattered (stably)
+// into the partition order.  Programs the short walk of pass 1 staged in
+// place stay there.  Otherwise (the whole command table, or node offsets
+// that decrease somewhere, so that programs' node ranges may overlap) each
+// program is staged here, at its block's base plus the exclusive scan of
+// staged sizes inside the block, so ranges never overlap whatever the
+// offsets.
+//
+// Staged instruction (8 bytes, one scalar load):
+//   x = flags | sel << 8 | cell << 16, y = payload
+//   kFPush  save the top into stack cell `cell`, then the top = leaf
+//   kFUn    the top = unary sel (SIN..ABS as 0..5) of the top
+//   kFSBin  the top = stack cell `cell`  OP_sel  top  (ADD..DIV as 0..3)
+//   kFLBin  the top = top  OP_sel  leaf
+//   kFLast  (with any of the above) the program's last instruction
+// A leaf is the constant with bits y when kFConst is set, else the input
+// row at LDS byte offset y (variable index * 1024, halved at two cases per
+// lane).  Eight bytes (not sixteen) keep the code of the programs that the
+// resident wavefronts run at once small enough to stay in the scalar cache
+// while each program passes over its window.
+__global__ __launch_bounds__(kBucketBlock) void k_stage(
+    int64_t n_programs, const DevDataset* __restrict__ ds, const DevRequest* __restrict__ reqs,
+    const int64_t* __restrict__ seg_start, const int32_t* __restrict__ pds, int32_t n_blk,
+    const int64_t* __restrict__ blk_code, const int32_t* __restrict__ blk_base,
+    const int32_t* __restrict__ overflow, const int32_t* __restrict__ restage, uint32_t allowed,
+    uint8_t* __restrict__ cls, ProgMeta* __restrict__ meta, uint2* __restrict__ code,
+    int32_t* __restrict__ order)
+{
+    __shared__ long long sc[kBucketBlock];
+    constexpr int kW = kBucketBlock / 64;
+    __shared__ int wcnt[kW][kKeys];
+    const int t = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * kBucketBlock + t;
+    int key = p < n_programs ? (int)cls[p] : 0xFF;
+    if (*overflow) {
+        // overlapping node ranges: no program of this call is staged
+        if (key < kKeys) {
+            cls[p] = 0xFF;
+            const int r = pds[p];
+            const DevRequest& R = reqs[r];
+            const int64_t q = p - seg_start[r];
+            if (R.out_status && q < R.n_programs) R.out_status[q] = GP_PROG_BAD_OFFSETS;
+        }
+        return;
+    }
+    const bool base = (allowed & ~GP_BASE_OPS) == 0u;
+    if (!base || *restage) {
+        __shared__ uint32_t cache_mem[kCacheWords];
+        __shared__ float pv_mem[kHeldConsts * kBucketBlock];
+        lds_u32* cache = (lds_u32*)cache_mem;
+        lds_u8* ops = (lds_u8*)(cache + kStageNodesEmit);
+        ProgMeta m;
+        m.start = 0;
+        m.len = 0;
+        m.slen = 0;
+        if (p < n_programs) m = meta[p];
+        // inclusive scan of staged sizes inside the block
+        sc[t] = m.slen;
+        __syncthreads();
+        for (int off = 1; off < kBucketBlock; off <<= 1) {
+            const long long v = t >= off ? sc[t - off] : 0;
+            __syncthreads();
+            sc[t] += v;
+            __syncthreads();
+        }
+        const int64_t start = blk_code[blockIdx.x] + sc[t] - m.slen;
+        int r = 0;
+        int64_t s = 0, e = 0;
+        DevRequest R{};
+        if (key < kKeys) {
+            r = pds[p];
+            R = reqs[r];
+            const int64_t q = p - seg_start[r];
+            s = R.offsets[q];
+            e = R.offsets[q + 1];
+        }
+        int64_t lo = 0;
+        const bool cached = base ? cache_block_stage(key < kKeys, r, s, e, reqs, ops, cache, &lo)
+                                 : cache_block_nodes(key < kKeys, r, s, e, reqs, cache, &lo);
+        if (key < kKeys) {
+            lds_f32* pvs = (lds_f32*)pv_mem + t;
+            const int32_t n_vars = ds[R.dataset].n_vars;
+            int st = 0, md = 0;
+            if (base && cached)
+                stage_check_base(LdsStageReader{ops, cache, lo}, s, e, allowed, n_vars,
+                                 code + start, pvs, st, md);
+            else if (base)
+                stage_check_base(GlobalStageReader{R.nodes, R.consts, R.n_consts}, s, e, allowed,
+                                 n_vars, code + start, pvs, st, md);
+            else if (cached)
+                stage_walk(LdsNodes{cache, lo}, s, e, GlobalConsts{R.consts}, code + start, m.slen,
+                           pvs);
+            else
+                stage_walk(GlobalNodes{R.nodes}, s, e, GlobalConsts{R.consts}, code + start,
+                           m.slen, pvs);
+            meta[p].start = start;
+        }
+    }
+    // stable scatter into the partition order
+    const int wave = t >> 6, lane = t & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int rank = 0;
+    for (int kk = 0; kk < kKeys; ++kk) {
+        const uint64_t bm = __ballot(key == kk);
+        if (lane == 0) wcnt[wave][kk] = __popcll(bm);
+        if (key == kk) rank = __popcll(bm & below);
+    }
+    __syncthreads();
+    if (key < kKeys) {
+        for (int w2 = 0; w2 < wave; ++w2) rank += wcnt[w2][key];
+        order[blk_base[key * n_blk + blockIdx.x] + rank] = (int32_t)p;
+    }
+}
+
+// One workgroup, calls of several requests: the programs of each depth
+// class inside each segment (seg_cnt[c * n_seg + s]; the partition keeps
+// each class in program order, so they are the class's entries between two
+// lower bounds of the segment's program range), then class_seg_tables per
+// class.  (A single request's tables come from k_class_scan.)
+__global__ __launch_bounds__(256) void k_seg_tables(
+    const int32_t* __restrict__ order, const int32_t* __restrict__ class_info,
+    const int64_t* __restrict__ seg_start, int32_t n_seg, const int32_t* __restrict__ tables_bad,
+    const int32_t* __restrict__ seg_ds, const DevDataset* __restrict__ ds, int32_t g_max,
+    int32_t target_items, int32_t* __restrict__ seg_cnt, int32_t* __restrict__ seg_pos,
+    uint32_t* __restrict__ item_pre, int32_t* __restrict__ class_g)
+{
+    const bool bad = *tables_bad != 0;              // then no program was staged
+    for (int i = threadIdx.x; i < kClasses * n_seg; i += blockDim.x) {
+        const int c = i / n_seg, sg = i - c * n_seg;
+        const int32_t* __restrict__ ord = order + class_info[2 * c];
+        const int n = class_info[2 * c + 1];
+        // first position whose program id is >= v
+        auto lower = [&](int64_t v) {
+            int lo = 0, hi = n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((int64_t)ord[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            return lo;
+        };
+        seg_cnt[i] = bad ? 0 : lower(seg_start[sg + 1]) - lower(seg_start[sg]);
+    }
+    __syncthreads();
+    if (threadIdx.x < kClasses)
+        class_seg_tables(threadIdx.x, n_seg, seg_cnt, seg_ds, ds, g_max, target_items, seg_pos,
+                         item_pre, class_g);
 }
 
 // ------------------------------------------------------------ evaluation
@@ -1133,8 +1194,8 @@ __device__ __forceinline__ void mse_case(float f, float ys, float s, float& hi, 
 // chunk c holds cases [c*J, (c+1)*J) of every slot, element index
 // slot*J + (case mod J), J = 32 / MAXD.  A uniform dynamic index into a
 // 32-element vector compiles to GPR-index-mode moves (smaller vectors would
-// be expanded into compare/select chains).  `ix` is the staged, pre-scaled
-// slot index (5 bits, so always inside the chunk).
+// be expanded into compare/select chains).  `ix` is a staged cell number
+// scaled by J, modulo 32 (so always inside the chunk).
 #define GP_CHUNK_PUT(ix, j, v)                                                     \
     do {                                                                           \
         const uint32_t i_ = (ix) + ((j) % J);                                      \
@@ -1172,11 +1233,12 @@ __device__ __forceinline__ void mse_case(float f, float ys, float s, float& hi, 
 
 // Runs one staged program on K cases per lane; xl points at this lane's
 // first case of the LDS input tile.  A sub-tile's cases are laid out case-
-// major: case j of lane t is element j*256 + t of a variable's row (row
-// stride SUB), so each of the K reads of a LOAD is a conflict-free,
+// major: case j of lane t is element j*64 + t of a variable's row (row
+// stride 64*K floats), so each of the K reads of a LOAD is a conflict-free,
 // lane-contiguous LDS access.  The top of the stack is returned in tos[].
 // Loads a leaf for K cases: the constant with bits `payload` when is_const,
-// else the input row at LDS byte offset `payload` from this lane's base.
+// else the input row whose byte offset at four cases per lane is `payload`
+// (halved at two cases per lane).
 #define GP_LEAF(is_const, payload, out)                                            \
     do {                                                                           \
         if (is_const) {                                                            \
@@ -1184,7 +1246,7 @@ __device__ __forceinline__ void mse_case(float f, float ys, float s, float& hi, 
             _Pragma("unroll") for (int j = 0; j < K; ++j) out[j] = c_;             \
         } else {                                                                   \
             const float* xp_ = reinterpret_cast<const float*>(                     \
-                reinterpret_cast<const char*>(xl) + (payload));                    \
+                reinterpret_cast<const char*>(xl) + ((payload) >> kRowShift));     \
             _Pragma("unroll") for (int j = 0; j < K; ++j) out[j] = xp_[j * 64];    \
         }                                                                          \
     } while (0)
@@ -1262,6 +1324,13 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
 {
     constexpr int J = 32 / MAXD;                  // cases per 32-float chunk
     static_assert(K % J == 0 && K / J <= 4, "chunking");
+    // staged cell numbers times J, by one shift of the word (bits 14-15 of
+    // a staged word are zero)
+    constexpr uint32_t kLogJ = J == 4 ? 2u : (J == 2 ? 1u : 0u);
+    static_assert((1 << kLogJ) == J, "J is 1, 2 or 4");
+    // variable payloads are row offsets at four cases per lane
+    constexpr uint32_t kRowShift = K == 4 ? 0u : 1u;
+    static_assert(K == 4 || K == 2, "row offsets for 4 or 2 cases per lane");
     float c0[32], c1[32], c2[32], c3[32];
 #pragma unroll
     for (int j = 0; j < K; ++j) tos[j] = 0.f;
@@ -1281,7 +1350,7 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
         off += 8u;
         f = w.x;
         const uint32_t sel = (f >> 8) & 0xFu;
-        const uint32_t slot = (f >> 16) & 31u;
+        const uint32_t slot = (f >> (16u - kLogJ)) & 31u;
         if (f & kFUn) {
             if (f & kFPush) {
                 // f(leaf): the old top is saved first
@@ -1384,11 +1453,11 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                 GP_BINARY_AB(GP_ADD + sel, tos, lv, tos);
             }
         } else if (EXT && (f & kFMove)) {
-            // cell move; every cell index is masked to a multiple of J
-            // inside the chunk
+            // cell move; every cell number is scaled by J and masked to a
+            // multiple of J inside the chunk
             constexpr uint32_t kCellMask = 32u - J;
             const uint32_t rs = slot & kCellMask;
-            const uint32_t ws = w.y & kCellMask;
+            const uint32_t ws = (w.y << kLogJ) & kCellMask;
             float tv[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) tv[j] = tos[j];
@@ -1405,7 +1474,8 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ pc,
                 for (int j = 0; j < K; ++j) tos[j] = tv[j];
             }
             if (sel & kMvCompact) {
-                const uint32_t cs = (w.y >> 8) & kCellMask, cd = (w.y >> 16) & kCellMask;
+                const uint32_t cs = ((w.y >> 8) << kLogJ) & kCellMask;
+                const uint32_t cd = ((w.y >> 16) << kLogJ) & kCellMask;
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     const float v = GP_CHUNK_GET(cs, j);
@@ -2005,7 +2075,7 @@ Layout make_layout(int64_t n_programs, int64_t n_nodes, int32_t part_stride, int
     L.seg_pos = off;    off = align_up(off + (size_t)kClasses * n_seg * 4);
     L.item_pre = off;   off = align_up(off + (size_t)kClasses * (n_seg + 1) * 4);
     L.pds = off;        off = align_up(off + (size_t)n_programs * 4);
-    L.bad = off;        off = align_up(off + 4);
+    L.bad = off;        off = align_up(off + 8);    // tables bad, restage
     L.overflow = off;   off = align_up(off + 4);
     L.total = off;
     return L;
@@ -2036,6 +2106,7 @@ struct Staged {
     uint32_t* item_pre;
     int32_t* pds;
     int32_t* bad;
+    int32_t* restage;
     int32_t* overflow;
 };
 
@@ -2066,6 +2137,7 @@ Staged carve(void* base, const Layout& L)
     st.item_pre = reinterpret_cast<uint32_t*>(ws + L.item_pre);
     st.pds = reinterpret_cast<int32_t*>(ws + L.pds);
     st.bad = reinterpret_cast<int32_t*>(ws + L.bad);
+    st.restage = st.bad + 1;
     st.overflow = reinterpret_cast<int32_t*>(ws + L.overflow);
     return st;
 }
@@ -2380,7 +2452,8 @@ int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
 
 // Dataset/segment tables, validation, staging and the stable (depth class,
 // length) partition.
-int enqueue_stage(const Problem& pb, const Tuning& tu, const Staged& st, hipStream_t stream)
+int enqueue_stage(const Problem& pb, const Tuning& tu, const Staged& st, int32_t target_items,
+                  hipStream_t stream)
 {
     const int32_t n_blk = (int32_t)((pb.n_programs + kBucketBlock - 1) / kBucketBlock);
     hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, stream, pb.ds_dev, pb.n_ds, pb.one,
@@ -2391,15 +2464,17 @@ int enqueue_stage(const Problem& pb, const Tuning& tu, const Staged& st, hipStre
     const int32_t lpt = pb.n_req == 1 ? 1 : 0;
     hipLaunchKernelGGL(k_validate, dim3(n_blk), dim3(kBucketBlock), 0, stream, pb.n_programs,
                        pb.allowed, st.ds, st.req, st.seg_start, pb.n_req, st.bad, lpt, n_blk,
-                       st.meta, st.cls, st.pds, st.blk_counts, st.blk_slen);
+                       st.meta, st.cls, st.pds, st.blk_counts, st.blk_slen, st.code, st.restage);
     GP_HIP_TRY(hipGetLastError());
+    SegOut so{pb.n_req == 1 ? 1 : 0, group_capacity(pb, tu), target_items, st.seg_ds, st.ds,
+              st.seg_cnt, st.seg_pos, st.item_pre, st.class_g};
     hipLaunchKernelGGL(k_class_scan, dim3(1), dim3(1024), 0, stream, st.blk_counts, st.blk_slen,
                        n_blk, pb.n_nodes, st.blk_base, st.blk_code, st.class_info, st.counters,
-                       st.overflow);
+                       st.overflow, so);
     GP_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_stage, dim3(n_blk), dim3(kBucketBlock), 0, stream, pb.n_programs, st.ds,
                        st.req, st.seg_start, st.pds, n_blk, st.blk_code, st.blk_base, st.overflow,
-                       pb.allowed, st.cls, st.meta, st.code, st.order);
+                       st.restage, pb.allowed, st.cls, st.meta, st.code, st.order);
     GP_HIP_TRY(hipGetLastError());
     return GP_OK;
 }
@@ -2429,15 +2504,13 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
 {
     int rc;
     if ((rc = ce.mark(0, stream)) != GP_OK) return rc;
-    if ((rc = enqueue_stage(pb, tu, st, stream)) != GP_OK) return rc;
-    hipLaunchKernelGGL(k_seg_count, dim3((unsigned)((kClasses * pb.n_req + 255) / 256)), dim3(256),
-                       0, stream, st.order, st.class_info, st.seg_start, pb.n_req, st.bad,
-                       st.seg_cnt);
-    GP_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(64), 0, stream, st.seg_cnt, st.seg_ds, st.ds,
-                       pb.n_req, group_capacity(pb, tu), el.target_items, st.seg_pos, st.item_pre,
-                       st.class_g);
-    GP_HIP_TRY(hipGetLastError());
+    if ((rc = enqueue_stage(pb, tu, st, el.target_items, stream)) != GP_OK) return rc;
+    if (pb.n_req > 1) {
+        hipLaunchKernelGGL(k_seg_tables, dim3(1), dim3(256), 0, stream, st.order, st.class_info,
+                           st.seg_start, pb.n_req, st.bad, st.seg_ds, st.ds, group_capacity(pb, tu),
+                           el.target_items, st.seg_cnt, st.seg_pos, st.item_pre, st.class_g);
+        GP_HIP_TRY(hipGetLastError());
+    }
 
     EvalConst ea{};
     ea.G = group_capacity(pb, tu);
@@ -3133,7 +3206,7 @@ int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs
     Workspace* w = nullptr;
     if ((rc = get_workspace(stream, L.total, &w)) != GP_OK) return rc;
     const Staged st = carve(w->ptr, L);
-    if ((rc = enqueue_stage(pb, Tuning(), st, stream)) != GP_OK) return rc;
+    if ((rc = enqueue_stage(pb, Tuning(), st, 1, stream)) != GP_OK) return rc;
     EvalPtrs ep{st.code, st.meta, st.order, st.class_info, nullptr, X, nullptr, nullptr, nullptr};
     EvalConst ea{};
     ea.ld_x = ld_x; ea.n_cases = n_cases; ea.n_vars = n_vars;

@@ -1,7 +1,7 @@
 // staging.h -- the interpreter's staged program format and the staging
 // walk: validation with the instruction count (check_program) and emission
-// (stage_walk), and their short forms for op masks within the benchmark set
-// (check_program_base, stage_walk_base).  Included by gpeval.hip for the
+// (stage_walk), and for op masks within the benchmark set both in one
+// shorter pass (stage_check_base).  Included by gpeval.hip for the
 // device passes (k_validate, k_stage) and by a host test harness, so the
 // count, the emission and the meaning of the staged words can be checked
 // without a GPU.
@@ -25,11 +25,26 @@ constexpr uint32_t kFLast = 0x80000000u;  // the program's last instruction (sig
 constexpr uint32_t kFConst = 32u;       // the leaf is a constant
 // Cell moves (DUP, SWAP, DEL, COPY, PASTE; full command table only):
 // slot field = cell read, payload = cell written | (compaction source << 8)
-// | (compaction target << 16), all pre-scaled; the selector says which
-// parts run, in this order: tmp = read cell; write cell = top; top = tmp;
-// compaction target = compaction source.
+// | (compaction target << 16); the selector says which parts run, in this
+// order: tmp = read cell; write cell = top; top = tmp; compaction target =
+// compaction source.
 constexpr uint32_t kFMove = 16u;
 constexpr uint32_t kMvRead = 1u, kMvWrite = 2u, kMvTop = 4u, kMvCompact = 8u;
+
+// Cell numbers (slot fields and move payloads, 5 bits each) do not depend
+// on the depth class, so a program is staged before its class is known:
+// stack element i is cell i, the held variable q places below the top of
+// the cell space is cell 31 - q.  A class of maximum depth MAXD keeps cell
+// c at register index (c * J) mod 32 of its 32-float chunks, J = 32 / MAXD:
+// element i at i * J, that variable at 32 - J * (q + 1).
+// A variable leaf's payload is its input row's byte offset in the
+// interpreter's window at four cases per lane (row stride 256 * 4 bytes);
+// a class with two cases per lane halves it.
+constexpr uint32_t kVarPayload = 1024u;
+// The cell written by a push onto an empty stack: no element sits there
+// below depth 2, and after a push depth + held variables <= MAXD keeps
+// every held variable above it.
+constexpr uint32_t kDummyCell = 0u;
 
 __host__ __device__ inline uint2 staged_word(uint32_t flags, uint32_t sel, uint32_t slot,
                                              uint32_t payload)
@@ -150,9 +165,8 @@ struct GclCheck {
 // What is folded depends only on the node kinds, never on values, so
 // counting and emitting agree.
 template <class Nodes, class Consts>
-GP_STAGING_FN int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts, uint32_t J,
-                              uint32_t row_bytes, uint2* __restrict__ out, int64_t cap,
-                              lds_f32* pvs)
+GP_STAGING_FN int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts consts,
+                              uint2* __restrict__ out, int64_t cap, lds_f32* pvs)
 {
     // held-back constant i of this thread is pvs[i * kBucketBlock] (LDS:
     // a per-lane index into a register array would become a select chain)
@@ -161,12 +175,8 @@ GP_STAGING_FN int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts const
     auto put = [&](int64_t i, uint2 v) {
         if (i < cap) out[i] = v;
     };
-    // A push onto an empty stack saves the meaningless old top in cell 0:
-    // no element sits there below depth 2, and after a push depth + held
-    // variables <= MAXD keeps every held variable above it.
-    const uint32_t dummy = 0u;
-    // cell (pre-scaled) of the held variable at position q from the top
-    auto vcell = [&](int q) { return 32u - J * (uint32_t)(q + 1); };
+    // cell of the held variable at position q from the top
+    auto vcell = [&](int q) { return 31u - (uint32_t)q; };
     GclCheck gc;
     int rt = 0;                                  // runtime stack depth
     int np = 0;                                  // held-back constants
@@ -177,7 +187,7 @@ GP_STAGING_FN int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts const
         // held-back constants become runtime elements, bottom up
         auto flush = [&]() {
             for (int i = 0; i < np; ++i) {
-                const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
+                const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) : kDummyCell;
                 put(n, staged_word(kFPush | kFConst, 0u, wr, __float_as_uint(pv(i))));
                 ++n;
                 ++rt;
@@ -196,9 +206,9 @@ GP_STAGING_FN int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts const
             continue;
         }
         if (op == GP_LOAD) {
-            const uint32_t payload = arg * row_bytes;
+            const uint32_t payload = arg * kVarPayload;
             const uint32_t nx = k + 1 < e ? (nodes(k + 1) & 0xFFu) : 0xFFu;
-            const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
+            const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) : kDummyCell;
             if (op_is_binary(nx)) {
                 // top = top OP x (the binary op has a runtime element below)
                 put(n, staged_word(kFLBin, bop_sel(nx), 0u, payload));
@@ -226,7 +236,7 @@ GP_STAGING_FN int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts const
                 ++n;
             } else {
                 // second from top (element rt-2) is read from slot rt-2
-                put(n, staged_word(kFSBin, bop, (uint32_t)(rt - 2) * J, 0u));
+                put(n, staged_word(kFSBin, bop, (uint32_t)(rt - 2), 0u));
                 ++n;
                 --rt;
             }
@@ -242,17 +252,17 @@ GP_STAGING_FN int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts const
             continue;
         }
         // cell moves
-        const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
+        const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) : kDummyCell;
         if (op == GP_DUP) {
             put(n++, staged_word(kFMove, kMvWrite, 0u, wr));
             ++rt;
         } else if (op == GP_SWAP) {
-            const uint32_t c2 = (uint32_t)(rt - 2) * J;
+            const uint32_t c2 = (uint32_t)(rt - 2);
             put(n++, staged_word(kFMove, kMvRead | kMvWrite | kMvTop, c2, c2));
         } else if (op == GP_DEL) {
             // the element below becomes the top; deleting the only element
             // moves nothing
-            if (rt >= 2) put(n++, staged_word(kFMove, kMvRead | kMvTop, (uint32_t)(rt - 2) * J, 0u));
+            if (rt >= 2) put(n++, staged_word(kFMove, kMvRead | kMvTop, (uint32_t)(rt - 2), 0u));
             --rt;
         } else if (op == GP_COPY) {
             const int q = gc.copy(arg);
@@ -275,7 +285,7 @@ GP_STAGING_FN int64_t stage_walk(Nodes nodes, int64_t s, int64_t e, Consts const
     }
     // a constant program: its value is pushed
     for (int i = 0; i < np; ++i) {
-        const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : dummy;
+        const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) : kDummyCell;
         put(n, staged_word(kFPush | kFConst, 0u, wr, __float_as_uint(pv(i))));
         ++n;
         ++rt;
@@ -337,137 +347,124 @@ GP_STAGING_FN void check_program(Nodes nodes, int64_t s, int64_t e, uint32_t all
 
 // ------------------------------------------------ the benchmark set alone
 // When the op mask stays within GP_BASE_OPS no command beyond the set can
-// pass validation, so the walks need neither the variable discipline nor
-// the cell moves.  These two take the same decisions as check_program and
-// stage_walk for such masks (the host harness compares them word for word)
-// with a loop a fraction of the size: one thread walks each program, and
-// the loop body is what the walk costs per node.
+// pass validation, so the walk needs neither the variable discipline nor
+// the cell moves, and it validates and emits in one pass: one thread walks
+// each program, and the loop body is what the walk costs per node.
+//
+// Its reader gives, for node k: op(k), the opcode, or kOpBadConst for a
+// constant whose index is out of range; arg(k), a variable's index; and
+// cval(k), a constant's value (asked for constants in range only).
+constexpr uint32_t kOpBadConst = 0x100u | GP_CONST;
 
-// check_program for a mask within GP_BASE_OPS: the same checks in the same
-// order (op, operand range, underflow, depth), the same count.
-template <class Nodes>
-GP_STAGING_FN void check_program_base(Nodes nodes, int64_t s, int64_t e, uint32_t allowed,
-                                      int32_t n_vars, int64_t n_consts, int& status, int& maxd,
-                                      int64_t& n_staged)
+// check_program and stage_walk in one pass, for a mask within
+// GP_BASE_OPS: the same checks in the same order (op, operand range,
+// underflow, depth at each node, then the final depth), the same maximum
+// depth and, for a valid program, the same words, stored to out[0, n) with
+// n returned (the staged count).  At most e - s words are stored, whatever
+// the program; for an invalid one they mean nothing.  A variable folds the
+// operator after it into its own word, so that operator is checked with it.
+template <class Reader>
+GP_STAGING_FN int64_t stage_check_base(Reader rd, int64_t s, int64_t e, uint32_t allowed,
+                                       int32_t n_vars, uint2* __restrict__ out, lds_f32* pvs,
+                                       int& status, int& maxd)
 {
-    // every lane of a wavefront walks a different program, so the step is
-    // written as selects (no branch per node kind): all lanes run the same
-    // instructions whatever their node is
-    int depth = 0, md = 0, np = 0, st = GP_PROG_OK;
-    int64_t n_st = 0;
-    bool taken = false;
-    uint32_t w = s < e ? nodes(s) : 0u;
-    for (int64_t k = s; k < e; ++k) {
-        const uint32_t op = w & 0xFFu, arg = w >> 8;
-        const uint32_t wn = k + 1 < e ? nodes(k + 1) : 0xFFu;   // next word, read early
+#define pv(i) pvs[(i) * kBucketBlock]
+    int rt = 0, np = 0, md = 0, st = GP_PROG_OK;
+    int64_t n = 0;
+    // each word is stored when the next one is made, so that the last one
+    // is stored once, with kFLast
+    uint2 prev = make_uint2(0u, 0u);
+    auto put = [&](uint2 v) {
+        if (n > 0) out[n - 1] = prev;
+        prev = v;
+        ++n;
+    };
+    // one node's checks at depth d: the last test that fails names the
+    // status, so they run from the least to the most important
+    auto check = [&](uint32_t oc, uint32_t arg, int d) {
+        const uint32_t op = oc == kOpBadConst ? (uint32_t)GP_CONST : oc;
         const bool leaf = op <= GP_CONST;
-        const bool bin = op - GP_ADD < 4u;                        // ADD..DIV
-        const bool un = op - GP_SIN < 6u;                         // SIN..ABS
+        const bool bin = op - GP_ADD < 4u;                    // ADD..DIV
         const int need = leaf ? 0 : (bin ? 2 : 1);
         const int eff = leaf ? 1 : (bin ? -1 : 0);
         const bool ok_op = op < 32u && ((allowed >> (op & 31u)) & 1u);
-        // the checks in check_program's order: the first failing one names it
-        int code = depth + eff > GP_MAX_STACK ? GP_PROG_TOO_DEEP : GP_PROG_OK;
-        code = depth < need ? GP_PROG_UNDERFLOW : code;
-        code = op == GP_CONST && (int64_t)arg >= n_consts ? GP_PROG_BAD_CONST : code;
+        int code = d + eff > GP_MAX_STACK ? GP_PROG_TOO_DEEP : GP_PROG_OK;
+        code = d < need ? GP_PROG_UNDERFLOW : code;
+        code = oc == kOpBadConst ? GP_PROG_BAD_CONST : code;
         code = op == GP_LOAD && (int64_t)arg >= (int64_t)n_vars ? GP_PROG_BAD_VAR : code;
-        code = ok_op ? code : GP_PROG_BAD_OP;
-        if (code != GP_PROG_OK) {
-            st = code;
-            break;
-        }
-        depth += eff;
-        md = depth > md ? depth : md;
-        // staged words, as stage_walk emits them: a full run of held
-        // constants is pushed before the next is held; a variable pushes
-        // the held ones, then itself; an operator folded into the variable
-        // before it adds nothing; a binary op over fewer than two held
-        // constants is one word, a unary op on the runtime top is one word
-        const bool cst = op == GP_CONST, var = op == GP_LOAD;
-        const bool cap = cst && np == kHeldConsts;
-        const bool run_bin = bin && !taken, run_un = un && !taken;
-        n_st += (cap ? np : 0) + (var ? np + 1 : 0) + (run_bin && np <= 1 ? 1 : 0) +
-                (run_un && np == 0 ? 1 : 0);
-        np = cst ? (cap ? 1 : np + 1) : (var ? 0 : (run_bin ? (np >= 2 ? np - 1 : 0) : np));
-        const uint32_t nx = wn & 0xFFu;
-        taken = var && nx >= GP_ADD && nx <= GP_ABS;
-        w = wn;
-    }
-    maxd = md;
-    if (st == GP_PROG_OK && depth != 1) st = GP_PROG_FINAL_DEPTH;
-    status = st;
-    n_staged = n_st + np;
-}
-
-// stage_walk for a program that check_program_base accepted.  The reader
-// gives op(k), arg(k) (a variable's index) and cval(k) (a constant node's
-// value), so the device can hand it node words and constant values already
-// gathered into LDS.  Emits the same words as stage_walk.
-template <class Reader>
-GP_STAGING_FN int64_t stage_walk_base(Reader rd, int64_t s, int64_t e, uint32_t J,
-                                      uint32_t row_bytes, uint2* __restrict__ out, int64_t cap,
-                                      lds_f32* pvs)
-{
-#define pv(i) pvs[(i) * kBucketBlock]
-    auto put = [&](int64_t i, uint2 v) {
-        if (i < cap) out[i] = v;
+        return ok_op ? code : GP_PROG_BAD_OP;
     };
-    int rt = 0, np = 0;
-    int64_t n = 0;
+    // held-back constants become runtime elements, bottom up
     auto flush = [&]() {
         for (int i = 0; i < np; ++i) {
-            const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : 0u;
-            put(n, staged_word(kFPush | kFConst, 0u, wr, __float_as_uint(pv(i))));
-            ++n;
+            const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) : kDummyCell;
+            put(staged_word(kFPush | kFConst, 0u, wr, __float_as_uint(pv(i))));
             ++rt;
         }
         np = 0;
     };
     for (int64_t k = s; k < e; ++k) {
         const uint32_t op = rd.op(k);
-        const uint32_t nx = k + 1 < e ? rd.op(k + 1) : 0xFFu;
+        const uint32_t arg = op == GP_LOAD ? rd.arg(k) : 0u;
+        int code = check(op, arg, rt + np);
+        if (code != GP_PROG_OK) {
+            st = code;
+            break;
+        }
         if (op == GP_CONST) {
             if (np == kHeldConsts) flush();
             pv(np) = rd.cval(k);
             ++np;
+            md = rt + np > md ? rt + np : md;
         } else if (op == GP_LOAD) {
             flush();
-            const uint32_t payload = rd.arg(k) * row_bytes;
-            const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) * J : 0u;
-            if (nx >= GP_ADD && nx <= GP_DIV) {
-                put(n, staged_word(kFLBin, nx - GP_ADD, 0u, payload));
+            md = rt + 1 > md ? rt + 1 : md;
+            const uint32_t nx = k + 1 < e ? rd.op(k + 1) : 0xFFu;
+            const bool fb = nx - GP_ADD < 4u, fu = nx - GP_SIN < 6u;
+            if (fb || fu) {
+                // the operator after the variable, at the depth the push left
+                code = check(nx, 0u, rt + 1);
+                if (code != GP_PROG_OK) {
+                    st = code;
+                    break;
+                }
                 ++k;
-            } else if (nx >= GP_SIN && nx <= GP_ABS) {
-                put(n, staged_word(kFPush | kFUn, nx - GP_SIN, wr, payload));
-                ++rt;
-                ++k;
+            }
+            const uint32_t payload = arg * kVarPayload;
+            const uint32_t wr = rt >= 1 ? (uint32_t)(rt - 1) : kDummyCell;
+            if (fb) {
+                // top = top OP x: the push and the pop cancel
+                put(staged_word(kFLBin, nx - GP_ADD, 0u, payload));
             } else {
-                put(n, staged_word(kFPush, 0u, wr, payload));
+                put(staged_word(fu ? kFPush | kFUn : kFPush, fu ? nx - GP_SIN : 0u, wr, payload));
                 ++rt;
             }
-            ++n;
         } else if (op <= GP_DIV) {
             if (np >= 2) {
                 --np;
                 pv(np - 1) = binary_value(op, pv(np - 1), pv(np));
             } else if (np == 1) {
+                // top = top OP c: the runtime top is the left operand
                 np = 0;
-                put(n, staged_word(kFLBin | kFConst, op - GP_ADD, 0u, __float_as_uint(pv(0))));
-                ++n;
+                put(staged_word(kFLBin | kFConst, op - GP_ADD, 0u, __float_as_uint(pv(0))));
             } else {
-                put(n, staged_word(kFSBin, op - GP_ADD, (uint32_t)(rt - 2) * J, 0u));
-                ++n;
+                // second from top (element rt-2) is read from cell rt-2
+                put(staged_word(kFSBin, op - GP_ADD, (uint32_t)(rt - 2), 0u));
                 --rt;
             }
         } else if (np >= 1) {
             pv(np - 1) = unary_value(op, pv(np - 1));
         } else {
-            put(n, staged_word(kFUn, op - GP_SIN, 0u, 0u));
-            ++n;
+            put(staged_word(kFUn, op - GP_SIN, 0u, 0u));
         }
     }
-    flush();
-    if (n > 0 && n <= cap) out[n - 1].x |= kFLast;
+    if (st == GP_PROG_OK && rt + np != 1) st = GP_PROG_FINAL_DEPTH;
+    if (st == GP_PROG_OK) {
+        flush();                                 // a constant program: its value is pushed
+        out[n - 1] = make_uint2(prev.x | kFLast, prev.y);
+    }
+    status = st;
+    maxd = md;
     return n;
 #undef pv
 }

@@ -16,8 +16,9 @@
 // Output: per program int64 {status, max_depth, counted, emitted,
 // end_flag_ok, within_nodes, base_check_agrees, base_words_agree}; then
 // float out[P][n_cases] (NaN for invalid programs).  The last two compare
-// the benchmark-set walks (check_program_base, stage_walk_base) with the
-// general ones under two masks within the benchmark set.
+// the benchmark-set walk (stage_check_base: status, maximum depth, count,
+// staged words) with the general ones (check_program, stage_walk) under
+// two masks within the benchmark set.
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -72,16 +73,22 @@ struct Consts {
     const float* p;
     float operator()(uint32_t j) const { return p[j]; }
 };
-// reader of the benchmark-set walk: op, variable index, constant value
+// reader of the benchmark-set walk: op (kOpBadConst for a constant out of
+// range), variable index, constant value
 struct BaseReader {
     const uint32_t* p;
     const float* c;
-    uint32_t op(int64_t k) const { return p[k] & 0xFFu; }
+    int64_t nc;
+    uint32_t op(int64_t k) const
+    {
+        const uint32_t o = p[k] & 0xFFu;
+        return o == GP_CONST && (int64_t)(p[k] >> 8) >= nc ? kOpBadConst : o;
+    }
     uint32_t arg(int64_t k) const { return p[k] >> 8; }
     float cval(int64_t k) const { return c[p[k] >> 8]; }
 };
 
-// The benchmark-set walks against the general ones for a mask within the
+// The benchmark-set walk against the general ones for a mask within the
 // set: same status, maximum depth and count, and the same staged words.
 static void compare_base_walks(const std::vector<uint32_t>& nodes, const std::vector<float>& consts,
                                int64_t s, int64_t e, int32_t NV, int64_t NCo, int64_t* I)
@@ -90,21 +97,20 @@ static void compare_base_walks(const std::vector<uint32_t>& nodes, const std::ve
                                GP_BASE_OPS & ~((1u << GP_SIN) | (1u << GP_DIV) | (1u << GP_LOAD))};
     bool check_ok = true, words_ok = true;
     for (uint32_t m : masks) {
+        if (e == s) continue;
         int st1 = GP_PROG_OK, md1 = 0, st2 = GP_PROG_OK, md2 = 0;
-        int64_t c1 = 0, c2 = 0;
-        if (e > s) {
-            check_program(Nodes{nodes.data()}, s, e, m, NV, NCo, st1, md1, c1);
-            check_program_base(Nodes{nodes.data()}, s, e, m, NV, NCo, st2, md2, c2);
-        }
-        check_ok = check_ok && st1 == st2 && (st1 != GP_PROG_OK || (md1 == md2 && c1 == c2));
-        if (st1 != GP_PROG_OK || st2 != GP_PROG_OK || e == s) continue;
-        const uint32_t J = 32u / (uint32_t)(md1 <= 8 ? 8 : (md1 <= 16 ? 16 : 32));
-        std::vector<uint2> a(c1 + 1, make_uint2(0u, 0u)), b(c1 + 1, make_uint2(0u, 0u));
+        int64_t c1 = 0;
+        check_program(Nodes{nodes.data()}, s, e, m, NV, NCo, st1, md1, c1);
+        // the short walk may store up to e - s words, whatever the program
+        std::vector<uint2> a(c1 + 1, make_uint2(0u, 0u)), b(e - s + 1, make_uint2(0u, 0u));
         float pa[kHeldConsts], pb[kHeldConsts];
-        const int64_t na = stage_walk(Nodes{nodes.data()}, s, e, Consts{consts.data()}, J, 12, a.data(),
+        const int64_t nb = stage_check_base(BaseReader{nodes.data(), consts.data(), NCo}, s, e, m,
+                                            NV, b.data(), pb, st2, md2);
+        check_ok = check_ok && st1 == st2 && nb <= e - s &&
+                   (st1 != GP_PROG_OK || (md1 == md2 && c1 == nb));
+        if (st1 != GP_PROG_OK || st2 != GP_PROG_OK) continue;
+        const int64_t na = stage_walk(Nodes{nodes.data()}, s, e, Consts{consts.data()}, a.data(),
                                       c1, pa);
-        const int64_t nb = stage_walk_base(BaseReader{nodes.data(), consts.data()}, s, e, J, 12,
-                                           b.data(), c1, pb);
         words_ok = words_ok && na == nb;
         for (int64_t k = 0; k < c1 && words_ok; ++k)
             words_ok = a[k].x == b[k].x && a[k].y == b[k].y;
@@ -164,7 +170,6 @@ int main(int argc, char** argv)
     fclose(in);
     std::vector<int64_t> info(P * 8, 0);
     std::vector<float> out(P * NC, NAN);
-    const uint32_t row_bytes = 4;              // a variable leaf's payload is 4 * index here
     for (int64_t p = 0; p < P; ++p) {
         int status = GP_PROG_OK, maxd = 0;
         int64_t counted = 0;
@@ -177,11 +182,11 @@ int main(int argc, char** argv)
         I[2] = counted;
         if (status != GP_PROG_OK) continue;
         const uint32_t J = 32u / (uint32_t)(maxd <= 8 ? 8 : (maxd <= 16 ? 16 : 32));
+        const uint32_t lj = J == 4 ? 2u : (J == 2 ? 1u : 0u);
         std::vector<uint2> code(counted + 1, make_uint2(0u, 0u));
         float pvs[kHeldConsts];
         const int64_t n = stage_walk(Nodes{nodes.data()}, off[p], off[p + 1],
-                                     Consts{consts.data()}, J, row_bytes, code.data(), counted,
-                                     pvs);
+                                     Consts{consts.data()}, code.data(), counted, pvs);
         I[3] = n;
         bool flag_ok = n > 0 && n <= counted;
         for (int64_t k = 0; k < n && k < counted; ++k)
@@ -200,14 +205,15 @@ int main(int argc, char** argv)
                     memcpy(&v, &pay, 4);
                     return v;
                 }
-                return X[(int64_t)(pay / row_bytes) * NC + c];
+                return X[(int64_t)(pay / kVarPayload) * NC + c];
             };
             int64_t k = 0;
             uint32_t f;
             do {
                 const uint2 w = code[k++];
                 f = w.x;
-                const uint32_t sel = (f >> 8) & 0xFu, cell = (f >> 16) & 31u;
+                // cells as the interpreter places them: times J, modulo 32
+                const uint32_t sel = (f >> 8) & 0xFu, cell = ((f >> 16) << lj) & 31u;
                 if (f & kFUn) {
                     if (f & kFPush) {
                         cells[cell] = top;
@@ -219,12 +225,13 @@ int main(int argc, char** argv)
                 } else if (f & kFLBin) {
                     top = binary_sel(sel, top, leaf(f & kFConst, w.y));
                 } else if (f & kFMove) {
-                    const uint32_t rs = cell & mask, ws = w.y & mask;
+                    const uint32_t rs = cell & mask, ws = (w.y << lj) & mask;
                     float t = top;
                     if (sel & kMvRead) t = cells[rs];
                     if (sel & kMvWrite) cells[ws] = top;
                     if (sel & kMvTop) top = t;
-                    if (sel & kMvCompact) cells[(w.y >> 16) & mask] = cells[(w.y >> 8) & mask];
+                    if (sel & kMvCompact)
+                        cells[((w.y >> 16) << lj) & mask] = cells[((w.y >> 8) << lj) & mask];
                 } else {
                     cells[cell] = top;
                     top = leaf(f & kFConst, w.y);

@@ -147,3 +147,33 @@ def test_invalid_programs_get_the_oracle_status(harness, tmp_path):
     info, _ = _run(harness, tmp_path, nodes, w.pop.offsets, w.pop.consts, w.data.X)
     ok = _check_structure(info, nodes, w.pop.offsets, w.pop.consts.size, 4)
     assert (~ok).sum() > 100
+
+
+def test_benchmark_set_walk_on_invalid_programs(harness, tmp_path):
+    """The one-pass benchmark-set walk names the same status as the general
+    check on broken benchmark-set programs (opcodes out of the set or out of
+    range, including the LDS copy's bad-constant byte, operands out of
+    range, underflow, a stack too deep, a wrong final depth); _run asserts
+    the agreement for every program under two masks."""
+    rng = np.random.default_rng(6)
+    w = synth.make_workload("generation", n_programs=3000, n_cases=4)
+    nodes = w.pop.nodes.copy()
+    offsets = w.pop.offsets.copy()
+    idx = rng.choice(nodes.size, 600, replace=False)
+    bytes_ = np.concatenate([rng.integers(0, 40, 200), [0x81, 0xFE, 0xFF] * 34])[:300]
+    nodes[idx[:300]] = (nodes[idx[:300]] & ~np.uint32(0xFF)) | bytes_.astype(np.uint32)
+    args = np.where(rng.random(300) < 0.5, rng.integers(0, 40, 300),
+                    w.pop.consts.size + rng.integers(0, 40, 300))
+    nodes[idx[300:]] = (nodes[idx[300:]] & 0xFF) | (args.astype(np.uint32) << 8)
+    # programs cut short (wrong final depth, underflow in what follows)
+    cut = rng.choice(offsets.size - 2, 200, replace=False) + 1
+    offsets[cut] = offsets[cut] - rng.integers(0, 3, 200)
+    offsets = np.maximum.accumulate(offsets)
+    # stacks deeper than the limit: 40 leaves, then 39 additions
+    deep = np.concatenate([np.full(40, oracle.CONST, np.uint32), np.full(39, ADD, np.uint32)])
+    nodes = np.concatenate([nodes, deep, deep[:33], np.full(32, ADD, np.uint32)])
+    offsets = np.concatenate([offsets, [offsets[-1] + 79, offsets[-1] + 79 + 65]])
+    info, _ = _run(harness, tmp_path, nodes, offsets, w.pop.consts, w.data.X)
+    st, _ = oracle.validate(nodes, offsets, w.pop.consts.size, 5, oracle.MASK_BENCH)
+    seen = set(np.unique(st).tolist())
+    assert {0, 2, 3, 4, 5, 6, 7} <= seen, seen
