@@ -650,7 +650,11 @@ __device__ bool cache_block_stage(bool mine, int r, int64_t s, int64_t e,
     int rq = 0, n = 0;
     const bool use = block_node_range(mine, r, s, e, kStageNodesEmit, &rq, lo, &n);
     if (use) {
-        constexpr int kU = 16;
+        // 24 loads in flight per thread and round: a round covers 3072
+        // nodes (24 per program), and the node loads and the constant
+        // gather are waited out once per round (more in flight would take
+        // registers beyond two wavefronts per SIMD)
+        constexpr int kU = 24;
         const uint32_t* __restrict__ src = reqs[rq].nodes + *lo;
         const float* __restrict__ cs = reqs[rq].consts;
         const int64_t nc = reqs[rq].n_consts;
@@ -820,6 +824,15 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
     if (threadIdx.x == 0) blk_slen[blockIdx.x] = (int64_t)s_slen;
 }
 
+// Programs per work item of a class with prog_tiles (program, case tile)
+// pairs: see class_seg_tables.
+__device__ __forceinline__ int class_group(double prog_tiles, int32_t g_max, int32_t target_items)
+{
+    int G = g_max;
+    while (G > 4 && prog_tiles / G < (double)target_items) G >>= 1;
+    return G < 1 ? 1 : G;
+}
+
 // Per depth class c, from its programs per segment (seg_cnt[c * n_seg +
 // s]): the group size (programs per work item) and, per segment, where its
 // programs start inside the class's range of `order` and the prefix of work
@@ -837,9 +850,7 @@ __device__ void class_seg_tables(int c, int32_t n_seg, const int32_t* __restrict
     double prog_tiles = 0.0;
     for (int s = 0; s < n_seg; ++s)
         prog_tiles += (double)seg_cnt[c * n_seg + s] * (double)ds[seg_ds[s]].n_tiles[c];
-    int G = g_max;
-    while (G > 4 && prog_tiles / G < (double)target_items) G >>= 1;
-    if (G < 1) G = 1;
+    const int G = class_group(prog_tiles, g_max, target_items);
     class_g[c] = G;
     int32_t pos = 0;
     uint32_t items = 0;
@@ -882,31 +893,22 @@ __global__ __launch_bounds__(1024) void k_class_scan(
 {
     __shared__ int part[1024];
     __shared__ long long lpart[1024];
-    __shared__ int s_bound[kClasses - 1];     // exclusive prefixes where classes 1, 2 begin
     const int t = threadIdx.x;
+    // a single request's dataset tiles, loaded while the scan runs
+    const int32_t tiles = so.single && t < kClasses ? so.ds[so.seg_ds[0]].n_tiles[t] : 0;
     const int total = kKeys * n_blk;
     const int chunk = (total + 1023) / 1024;
     const int lo = t * chunk, hi = min(total, lo + chunk);
-    if (t < kClasses - 1) s_bound[t] = 0;
-    // a thread's counts stay in registers when they fit (all its loads in
-    // flight at once, read once); otherwise loads in batches of 8
-    constexpr int kR = 24;
-    const bool inreg = chunk <= kR;
-    int v[kR];
+    // loads in batches of 8, so that a thread's loads are in flight together
     int sum = 0;
-    if (inreg) {
-#pragma unroll
-        for (int u = 0; u < kR; ++u) v[u] = lo + u < hi ? blk_counts[lo + u] : 0;
-#pragma unroll
-        for (int u = 0; u < kR; ++u) sum += v[u];
-    } else {
+    {
         int i = lo;
         for (; i + 8 <= hi; i += 8) {
-            int w[8];
+            int v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) w[u] = blk_counts[i + u];
+            for (int u = 0; u < 8; ++u) v[u] = blk_counts[i + u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) sum += w[u];
+            for (int u = 0; u < 8; ++u) sum += v[u];
         }
         for (; i < hi; ++i) sum += blk_counts[i];
     }
@@ -919,57 +921,62 @@ __global__ __launch_bounds__(1024) void k_class_scan(
     __syncthreads();
     // inclusive Hillis-Steele scans of the chunk sums
     for (int off = 1; off < 1024; off <<= 1) {
-        const int x = t >= off ? part[t - off] : 0;
-        const long long x2 = t >= off ? lpart[t - off] : 0;
+        const int v = t >= off ? part[t - off] : 0;
+        const long long v2 = t >= off ? lpart[t - off] : 0;
         __syncthreads();
-        part[t] += x;
-        lpart[t] += x2;
+        part[t] += v;
+        lpart[t] += v2;
         __syncthreads();
     }
-    // exclusive prefixes; the first keys of classes 1 and 2 (keys are
-    // class-major) give the class boundaries
-    const int b1 = kLenBuckets * n_blk, b2 = 2 * kLenBuckets * n_blk;
     int run = part[t] - sum;
-    auto emit = [&](int i, int cnt) {
-        blk_base[i] = run;
-        if (i == b1) s_bound[0] = run;
-        if (i == b2) s_bound[1] = run;
-        run += cnt;
-    };
-    if (inreg) {
-#pragma unroll
-        for (int u = 0; u < kR; ++u)
-            if (lo + u < hi) emit(lo + u, v[u]);
-    } else {
+    {
         int i = lo;
         for (; i + 8 <= hi; i += 8) {
-            int w[8];
+            int v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) w[u] = blk_counts[i + u];
+            for (int u = 0; u < 8; ++u) v[u] = blk_counts[i + u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) emit(i + u, w[u]);
+            for (int u = 0; u < 8; ++u) {
+                blk_base[i + u] = run;
+                run += v[u];
+            }
         }
-        for (; i < hi; ++i) emit(i, blk_counts[i]);
+        for (; i < hi; ++i) {
+            blk_base[i] = run;
+            run += blk_counts[i];
+        }
     }
     long long run2 = lpart[t] - sum2;
     for (int i = lo2; i < hi2; ++i) {
         blk_code[i] = run2;
         run2 += blk_slen[i];
     }
-    __syncthreads();
     if (t < kClasses) {
+        // exclusive prefix of entry i from the scanned chunk sums (LDS)
+        auto prefix = [&](int i) {
+            if (i >= total) return part[1023];
+            const int owner = i / chunk;
+            int b = owner > 0 ? part[owner - 1] : 0;
+            for (int j = owner * chunk; j < i; ++j) b += blk_counts[j];
+            return b;
+        };
         const bool ovf = lpart[1023] > code_capacity;
-        const int start = t == 0 ? 0 : s_bound[t - 1];
-        const int end = t == kClasses - 1 ? part[1023] : s_bound[t];
+        const int start = prefix(t * kLenBuckets * n_blk);
+        const int end = prefix((t + 1) * kLenBuckets * n_blk);
         class_info[2 * t] = start;
         class_info[2 * t + 1] = ovf ? 0 : end - start;
         work_counters[t] = 0u;
         if (t == 0) *overflow = ovf ? 1 : 0;
         if (so.single) {
-            // one request holds the whole class
-            so.seg_cnt[t] = ovf ? 0 : end - start;
-            class_seg_tables(t, 1, so.seg_cnt, so.seg_ds, so.ds, so.g_max, so.target_items,
-                             so.seg_pos, so.item_pre, so.class_g);
+            // one request holds the whole class (class_seg_tables with one
+            // segment)
+            const int32_t n = ovf ? 0 : end - start;
+            const int G = class_group((double)n * (double)tiles, so.g_max, so.target_items);
+            so.seg_cnt[t] = n;
+            so.class_g[t] = G;
+            so.seg_pos[t] = 0;
+            so.item_pre[2 * t] = 0u;
+            so.item_pre[2 * t + 1] = (uint32_t)((n + G - 1) / G) * (uint32_t)tiles;
         }
     }
 }
