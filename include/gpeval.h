@@ -365,7 +365,7 @@ int gp_predict(const uint32_t* nodes, const int64_t* offsets, int64_t n_programs
  * With autotune != 0, gp_plan_create times candidate knobs on the given
  * inputs (coordinate descent over the five knobs, two sweeps, the median
  * of five runs per candidate, then a run-off of the three fastest: this
- * runs the evaluation about 130 times and synchronizes `stream`) and keeps
+ * runs the evaluation about 140 times and synchronizes `stream`) and keeps
  * the fastest; results are cached per workload shape (device, cases, variables,
  * programs, mean length, requests) in the process and, if the environment
  * variable GPEVAL_TUNE_CACHE names a file, there too.
@@ -383,7 +383,10 @@ typedef struct {
     int32_t programs_per_item;   /* most programs per work item, 1..128 (default 64);
                                     a depth class with few programs uses fewer */
     int32_t wg_per_cu;           /* persistent workgroups per CU, 0 = occupancy limit */
-    int32_t concurrent_classes;  /* 1: depth classes run on forked streams */
+    int32_t concurrent_classes;  /* 1: depth classes run on forked streams; 2: as 1,
+                                    and the depth <= 8 class runs one workgroup
+                                    per CU below its limit, so that the deeper
+                                    classes run beside it from the start */
     int32_t tile_lds_bytes;      /* LDS budget of an input window, 4096..65536
                                     (default 24576) */
     int32_t max_tiles;           /* case tiles per program, at most, 1..32

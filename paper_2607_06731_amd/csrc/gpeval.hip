@@ -2345,7 +2345,8 @@ int check_problem(const Problem& pb)
 struct Tuning {
     int G = 64;             // programs per work item, at most (small classes use fewer)
     int wg_per_cu = 0;      // persistent workgroups per CU (0: occupancy limit)
-    int concurrent = 0;     // depth classes on forked streams
+    int concurrent = 0;     // depth classes on forked streams (2: and the depth <= 8
+                            // class leaves one workgroup slot per CU to the others)
     int tile_lds = kTileLds;    // LDS bytes of an input window
     int tile_max = kMaxTiles;   // case tiles per program, at most
 };
@@ -2399,6 +2400,11 @@ int eval_grid(int n_vars, int G, const Tuning& tu, int cus, int* grid, size_t* l
     GP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval<MAXD, K, FIT, EXT>, kWG, lds));
     if (per_cu < 1) return set_error(GP_E_TOO_LARGE, "n_vars=%d needs %zu bytes of LDS per workgroup", n_vars, lds);
     if (wg_per_cu > 0 && wg_per_cu < per_cu) per_cu = wg_per_cu;
+    // overlapped classes: the depth <= 8 class (launched first) runs one
+    // workgroup per CU below its limit, so that the registers and LDS left
+    // over hold a deeper class's workgroup from the start instead of its
+    // whole run waiting for the first class to drain
+    if (MAXD == 8 && tu.concurrent == 2 && per_cu > 1) --per_cu;
     *grid = cus * per_cu;
     *lds_out = lds;
     return GP_OK;
@@ -2780,7 +2786,7 @@ int plan_autotune(gp_plan* p, hipStream_t stream)
     GP_HIP_TRY(hipEventCreate(&e0));
     GP_HIP_TRY(hipEventCreate(&e1));
     const int kAxes = 5;
-    const std::vector<int> values[kAxes] = {{32, 64, 128}, {0, 3, 4}, {0, 1},
+    const std::vector<int> values[kAxes] = {{32, 64, 128}, {0, 3, 4}, {0, 1, 2},
                                             {12 * 1024, 24 * 1024, 40 * 1024}, {2, 8, 32}};
     auto field = [](Tuning& t, int a) -> int& {
         return a == 0 ? t.G : a == 1 ? t.wg_per_cu : a == 2 ? t.concurrent
@@ -3250,13 +3256,14 @@ int gp_plan_create(gp_plan** plan, const gp_problem* problem, const gp_tuning* t
         if (tuning->programs_per_item < 0 || tuning->programs_per_item > 128 || tuning->wg_per_cu < 0 ||
             tuning->tile_lds_bytes < 0 || (tuning->tile_lds_bytes > 0 && (tuning->tile_lds_bytes < 4096 ||
                                                                          tuning->tile_lds_bytes > 65536)) ||
-            tuning->max_tiles < 0 || tuning->max_tiles > kMaxTiles) {
+            tuning->max_tiles < 0 || tuning->max_tiles > kMaxTiles ||
+            tuning->concurrent_classes < 0 || tuning->concurrent_classes > 2) {
             delete p;
             return set_error(GP_E_INVALID_ARG, "tuning out of range");
         }
         if (tuning->programs_per_item > 0) p->tu.G = tuning->programs_per_item;
         p->tu.wg_per_cu = tuning->wg_per_cu;
-        p->tu.concurrent = tuning->concurrent_classes != 0;
+        p->tu.concurrent = tuning->concurrent_classes;
         if (tuning->tile_lds_bytes > 0) p->tu.tile_lds = tuning->tile_lds_bytes;
         if (tuning->max_tiles > 0) p->tu.tile_max = tuning->max_tiles;
     }

@@ -193,6 +193,27 @@ def test_overlapping_node_ranges():
     assert st.tolist() == [8, 8, 8] and np.isnan(F).all()
 
 
+def test_packed_restaging_gives_the_same_bits():
+    """A decreasing offset pair anywhere in a call (after which node ranges
+    may overlap) makes every program be staged again, packed, instead of
+    in place by the validating walk: on the generation workload's programs
+    the scores are bit-identical either way, and the extra program gets
+    GP_PROG_BAD_OFFSETS."""
+    gp = _gp()
+    from paper_2607_06731_amd import synth
+    w = synth.make_workload("generation", n_programs=20_000, n_cases=2_000)
+    _say("staging in place and packed, P=20000 n=2000")
+    F0, st0 = gp.evaluate(w.pop.nodes, w.pop.offsets, w.pop.consts, w.data.X, w.data.y, w.tax,
+                          w.allowed_mask, return_status=True)
+    off = np.concatenate([w.pop.offsets, [w.pop.offsets[-1] - 7]])
+    F1, st1 = gp.evaluate(w.pop.nodes, off, w.pop.consts, w.data.X, w.data.y, w.tax,
+                          w.allowed_mask, return_status=True)
+    assert st1[-1] == 8 and np.isnan(F1[-1])
+    assert np.array_equal(st0, st1[:-1])
+    assert (st0 == 0).sum() > 19_000
+    assert np.array_equal(F0.view(np.uint64), F1[:-1].view(np.uint64))
+
+
 def test_constant_subtrees_fold_to_the_same_bits():
     """Constant subtrees are computed once while staging, with the
     interpreter's own arithmetic: every per-case output must equal, bit for

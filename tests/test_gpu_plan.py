@@ -50,7 +50,8 @@ def test_plan_matches_eval_for_every_tuning():
     ref = ref.cpu().numpy()
     for tuning in ({"programs_per_item": 1}, {"programs_per_item": 32, "wg_per_cu": 2},
                    {"programs_per_item": 128},
-                   {"programs_per_item": 4, "concurrent_classes": 1}):
+                   {"programs_per_item": 4, "concurrent_classes": 1},
+                   {"programs_per_item": 64, "concurrent_classes": 2}):
         out = torch.full((pop.n_programs,), -1.0, dtype=torch.float64, device="cuda")
         plan = gp.Plan(pop, data, w.tax, out, allowed_op_mask=w.allowed_mask, tuning=tuning)
         for _ in range(3):          # replays with host work in between
