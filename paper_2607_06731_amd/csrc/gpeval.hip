@@ -531,11 +531,6 @@ __device__ __forceinline__ float unary_value(uint32_t op, float x)
 }
 
 // ------------------------------------------------------------- staging
-// Stack slots are stored pre-scaled: element `slot` of a class with maximum
-// depth MAXD lives at index slot * (32 / MAXD) of each 32-float VGPR chunk,
-// so the kernel uses the index directly (always inside the chunk).
-__host__ __device__ constexpr int class_depth(int c) { return c == 0 ? 8 : (c == 1 ? 16 : 32); }
-
 // Request of program p: the last request whose first program is <= p.
 __device__ __forceinline__ int request_of(const int64_t* __restrict__ seg_start, int32_t n_seg,
                                           int64_t p)
