@@ -688,8 +688,9 @@ __device__ bool cache_block_stage(bool mine, int r, int64_t s, int64_t e,
 #include "staging.h"
 
 // Readers of the benchmark-set walk (stage_check_base): op (kOpBadConst
-// for a constant out of range), variable index, constant value, from the
-// block's LDS copy or straight from the request's arrays.
+// for a constant out of range), payload word, constant value, from the
+// block's LDS copy (the payload holds the constant's value) or straight
+// from the request's arrays (the payload is the constant's index).
 struct LdsStageReader {
     const lds_u8* o;
     const lds_u32* p;
@@ -699,8 +700,8 @@ struct LdsStageReader {
         const uint32_t b = o[k - lo];
         return b == kOpByteBadConst ? kOpBadConst : b;
     }
-    __device__ uint32_t arg(int64_t k) const { return p[k - lo]; }
-    __device__ float cval(int64_t k) const { return __uint_as_float(p[k - lo]); }
+    __device__ uint32_t pay(int64_t k) const { return p[k - lo]; }
+    __device__ float cval(int64_t, uint32_t pay) const { return __uint_as_float(pay); }
 };
 struct GlobalStageReader {
     const uint32_t* __restrict__ n;
@@ -711,8 +712,8 @@ struct GlobalStageReader {
         const uint32_t w = n[k], op = w & 0xFFu;
         return op == GP_CONST && (int64_t)(w >> 8) >= n_consts ? kOpBadConst : op;
     }
-    __device__ uint32_t arg(int64_t k) const { return n[k] >> 8; }
-    __device__ float cval(int64_t k) const { return c[n[k] >> 8]; }
+    __device__ uint32_t pay(int64_t k) const { return n[k] >> 8; }
+    __device__ float cval(int64_t, uint32_t pay) const { return c[pay]; }
 };
 
 // LDS words of a staging block's node copy: the general walk's node

@@ -10,7 +10,7 @@
 // make_uint2, __float_as_uint, the LDS float type lds_f32, kHeldConsts and
 // kBucketBlock, the folding functions binary_value(op, a, b) and
 // unary_value(op, x) for the benchmark set, and GP_STAGING_FN (the
-// qualifier of the two walks: __device__ in the library).
+// qualifier of the walks: __device__ in the library).
 #pragma once
 
 // Staged instruction flags (see k_stage).  A leaf directly followed by a
@@ -352,8 +352,11 @@ GP_STAGING_FN void check_program(Nodes nodes, int64_t s, int64_t e, uint32_t all
 // each program, and the loop body is what the walk costs per node.
 //
 // Its reader gives, for node k: op(k), the opcode, or kOpBadConst for a
-// constant whose index is out of range; arg(k), a variable's index; and
-// cval(k), a constant's value (asked for constants in range only).
+// constant whose index is out of range; pay(k), the node's payload word (a
+// variable's index, or what cval turns into a constant's value); and
+// cval(k, pay(k)), a constant's value (asked for constants in range only).
+// The walk reads op(k), pay(k) and op(k + 1) together at each step, so one
+// memory round trip serves the step.
 constexpr uint32_t kOpBadConst = 0x100u | GP_CONST;
 
 // check_program and stage_walk in one pass, for a mask within
@@ -403,9 +406,12 @@ GP_STAGING_FN int64_t stage_check_base(Reader rd, int64_t s, int64_t e, uint32_t
         }
         np = 0;
     };
+    float top = 0.f;                             // pv(np - 1) while np >= 1
     for (int64_t k = s; k < e; ++k) {
         const uint32_t op = rd.op(k);
-        const uint32_t arg = op == GP_LOAD ? rd.arg(k) : 0u;
+        const uint32_t pay = rd.pay(k);
+        const uint32_t nx = k + 1 < e ? rd.op(k + 1) : 0xFFu;
+        const uint32_t arg = op == GP_LOAD ? pay : 0u;
         int code = check(op, arg, rt + np);
         if (code != GP_PROG_OK) {
             st = code;
@@ -413,13 +419,13 @@ GP_STAGING_FN int64_t stage_check_base(Reader rd, int64_t s, int64_t e, uint32_t
         }
         if (op == GP_CONST) {
             if (np == kHeldConsts) flush();
-            pv(np) = rd.cval(k);
+            top = rd.cval(k, pay);
+            pv(np) = top;
             ++np;
             md = rt + np > md ? rt + np : md;
         } else if (op == GP_LOAD) {
             flush();
             md = rt + 1 > md ? rt + 1 : md;
-            const uint32_t nx = k + 1 < e ? rd.op(k + 1) : 0xFFu;
             const bool fb = nx - GP_ADD < 4u, fu = nx - GP_SIN < 6u;
             if (fb || fu) {
                 // the operator after the variable, at the depth the push left
@@ -442,18 +448,20 @@ GP_STAGING_FN int64_t stage_check_base(Reader rd, int64_t s, int64_t e, uint32_t
         } else if (op <= GP_DIV) {
             if (np >= 2) {
                 --np;
-                pv(np - 1) = binary_value(op, pv(np - 1), pv(np));
+                top = binary_value(op, pv(np - 1), top);
+                pv(np - 1) = top;
             } else if (np == 1) {
                 // top = top OP c: the runtime top is the left operand
                 np = 0;
-                put(staged_word(kFLBin | kFConst, op - GP_ADD, 0u, __float_as_uint(pv(0))));
+                put(staged_word(kFLBin | kFConst, op - GP_ADD, 0u, __float_as_uint(top)));
             } else {
                 // second from top (element rt-2) is read from cell rt-2
                 put(staged_word(kFSBin, op - GP_ADD, (uint32_t)(rt - 2), 0u));
                 --rt;
             }
         } else if (np >= 1) {
-            pv(np - 1) = unary_value(op, pv(np - 1));
+            top = unary_value(op, top);
+            pv(np - 1) = top;
         } else {
             put(staged_word(kFUn, op - GP_SIN, 0u, 0u));
         }

@@ -74,7 +74,7 @@ struct Consts {
     float operator()(uint32_t j) const { return p[j]; }
 };
 // reader of the benchmark-set walk: op (kOpBadConst for a constant out of
-// range), variable index, constant value
+// range), payload (the node's argument), constant value
 struct BaseReader {
     const uint32_t* p;
     const float* c;
@@ -84,8 +84,8 @@ struct BaseReader {
         const uint32_t o = p[k] & 0xFFu;
         return o == GP_CONST && (int64_t)(p[k] >> 8) >= nc ? kOpBadConst : o;
     }
-    uint32_t arg(int64_t k) const { return p[k] >> 8; }
-    float cval(int64_t k) const { return c[p[k] >> 8]; }
+    uint32_t pay(int64_t k) const { return p[k] >> 8; }
+    float cval(int64_t, uint32_t pay) const { return c[pay]; }
 };
 
 // The benchmark-set walk against the general ones for a mask within the
