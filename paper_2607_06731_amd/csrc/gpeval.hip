@@ -1956,10 +1956,19 @@ struct ReduceArgs {
     int64_t n_programs;
     int32_t part_stride;    // tile stride of the partials (the program count)
     double max_score;
+    int32_t* restage;       // k_validate's restage flag, cleared for the next call
 };
+
+// The restage flag is cleared here as well as by k_tables, for plans that
+// run k_tables once, when they are captured.
+__device__ __forceinline__ void clear_restage(const ReduceArgs& a)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.restage = 0;
+}
 
 __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
 {
+    clear_restage(a);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n_programs) return;
     const int r = a.pds[p];
@@ -1989,6 +1998,7 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceArgs a)
 // constant output or target gives exactly zero: every shifted value is 0).
 __global__ __launch_bounds__(256) void k_reduce_corr(ReduceArgs a)
 {
+    clear_restage(a);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n_programs) return;
     const int r = a.pds[p];
@@ -2021,6 +2031,7 @@ __global__ __launch_bounds__(256) void k_reduce_corr(ReduceArgs a)
 // int64 totals added exactly, returned as a double (exact below 2^53).
 __global__ __launch_bounds__(256) void k_reduce_reward(ReduceArgs a)
 {
+    clear_restage(a);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n_programs) return;
     const int r = a.pds[p];
@@ -2461,15 +2472,25 @@ int configure_eval(const Problem& pb, const Tuning& tu, EvalLaunch* el)
 
 // Dataset/segment tables, validation, staging and the stable (depth class,
 // length) partition.
-int enqueue_stage(const Problem& pb, const Tuning& tu, const Staged& st, int32_t target_items,
-                  hipStream_t stream)
+int enqueue_tables(const Problem& pb, const Tuning& tu, const Staged& st, hipStream_t stream)
 {
-    const int32_t n_blk = (int32_t)((pb.n_programs + kBucketBlock - 1) / kBucketBlock);
     hipLaunchKernelGGL(k_tables, dim3(1), dim3(256), 0, stream, pb.ds_dev, pb.n_ds, pb.one,
                        pb.req_dev, pb.n_req, pb.one_req, pb.n_programs, pb.n_nodes, pb.max_vars,
                        pb.max_cases, pb.need_out, tu.tile_lds, tu.tile_max, st.ds, st.req,
                        st.seg_ds, st.seg_start, st.bad);
     GP_HIP_TRY(hipGetLastError());
+    return GP_OK;
+}
+
+// tables_ready: the dataset and request tables in `st` are already those
+// of this problem and tuning (a plan derives them once, when captured:
+// its tables are kernel arguments, fixed for its life).
+int enqueue_stage(const Problem& pb, const Tuning& tu, const Staged& st, int32_t target_items,
+                  hipStream_t stream, bool tables_ready = false)
+{
+    const int32_t n_blk = (int32_t)((pb.n_programs + kBucketBlock - 1) / kBucketBlock);
+    int rc;
+    if (!tables_ready && (rc = enqueue_tables(pb, tu, st, stream)) != GP_OK) return rc;
     const int32_t lpt = pb.n_req == 1 ? 1 : 0;
     hipLaunchKernelGGL(k_validate, dim3(n_blk), dim3(kBucketBlock), 0, stream, pb.n_programs,
                        pb.allowed, st.ds, st.req, st.seg_start, pb.n_req, st.bad, lpt, n_blk,
@@ -2509,11 +2530,11 @@ void launch_eval(bool ext, dim3 g, size_t lds, hipStream_t sc, const Staged& st,
 // The whole evaluation as stream work (no allocation, no synchronization:
 // safe to capture into a graph).
 int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, const Staged& st,
-                 SideStreams& side, hipStream_t stream, CallEvents& ce)
+                 SideStreams& side, hipStream_t stream, CallEvents& ce, bool tables_ready = false)
 {
     int rc;
     if ((rc = ce.mark(0, stream)) != GP_OK) return rc;
-    if ((rc = enqueue_stage(pb, tu, st, el.target_items, stream)) != GP_OK) return rc;
+    if ((rc = enqueue_stage(pb, tu, st, el.target_items, stream, tables_ready)) != GP_OK) return rc;
     if (pb.n_req > 1) {
         hipLaunchKernelGGL(k_seg_tables, dim3(1), dim3(256), 0, stream, st.order, st.class_info,
                            st.seg_start, pb.n_req, st.bad, st.seg_ds, st.ds, group_capacity(pb, tu),
@@ -2575,6 +2596,7 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
     ra.part = st.part; ra.part_bad = st.part_bad; ra.part_corr = st.part_corr;
     ra.n_programs = pb.n_programs; ra.part_stride = (int32_t)pb.n_programs;
     ra.max_score = pb.max_score;
+    ra.restage = st.restage;
     if ((rc = ce.mark(4, stream)) != GP_OK) return rc;
     if (pb.fit == kFitCorr)
         hipLaunchKernelGGL(k_reduce_corr, dim3((unsigned)((pb.n_programs + 255) / 256)), dim3(256),
@@ -2711,11 +2733,16 @@ int plan_build(gp_plan* p)
         p->ws_bytes = p->el.layout.total;
     }
     p->st = carve(p->ws, p->el.layout);
+    // replays of a previous graph may still read the workspace
+    if (p->exec) GP_HIP_TRY(hipDeviceSynchronize());
     plan_release_graph(p);
+    // the plan's tables (kernel arguments only) once, outside the graph
+    if ((rc = enqueue_tables(p->pb, p->tu, p->st, p->cap)) != GP_OK) return rc;
+    GP_HIP_TRY(hipStreamSynchronize(p->cap));
     GP_HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
     CallEvents none;
     (void)none.begin(false);
-    rc = enqueue_eval(p->pb, p->tu, p->el, p->st, p->side, p->cap, none);
+    rc = enqueue_eval(p->pb, p->tu, p->el, p->st, p->side, p->cap, none, true);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(p->cap, &g);
     if (rc != GP_OK) {

@@ -109,6 +109,34 @@ def test_plan_autotune_and_inplace_update():
     plan.close()
 
 
+def test_plan_replays_follow_offsets_written_in_place():
+    """A plan derives its dataset and request tables once; each replay still
+    follows the offsets as they are then: offsets rewritten to decrease
+    somewhere (every program staged again, packed) and back (staged in
+    place) give gp_eval's bits on every replay."""
+    gp = _gp()
+    import torch
+    from paper_2607_06731_amd import synth
+    w = synth.make_workload("generation", n_programs=20000, n_cases=1500)
+    pop = gp.DevicePopulation(w.pop.nodes, w.pop.offsets, w.pop.consts)
+    data = gp.DeviceDataset(w.data.X, w.data.y)
+    out = torch.empty(pop.n_programs, dtype=torch.float64, device="cuda")
+    _say("plan replays with offsets rewritten in place")
+    plan = gp.Plan(pop, data, w.tax, out, allowed_op_mask=w.allowed_mask,
+                   tuning={"concurrent_classes": 2})
+    bad = w.pop.offsets.copy()
+    bad[101] = bad[100] - 1                  # program 100 ends before it starts
+    for off in (w.pop.offsets, bad, w.pop.offsets, bad):
+        pop.offsets.copy_(torch.from_numpy(off).cuda())
+        plan.launch()
+        torch.cuda.synchronize()
+        ref, st = gp.evaluate(w.pop.nodes, off, w.pop.consts, w.data.X, w.data.y, w.tax,
+                              w.allowed_mask, return_status=True)
+        assert np.array_equal(out.cpu().numpy(), ref, equal_nan=True)
+        assert (st[100] == 8) == (off is bad)
+    plan.close()
+
+
 def test_tile_knobs_deterministic_and_gated():
     """Window budgets and tile caps other than gp_eval's group the cases
     differently: every replay gives the same bits, and the results pass the
