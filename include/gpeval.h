@@ -386,7 +386,8 @@ typedef struct {
     int32_t concurrent_classes;  /* 1: depth classes run on forked streams; 2: as 1,
                                     and the depth <= 8 class runs one workgroup
                                     per CU below its limit, so that the deeper
-                                    classes run beside it from the start */
+                                    classes (whose wavefronts issue first) run
+                                    beside it from the start */
     int32_t tile_lds_bytes;      /* LDS budget of an input window, 4096..65536
                                     (default 24576) */
     int32_t max_tiles;           /* case tiles per program, at most, 1..32

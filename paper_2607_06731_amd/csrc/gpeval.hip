@@ -1638,6 +1638,11 @@ __global__ __launch_bounds__(kWG) void k_eval(
     // integer reward mode: one int64 total per program
     long long* racc = reinterpret_cast<long long*>(lds + a.tile_floats);     // [G]
     __shared__ uint32_t s_item, s_next;
+    // With the classes overlapped, a deeper class's workgroups run beside
+    // the depth <= 8 class's; their wavefronts issue first there, so the
+    // deeper classes, which end last, finish sooner (alone, all wavefronts
+    // of a kernel share one priority and nothing changes).
+    if constexpr (MAXD >= 16) __builtin_amdgcn_s_setprio(1);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -2410,7 +2415,8 @@ int eval_grid(int n_vars, int G, const Tuning& tu, int cus, int* grid, size_t* l
     // overlapped classes: the depth <= 8 class (launched first) runs one
     // workgroup per CU below its limit, so that the registers and LDS left
     // over hold a deeper class's workgroup from the start instead of its
-    // whole run waiting for the first class to drain
+    // whole run waiting for the first class to drain (and k_eval gives the
+    // deeper classes' wavefronts issue priority)
     if (MAXD == 8 && tu.concurrent == 2 && per_cu > 1) --per_cu;
     *grid = cus * per_cu;
     *lds_out = lds;
