@@ -2400,7 +2400,8 @@ inline bool pb_ext(uint32_t allowed) { return (allowed & ~GP_BASE_OPS) != 0u; }
 
 // Grid size of one class kernel (LDS attribute set outside any capture).
 template <int MAXD, int K, int FIT, bool EXT>
-int eval_grid(int n_vars, int G, const Tuning& tu, int cus, int* grid, size_t* lds_out)
+int eval_grid(int n_vars, int G, const Tuning& tu, int cus, int* grid, size_t* lds_out,
+              int* refill = nullptr)
 {
     const int wg_per_cu = tu.wg_per_cu;
     const size_t lds = eval_lds_bytes<MAXD, K, FIT>(n_vars, G, tu.tile_lds);
@@ -2417,7 +2418,13 @@ int eval_grid(int n_vars, int G, const Tuning& tu, int cus, int* grid, size_t* l
     // over hold a deeper class's workgroup from the start instead of its
     // whole run waiting for the first class to drain (and k_eval gives the
     // deeper classes' wavefronts issue priority)
-    if (MAXD == 8 && tu.concurrent == 2 && per_cu > 1) --per_cu;
+    if (MAXD == 8 && tu.concurrent == 2 && per_cu > 1) {
+        --per_cu;
+        // the slot comes back once the deeper classes are done: a second
+        // launch of one workgroup per CU on the stream of the last of them
+        // joins the same work queue
+        if (refill) *refill = cus;
+    }
     *grid = cus * per_cu;
     *lds_out = lds;
     return GP_OK;
@@ -2427,6 +2434,7 @@ struct EvalLaunch {
     int32_t stride = 1;
     int32_t target_items = 1;   // work items per class worth keeping large groups for
     int grid[kClasses] = {0, 0, 0};
+    int refill0 = 0;            // workgroups of the depth <= 8 class's second launch
     size_t lds[kClasses] = {0, 0, 0};
     Layout layout;
 };
@@ -2442,7 +2450,8 @@ template <int FIT, bool EXT>
 int eval_grids(const Problem& pb, const Tuning& tu, int G, int cus, EvalLaunch* el)
 {
     int rc;
-    if ((rc = eval_grid<8, 4, FIT, EXT>(pb.max_vars, G, tu, cus, &el->grid[0], &el->lds[0])) != GP_OK) return rc;
+    if ((rc = eval_grid<8, 4, FIT, EXT>(pb.max_vars, G, tu, cus, &el->grid[0], &el->lds[0],
+                                        &el->refill0)) != GP_OK) return rc;
     if ((rc = eval_grid<16, kK1, FIT, EXT>(pb.max_vars, G, tu, cus, &el->grid[1], &el->lds[1])) != GP_OK) return rc;
     return eval_grid<32, 2, FIT, EXT>(pb.max_vars, G, tu, cus, &el->grid[2], &el->lds[2]);
 }
@@ -2588,6 +2597,19 @@ int enqueue_eval(const Problem& pb, const Tuning& tu, const EvalLaunch& el, cons
             GP_LAUNCH_EVAL(32, 2);
         }
 #undef GP_LAUNCH_EVAL
+        GP_HIP_TRY(hipGetLastError());
+    }
+    if (el.refill0 > 0 && tu.concurrent == 2) {
+        // the depth <= 8 class takes back its slot after the depth <= 16
+        // class (same work counter: the items are shared, each taken once)
+        ea.cls = 0;
+        ea.tile_floats = (int32_t)eval_tile_floats<8, 4>(pb.max_vars, tu.tile_lds);
+        const dim3 g(el.refill0);
+        const int c = 0;
+        const hipStream_t sc = side.s[0];
+        if (pb.fit == kFitCorr) launch_eval<8, 4, kFitCorr>(ext, g, el.lds[c], sc, st, c, ea);
+        else if (pb.fit == kFitReward) launch_eval<8, 4, kFitReward>(ext, g, el.lds[c], sc, st, c, ea);
+        else launch_eval<8, 4, kFitMse>(ext, g, el.lds[c], sc, st, c, ea);
         GP_HIP_TRY(hipGetLastError());
     }
     if (tu.concurrent) {
