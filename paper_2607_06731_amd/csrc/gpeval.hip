@@ -116,6 +116,8 @@ constexpr int kStageNodes = 6656;        // LDS node cache of a staging block (2
 // which with the held constants keeps four staging blocks per CU.
 constexpr int kStageNodesEmit = 6144;
 constexpr uint32_t kOpByteBadConst = 0xFEu;   // its op byte of a constant out of range
+// Fourth word of a raw buffer resource on gfx9 parts (32-bit data format).
+constexpr int kBufferWord3 = 0x00020000;
 // Constants held back for folding per program while staging: a longer run
 // of constants is pushed (as runtime values) before the next one is held.
 // 16 keeps the staging block at four per CU (with the node cache).
@@ -583,10 +585,20 @@ __device__ bool block_node_range(bool mine, int r, int64_t s, int64_t e, int cap
         s_any = 0;
     }
     __syncthreads();
-    if (mine) {
-        atomicMin(&s_lo, (long long)s);
-        atomicMax(&s_hi, (long long)e);
-        atomicMax(&s_r, r);
+    // reduced inside each wavefront first: one LDS atomic per wavefront
+    // instead of one per thread
+    long long wlo = mine ? (long long)s : LLONG_MAX, whi = mine ? (long long)e : LLONG_MIN;
+    int wr = mine ? r : -1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        wlo = min(wlo, __shfl_xor(wlo, off));
+        whi = max(whi, __shfl_xor(whi, off));
+        wr = max(wr, __shfl_xor(wr, off));
+    }
+    if ((threadIdx.x & 63) == 0 && wr >= 0) {
+        atomicMin(&s_lo, wlo);
+        atomicMax(&s_hi, whi);
+        atomicMax(&s_r, wr);
         s_any = 1;
     }
     __syncthreads();
@@ -645,38 +657,38 @@ __device__ bool cache_block_stage(bool mine, int r, int64_t s, int64_t e,
     int rq = 0, n = 0;
     const bool use = block_node_range(mine, r, s, e, kStageNodesEmit, &rq, lo, &n);
     if (use) {
-        // 24 loads in flight per thread and round: a round covers 3072
-        // nodes (24 per program), and the node loads and the constant
-        // gather are waited out once per round (more in flight would take
-        // registers beyond two wavefronts per SIMD)
-        constexpr int kU = 24;
-        const uint32_t* __restrict__ src = reqs[rq].nodes + *lo;
-        const float* __restrict__ cs = reqs[rq].consts;
+        // one round: each thread has all its loads in flight at once (the
+        // block's cache, 48 nodes per program), then all its constants'
+        // gathers; raw buffer loads take a 32-bit lane offset plus the
+        // round-invariant row offset as a scalar, so the loads in flight
+        // cost one register each (loads past a range read 0)
+        constexpr int kU = kStageNodesEmit / kBucketBlock;
         const int64_t nc = reqs[rq].n_consts;
-        const int step = (int)blockDim.x * kU;
-        for (int i0 = 0; i0 < n; i0 += step) {
-            uint32_t v[kU];
+        const __amdgpu_buffer_rsrc_t nr = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint32_t*>(reqs[rq].nodes + *lo), 0, n * 4, kBufferWord3);
+        const __amdgpu_buffer_rsrc_t cr = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(reqs[rq].consts), 0, (int)(nc * 4), kBufferWord3);
+        const int t4 = (int)threadIdx.x * 4;
+        uint32_t v[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
-                v[u] = i < n ? src[i] : 0xFFu;
-            }
-            float c[kU];
+        for (int u = 0; u < kU; ++u)
+            v[u] = __builtin_amdgcn_raw_buffer_load_b32(nr, t4, u * kBucketBlock * 4, 0);
+        uint32_t c[kU];
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const uint32_t a = v[u] >> 8;
-                c[u] = (v[u] & 0xFFu) == GP_CONST && (int64_t)a < nc ? cs[a] : 0.f;
-            }
+        for (int u = 0; u < kU; ++u) {
+            const uint32_t a = v[u] >> 8;
+            c[u] = (v[u] & 0xFFu) == GP_CONST ? __builtin_amdgcn_raw_buffer_load_b32(cr, (int)(a * 4u), 0, 0)
+                                              : 0u;
+        }
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
-                if (i < n) {
-                    const uint32_t op = v[u] & 0xFFu;
-                    const bool cst = op == GP_CONST;
-                    const bool bad = cst && (int64_t)(v[u] >> 8) >= nc;
-                    ops[i] = (uint8_t)(bad ? kOpByteBadConst : (op < 32u ? op : 0xFFu));
-                    pay[i] = cst ? __float_as_uint(c[u]) : v[u] >> 8;
-                }
+        for (int u = 0; u < kU; ++u) {
+            const int i = u * kBucketBlock + (int)threadIdx.x;
+            if (i < n) {
+                const uint32_t op = v[u] & 0xFFu;
+                const bool cst = op == GP_CONST;
+                const bool bad = cst && (int64_t)(v[u] >> 8) >= nc;
+                ops[i] = (uint8_t)(bad ? kOpByteBadConst : (op < 32u ? op : 0xFFu));
+                pay[i] = cst ? (bad ? 0u : c[u]) : v[u] >> 8;
             }
         }
     }
@@ -770,6 +782,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
     int64_t lo = 0;
     const bool cached = base ? cache_block_stage(mine, r, s, e, reqs, ops, cache, &lo)
                              : cache_block_nodes(mine, r, s, e, reqs, cache, &lo);
+    long long slen = 0;                       // this program's staged size
     if (have) {
         int status = GP_PROG_OK;
         int maxd = 0;
@@ -812,9 +825,13 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
         const int key = c >= 0 ? c * kLenBuckets + (lpt ? kLenBuckets - 1 - lb : 0) : 0xFF;
         cls[p] = (uint8_t)key;
         if (key < kKeys) atomicAdd(&cnt[key], 1);
-        if (m.slen) atomicAdd(&s_slen, (unsigned long long)m.slen);
+        slen = m.slen;
         if (R.out_status && q < R.n_programs) R.out_status[q] = status;
     }
+    // the block's staged size, summed in each wavefront first
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) slen += __shfl_xor(slen, off);
+    if ((threadIdx.x & 63) == 0 && slen) atomicAdd(&s_slen, (unsigned long long)slen);
     __syncthreads();
     if (threadIdx.x < kKeys) blk_counts[threadIdx.x * n_blk + blockIdx.x] = cnt[threadIdx.x];
     if (threadIdx.x == 0) blk_slen[blockIdx.x] = (int64_t)s_slen;
