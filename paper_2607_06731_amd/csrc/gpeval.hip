@@ -783,6 +783,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
     const bool cached = base ? cache_block_stage(mine, r, s, e, reqs, ops, cache, &lo)
                              : cache_block_nodes(mine, r, s, e, reqs, cache, &lo);
     long long slen = 0;                       // this program's staged size
+    int pkey = 0xFF;                          // and its partition key
     if (have) {
         int status = GP_PROG_OK;
         int maxd = 0;
@@ -824,14 +825,23 @@ __global__ __launch_bounds__(kBucketBlock) void k_validate(
         lb = lb < kLenBuckets - 1 ? lb : kLenBuckets - 1;
         const int key = c >= 0 ? c * kLenBuckets + (lpt ? kLenBuckets - 1 - lb : 0) : 0xFF;
         cls[p] = (uint8_t)key;
-        if (key < kKeys) atomicAdd(&cnt[key], 1);
+        pkey = key;
         slen = m.slen;
         if (R.out_status && q < R.n_programs) R.out_status[q] = status;
+    }
+    // per-key counts: one LDS atomic per distinct key in the wavefront
+    const int lane = threadIdx.x & 63;
+    for (uint64_t todo = __ballot(pkey < kKeys); todo != 0ull;) {
+        const int first = __ffsll((unsigned long long)todo) - 1;
+        const int k0 = __shfl(pkey, first);
+        const uint64_t same = __ballot(pkey == k0);
+        if (lane == first) atomicAdd(&cnt[k0], (int)__popcll(same));
+        todo &= ~same;
     }
     // the block's staged size, summed in each wavefront first
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) slen += __shfl_xor(slen, off);
-    if ((threadIdx.x & 63) == 0 && slen) atomicAdd(&s_slen, (unsigned long long)slen);
+    if (lane == 0 && slen) atomicAdd(&s_slen, (unsigned long long)slen);
     __syncthreads();
     if (threadIdx.x < kKeys) blk_counts[threadIdx.x * n_blk + blockIdx.x] = cnt[threadIdx.x];
     if (threadIdx.x == 0) blk_slen[blockIdx.x] = (int64_t)s_slen;
@@ -1096,10 +1106,15 @@ __global__ __launch_bounds__(kBucketBlock) void k_stage(
     const int wave = t >> 6, lane = t & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int rank = 0;
-    for (int kk = 0; kk < kKeys; ++kk) {
-        const uint64_t bm = __ballot(key == kk);
-        if (lane == 0) wcnt[wave][kk] = __popcll(bm);
-        if (key == kk) rank = __popcll(bm & below);
+    if (lane < kKeys) wcnt[wave][lane] = 0;
+    // one pass per distinct key in the wavefront
+    for (uint64_t todo = __ballot(key < kKeys); todo != 0ull;) {
+        const int first = __ffsll((unsigned long long)todo) - 1;
+        const int k0 = __shfl(key, first);
+        const uint64_t bm = __ballot(key == k0);
+        if (lane == first) wcnt[wave][k0] = __popcll(bm);
+        if (key == k0) rank = __popcll(bm & below);
+        todo &= ~bm;
     }
     __syncthreads();
     if (key < kKeys) {
