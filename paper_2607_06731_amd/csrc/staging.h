@@ -374,12 +374,12 @@ GP_STAGING_FN int64_t stage_check_base(Reader rd, int64_t s, int64_t e, uint32_t
 #define pv(i) pvs[(i) * kBucketBlock]
     int rt = 0, np = 0, md = 0, st = GP_PROG_OK;
     int64_t n = 0;
-    // each word is stored when the next one is made, so that the last one
-    // is stored once, with kFLast
-    uint2 prev = make_uint2(0u, 0u);
+    // each word is stored as it is made; the last one is stored again at
+    // the end, with kFLast
+    uint2 last = make_uint2(0u, 0u);
     auto put = [&](uint2 v) {
-        if (n > 0) out[n - 1] = prev;
-        prev = v;
+        out[n] = v;
+        last = v;
         ++n;
     };
     // one node's checks at depth d: the last test that fails names the
@@ -469,7 +469,7 @@ GP_STAGING_FN int64_t stage_check_base(Reader rd, int64_t s, int64_t e, uint32_t
     if (st == GP_PROG_OK && rt + np != 1) st = GP_PROG_FINAL_DEPTH;
     if (st == GP_PROG_OK) {
         flush();                                 // a constant program: its value is pushed
-        out[n - 1] = make_uint2(prev.x | kFLast, prev.y);
+        out[n - 1] = make_uint2(last.x | kFLast, last.y);
     }
     status = st;
     maxd = md;
