@@ -698,6 +698,7 @@ __device__ bool cache_block_stage(bool mine, int r, int64_t s, int64_t e,
 
 #define GP_STAGING_FN __device__
 #include "staging.h"
+static_assert(kOpByteBadConst == kOpBadConst, "the LDS copy stores the walk's opcodes as they are");
 
 // Readers of the benchmark-set walk (stage_check_base): op (kOpBadConst
 // for a constant out of range), payload word, constant value, from the
@@ -707,11 +708,7 @@ struct LdsStageReader {
     const lds_u8* o;
     const lds_u32* p;
     int64_t lo;
-    __device__ uint32_t op(int64_t k) const
-    {
-        const uint32_t b = o[k - lo];
-        return b == kOpByteBadConst ? kOpBadConst : b;
-    }
+    __device__ uint32_t op(int64_t k) const { return o[k - lo]; }
     __device__ uint32_t pay(int64_t k) const { return p[k - lo]; }
     __device__ float cval(int64_t, uint32_t pay) const { return __uint_as_float(pay); }
 };
@@ -721,7 +718,7 @@ struct GlobalStageReader {
     int64_t n_consts;
     __device__ uint32_t op(int64_t k) const
     {
-        const uint32_t w = n[k], op = w & 0xFFu;
+        const uint32_t w = n[k], op = (w & 0xFFu) < 32u ? (w & 0xFFu) : 0xFFu;
         return op == GP_CONST && (int64_t)(w >> 8) >= n_consts ? kOpBadConst : op;
     }
     __device__ uint32_t pay(int64_t k) const { return n[k] >> 8; }

@@ -351,13 +351,14 @@ GP_STAGING_FN void check_program(Nodes nodes, int64_t s, int64_t e, uint32_t all
 // the cell moves, and it validates and emits in one pass: one thread walks
 // each program, and the loop body is what the walk costs per node.
 //
-// Its reader gives, for node k: op(k), the opcode, or kOpBadConst for a
-// constant whose index is out of range; pay(k), the node's payload word (a
+// Its reader gives, for node k: op(k), the opcode (0xFF for any opcode
+// from 32 up), or kOpBadConst for a constant whose index is out of range;
+// pay(k), the node's payload word (a
 // variable's index, or what cval turns into a constant's value); and
 // cval(k, pay(k)), a constant's value (asked for constants in range only).
 // The walk reads op(k), pay(k) and op(k + 1) together at each step, so one
 // memory round trip serves the step.
-constexpr uint32_t kOpBadConst = 0x100u | GP_CONST;
+constexpr uint32_t kOpBadConst = 0xFEu;
 
 // check_program and stage_walk in one pass, for a mask within
 // GP_BASE_OPS: the same checks in the same order (op, operand range,

@@ -81,7 +81,7 @@ struct BaseReader {
     int64_t nc;
     uint32_t op(int64_t k) const
     {
-        const uint32_t o = p[k] & 0xFFu;
+        const uint32_t o = (p[k] & 0xFFu) < 32u ? (p[k] & 0xFFu) : 0xFFu;
         return o == GP_CONST && (int64_t)(p[k] >> 8) >= nc ? kOpBadConst : o;
     }
     uint32_t pay(int64_t k) const { return p[k] >> 8; }
