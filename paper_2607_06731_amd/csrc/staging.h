@@ -429,8 +429,11 @@ GP_STAGING_FN int64_t stage_check_base(Reader rd, int64_t s, int64_t e, uint32_t
             md = rt + 1 > md ? rt + 1 : md;
             const bool fb = nx - GP_ADD < 4u, fu = nx - GP_SIN < 6u;
             if (fb || fu) {
-                // the operator after the variable, at the depth the push left
-                code = check(nx, 0u, rt + 1);
+                // the operator after the variable, at the depth rt + 1 the
+                // push left (within the limit, as the push was checked):
+                // only its mask bit and, for a binary op, underflow remain
+                code = !((allowed >> nx) & 1u) ? GP_PROG_BAD_OP
+                                               : (fb && rt == 0 ? GP_PROG_UNDERFLOW : GP_PROG_OK);
                 if (code != GP_PROG_OK) {
                     st = code;
                     break;
