@@ -973,11 +973,21 @@ __global__ __launch_bounds__(1024) void k_class_scan(
     }
     if (t < kClasses) {
         // exclusive prefix of entry i from the scanned chunk sums (LDS)
+        // and the entries before it in its chunk, loaded all at once
         auto prefix = [&](int i) {
             if (i >= total) return part[1023];
             const int owner = i / chunk;
             int b = owner > 0 ? part[owner - 1] : 0;
-            for (int j = owner * chunk; j < i; ++j) b += blk_counts[j];
+            const int j0 = owner * chunk;
+            if (chunk <= 32) {
+                int v[32];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) v[u] = j0 + u < i ? blk_counts[j0 + u] : 0;
+#pragma unroll
+                for (int u = 0; u < 32; ++u) b += v[u];
+            } else {
+                for (int j = j0; j < i; ++j) b += blk_counts[j];
+            }
             return b;
         };
         const bool ovf = lpart[1023] > code_capacity;
